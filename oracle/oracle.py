@@ -1,0 +1,338 @@
+"""Python side of the FP64 CPU oracle (test infrastructure only).
+
+Only the test-suite, the smoke check and the benchmark's CPU-baseline leg may
+import this module.  It loads ``oracle/liboracle.so`` (built from
+``oracle/rco.c`` by ``oracle/build.py``) and adds the parts of the method that
+are plain linear algebra, written here in numpy:
+
+* the validity radius of a record (Sec. 5, Eq. radiusAniso3D, with the
+  isotropic choice of the largest |eigenvalue| as in Sec. 6);
+* the multi-point interpolation of a cache (Sec. 5, Eq. radianceTaylor, with
+  the cubic kernel);
+* an FP64 reference of the small MLP used for learned placement (not part of
+  the paper).
+
+Nothing here is shared with the GPU library.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from pathlib import Path
+
+import numpy as np
+
+_HERE = Path(__file__).resolve().parent
+_LIB = None
+
+
+def lib():
+    global _LIB
+    if _LIB is None:
+        path = _HERE / "liboracle.so"
+        if not path.exists():
+            from . import build as _b  # noqa: F401  (oracle/build.py)
+            _b.build()
+        L = C.CDLL(str(path))
+        vp, i64, f32, i32, u64 = C.c_void_p, C.c_int64, C.c_float, C.c_int, C.c_uint64
+        L.rco_scene_create.argtypes = [vp, vp, vp, i64, vp, vp, C.POINTER(vp)]
+        L.rco_scene_create.restype = i32
+        L.rco_scene_destroy.argtypes = [vp]
+        L.rco_scene_destroy.restype = None
+        L.rco_records.argtypes = [vp, f32, f32, vp, i32, vp, vp, vp, vp, i64, f32, i32, u64, vp,
+                                  vp, vp, vp, vp, i32]
+        L.rco_records.restype = i32
+        L.rco_trace.argtypes = [vp, vp, vp, i64, i32, vp, vp, vp]
+        L.rco_trace.restype = i32
+        L.rco_occluded.argtypes = [vp, vp, vp, vp, i64, i32, vp]
+        L.rco_occluded.restype = i32
+        L.rco_formfactor.argtypes = [vp, vp, vp, vp, vp, vp]
+        L.rco_formfactor.restype = None
+        L.rco_transmittance.argtypes = [vp, vp, C.c_double, vp, vp, vp]
+        L.rco_transmittance.restype = None
+        L.rco_directions.argtypes = [u64, u64, i32, i32, vp]
+        L.rco_directions.restype = i32
+        L.rco_triangles.argtypes = [vp, i32, i32, vp]
+        L.rco_triangles.restype = i32
+        L.rco_unif.argtypes = [u64, u64, u64, u64]
+        L.rco_unif.restype = f32
+        L.rco_splitmix64.argtypes = [u64]
+        L.rco_splitmix64.restype = u64
+        L.rco_nstat.restype = i32
+        _LIB = L
+    return _LIB
+
+
+def _p(a):
+    return None if a is None else a.ctypes.data_as(C.c_void_p)
+
+
+def _c(a, dt):
+    return np.ascontiguousarray(a, dtype=dt)
+
+
+STAT_NAMES = ["rays", "terms_ss", "terms_ms", "SG_ss", "SH_ss", "SG_ms", "SH_ms", "tri_value_ss",
+              "tri_value_ms", "hess_asym", "max_rings_used", "n_triangles"]
+
+
+class Scene:
+    """Host copy of a triangle scene with the oracle's own acceleration."""
+
+    def __init__(self, tri, albedo, emission=None, box_lo=(0, 0, 0), box_hi=(1, 1, 1)):
+        self.tri = _c(tri, np.float32).reshape(-1, 9)
+        self.albedo = _c(albedo, np.float32)
+        self.emission = None if emission is None else _c(emission, np.float32)
+        self.box_lo = _c(box_lo, np.float32)
+        self.box_hi = _c(box_hi, np.float32)
+        h = C.c_void_p()
+        rc = lib().rco_scene_create(_p(self.tri), _p(self.albedo), _p(self.emission), self.tri.shape[0],
+                                    _p(self.box_lo), _p(self.box_hi), C.byref(h))
+        if rc != 0:
+            raise RuntimeError(f"rco_scene_create failed ({rc})")
+        self._h = h
+
+    @classmethod
+    def from_workload(cls, w):
+        return cls(w.tri, w.albedo, w.emission, w.box_lo, w.box_hi)
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value:
+            lib().rco_scene_destroy(h)
+            self._h = None
+
+    def trace(self, orig, dirs, brute=False):
+        o = _c(orig, np.float32).reshape(-1, 3)
+        d = _c(dirs, np.float32).reshape(-1, 3)
+        n = o.shape[0]
+        hid = np.empty(n, np.int64)
+        t = np.empty(n, np.float32)
+        fr = np.empty(n, np.int32)
+        rc = lib().rco_trace(self._h, _p(o), _p(d), n, int(brute), _p(hid), _p(t), _p(fr))
+        assert rc == 0
+        return hid, t, fr
+
+    def occluded(self, orig, seg, skip=None, brute=False):
+        o = _c(orig, np.float32).reshape(-1, 3)
+        d = _c(seg, np.float32).reshape(-1, 3)
+        n = o.shape[0]
+        sk = None if skip is None else _c(skip, np.int64)
+        occ = np.empty(n, np.int32)
+        rc = lib().rco_occluded(self._h, _p(o), _p(d), _p(sk), n, int(brute), _p(occ))
+        assert rc == 0
+        return occ.astype(bool)
+
+
+def records(scene: Scene, sigma_s, sigma_a, lights, pos, n_theta, n_phi, rec_id=None, ring_step=0.1,
+            max_rings=20, seed=0, xeval=None, nthreads=0, want_stats=True):
+    """Oracle records.  Returns dict(value [P,2], grad [P,2,3], hess [P,2,6], stats [P,12])."""
+    pos = _c(pos, np.float32).reshape(-1, 3)
+    P = pos.shape[0]
+    nt = _c(np.broadcast_to(n_theta, (P,)), np.int32)
+    npf = _c(np.broadcast_to(n_phi, (P,)), np.int32)
+    rid = _c(np.arange(P) if rec_id is None else rec_id, np.uint64)
+    li = _c(lights, np.float32).reshape(-1, 4)
+    xe = None if xeval is None else _c(xeval, np.float64).reshape(-1, 3)
+    val = np.zeros((P, 2))
+    grad = np.zeros((P, 2, 3))
+    hess = np.zeros((P, 2, 6))
+    st = np.zeros((P, len(STAT_NAMES))) if want_stats else None
+    rc = lib().rco_records(scene._h, float(sigma_s), float(sigma_a), _p(li), li.shape[0], _p(pos), _p(nt), _p(npf),
+                           _p(rid), P, float(ring_step), int(max_rings), int(seed) & (2**64 - 1), _p(xe),
+                           _p(val), _p(grad), _p(hess), _p(st), int(nthreads))
+    if rc != 0:
+        raise ValueError(f"rco_records failed ({rc})")
+    out = {"value": val, "grad": grad, "hess": hess}
+    if want_stats:
+        out["stats"] = st
+    return out
+
+
+def records_for(w, idx=None, xeval=None, nthreads=0, scene=None):
+    """Oracle records for (a subset of) a workload; record ids are the indices."""
+    idx = np.arange(w.n_rec) if idx is None else np.asarray(idx)
+    sc = scene if scene is not None else Scene.from_workload(w)
+    return records(sc, w.sigma_s, w.sigma_a, w.lights, w.pos[idx], w.n_theta[idx], w.n_phi[idx], rec_id=idx,
+                   ring_step=w.ring_step, max_rings=w.max_rings, seed=w.seed, xeval=xeval, nthreads=nthreads)
+
+
+def formfactor(r1, r2, r3):
+    """App. C: F, grad F, Hessian F for vertices r_i = y_i - x (FP64)."""
+    a = [_c(r, np.float64) for r in (r1, r2, r3)]
+    F = np.zeros(1)
+    g = np.zeros(3)
+    H = np.zeros(9)
+    lib().rco_formfactor(_p(a[0]), _p(a[1]), _p(a[2]), _p(F), _p(g), _p(H))
+    return F[0], g, H.reshape(3, 3)
+
+
+def transmittance(x, y, mu):
+    """App. A: T, grad T, Hessian T w.r.t. the shaded point x."""
+    xx = _c(x, np.float64)
+    yy = _c(y, np.float64)
+    T = np.zeros(1)
+    g = np.zeros(3)
+    H = np.zeros(9)
+    lib().rco_transmittance(_p(xx), _p(yy), float(mu), _p(T), _p(g), _p(H))
+    return T[0], g, H.reshape(3, 3)
+
+
+def directions(seed, rec, nth, nph):
+    out = np.zeros((nth * nph + 2, 3), np.float32)
+    assert lib().rco_directions(int(seed), int(rec), nth, nph, _p(out)) == 0
+    return out
+
+
+def triangles(dirs, nth, nph):
+    d = _c(dirs, np.float32).reshape(-1, 3)
+    out = np.zeros((2 * nth * nph, 3), np.int32)
+    n = lib().rco_triangles(_p(d), nth, nph, _p(out))
+    assert n == 2 * nth * nph
+    return out
+
+
+def unif(seed, rec, idx, dim):
+    return float(lib().rco_unif(int(seed), int(rec), int(idx), int(dim)))
+
+
+def splitmix64(x):
+    return int(lib().rco_splitmix64(int(x) & (2**64 - 1)))
+
+
+# --------------------------------------------------------------------------
+# Sec. 5: validity radius (Eq. radiusAniso3D)
+# --------------------------------------------------------------------------
+def hess6_to_mat(h6):
+    h6 = np.asarray(h6, np.float64)
+    H = np.empty(h6.shape[:-1] + (3, 3))
+    H[..., 0, 0] = h6[..., 0]
+    H[..., 0, 1] = H[..., 1, 0] = h6[..., 1]
+    H[..., 0, 2] = H[..., 2, 0] = h6[..., 2]
+    H[..., 1, 1] = h6[..., 3]
+    H[..., 1, 2] = H[..., 2, 1] = h6[..., 4]
+    H[..., 2, 2] = h6[..., 5]
+    return H
+
+
+def radius(value, hess6, eps, r_min, r_max, anisotropic=False):
+    """R_i = (15 L eps / (4 pi |lambda_i|))^(1/5) per eigen-axis of the radiance
+    Hessian (Eq. radiusAniso3D); the isotropic radius uses the largest
+    |lambda| (Sec. 6: isotropic points with the smallest principal axis).
+    Radii are clamped to [r_min, r_max]; lambda = 0 gives r_max; L <= 0 gives
+    r_min.  value [P], hess6 [P,6] (already summed over channels)."""
+    L = np.asarray(value, np.float64)
+    H = hess6_to_mat(hess6)
+    lam, vec = np.linalg.eigh(H)
+    absl = np.abs(lam)
+    with np.errstate(divide="ignore", invalid="ignore"):
+        Ri = (15.0 * L[:, None] * eps / (4.0 * np.pi * absl)) ** 0.2
+    Ri = np.where(absl == 0, r_max, Ri)
+    Ri = np.where(L[:, None] <= 0, r_min, Ri)
+    Ri = np.clip(Ri, r_min, r_max)
+    R = Ri.min(axis=1)
+    if anisotropic:
+        return R, Ri, vec
+    return R
+
+
+# --------------------------------------------------------------------------
+# Sec. 5: interpolation from several cache points (Eq. radianceTaylor)
+# --------------------------------------------------------------------------
+def interpolate(cache_pos, cache_val, cache_grad, cache_R, query):
+    """L(x') = sum_k [L_k + grad L_k . (x' - x_k)] w_k / sum_k w_k over the
+    cache points whose radius contains x', with w = 3d^2 - 2d^3,
+    d = 1 - |x' - x_k| / R_k.  Returns (L [Q], covered [Q])."""
+    cp = np.asarray(cache_pos, np.float64)
+    cv = np.asarray(cache_val, np.float64)
+    cg = np.asarray(cache_grad, np.float64)
+    cR = np.asarray(cache_R, np.float64)
+    q = np.asarray(query, np.float64)
+    out = np.zeros(len(q))
+    cov = np.zeros(len(q), bool)
+    for i, x in enumerate(q):
+        dx = x[None, :] - cp
+        dist = np.sqrt((dx * dx).sum(1))
+        m = dist < cR
+        if not m.any():
+            continue
+        d = 1.0 - dist[m] / cR[m]
+        w = 3 * d * d - 2 * d * d * d
+        num = ((cv[m] + (cg[m] * dx[m]).sum(1)) * w).sum()
+        den = w.sum()
+        if den > 0:
+            out[i] = num / den
+            cov[i] = True
+    return out, cov
+
+
+# --------------------------------------------------------------------------
+# FP64 reference of the placement MLP (project-defined, not in the paper)
+# --------------------------------------------------------------------------
+def gelu(x):
+    """tanh-form GELU (Hendrycks & Gimpel 2016)."""
+    k = np.sqrt(2.0 / np.pi)
+    return 0.5 * x * (1.0 + np.tanh(k * (x + 0.044715 * x ** 3)))
+
+
+def gelu_grad(x):
+    k = np.sqrt(2.0 / np.pi)
+    u = k * (x + 0.044715 * x ** 3)
+    t = np.tanh(u)
+    du = k * (1.0 + 3 * 0.044715 * x * x)
+    return 0.5 * (1.0 + t) + 0.5 * x * (1.0 - t * t) * du
+
+
+def mlp_forward(params, X):
+    """params: dict W1 [128,32], b1 [128], W2 [128,128], b2, W3 [1,128], b3 [1]."""
+    X = np.asarray(X, np.float64)
+    z1 = X @ params["W1"].T + params["b1"]
+    a1 = gelu(z1)
+    z2 = a1 @ params["W2"].T + params["b2"]
+    a2 = gelu(z2)
+    y = a2 @ params["W3"].T + params["b3"]
+    return y[:, 0], (X, z1, a1, z2, a2)
+
+
+def mlp_loss_grad(params, X, target):
+    """Mean squared error and its gradient w.r.t. every parameter (FP64)."""
+    y, (X, z1, a1, z2, a2) = mlp_forward(params, X)
+    B = X.shape[0]
+    r = y - np.asarray(target, np.float64)
+    loss = float((r * r).mean())
+    dy = (2.0 / B) * r[:, None]
+    g = {}
+    g["W3"] = dy.T @ a2
+    g["b3"] = dy.sum(0)
+    da2 = dy @ params["W3"]
+    dz2 = da2 * gelu_grad(z2)
+    g["W2"] = dz2.T @ a1
+    g["b2"] = dz2.sum(0)
+    da1 = dz2 @ params["W2"]
+    dz1 = da1 * gelu_grad(z1)
+    g["W1"] = dz1.T @ X
+    g["b1"] = dz1.sum(0)
+    return loss, g
+
+
+def adam_step(params, grads, m, v, t, lr, b1=0.9, b2=0.999, eps=1e-8):
+    """Adam (Kingma & Ba 2015), bias-corrected, one step; updates in place."""
+    for k in params:
+        m[k] = b1 * m[k] + (1 - b1) * grads[k]
+        v[k] = b2 * v[k] + (1 - b2) * grads[k] ** 2
+        mh = m[k] / (1 - b1 ** t)
+        vh = v[k] / (1 - b2 ** t)
+        params[k] = params[k] - lr * mh / (np.sqrt(vh) + eps)
+    return params
+
+
+def cpu_info():
+    n = os.cpu_count() or 1
+    model = ""
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return {"nproc": n, "model": model}

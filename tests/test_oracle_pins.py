@@ -1,0 +1,582 @@
+"""Pins of the FP64 CPU oracle against things other than itself.
+
+Each test checks the oracle against mathematics or published values:
+closed forms, invariants, finite differences of independently computed
+quantities, brute force, and a published generator test vector.  A plausible
+mistake in the oracle (a dropped term, a wrong sign or index, a transposed
+operand, a wrong constant) fails at least one of these.
+"""
+import math
+from pathlib import Path
+
+import numpy as np
+import pytest
+from scipy.special import expn
+
+from oracle import oracle as O
+from paper_1805_09258_amd import workloads as W
+
+GOLDEN = Path(__file__).resolve().parent / "golden"
+NO_LIGHTS = np.zeros((0, 4), np.float32)
+
+
+# ---------------------------------------------------------------------------
+# random numbers and sampling layout
+# ---------------------------------------------------------------------------
+def test_splitmix64_published_vector():
+    vals = [int(l) for l in (GOLDEN / "splitmix64_seed1234567.txt").read_text().split("\n")
+            if l.strip() and not l.startswith("#")]
+    g = 0x9E3779B97F4A7C15
+    got = [O.splitmix64((1234567 + i * g) % 2**64) for i in range(len(vals))]
+    assert got == vals
+
+
+def test_uniform_floats_are_24bit_and_uniform():
+    u = np.array([O.unif(9, r, i, d) for r in range(40) for i in range(500) for d in range(2)])
+    assert np.all(u >= 0) and np.all(u < 1)
+    assert np.all(np.floor(u * 2**24) == u * 2**24)
+    h, _ = np.histogram(u, bins=16, range=(0, 1))
+    e = len(u) / 16
+    chi2 = ((h - e) ** 2 / e).sum()
+    assert chi2 < 40.0  # 15 dof, p ~ 5e-4
+    # different dims / records decorrelated
+    a = np.array([O.unif(9, 3, i, 0) for i in range(4000)])
+    b = np.array([O.unif(9, 3, i, 1) for i in range(4000)])
+    assert abs(np.corrcoef(a, b)[0, 1]) < 0.05
+
+
+@pytest.mark.parametrize("nth,nph", [(4, 16), (8, 32), (16, 64), (5, 7)])
+def test_directions_lie_in_their_equal_area_strata(nth, nph):
+    d = O.directions(11, 5, nth, nph).astype(np.float64)
+    N = nth * nph
+    assert d.shape == (N + 2, 3)
+    assert np.array_equal(d[0], [0, 0, 1]) and np.array_equal(d[-1], [0, 0, -1])
+    nrm = np.linalg.norm(d, axis=1)
+    assert np.all(np.abs(nrm - 1) < 3e-7)
+    for a in range(nth):
+        for b in range(nph):
+            w = d[1 + a * nph + b]
+            z = w[2]
+            # z-bands of equal width have equal area (Archimedes), phi split evenly
+            assert 1 - 2 * (a + 1) / nth - 1e-6 <= z <= 1 - 2 * a / nth + 1e-6
+            phi = math.atan2(w[1], w[0]) % (2 * math.pi)
+            lo, hi = 2 * math.pi * b / nph, 2 * math.pi * (b + 1) / nph
+            assert lo - 1e-5 <= phi <= hi + 1e-5 or (b == 0 and phi > 2 * math.pi - 1e-5)
+
+
+def test_directions_uniform_on_sphere():
+    # moments of the uniform distribution: E[w] = 0, E[w w^T] = I/3
+    d = np.concatenate([O.directions(3, r, 8, 32)[1:-1] for r in range(60)]).astype(np.float64)
+    assert np.abs(d.mean(0)).max() < 3e-3
+    M = d.T @ d / len(d)
+    assert np.abs(M - np.eye(3) / 3).max() < 3e-3
+
+
+# ---------------------------------------------------------------------------
+# angular triangulation: a closed, consistently oriented star mesh
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("nth,nph,rec", [(4, 16, 0), (8, 32, 1), (16, 64, 2), (8, 32, 77)])
+def test_triangulation_is_closed_star_mesh(nth, nph, rec):
+    d = O.directions(5, rec, nth, nph)
+    t = O.triangles(d, nth, nph)
+    N = nth * nph
+    assert t.shape == (2 * N, 3)
+    dd = d.astype(np.float64)
+    det = np.einsum("ij,ij->i", dd[t[:, 0]], np.cross(dd[t[:, 1]], dd[t[:, 2]]))
+    assert np.all(det > 0)                       # no folded triangle
+    edges = {}
+    for a, b, c in t:
+        for u, v in ((a, b), (b, c), (c, a)):
+            edges[(u, v)] = edges.get((u, v), 0) + 1
+    assert all(n == 1 for n in edges.values())
+    assert all((v, u) in edges for (u, v) in edges)   # every edge shared, opposite orientation
+    V, E, F = N + 2, len(edges) // 2, len(t)
+    assert V - E + F == 2                        # sphere topology
+    # with every vertex pushed to an arbitrary distance, the mesh still
+    # encloses x: total solid angle 4 pi and translation-invariant (grad = H = 0)
+    rng = np.random.default_rng(rec)
+    dist = rng.uniform(0.05, 3.0, size=N + 2)
+    Y = dd * dist[:, None]
+    Fs, G, H, S = 0.0, np.zeros(3), np.zeros((3, 3)), 0.0
+    for a, b, c in t:
+        f, g, h = O.formfactor(Y[a], Y[b], Y[c])
+        Fs += f
+        G += g
+        H += h
+        S += np.abs(h).sum()
+    assert abs(Fs - 1.0) < 1e-12
+    assert np.abs(G).max() < 1e-11 * max(1.0, S)
+    assert np.abs(H).max() < 1e-11 * S
+
+
+# ---------------------------------------------------------------------------
+# App. C: triangle form factor
+# ---------------------------------------------------------------------------
+def test_formfactor_octant_triangle():
+    F, _, _ = O.formfactor([1, 0, 0], [0, 1, 0], [0, 0, 1])
+    assert abs(F - 1.0 / 8.0) < 1e-15               # one octant = pi/2 sr
+
+
+def test_formfactor_large_triangle_above_pi_branch():
+    # a large near-planar triangle seen from just above its centroid covers
+    # almost a hemisphere: Omega > pi needs the branch of atan2 (pi added)
+    F, _, _ = O.formfactor([100, -50, -1e-2], [-100, -50, -1e-2], [0, 100, -1e-2])
+    assert 0.25 < F < 0.5
+
+
+def _quad_solid_angle(y1, y2, y3, n=400):
+    """Solid angle by midpoint quadrature of cos(theta)/r^2 over the triangle."""
+    y1, y2, y3 = map(np.asarray, (y1, y2, y3))
+    e1, e2 = y2 - y1, y3 - y1
+    nrm = np.cross(e1, e2)
+    area = np.linalg.norm(nrm) / 2
+    nh = nrm / np.linalg.norm(nrm)
+    s = 0.0
+    i, j = np.meshgrid(np.arange(n), np.arange(n), indexing="ij")
+    m = (i + j) < n
+    for off in ((1 / 3, 1 / 3), (2 / 3, 2 / 3)):
+        u = (i[m] + off[0]) / n
+        v = (j[m] + off[1]) / n
+        ok = u + v <= 1
+        p = y1 + u[ok, None] * e1 + v[ok, None] * e2
+        r = np.linalg.norm(p, axis=1)
+        s += np.sum(np.abs(p @ nh) / r ** 3)
+    return s * area / n ** 2
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_formfactor_matches_solid_angle_quadrature(seed):
+    rng = np.random.default_rng(seed)
+    y = rng.uniform(-1, 1, size=(3, 3)) + np.array([0, 0, 1.5])
+    F, _, _ = O.formfactor(*y)
+    Om = _quad_solid_angle(*y)
+    assert abs(F - Om / (4 * np.pi)) < 2e-4 * max(F, 1e-3)
+
+
+def _fd(f, x, h):
+    x = np.asarray(x, np.float64)
+    g = np.zeros((3,) + np.shape(f(x)))
+    for i in range(3):
+        e = np.zeros(3)
+        e[i] = h
+        g[i] = (f(x + e) - f(x - e)) / (2 * h)
+    return g
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_formfactor_derivatives_vs_finite_differences(seed):
+    rng = np.random.default_rng(100 + seed)
+    y = rng.uniform(-1, 1, size=(3, 3)) + rng.uniform(-1, 1, 3) * 3
+    x0 = rng.uniform(-0.5, 0.5, 3)
+
+    def Fx(x):
+        return O.formfactor(*(y - x))[0]
+
+    def Gx(x):
+        return O.formfactor(*(y - x))[1]
+
+    F, g, H = O.formfactor(*(y - x0))
+    gfd = _fd(Fx, x0, 1e-5)
+    Hfd = _fd(Gx, x0, 1e-5)            # rows: d/dx_i of grad
+    assert np.linalg.norm(g - gfd) <= 1e-7 * np.linalg.norm(g) + 1e-12
+    assert np.linalg.norm(H - Hfd.T) <= 1e-6 * np.linalg.norm(H) + 1e-10
+    assert np.linalg.norm(H - H.T) <= 1e-12 * np.linalg.norm(H)
+
+
+def test_paper_boxed_gradA_sign_reading():
+    """App. C boxes grad A = <r3 - r2> r1 - (r2 x r3).  Finite differences of
+    A = r1 . (r2 x r3) (r_i = y_i - x) contradict it and confirm
+    grad A = -(r1 x r2 + r2 x r3 + r3 x r1), the reading the oracle uses."""
+    rng = np.random.default_rng(5)
+    y = rng.uniform(-1, 1, size=(3, 3))
+    x0 = rng.uniform(-0.3, 0.3, 3)
+
+    def A(x):
+        r = y - x
+        return float(np.dot(r[0], np.cross(r[1], r[2])))
+
+    gfd = _fd(A, x0, 1e-6)
+    r1, r2, r3 = y - x0
+    boxed = np.cross(r3 - r2, r1) - np.cross(r2, r3)
+    ours = -(np.cross(r1, r2) + np.cross(r2, r3) + np.cross(r3, r1))
+    assert np.linalg.norm(ours - gfd) < 1e-8 * np.linalg.norm(gfd)
+    assert np.linalg.norm(boxed - gfd) > 0.1 * np.linalg.norm(gfd)
+    # and the oracle's grad F is consistent with the corrected grad A
+    F, g, _ = O.formfactor(r1, r2, r3)
+    gfdF = _fd(lambda x: O.formfactor(*(y - x))[0], x0, 1e-6)
+    assert np.linalg.norm(g - gfdF) < 1e-6 * np.linalg.norm(g)
+
+
+# ---------------------------------------------------------------------------
+# App. A: transmittance
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("mu", [0.0, 0.3, 2.5])
+def test_transmittance_closed_form_and_fd(mu):
+    y = np.array([0.3, -0.2, 0.9])
+    x0 = np.array([-0.1, 0.25, 0.05])
+    T, g, H = O.transmittance(x0, y, mu)
+    assert abs(T - math.exp(-mu * np.linalg.norm(x0 - y))) < 1e-15
+    gfd = _fd(lambda x: O.transmittance(x, y, mu)[0], x0, 1e-5)
+    Hfd = _fd(lambda x: O.transmittance(x, y, mu)[1], x0, 1e-5)
+    assert np.linalg.norm(g - gfd) <= 1e-8 * max(np.linalg.norm(g), 1e-12) + 1e-14
+    assert np.linalg.norm(H - Hfd) <= 1e-7 * max(np.linalg.norm(H), 1e-12) + 1e-12
+
+
+# ---------------------------------------------------------------------------
+# whole records: closed forms
+# ---------------------------------------------------------------------------
+def _emitting_box_scene(extra_tri=None, lo=(0, 0, 0), hi=(1, 1, 1)):
+    box = W.room_triangles(lo, hi)
+    tri = box if extra_tri is None else np.concatenate([box, extra_tri])
+    em = np.zeros(len(tri), np.float32)
+    em[:12] = 1.0
+    return O.Scene(tri.astype(np.float32), np.zeros(len(tri), np.float32), em, lo, hi)
+
+
+def test_uniform_unoccluded_field_has_zero_derivatives():
+    sc = _emitting_box_scene()
+    rng = np.random.default_rng(3)
+    pts = rng.uniform(0.1, 0.9, size=(12, 3)).astype(np.float32)
+    r = O.records(sc, 0.0, 0.0, NO_LIGHTS, pts, 8, 32, ring_step=0.1, max_rings=20, seed=4)
+    st = r["stats"]
+    assert np.allclose(r["value"][:, 0], 1.0, atol=1e-15)
+    assert np.allclose(r["value"][:, 1], 0.0)
+    assert np.allclose(st[:, 7], 1.0, atol=1e-12)                 # sum of form factors
+    assert np.all(np.linalg.norm(r["grad"][:, 0], axis=1) < 1e-11 * st[:, 3])
+    assert np.all(np.linalg.norm(r["hess"][:, 0], axis=1) < 1e-11 * st[:, 4])
+
+
+def _rect_omega(p, x1, x2, y1, y2):
+    """Solid angle of the rectangle [x1,x2]x[y1,y2] in the plane z = 0 seen
+    from p (textbook corner formula)."""
+    h = p[2]
+
+    def F(a, b):
+        return np.arctan(a * b / (h * np.sqrt(a * a + b * b + h * h)))
+
+    X1, X2, Y1, Y2 = x1 - p[0], x2 - p[0], y1 - p[1], y2 - p[1]
+    return F(X2, Y2) - F(X1, Y2) - F(X2, Y1) + F(X1, Y1)
+
+
+def _fd_grad_hess(f, p, h=1e-4):
+    g = np.zeros(3)
+    H = np.zeros((3, 3))
+    E = np.eye(3) * h
+    for i in range(3):
+        g[i] = (f(p + E[i]) - f(p - E[i])) / (2 * h)
+        for j in range(3):
+            H[i, j] = (f(p + E[i] + E[j]) - f(p + E[i] - E[j]) - f(p - E[i] + E[j]) + f(p - E[i] - E[j])) / (4 * h * h)
+    return g, H
+
+
+def test_black_occluder_in_uniform_field_converges_to_closed_form():
+    """Vacuum, every wall of the box emits 1, a black rectangle hangs inside.
+    V(x) = 1 - Omega_rect(x)/(4 pi) exactly; its gradient and Hessian are the
+    occlusion derivatives.  The triangulated estimator is biased but
+    consistent (Sec. 4): errors must fall roughly like N^-1/2."""
+    x1, x2, y1, y2 = -0.3, 0.3, -0.2, 0.2
+    rect = np.array([[x1, y1, 0, x2, y1, 0, x2, y2, 0], [x1, y1, 0, x2, y2, 0, x1, y2, 0]], np.float32)
+    sc = _emitting_box_scene(rect, (-1, -1, -1), (1, 1, 1))
+    pts = np.array([[0.25, 0.1, 0.15], [0.0, 0.0, 0.3], [0.35, -0.1, 0.1], [-0.5, 0.3, 0.4]], np.float32)
+    errs = {}
+    for N in (1024, 4096, 16384):
+        nt, npf = W.strata_shape(N)
+        eg, eh = [], []
+        for s in range(4):
+            r = O.records(sc, 0.0, 0.0, NO_LIGHTS, pts, nt, npf, ring_step=0.1, max_rings=0, seed=100 + s)
+            for k, p in enumerate(pts.astype(np.float64)):
+                f = lambda q: 1 - _rect_omega(q, x1, x2, y1, y2) / (4 * np.pi)  # noqa: E731
+                g, H = _fd_grad_hess(f, p)
+                if N == 16384:
+                    assert abs(r["value"][k, 0] - f(p)) < 3e-3
+                eg.append(np.linalg.norm(r["grad"][k, 0] - g) / np.linalg.norm(g))
+                eh.append(np.linalg.norm(O.hess6_to_mat(r["hess"][k, 0]) - H) / np.linalg.norm(H))
+        errs[N] = (np.mean(eg), np.mean(eh))
+    slope_g = math.log(errs[16384][0] / errs[1024][0]) / math.log(16)
+    slope_h = math.log(errs[16384][1] / errs[1024][1]) / math.log(16)
+    assert slope_g < -0.35 and slope_h < -0.35, errs
+    assert errs[16384][0] < 0.10 and errs[16384][1] < 0.10, errs
+
+
+def test_emitting_plane_under_medium_matches_exponential_integrals():
+    """Emitter L_e = 1 on z = 0, homogeneous absorbing medium above, point at
+    height h: V = E2(mu h)/2, dV/dz = -mu E1(mu h)/2,
+    d2V/dz2 = mu exp(-mu h)/(2h), lateral derivatives 0."""
+    Wd = 30.0
+    floor = np.array([[-Wd, -Wd, 0, Wd, -Wd, 0, Wd, Wd, 0], [-Wd, -Wd, 0, Wd, Wd, 0, -Wd, Wd, 0]], np.float32)
+    sc = O.Scene(floor, np.zeros(2, np.float32), np.ones(2, np.float32), (-Wd, -Wd, 0), (Wd, Wd, 4))
+    mu, h = 1.0, 0.5
+    V = expn(2, mu * h) / 2
+    Gz = -mu * expn(1, mu * h) / 2
+    Hzz = mu * math.exp(-mu * h) / (2 * h)
+    res = {}
+    for N in (1024, 16384):
+        nt, npf = W.strata_shape(N)
+        r = O.records(sc, 0.0, mu, NO_LIGHTS, np.array([[0.1, -0.2, h]] * 8, np.float32), nt, npf,
+                      ring_step=0.1, max_rings=0, seed=7)
+        res[N] = (r["value"][:, 0].mean(), r["grad"][:, 0].mean(0), r["hess"][:, 0].mean(0))
+    v, g, H = res[16384]
+    assert abs(v - V) < 2e-4
+    assert abs(g[2] - Gz) / abs(Gz) < 0.02
+    assert abs(H[5] - Hzz) / Hzz < 0.02
+    assert np.abs(g[:2]).max() < 1e-3 and abs(H[1]) < 1e-2 and abs(H[2]) < 1e-2 and abs(H[4]) < 1e-2
+    # consistency: the error shrinks with N
+    assert abs(res[16384][1][2] - Gz) < 0.5 * abs(res[1024][1][2] - Gz)
+    assert abs(res[16384][2][5] - Hzz) < 0.5 * abs(res[1024][2][5] - Hzz)
+
+
+def test_record_derivatives_are_exact_calculus_of_triangulated_value():
+    """With the vertices frozen, the oracle's gradient and Hessian must be the
+    exact derivatives of sum_j w L_far T(x, y_far) F_j(x): checked by central
+    differences of the triangulated value and of the gradient."""
+    w = W.make_c1(P=6)
+    sc = O.Scene.from_workload(w)
+    idx = np.arange(6)
+    base = O.records_for(w, idx, scene=sc, xeval=w.pos.astype(np.float64))
+    h = 1e-6
+    for c, st in ((0, 7), (1, 8)):
+        gfd = np.zeros((6, 3))
+        Hfd = np.zeros((6, 3, 3))
+        for i in range(3):
+            e = np.zeros(3)
+            e[i] = h
+            rp = O.records_for(w, idx, scene=sc, xeval=w.pos.astype(np.float64) + e)
+            rm = O.records_for(w, idx, scene=sc, xeval=w.pos.astype(np.float64) - e)
+            gfd[:, i] = (rp["stats"][:, st] - rm["stats"][:, st]) / (2 * h)
+            Hfd[:, i, :] = (rp["grad"][:, c] - rm["grad"][:, c]) / (2 * h)
+        G = base["grad"][:, c]
+        H = O.hess6_to_mat(base["hess"][:, c])
+        for k in range(6):
+            sg = base["stats"][k, 3 + 2 * c]
+            sh = base["stats"][k, 4 + 2 * c]
+            assert np.linalg.norm(G[k] - gfd[k]) <= 1e-6 * sg + 1e-12
+            assert np.linalg.norm(H[k] - 0.5 * (Hfd[k] + Hfd[k].T)) <= 1e-5 * sh + 1e-10
+
+
+def test_hessian_paper_form_is_symmetric_on_records():
+    w = W.make_c1(P=16)
+    r = O.records_for(w)
+    assert np.all(r["stats"][:, 9] < 1e-9)
+
+
+def test_mc_value_of_uniform_medium_vertex_radiance():
+    """MS channel in an open box with no geometry, one light, no absorption
+    along the light path: compare the ring Monte Carlo estimator with direct
+    numerical integration over a sphere of directions and distances."""
+    lo, hi = np.zeros(3, np.float32), np.ones(3, np.float32)
+    sc = O.Scene(np.zeros((0, 9), np.float32), np.zeros(0, np.float32), None, lo, hi)
+    light = np.array([[0.5, 0.95, 0.5, 10.0]], np.float32)
+    x = np.array([[0.4, 0.3, 0.55]], np.float32)
+    ss, sa = 0.5, 0.1
+    mu = ss + sa
+    vals = [O.records(sc, ss, sa, light, x, 16, 64, rec_id=[r], ring_step=0.05, max_rings=40,
+                      seed=21)["value"][0, 1] for r in range(24)]
+    # reference: (1/4pi) int dw int_0^s(w) mu_s/(4pi) I e^{-mu t} e^{-mu d}/d^2 dt
+    n = 200
+    u = (np.arange(n) + 0.5) / n
+    z = 1 - 2 * u
+    phi = 2 * np.pi * (np.arange(2 * n) + 0.5) / (2 * n)
+    Z, PH = np.meshgrid(z, phi, indexing="ij")
+    st = np.sqrt(1 - Z * Z)
+    dirs = np.stack([st * np.cos(PH), st * np.sin(PH), Z], -1).reshape(-1, 3)
+    x0 = x[0].astype(np.float64)
+    with np.errstate(divide="ignore"):
+        t_exit = np.min(np.where(dirs > 0, (1 - x0) / dirs, np.where(dirs < 0, -x0 / dirs, np.inf)), axis=1)
+    ref = 0.0
+    m = 400
+    for k, wv in enumerate(dirs):
+        t = (np.arange(m) + 0.5) / m * t_exit[k]
+        y = x0 + t[:, None] * wv
+        d = np.linalg.norm(light[0, :3].astype(np.float64) - y, axis=1)
+        f = ss / (4 * np.pi) * 10.0 * np.exp(-mu * t) * np.exp(-mu * d) / d ** 2
+        ref += f.sum() * t_exit[k] / m
+    ref *= (4 * np.pi / len(dirs)) / (4 * np.pi)
+    assert abs(np.mean(vals) - ref) / ref < 0.01
+
+
+# ---------------------------------------------------------------------------
+# ray decisions
+# ---------------------------------------------------------------------------
+def test_hierarchical_trace_equals_brute_force():
+    w = W.make_c2(P=4, n_soup=3000)
+    sc = O.Scene.from_workload(w)
+    rng = np.random.default_rng(8)
+    n = 6000
+    o = rng.uniform(0.02, 0.98, size=(n, 3)).astype(np.float32)
+    d = rng.normal(size=(n, 3))
+    d = (d / np.linalg.norm(d, axis=1, keepdims=True)).astype(np.float32)
+    a = sc.trace(o, d, brute=False)
+    b = sc.trace(o, d, brute=True)
+    assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1]) and np.array_equal(a[2], b[2])
+    seg = (rng.uniform(0, 1, size=(n, 3)) - o).astype(np.float32)
+    skip = np.where(a[0] >= 0, a[0], -1)
+    assert np.array_equal(sc.occluded(o, seg, skip), sc.occluded(o, seg, skip, brute=True))
+
+
+def test_trace_decisions_agree_with_exact_geometry_away_from_edges():
+    """Rays aimed at interior points of random triangles (barycentric margin
+    >= 0.05, no nearer triangle) must hit exactly that triangle at the exact
+    FP64 distance (to FP32 rounding)."""
+    rng = np.random.default_rng(2)
+    tri = rng.uniform(-1, 1, size=(30, 3, 3))
+    tri[:, :, 2] += np.arange(30)[:, None] * 0.0 + 5.0 + np.arange(30)[:, None] * 0.5
+    sc = O.Scene(tri.reshape(-1, 9).astype(np.float32), np.zeros(30, np.float32), None, (-10, -10, -10), (10, 10, 30))
+    o = np.zeros((30, 3), np.float32)
+    bc = rng.dirichlet([1, 1, 1], size=30) * 0.85 + 0.05
+    tgt = np.einsum("nk,nkj->nj", bc, tri)
+    d = (tgt / np.linalg.norm(tgt, axis=1, keepdims=True)).astype(np.float32)
+    hid, t, _ = sc.trace(o, d, brute=True)
+    # exact first hit in FP64 (Moller-Trumbore in numpy, double precision)
+    for i in range(30):
+        best, bj = np.inf, -1
+        for j in range(30):
+            v0, v1, v2 = tri[j]
+            e1, e2 = v1 - v0, v2 - v0
+            p = np.cross(d[i].astype(np.float64), e2)
+            det = e1 @ p
+            s = -v0
+            u = s @ p / det
+            q = np.cross(s, e1)
+            v = d[i].astype(np.float64) @ q / det
+            tt = e2 @ q / det
+            if u >= 0 and v >= 0 and u + v <= 1 and tt > 0 and tt < best:
+                best, bj = tt, j
+        assert hid[i] == bj
+        assert abs(t[i] - best) <= 1e-5 * best
+
+
+# ---------------------------------------------------------------------------
+# Sec. 5: radius and interpolation
+# ---------------------------------------------------------------------------
+def test_radius_constant_integrates_the_error_bound_to_eps():
+    """With R = (15 L eps / (4 pi |lambda|))^(1/5) the bound of Eq. S.11 for a
+    single axis, integral over the ball of |lambda| x1^2 / L, equals eps."""
+    L, lam, eps = 0.7, -3.2, 1.5e-4
+    H = np.zeros(6)
+    H[0] = lam
+    R = O.radius(np.array([L]), H[None, :], eps, 1e-9, 1e9)[0]
+    # spherical-shell quadrature of x1^2 over the ball: 4 pi R^5 / 15
+    n = 2000
+    r = (np.arange(n) + 0.5) / n * R
+    ct = (np.arange(n) + 0.5) / n * 2 - 1
+    integ = 0.0
+    for c in ct[::10]:
+        integ += np.sum(r ** 2 * r ** 2 * c ** 2) * (R / n) * (2.0 / (n / 10)) * 2 * np.pi
+    assert abs(abs(lam) * integ / L - eps) / eps < 1e-3
+    # two dimensions: the paper's 2-D constant (4/pi) comes from pi R^4 / 4
+    R2 = (4 * L * eps / (np.pi * abs(lam))) ** 0.25
+    ints = np.sum(((np.arange(n) + 0.5) / n * R2) ** 3) * (R2 / n) * np.pi  # int r^2 cos^2 r dr dphi
+    assert abs(abs(lam) * ints / L - eps) / eps < 1e-3
+
+
+def test_radius_edge_cases_and_isotropic_choice():
+    H = np.array([[1.0, 0, 0, -8.0, 0, 2.0], [0, 0, 0, 0, 0, 0], [1, 0, 0, 1, 0, 1], [1, 0, 0, 1, 0, 1]])
+    L = np.array([1.0, 1.0, 0.0, 2.0])
+    R, Ri, vec = O.radius(L, H, 1.5e-4, 1e-3, 0.4, anisotropic=True)
+    assert abs(R[0] - (15 * 1.0 * 1.5e-4 / (4 * np.pi * 8.0)) ** 0.2) < 1e-12   # largest |lambda|
+    assert R[1] == 0.4                      # lambda = 0 -> r_max
+    assert R[2] == 1e-3                     # L <= 0 -> r_min
+    assert np.all(Ri[0] >= R[0])
+    # rotating the Hessian rotates the axes and keeps the radii
+    Q = np.linalg.qr(np.random.default_rng(0).normal(size=(3, 3)))[0]
+    Hm = O.hess6_to_mat(H[0])
+    Hr = Q @ Hm @ Q.T
+    h6 = np.array([Hr[0, 0], Hr[0, 1], Hr[0, 2], Hr[1, 1], Hr[1, 2], Hr[2, 2]])
+    assert abs(O.radius(L[:1], h6[None], 1.5e-4, 1e-3, 0.4)[0] - R[0]) < 1e-12
+
+
+def test_interpolation_reproduces_linear_fields_and_kernel():
+    rng = np.random.default_rng(1)
+    cp = rng.uniform(0, 1, size=(20, 3))
+    a, g = 0.7, np.array([0.3, -0.2, 0.5])
+    cv = a + cp @ g
+    cg = np.tile(g, (20, 1))
+    cR = np.full(20, 0.45)
+    q = rng.uniform(0.2, 0.8, size=(50, 3))
+    L, cov = O.interpolate(cp, cv, cg, cR, q)
+    assert cov.all()
+    assert np.allclose(L, a + q @ g, atol=1e-12)      # first-order Taylor is exact for linear fields
+    # kernel: single point, weight irrelevant; outside radius -> not covered
+    L1, c1 = O.interpolate(cp[:1], cv[:1], cg[:1] * 0, np.array([0.1]), cp[:1] + [0.2, 0, 0])
+    assert not c1[0]
+    # two points, equal values 1 and 3: weights 3d^2 - 2d^3 at d = 1 - dist/R
+    cp2 = np.array([[0, 0, 0], [1, 0, 0]], float)
+    L2, _ = O.interpolate(cp2, np.array([1.0, 3.0]), np.zeros((2, 3)), np.array([2.0, 2.0]), [[0.25, 0, 0]])
+    d1, d2 = 1 - 0.25 / 2, 1 - 0.75 / 2
+    w1, w2 = 3 * d1 ** 2 - 2 * d1 ** 3, 3 * d2 ** 2 - 2 * d2 ** 3
+    assert abs(L2[0] - (w1 * 1 + w2 * 3) / (w1 + w2)) < 1e-14
+
+
+# ---------------------------------------------------------------------------
+# MLP reference
+# ---------------------------------------------------------------------------
+def _mlp_params(rng):
+    return {"W1": rng.normal(size=(128, 32)) * 0.2, "b1": rng.normal(size=128) * 0.1,
+            "W2": rng.normal(size=(128, 128)) * 0.1, "b2": rng.normal(size=128) * 0.1,
+            "W3": rng.normal(size=(1, 128)) * 0.1, "b3": rng.normal(size=1) * 0.1}
+
+
+def test_gelu_matches_erf_form_closely_and_its_derivative():
+    from scipy.special import erf
+    x = np.linspace(-5, 5, 2001)
+    exact = 0.5 * x * (1 + erf(x / np.sqrt(2)))
+    assert np.abs(O.gelu(x) - exact).max() < 1e-3          # tanh approximation of the erf form
+    h = 1e-6
+    assert np.abs(O.gelu_grad(x) - (O.gelu(x + h) - O.gelu(x - h)) / (2 * h)).max() < 1e-8
+
+
+def test_mlp_gradients_vs_finite_differences():
+    rng = np.random.default_rng(4)
+    p = _mlp_params(rng)
+    X = rng.normal(size=(16, 32))
+    y = rng.normal(size=16)
+    loss, g = O.mlp_loss_grad(p, X, y)
+    h = 1e-6
+    for k in p:
+        flat = p[k].reshape(-1)
+        for idx in rng.choice(flat.size, size=min(5, flat.size), replace=False):
+            old = flat[idx]
+            flat[idx] = old + h
+            lp, _ = O.mlp_loss_grad(p, X, y)
+            flat[idx] = old - h
+            lm, _ = O.mlp_loss_grad(p, X, y)
+            flat[idx] = old
+            fd = (lp - lm) / (2 * h)
+            assert abs(g[k].reshape(-1)[idx] - fd) <= 1e-6 * max(1.0, abs(fd))
+
+
+def test_adam_first_step_is_signed_lr():
+    p = {"a": np.array([1.0, -2.0, 3.0])}
+    g = {"a": np.array([0.5, -1e-3, 2.0])}
+    m = {"a": np.zeros(3)}
+    v = {"a": np.zeros(3)}
+    O.adam_step(p, g, m, v, 1, 0.01)
+    assert np.allclose(p["a"], [1.0 - 0.01, -2.0 + 0.01, 3.0 - 0.01], atol=1e-7)
+
+
+def test_lit_lambertian_floor_matches_surface_quadrature():
+    """SS value of a point above a Lambertian floor lit by a point light in a
+    homogeneous medium, against direct quadrature over the floor:
+    V = 1/(4 pi) int (rho/pi) I cos_l e^{-mu d_l} / d_l^2 e^{-mu r} cos_y / r^2 dA."""
+    Wd = 2.0
+    floor = np.array([[-Wd, -Wd, 0, Wd, -Wd, 0, Wd, Wd, 0], [-Wd, -Wd, 0, Wd, Wd, 0, -Wd, Wd, 0]], np.float32)
+    sc = O.Scene(floor, np.full(2, 0.5, np.float32), None, (-Wd, -Wd, 0), (Wd, Wd, 3))
+    light = np.array([[0.3, 0.2, 1.0, 5.0]], np.float32)
+    x = np.array([-0.2, 0.1, 0.4])
+    ss, sa = 0.0, 0.4
+    mu = ss + sa
+    vals = [O.records(sc, ss, sa, light, x[None].astype(np.float32), 32, 128, rec_id=[r], ring_step=0.1,
+                      max_rings=0, seed=3)["value"][0, 0] for r in range(6)]
+    n = 1200
+    g = (np.arange(n) + 0.5) / n * 2 * Wd - Wd
+    X, Y = np.meshgrid(g, g, indexing="ij")
+    P = np.stack([X, Y, np.zeros_like(X)], -1)
+    dl = light[0, :3].astype(np.float64) - P
+    d = np.linalg.norm(dl, axis=-1)
+    cl = dl[..., 2] / d
+    Ls = 0.5 / np.pi * 5.0 * cl * np.exp(-mu * d) / d ** 2
+    rv = x - P
+    r = np.linalg.norm(rv, axis=-1)
+    cy = rv[..., 2] / r
+    ref = np.sum(Ls * np.exp(-mu * r) * cy / r ** 2) * (2 * Wd / n) ** 2 / (4 * np.pi)
+    assert abs(np.mean(vals) - ref) / ref < 3e-3
