@@ -1,0 +1,189 @@
+#!/usr/bin/env python3
+"""Benchmark: radiance-cache records (value + gradient + Hessian) per second.
+
+Workload: 10k cache points uniform in a closed unit room (12 triangles) with
+a 10k-triangle random soup (edge 0.02), 1024 stratified directions per point
+(16 x 64), sigma_s = 1.0, sigma_a = 0.2, four point lights, ring step 0.1;
+seeded synthetic inputs resident in device memory before timing.
+
+One step = the whole record path over the batch: the persistent,
+graph-replayed record kernel (directions, BVH traversal, shading, rings,
+triangulation, per-triangle derivative terms, reductions) followed by the
+validity-radius kernel.
+
+Prints one JSON line.  Extra fields: Mrays/s (counted rays), the roofline of
+the dominant kernel (record_kernel) and the FP64 CPU oracle's rate on a
+bounded sample of the same workload.
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+from pathlib import Path
+
+import numpy as np
+
+ROOT = Path(__file__).resolve().parent
+sys.path.insert(0, str(ROOT))
+
+HBM_PEAK_GBS = 8000.0
+NODE_BYTES, TRI_BYTES = 64, 48
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for p in sorted((ROOT / "paper_1805_09258_amd" / "csrc").glob("*")):
+        if p.suffix in (".hip", ".hpp", ".cpp"):
+            h.update(p.read_bytes())
+    return h.hexdigest()[:16]
+
+
+def traffic_from_profile(per_launch_alg_bytes):
+    """HBM bytes per record-kernel launch from the committed counter summary,
+    if it was taken on the current kernel source; else None."""
+    f = ROOT / "profiles" / "record_kernel_C2_traffic.json"
+    if not f.exists():
+        return None
+    try:
+        d = json.loads(f.read_text())
+    except ValueError:
+        return None
+    if d.get("kernel_source_sha") != kernel_source_hash():
+        return None
+    return d.get("hbm_bytes_per_launch")
+
+
+def cpu_baseline(w, budget_s=15.0):
+    """The FP64 oracle, as it stands, on a bounded sample of the workload."""
+    from oracle import oracle as O
+    sc = O.Scene.from_workload(w)
+    rng = np.random.default_rng(2024)
+    idx = np.sort(rng.choice(w.n_rec, size=16, replace=False))
+    t0 = time.perf_counter()
+    O.records_for(w, idx, scene=sc)
+    t1 = time.perf_counter() - t0
+    n = int(min(w.n_rec, max(16, 16 * budget_s / max(t1, 1e-3))))
+    idx = np.sort(rng.choice(w.n_rec, size=n, replace=False))
+    t0 = time.perf_counter()
+    O.records_for(w, idx, scene=sc)
+    dt = time.perf_counter() - t0
+    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    cores = min(cores, os.cpu_count() or cores)
+    return {"value": n / dt, "unit": "records/s", "cores": cores, "kind": "oracle",
+            "sample": f"{n} of {w.n_rec} records (seeded), same scene, 1024 directions each, {dt:.1f} s",
+            "cpu": O.cpu_info()["model"]}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--profile-steps", type=int, default=None, help=argparse.SUPPRESS)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py: this build measures one GPU only (--gpus {args.gpus} requested); records are independent "
+              "and the multi-GPU path is not built.", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_1805_09258_amd import rc
+    from paper_1805_09258_amd import workloads as W
+
+    if not torch.cuda.is_available():
+        print("bench.py: no GPU visible", file=sys.stderr)
+        sys.exit(1)
+    dev = torch.device("cuda:0")
+    w = W.make_c2()
+    log(f"workload C2: {w.n_rec} records, {w.n_tri} triangles, N={int(w.n_theta[0] * w.n_phi[0])}")
+    scene = rc.Scene.from_workload(w)
+    info = scene.info()
+    dw = rc.DeviceWorkload(w, device=dev)
+    value, grad, hess = dw.outputs()
+    ws = dw.workspace()
+    R = torch.empty(w.n_rec, dtype=torch.float32, device=dev)
+    stream = torch.cuda.Stream()
+    eps, r_min, r_max = 1.5e-4, 1e-3, 0.25 * float(np.linalg.norm(w.box_hi - w.box_lo))
+
+    # untimed: algorithmic work of one launch (rays, node and triangle fetches)
+    cnt = torch.zeros(4, dtype=torch.int64, device=dev)
+    with torch.cuda.stream(stream):
+        rc.compute_records(scene, dw, batched=True, counters=cnt, out=(value, grad, hess), workspace=ws,
+                           stream=stream)
+    stream.synchronize()
+    rays, nodes, tris, terms = (int(x) for x in cnt.cpu().tolist())
+    alg_bytes = nodes * NODE_BYTES + tris * TRI_BYTES + w.n_rec * (12 + 8 + 16 + 48 + 96 + 4)
+    log(f"per launch: {rays} rays, {nodes} node fetches, {tris} triangle tests, {terms} triangle terms")
+
+    def step(ev=None):
+        with torch.cuda.stream(stream):
+            if ev is not None:
+                ev[0].record(stream)
+            rc.compute_records(scene, dw, batched=True, use_graph=True, out=(value, grad, hess), workspace=ws,
+                               stream=stream)
+            if ev is not None:
+                ev[1].record(stream)
+            rc.rc_radius(value, hess, eps, r_min, r_max, R, None, stream=stream)
+
+    for i in range(args.warmup):
+        step()
+        stream.synchronize()
+        log(f"warmup {i + 1}/{args.warmup}")
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        step(evs[i])
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    kern_ms = float(np.mean([a.elapsed_time(b) for a, b in evs]))
+    errs = rc.rc_workspace_errors(ws)
+    assert errs == 0, f"{errs} invalid records"
+    ms_step = dt / args.steps * 1e3
+    rec_s = w.n_rec * args.steps / dt
+    log(f"timed {args.steps} steps: {ms_step:.3f} ms/step, record kernel {kern_ms:.3f} ms")
+
+    achieved = alg_bytes / (kern_ms * 1e-3) / 1e9
+    traffic = traffic_from_profile(alg_bytes)
+    out = {
+        "metric": "cache records/s (value+grad+Hessian) & Mrays/s; learned vs plain at equal error",
+        "value": rec_s,
+        "unit": "records/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "C2: 10k points, closed unit room + 10k-triangle soup (edge 0.02), 1024 directions "
+                               "(16x64), sigma_s=1.0 sigma_a=0.2, 4 point lights, ring step 0.1",
+                   "records_per_step": w.n_rec, "n_triangles": w.n_tri, "directions": 1024,
+                   "bvh_nodes": info["n_nodes"], "bvh_depth": info["depth"]},
+        "mrays_per_s": rays * args.steps / dt / 1e6,
+        "rays_per_record": rays / w.n_rec,
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                     "kernel": "record_kernel", "kernel_ms": kern_ms,
+                     "alg_bytes_per_launch": alg_bytes,
+                     "alg_bytes_per_ray": (nodes * NODE_BYTES + tris * TRI_BYTES) / max(rays, 1)},
+    }
+    if not args.no_cpu_baseline:
+        log("cpu baseline (oracle) ...")
+        out["cpu_baseline"] = cpu_baseline(w)
+        log(f"cpu baseline {out['cpu_baseline']['value']:.2f} records/s")
+    scene.close()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

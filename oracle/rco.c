@@ -139,6 +139,20 @@ static uint64_t morton_expand(uint64_t v) { /* 21 bits -> every third bit */
   v = (v | v << 2) & 0x1249249249249249ULL;
   return v;
 }
+/* Padding of a triangle's box: the FP32 hit test can accept points about
+ * 4e-5 * scale / sin(smallest angle) away from the exact triangle; pad by
+ * 50 times that (capped at the scene scale) so culling never removes a
+ * triangle the test would accept. */
+static double tri_pad(const float* t, double scale) {
+  double e1[3], e2[3], e3[3];
+  for (int k = 0; k < 3; k++) { e1[k] = (double)t[3 + k] - t[k]; e2[k] = (double)t[6 + k] - t[k]; e3[k] = (double)t[6 + k] - t[3 + k]; }
+  double c[3]; d3_cross(e1, e2, c);
+  double a2 = d3_norm(c), L[3] = {d3_norm(e1), d3_norm(e2), d3_norm(e3)};
+  for (int i = 0; i < 2; i++) for (int j = 0; j < 2 - i; j++) if (L[j] > L[j + 1]) { double x = L[j]; L[j] = L[j + 1]; L[j + 1] = x; }
+  double sinb = (L[1] * L[2] > 0) ? a2 / (L[1] * L[2]) : 0.0;
+  double p = sinb > 0 ? 2e-3 * scale / sinb : scale;
+  return p < scale ? p : scale;
+}
 typedef struct { uint64_t key; int64_t idx; } kv;
 static int kv_cmp(const void* a, const void* b) {
   const kv* x = (const kv*)a; const kv* y = (const kv*)b;
@@ -190,8 +204,8 @@ int rco_scene_create(const float* tri, const float* albedo, const float* emissio
     s->emission[j] = emission ? emission[j] : 0.0f;
     for (int k = 0; k < 9; k++) ext = fmax(ext, fabs((double)t[k] - (double)box_lo[k % 3]));
   }
-  /* padding of every box: much larger than the FP32 error of an accepted hit */
-  s->pad = 1e-3 * (ext > 0 ? ext : 1.0);
+  /* scale for the box padding (see tri_pad) */
+  s->pad = ext > 0 ? ext : 1.0;
   /* Morton order of centroids inside the scene bounds */
   double smin[3] = {1e300, 1e300, 1e300}, smax[3] = {-1e300, -1e300, -1e300};
   for (int64_t j = 0; j < T; j++)
@@ -229,9 +243,10 @@ int rco_scene_create(const float* tri, const float* albedo, const float* emissio
       for (int64_t c = i * RCO_FAN; c < (i + 1) * RCO_FAN && c < nprev; c++) {
         if (l == 0) {
           const float* t = tri + 9 * s->perm[c];
+          double pd = tri_pad(t, s->pad);
           for (int k = 0; k < 9; k++) {
-            b[k % 3] = fmin(b[k % 3], (double)t[k] - s->pad);
-            b[3 + k % 3] = fmax(b[3 + k % 3], (double)t[k] + s->pad);
+            b[k % 3] = fmin(b[k % 3], (double)t[k] - pd);
+            b[3 + k % 3] = fmax(b[3 + k % 3], (double)t[k] + pd);
           }
         } else {
           const double* cb = s->lev_box[l - 1] + 6 * c;

@@ -1,0 +1,481 @@
+// api.cpp -- the C ABI of librc (see include/rc.h).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <fstream>
+#include <mutex>
+#include <sstream>
+#include <string>
+#include <vector>
+
+#include "internal.hpp"
+#include "kernels.hpp"
+
+namespace {
+
+thread_local std::string g_last_error;
+
+int fail(int code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_last_error = buf;
+  return code;
+}
+
+#define RC_HIP(call)                                                                                   \
+  do {                                                                                                 \
+    hipError_t e_ = (call);                                                                            \
+    if (e_ != hipSuccess) return fail(RC_EDEVICE, "%s failed: %s", #call, hipGetErrorString(e_));      \
+  } while (0)
+
+bool finite3(const float* v) { return std::isfinite(v[0]) && std::isfinite(v[1]) && std::isfinite(v[2]); }
+
+struct GraphCache {
+  bool valid = false;
+  rc::RecordArgs args{};
+  int grid = 0, stack = 0;
+  size_t lds = 0;
+  hipStream_t stream = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  void clear() {
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (graph) (void)hipGraphDestroy(graph);
+    exec = nullptr;
+    graph = nullptr;
+    valid = false;
+  }
+};
+
+}  // namespace
+
+struct rc_scene {
+  int device = 0;
+  int n_cu = 0;
+  std::string arch;
+  int64_t T = 0;
+  int64_t n_nodes = 0;
+  int depth = 0;
+  float pad = 0.f;
+  float box_lo[3], box_hi[3];
+  float4* nodes = nullptr;
+  float4* tris = nullptr;
+  float4* shade = nullptr;
+  float* emission = nullptr;
+  std::mutex mu;
+  GraphCache graph;
+  ~rc_scene() {
+    graph.clear();
+    if (nodes) (void)hipFree(nodes);
+    if (tris) (void)hipFree(tris);
+    if (shade) (void)hipFree(shade);
+    if (emission) (void)hipFree(emission);
+  }
+};
+
+namespace {
+
+constexpr size_t kWsQueue = 0, kWsHist = 256, kWsCursor = 256 + 4 * rc::kOrderBuckets,
+                 kWsOrder = 256 + 8 * rc::kOrderBuckets;
+
+int check_inputs(const rc_scene* s, const rc_medium* m, const rc_point_light* lights, int n_lights, const float* pos,
+                 const int32_t* nth, const int32_t* nph, int64_t P, const rc_params* p, double* value, double* grad,
+                 double* hess, void* ws) {
+  if (!s) return fail(RC_EINVAL, "scene is NULL");
+  if (!m || !std::isfinite(m->sigma_s) || !std::isfinite(m->sigma_a) || m->sigma_s < 0 || m->sigma_a < 0)
+    return fail(RC_EINVAL, "medium coefficients must be finite and >= 0");
+  if (n_lights < 0 || n_lights > RC_MAX_LIGHTS) return fail(RC_EINVAL, "n_lights must be in [0, %d]", RC_MAX_LIGHTS);
+  if (n_lights > 0 && !lights) return fail(RC_EINVAL, "lights is NULL");
+  for (int l = 0; l < n_lights; l++)
+    if (!finite3(lights[l].pos) || !std::isfinite(lights[l].intensity) || lights[l].intensity < 0)
+      return fail(RC_EINVAL, "light %d is not finite or has negative intensity", l);
+  if (P < 0 || P > 0x7fffffff) return fail(RC_EINVAL, "P out of range");
+  if (!p) return fail(RC_EINVAL, "params is NULL");
+  if (!(p->ring_step > 0.f) || !std::isfinite(p->ring_step)) return fail(RC_EINVAL, "ring_step must be > 0");
+  if (p->max_rings < 1 || p->max_rings > RC_MAX_RINGS) return fail(RC_EINVAL, "max_rings must be in [1, %d]", RC_MAX_RINGS);
+  if (p->max_n_phi < 5 || p->max_n_phi > RC_MAX_NPHI) return fail(RC_EINVAL, "max_n_phi must be in [5, %d]", RC_MAX_NPHI);
+  if (p->precision != 0 && p->precision != 1) return fail(RC_EINVAL, "precision must be 0 or 1");
+  if (p->rec_base < 0) return fail(RC_EINVAL, "rec_base must be >= 0");
+  if (P > 0 && (!pos || !nth || !nph || !value || !grad || !hess))
+    return fail(RC_EINVAL, "NULL input or output pointer");
+  if (P > 0 && !ws) return fail(RC_EINVAL, "workspace is NULL");
+  return RC_OK;
+}
+
+rc::RecordArgs make_args(const rc_scene* s, const rc_medium* m, const rc_point_light* lights, int n_lights,
+                         const float* pos, const int32_t* nth, const int32_t* nph, int64_t P, const rc_params* p,
+                         double* value, double* grad, double* hess, void* ws, const int32_t* order) {
+  rc::RecordArgs a{};
+  a.nodes = s->nodes;
+  a.tris = s->tris;
+  a.shade = s->shade;
+  a.emission = s->emission;
+  a.box_lo = make_float3(s->box_lo[0], s->box_lo[1], s->box_lo[2]);
+  a.box_hi = make_float3(s->box_hi[0], s->box_hi[1], s->box_hi[2]);
+  a.n_lights = n_lights;
+  for (int l = 0; l < n_lights; l++)
+    a.lights[l] = make_float4(lights[l].pos[0], lights[l].pos[1], lights[l].pos[2], lights[l].intensity);
+  a.sigma_s = m->sigma_s;
+  a.sigma_a = m->sigma_a;
+  a.pos = pos;
+  a.n_theta = nth;
+  a.n_phi = nph;
+  a.P = (int)P;
+  a.rec_base = p->rec_base;
+  a.ring_step = p->ring_step;
+  a.max_rings = p->max_rings;
+  a.max_n_phi = p->max_n_phi;
+  a.precision = p->precision;
+  a.seed = p->seed;
+  a.value = value;
+  a.grad = grad;
+  a.hess = hess;
+  a.order = order;
+  a.queue = reinterpret_cast<unsigned int*>(static_cast<char*>(ws) + kWsQueue);
+  a.counters = reinterpret_cast<unsigned long long*>(p->counters);
+  return a;
+}
+
+// launch configurations ("tiles"): persistent grid as a multiple of the
+// resident wave capacity
+constexpr int kNTiles = 4;
+constexpr float kTileGrid[kNTiles] = {1.0f, 2.0f, 0.5f, 4.0f};
+
+int plan(const rc_scene* s, const rc_params* p, int64_t P, int tile, int& stack, size_t& lds, int& grid) {
+  stack = rc::stack_variant(s->depth);
+  lds = rc::record_lds_bytes(stack, p->max_n_phi, p->max_rings);
+  if (lds > 160 * 1024) return fail(RC_EINVAL, "max_n_phi x max_rings needs %zu bytes of LDS (> 160 KiB)", lds);
+  hipError_t e = rc::prepare_record(stack, p->counters != nullptr, p->precision == 1, lds);
+  if (e != hipSuccess) return fail(RC_EDEVICE, "kernel attribute: %s", hipGetErrorString(e));
+  int occ = rc::record_occupancy(stack, p->counters != nullptr, p->precision == 1, lds);
+  if (occ < 1) occ = 1;
+  int t = (tile >= 0 && tile < kNTiles) ? tile : 0;
+  int64_t resident = (int64_t)occ * s->n_cu;
+  int64_t gsz = (int64_t)std::llround((double)resident * kTileGrid[t]);
+  gsz = std::max<int64_t>(1, std::min<int64_t>(gsz, P));
+  grid = (int)gsz;
+  return RC_OK;
+}
+
+int launch_direct(rc_scene* s, const rc::RecordArgs& a, int stack, size_t lds, int grid, hipStream_t st) {
+  RC_HIP(rc::launch_reset(a.queue, st));
+  RC_HIP(rc::launch_record(a, stack, a.counters != nullptr, a.precision == 1, grid, lds, st));
+  return RC_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* rc_last_error(void) { return g_last_error.c_str(); }
+const char* rc_version(void) { return "librc 0.1 (gfx950)"; }
+
+int rc_scene_create(const float* tri, const float* albedo, const float* emission, int64_t T, const float box_lo[3],
+                    const float box_hi[3], rc_scene** out) {
+  if (!out) return fail(RC_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (T < 0) return fail(RC_EINVAL, "T < 0");
+  if (T > 0 && (!tri || !albedo)) return fail(RC_EINVAL, "tri/albedo NULL");
+  if (!box_lo || !box_hi || !finite3(box_lo) || !finite3(box_hi)) return fail(RC_EINVAL, "box not finite");
+  for (int k = 0; k < 3; k++)
+    if (!(box_hi[k] > box_lo[k])) return fail(RC_EINVAL, "empty box");
+  float tol[3];
+  for (int k = 0; k < 3; k++) tol[k] = 1e-4f * (box_hi[k] - box_lo[k]);
+  for (int64_t i = 0; i < 9 * T; i++) {
+    if (!std::isfinite(tri[i])) return fail(RC_EINVAL, "triangle %lld not finite", (long long)(i / 9));
+    int k = (int)(i % 3);
+    if (tri[i] < box_lo[k] - tol[k] || tri[i] > box_hi[k] + tol[k])
+      return fail(RC_EINVAL, "triangle %lld outside the medium box", (long long)(i / 9));
+  }
+  for (int64_t i = 0; i < T; i++) {
+    if (!std::isfinite(albedo[i]) || albedo[i] < 0) return fail(RC_EINVAL, "albedo %lld invalid", (long long)i);
+    if (emission && (!std::isfinite(emission[i]) || emission[i] < 0))
+      return fail(RC_EINVAL, "emission %lld invalid", (long long)i);
+  }
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) return fail(RC_ENODEV, "no HIP device");
+  int dev = 0;
+  RC_HIP(hipGetDevice(&dev));
+  hipDeviceProp_t prop;
+  RC_HIP(hipGetDeviceProperties(&prop, dev));
+  std::string arch = prop.gcnArchName;
+  if (arch.find("gfx950") == std::string::npos) return fail(RC_ENODEV, "device %d is %s, not gfx950", dev, arch.c_str());
+
+  rc::HostBvh bvh;
+  std::string err;
+  float pad = rc::bvh_pad_for(tri, T, box_lo, box_hi);
+  int rc_ = rc::build_bvh(tri, T, pad, bvh, err);
+  if (rc_ != RC_OK) return fail(rc_, "BVH build: %s", err.c_str());
+
+  rc_scene* s = new (std::nothrow) rc_scene();
+  if (!s) return fail(RC_ENOMEM, "host allocation");
+  s->device = dev;
+  s->n_cu = prop.multiProcessorCount;
+  s->arch = arch;
+  s->T = T;
+  s->n_nodes = (int64_t)bvh.nodes.size() / 16;
+  s->depth = bvh.depth;
+  s->pad = pad;
+  for (int k = 0; k < 3; k++) { s->box_lo[k] = box_lo[k]; s->box_hi[k] = box_hi[k]; }
+  // per-triangle shading data
+  std::vector<float> shade(4 * std::max<int64_t>(T, 1), 0.f), em(std::max<int64_t>(T, 1), 0.f);
+  for (int64_t i = 0; i < T; i++) {
+    const float* t = tri + 9 * i;
+    double e1[3] = {(double)t[3] - t[0], (double)t[4] - t[1], (double)t[5] - t[2]};
+    double e2[3] = {(double)t[6] - t[0], (double)t[7] - t[1], (double)t[8] - t[2]};
+    double n[3] = {e1[1] * e2[2] - e1[2] * e2[1], e1[2] * e2[0] - e1[0] * e2[2], e1[0] * e2[1] - e1[1] * e2[0]};
+    double ln = std::sqrt(n[0] * n[0] + n[1] * n[1] + n[2] * n[2]);
+    for (int k = 0; k < 3; k++) shade[4 * i + k] = ln > 0 ? (float)(n[k] / ln) : 0.f;
+    shade[4 * i + 3] = albedo[i];
+    em[i] = emission ? emission[i] : 0.f;
+  }
+  auto up = [&](void** dst, const void* src, size_t bytes) -> int {
+    if (hipMalloc(dst, std::max<size_t>(bytes, 16)) != hipSuccess) return fail(RC_ENOMEM, "hipMalloc %zu", bytes);
+    if (bytes && hipMemcpy(*dst, src, bytes, hipMemcpyHostToDevice) != hipSuccess)
+      return fail(RC_EDEVICE, "hipMemcpy");
+    return RC_OK;
+  };
+  int r = up((void**)&s->nodes, bvh.nodes.data(), bvh.nodes.size() * 4);
+  if (!r) r = up((void**)&s->tris, bvh.tris.data(), bvh.tris.size() * 4);
+  if (!r) r = up((void**)&s->shade, shade.data(), shade.size() * 4);
+  if (!r) r = up((void**)&s->emission, em.data(), em.size() * 4);
+  if (r) {
+    delete s;
+    return r;
+  }
+  *out = s;
+  return RC_OK;
+}
+
+int rc_scene_destroy(rc_scene* s) {
+  if (!s) return fail(RC_EINVAL, "scene is NULL");
+  delete s;
+  return RC_OK;
+}
+
+int rc_scene_info(const rc_scene* s, rc_scene_stats* o) {
+  if (!s || !o) return fail(RC_EINVAL, "NULL argument");
+  o->n_tri = s->T;
+  o->n_nodes = s->n_nodes;
+  o->depth = s->depth;
+  o->leaf_max = rc::kLeafMax;
+  o->node_bytes = 64;
+  o->tri_bytes = 48;
+  o->pad = s->pad;
+  return RC_OK;
+}
+
+int64_t rc_bvh_build_host(const float* tri, int64_t T, const float box_lo[3], const float box_hi[3], float* nodes,
+                          int64_t max_nodes, float* tris, rc_scene_stats* stats) {
+  if (T < 0 || (T > 0 && !tri) || !box_lo || !box_hi) return fail(RC_EINVAL, "invalid arguments");
+  rc::HostBvh bvh;
+  std::string err;
+  float pad = rc::bvh_pad_for(tri, T, box_lo, box_hi);
+  int r = rc::build_bvh(tri, T, pad, bvh, err);
+  if (r != RC_OK) return fail(r, "BVH build: %s", err.c_str());
+  int64_t nn = (int64_t)bvh.nodes.size() / 16;
+  if (nodes) {
+    if (max_nodes < nn) return fail(RC_EINVAL, "max_nodes %lld < %lld", (long long)max_nodes, (long long)nn);
+    std::memcpy(nodes, bvh.nodes.data(), bvh.nodes.size() * 4);
+  }
+  if (tris) std::memcpy(tris, bvh.tris.data(), bvh.tris.size() * 4);
+  if (stats) {
+    stats->n_tri = T;
+    stats->n_nodes = nn;
+    stats->depth = bvh.depth;
+    stats->leaf_max = rc::kLeafMax;
+    stats->node_bytes = 64;
+    stats->tri_bytes = 48;
+    stats->pad = pad;
+  }
+  return nn;
+}
+
+size_t rc_workspace_size(int64_t P) {
+  size_t b = kWsOrder + 4 * (size_t)std::max<int64_t>(P, 0);
+  return (b + 255) & ~size_t(255);
+}
+
+int64_t rc_workspace_errors(const void* ws, void* stream) {
+  if (!ws) return fail(RC_EINVAL, "workspace is NULL");
+  unsigned int q[2];
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  RC_HIP(hipMemcpyAsync(q, ws, sizeof q, hipMemcpyDeviceToHost, st));
+  RC_HIP(hipStreamSynchronize(st));
+  return (int64_t)q[1];
+}
+
+int rc_records(const rc_scene* scene, const rc_medium* medium, const rc_point_light* lights, int n_lights,
+               const float* pos, const int32_t* n_theta, const int32_t* n_phi, int64_t P, const rc_params* params,
+               double* value, double* grad, double* hess, void* workspace, void* stream) {
+  int r = check_inputs(scene, medium, lights, n_lights, pos, n_theta, n_phi, P, params, value, grad, hess, workspace);
+  if (r) return r;
+  if (P == 0) return RC_OK;
+  rc_scene* s = const_cast<rc_scene*>(scene);
+  int stack, grid;
+  size_t lds;
+  if ((r = plan(s, params, P, 0, stack, lds, grid))) return r;
+  rc::RecordArgs a = make_args(s, medium, lights, n_lights, pos, n_theta, n_phi, P, params, value, grad, hess,
+                               workspace, nullptr);
+  return launch_direct(s, a, stack, lds, grid, static_cast<hipStream_t>(stream));
+}
+
+int rc_records_batched(const rc_scene* scene, const rc_medium* medium, const rc_point_light* lights, int n_lights,
+                       const float* pos, const int32_t* n_theta, const int32_t* n_phi, int64_t P,
+                       const rc_params* params, const int32_t* order, int use_graph, int tile, double* value,
+                       double* grad, double* hess, void* workspace, void* stream) {
+  int r = check_inputs(scene, medium, lights, n_lights, pos, n_theta, n_phi, P, params, value, grad, hess, workspace);
+  if (r) return r;
+  if (tile < -1 || tile >= kNTiles) return fail(RC_EINVAL, "tile must be in [-1, %d)", kNTiles);
+  if (P == 0) return RC_OK;
+  rc_scene* s = const_cast<rc_scene*>(scene);
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  int stack, grid;
+  size_t lds;
+  if ((r = plan(s, params, P, tile, stack, lds, grid))) return r;
+  char* ws = static_cast<char*>(workspace);
+  const int32_t* ord = order;
+  if (!ord) {
+    int32_t* o = reinterpret_cast<int32_t*>(ws + kWsOrder);
+    RC_HIP(rc::launch_order(n_theta, n_phi, (int)P, reinterpret_cast<unsigned int*>(ws + kWsHist),
+                            reinterpret_cast<unsigned int*>(ws + kWsCursor), o, st));
+    ord = o;
+  }
+  rc::RecordArgs a = make_args(s, medium, lights, n_lights, pos, n_theta, n_phi, P, params, value, grad, hess,
+                               workspace, ord);
+  if (!use_graph || st == nullptr) return launch_direct(s, a, stack, lds, grid, st);
+  std::lock_guard<std::mutex> lk(s->mu);
+  GraphCache& gc = s->graph;
+  bool same = gc.valid && gc.grid == grid && gc.stack == stack && gc.lds == lds && gc.stream == st &&
+              std::memcmp(&gc.args, &a, sizeof a) == 0;
+  if (!same) {
+    gc.clear();
+    RC_HIP(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+    hipError_t e1 = rc::launch_reset(a.queue, st);
+    hipError_t e2 = e1 == hipSuccess ? rc::launch_record(a, stack, a.counters != nullptr, a.precision == 1, grid, lds, st) : e1;
+    hipGraph_t g = nullptr;
+    hipError_t e3 = hipStreamEndCapture(st, &g);
+    if (e2 != hipSuccess || e3 != hipSuccess) {
+      if (g) (void)hipGraphDestroy(g);
+      return fail(RC_EDEVICE, "graph capture failed: %s", hipGetErrorString(e2 != hipSuccess ? e2 : e3));
+    }
+    hipGraphExec_t ex = nullptr;
+    hipError_t e4 = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+    if (e4 != hipSuccess) {
+      (void)hipGraphDestroy(g);
+      return fail(RC_EDEVICE, "graph instantiate failed: %s", hipGetErrorString(e4));
+    }
+    gc.graph = g;
+    gc.exec = ex;
+    gc.args = a;
+    gc.grid = grid;
+    gc.stack = stack;
+    gc.lds = lds;
+    gc.stream = st;
+    gc.valid = true;
+  }
+  RC_HIP(hipGraphLaunch(gc.exec, st));
+  return RC_OK;
+}
+
+int rc_autotune(const rc_scene* scene, const rc_medium* medium, const rc_point_light* lights, int n_lights,
+                const float* pos, const int32_t* n_theta, const int32_t* n_phi, int64_t P, const rc_params* params,
+                double* value, double* grad, double* hess, void* workspace, const char* cache_path, int* best_tile,
+                float* ms_out, int* n_tiles, void* stream) {
+  int r = check_inputs(scene, medium, lights, n_lights, pos, n_theta, n_phi, P, params, value, grad, hess, workspace);
+  if (r) return r;
+  if (!best_tile) return fail(RC_EINVAL, "best_tile is NULL");
+  if (n_tiles) *n_tiles = kNTiles;
+  *best_tile = 0;
+  if (P == 0) return RC_OK;
+  const rc_scene* s = scene;
+  std::ostringstream key;
+  key << s->arch << "|T=" << s->T << "|P=" << P << "|nphi=" << params->max_n_phi << "|rings=" << params->max_rings
+      << "|L=" << n_lights;
+  if (cache_path && !ms_out) {
+    std::ifstream in(cache_path);
+    std::string line;
+    while (std::getline(in, line)) {
+      auto p = line.rfind(' ');
+      if (p != std::string::npos && line.substr(0, p) == key.str()) {
+        int t = std::atoi(line.c_str() + p + 1);
+        if (t >= 0 && t < kNTiles) {
+          *best_tile = t;
+          return RC_OK;
+        }
+      }
+    }
+  }
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  hipEvent_t e0, e1;
+  RC_HIP(hipEventCreate(&e0));
+  RC_HIP(hipEventCreate(&e1));
+  float best = 1e30f;
+  for (int t = 0; t < kNTiles; t++) {
+    float tot = 0.f;
+    for (int rep = 0; rep < 3; rep++) {
+      RC_HIP(hipEventRecord(e0, st));
+      r = rc_records_batched(scene, medium, lights, n_lights, pos, n_theta, n_phi, P, params, nullptr, 0, t, value,
+                             grad, hess, workspace, stream);
+      if (r) return r;
+      RC_HIP(hipEventRecord(e1, st));
+      RC_HIP(hipEventSynchronize(e1));
+      float ms = 0.f;
+      RC_HIP(hipEventElapsedTime(&ms, e0, e1));
+      if (rep > 0) tot += ms;  // first repetition warms up
+    }
+    tot *= 0.5f;
+    if (ms_out) ms_out[t] = tot;
+    if (tot < best) {
+      best = tot;
+      *best_tile = t;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (cache_path) {
+    std::ofstream out(cache_path, std::ios::app);
+    out << key.str() << " " << *best_tile << "\n";
+  }
+  return RC_OK;
+}
+
+int rc_radius(const double* value, const double* hess, int64_t P, float eps, float r_min, float r_max, float* R,
+              float* axes, void* stream) {
+  if (P < 0 || P > 0x7fffffff) return fail(RC_EINVAL, "P out of range");
+  if (P > 0 && (!value || !hess || !R)) return fail(RC_EINVAL, "NULL pointer");
+  if (!(eps > 0.f) || !(r_min > 0.f) || !(r_max >= r_min) || !std::isfinite(r_max))
+    return fail(RC_EINVAL, "need eps > 0 and 0 < r_min <= r_max");
+  if (P == 0) return RC_OK;
+  RC_HIP(rc::launch_radius(value, hess, (int)P, eps, r_min, r_max, R, axes, static_cast<hipStream_t>(stream)));
+  return RC_OK;
+}
+
+int rc_trace_rays(const rc_scene* s, const float* orig, const float* dir, int64_t n, int32_t* hit_id, float* t,
+                  int32_t* front, void* stream) {
+  if (!s || n < 0 || n > 0x7fffffff) return fail(RC_EINVAL, "invalid arguments");
+  if (n > 0 && (!orig || !dir || !hit_id || !t || !front)) return fail(RC_EINVAL, "NULL pointer");
+  RC_HIP(rc::launch_trace_rays(s->nodes, s->tris, s->depth, orig, dir, (int)n, hit_id, t, front,
+                               make_float3(s->box_lo[0], s->box_lo[1], s->box_lo[2]),
+                               make_float3(s->box_hi[0], s->box_hi[1], s->box_hi[2]), static_cast<hipStream_t>(stream)));
+  return RC_OK;
+}
+
+int rc_occluded_rays(const rc_scene* s, const float* orig, const float* seg, const int32_t* skip, int64_t n,
+                     int32_t* occ, void* stream) {
+  if (!s || n < 0 || n > 0x7fffffff) return fail(RC_EINVAL, "invalid arguments");
+  if (n > 0 && (!orig || !seg || !occ)) return fail(RC_EINVAL, "NULL pointer");
+  RC_HIP(rc::launch_occluded_rays(s->nodes, s->tris, s->depth, orig, seg, skip, (int)n, occ,
+                                  static_cast<hipStream_t>(stream)));
+  return RC_OK;
+}
+
+}  // extern "C"

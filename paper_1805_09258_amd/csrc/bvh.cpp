@@ -1,0 +1,261 @@
+// bvh.cpp -- host builder of the flat binary BVH traversed by the record
+// kernel.  Binned surface-area heuristic (16 bins per axis over centroid
+// bounds), leaves of at most kLeafMax triangles, object-median fallback when
+// the heuristic finds no split or the tree gets deep.  The paper relies on
+// Embree for tracing (Sec. 6) and describes no acceleration structure; this
+// one is laid out for the GPU: both children's boxes in one 64-byte node, and
+// the triangles of a leaf contiguous in the order the leaf lists them.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <limits>
+
+#include "internal.hpp"
+
+namespace rc {
+namespace {
+
+struct Prim {
+  float lo[3], hi[3], c[3];
+  int32_t id;
+};
+
+struct Box {
+  float lo[3] = {std::numeric_limits<float>::infinity(), std::numeric_limits<float>::infinity(),
+                 std::numeric_limits<float>::infinity()};
+  float hi[3] = {-std::numeric_limits<float>::infinity(), -std::numeric_limits<float>::infinity(),
+                 -std::numeric_limits<float>::infinity()};
+  void grow(const float* l, const float* h) {
+    for (int k = 0; k < 3; k++) {
+      lo[k] = std::min(lo[k], l[k]);
+      hi[k] = std::max(hi[k], h[k]);
+    }
+  }
+  void grow(const Box& b) { grow(b.lo, b.hi); }
+  double area() const {
+    if (!(hi[0] >= lo[0])) return 0.0;
+    double dx = hi[0] - lo[0], dy = hi[1] - lo[1], dz = hi[2] - lo[2];
+    return 2.0 * (dx * dy + dy * dz + dz * dx);
+  }
+};
+
+struct Builder {
+  std::vector<Prim>& prims;
+  const float* tri;
+  float pad;
+  std::vector<float>& nodes;
+  std::vector<float>& tris;
+  int max_depth_seen = 0;
+
+  Box bounds(int64_t b, int64_t e) const {
+    Box bx;
+    for (int64_t i = b; i < e; i++) bx.grow(prims[i].lo, prims[i].hi);
+    return bx;
+  }
+
+  static int32_t as_i(float f) {
+    int32_t i;
+    std::memcpy(&i, &f, 4);
+    return i;
+  }
+  static float as_f(int32_t i) {
+    float f;
+    std::memcpy(&f, &i, 4);
+    return f;
+  }
+
+  int32_t make_leaf(int64_t b, int64_t e) {
+    int64_t first = (int64_t)tris.size() / 12;
+    for (int64_t i = b; i < e; i++) {
+      const float* t = tri + 9 * (int64_t)prims[i].id;
+      float v0[3] = {t[0], t[1], t[2]};
+      float e1[3] = {t[3] - t[0], t[4] - t[1], t[5] - t[2]};
+      float e2[3] = {t[6] - t[0], t[7] - t[1], t[8] - t[2]};
+      // n = e1 x e2 and |n|^2, rounded exactly as the hit test expects
+      float n0 = e1[1] * e2[2] - e1[2] * e2[1];
+      float n1 = e1[2] * e2[0] - e1[0] * e2[2];
+      float n2 = e1[0] * e2[1] - e1[1] * e2[0];
+      float nn = (n0 * n0 + n1 * n1) + n2 * n2;
+      float rec[12] = {v0[0], v0[1], v0[2], as_f(prims[i].id), e1[0], e1[1], e1[2], nn, e2[0], e2[1], e2[2], 0.f};
+      tris.insert(tris.end(), rec, rec + 12);
+    }
+    int64_t cnt = e - b;
+    return ~(int32_t)((first << 3) | (cnt - 1));
+  }
+
+  // Split [b, e) -> mid; returns mid (b < mid < e)
+  int64_t split(int64_t b, int64_t e, int depth) {
+    int64_t n = e - b;
+    Box cb;
+    for (int64_t i = b; i < e; i++) cb.grow(prims[i].c, prims[i].c);
+    int axis = 0;
+    float ext = cb.hi[0] - cb.lo[0];
+    for (int k = 1; k < 3; k++)
+      if (cb.hi[k] - cb.lo[k] > ext) { ext = cb.hi[k] - cb.lo[k]; axis = k; }
+    auto median = [&](int ax) {
+      int64_t mid = b + n / 2;
+      std::nth_element(prims.begin() + b, prims.begin() + mid, prims.begin() + e,
+                       [ax](const Prim& p, const Prim& q) { return p.c[ax] < q.c[ax] || (p.c[ax] == q.c[ax] && p.id < q.id); });
+      return mid;
+    };
+    if (!(ext > 0.f) || depth > 40) return median(axis);
+    constexpr int NB = 16;
+    double best = std::numeric_limits<double>::infinity();
+    int best_axis = -1, best_bin = -1;
+    for (int ax = 0; ax < 3; ax++) {
+      float lo = cb.lo[ax], w = cb.hi[ax] - cb.lo[ax];
+      if (!(w > 0.f)) continue;
+      Box bb[NB];
+      int64_t cnt[NB] = {0};
+      for (int64_t i = b; i < e; i++) {
+        int k = (int)((prims[i].c[ax] - lo) / w * NB);
+        k = std::min(std::max(k, 0), NB - 1);
+        cnt[k]++;
+        bb[k].grow(prims[i].lo, prims[i].hi);
+      }
+      double ra[NB];
+      int64_t rc[NB];
+      Box acc;
+      int64_t c = 0;
+      for (int k = NB - 1; k > 0; k--) {
+        acc.grow(bb[k]);
+        c += cnt[k];
+        ra[k] = acc.area();
+        rc[k] = c;
+      }
+      Box accl;
+      int64_t cl = 0;
+      for (int k = 0; k < NB - 1; k++) {
+        accl.grow(bb[k]);
+        cl += cnt[k];
+        if (cl == 0 || rc[k + 1] == 0) continue;
+        double cost = accl.area() * (double)cl + ra[k + 1] * (double)rc[k + 1];
+        if (cost < best) { best = cost; best_axis = ax; best_bin = k; }
+      }
+    }
+    if (best_axis < 0) return median(axis);
+    float lo = cb.lo[best_axis], w = cb.hi[best_axis] - cb.lo[best_axis];
+    auto mid_it = std::partition(prims.begin() + b, prims.begin() + e, [&](const Prim& p) {
+      int k = (int)((p.c[best_axis] - lo) / w * NB);
+      k = std::min(std::max(k, 0), NB - 1);
+      return k <= best_bin;
+    });
+    int64_t mid = mid_it - prims.begin();
+    if (mid <= b || mid >= e) return median(axis);
+    return mid;
+  }
+
+  // Build the subtree over [b, e); returns its child code.
+  int32_t build(int64_t b, int64_t e, int depth) {
+    max_depth_seen = std::max(max_depth_seen, depth);
+    int64_t n = e - b;
+    if (n <= kLeafMax) return make_leaf(b, e);
+    int64_t mid = split(b, e, depth);
+    int64_t idx = (int64_t)nodes.size() / 16;
+    nodes.resize(nodes.size() + 16, 0.f);
+    Box l = bounds(b, mid), r = bounds(mid, e);
+    int32_t c0 = build(b, mid, depth + 1);
+    int32_t c1 = build(mid, e, depth + 1);
+    write_node(idx, l, r, c0, c1);
+    return (int32_t)idx;
+  }
+
+  void write_node(int64_t idx, const Box& l, const Box& r, int32_t c0, int32_t c1) {
+    float* nd = nodes.data() + 16 * idx;
+    auto plo = [&](float v) { return v - pad; };
+    auto phi = [&](float v) { return v + pad; };
+    nd[0] = plo(l.lo[0]); nd[1] = phi(l.hi[0]); nd[2] = plo(l.lo[1]); nd[3] = phi(l.hi[1]);
+    nd[4] = plo(r.lo[0]); nd[5] = phi(r.hi[0]); nd[6] = plo(r.lo[1]); nd[7] = phi(r.hi[1]);
+    nd[8] = plo(l.lo[2]); nd[9] = phi(l.hi[2]); nd[10] = plo(r.lo[2]); nd[11] = phi(r.hi[2]);
+    nd[12] = as_f(c0); nd[13] = as_f(c1); nd[14] = 0.f; nd[15] = 0.f;
+  }
+};
+
+}  // namespace
+
+float bvh_pad_for(const float* tri, int64_t T, const float* lo, const float* hi) {
+  double m = 0.0;
+  for (int k = 0; k < 3; k++) m = std::max({m, std::fabs((double)lo[k]), std::fabs((double)hi[k]),
+                                            (double)hi[k] - (double)lo[k]});
+  for (int64_t i = 0; i < 9 * T; i++) m = std::max(m, std::fabs((double)tri[i]));
+  return (float)(m > 0 ? m : 1.0);
+}
+
+// Padding of one triangle's box.  The FP32 hit test can accept a point up to
+// ~4e-5 * scale / sin(beta_min) away from the exact triangle (beta_min: the
+// triangle's smallest angle; rays within ~0.6 degrees of the plane are
+// rejected); the pad is 5x that bound, capped at the scene scale.
+float triangle_pad(const float* t, float scale) {
+  double e1[3], e2[3], e3[3];
+  for (int k = 0; k < 3; k++) {
+    e1[k] = (double)t[3 + k] - t[k];
+    e2[k] = (double)t[6 + k] - t[k];
+    e3[k] = (double)t[6 + k] - t[3 + k];
+  }
+  double c[3] = {e1[1] * e2[2] - e1[2] * e2[1], e1[2] * e2[0] - e1[0] * e2[2], e1[0] * e2[1] - e1[1] * e2[0]};
+  double area2 = std::sqrt(c[0] * c[0] + c[1] * c[1] + c[2] * c[2]);
+  double L[3] = {std::sqrt(e1[0] * e1[0] + e1[1] * e1[1] + e1[2] * e1[2]),
+                 std::sqrt(e2[0] * e2[0] + e2[1] * e2[1] + e2[2] * e2[2]),
+                 std::sqrt(e3[0] * e3[0] + e3[1] * e3[1] + e3[2] * e3[2])};
+  std::sort(L, L + 3);
+  double sinb = (L[1] * L[2] > 0) ? area2 / (L[1] * L[2]) : 0.0;
+  double p = sinb > 0 ? 2e-4 * scale / sinb : scale;
+  return (float)std::min(p, (double)scale);
+}
+
+int build_bvh(const float* tri, int64_t T, float pad, HostBvh& out, std::string& err) {
+  out.nodes.clear();
+  out.tris.clear();
+  out.pad = pad;
+  if (T >= (int64_t(1) << 28)) {
+    err = "too many triangles";
+    return RC_EINVAL;
+  }
+  std::vector<Prim> prims((size_t)T);
+  for (int64_t i = 0; i < T; i++) {
+    Prim& p = prims[i];
+    const float* t = tri + 9 * i;
+    float pi = triangle_pad(t, pad);
+    for (int k = 0; k < 3; k++) {
+      p.lo[k] = std::min({t[k], t[3 + k], t[6 + k]}) - pi;
+      p.hi[k] = std::max({t[k], t[3 + k], t[6 + k]}) + pi;
+      p.c[k] = (t[k] + t[3 + k] + t[6 + k]) * (1.0f / 3.0f);
+    }
+    p.id = (int32_t)i;
+  }
+  Builder bd{prims, tri, 0.0f, out.nodes, out.tris};
+  // The root is always an internal node (the traversal starts by testing
+  // both of its children).
+  out.nodes.resize(16, 0.f);
+  Box empty;  // inverted box: never hit
+  if (T <= kLeafMax) {
+    int32_t c0 = T > 0 ? bd.make_leaf(0, T) : ~0;
+    Box l = T > 0 ? bd.bounds(0, T) : empty;
+    bd.write_node(0, l, empty, c0, ~0);
+    // the empty child keeps its inverted box (padding must not make it valid)
+    float* nd = out.nodes.data();
+    nd[4] = std::numeric_limits<float>::infinity(); nd[5] = -std::numeric_limits<float>::infinity();
+    nd[6] = std::numeric_limits<float>::infinity(); nd[7] = -std::numeric_limits<float>::infinity();
+    nd[10] = std::numeric_limits<float>::infinity(); nd[11] = -std::numeric_limits<float>::infinity();
+    if (T == 0) {
+      nd[0] = std::numeric_limits<float>::infinity(); nd[1] = -std::numeric_limits<float>::infinity();
+      nd[2] = std::numeric_limits<float>::infinity(); nd[3] = -std::numeric_limits<float>::infinity();
+      nd[8] = std::numeric_limits<float>::infinity(); nd[9] = -std::numeric_limits<float>::infinity();
+    }
+    out.depth = 1;
+    return RC_OK;
+  }
+  int64_t mid = bd.split(0, T, 0);
+  Box l = bd.bounds(0, mid), r = bd.bounds(mid, T);
+  int32_t c0 = bd.build(0, mid, 1);
+  int32_t c1 = bd.build(mid, T, 1);
+  bd.write_node(0, l, r, c0, c1);
+  out.depth = bd.max_depth_seen + 1;
+  if (out.depth > kMaxDepth) {
+    err = "BVH deeper than the traversal stack";
+    return RC_EINVAL;
+  }
+  return RC_OK;
+}
+
+}  // namespace rc

@@ -1,0 +1,400 @@
+// device.hpp -- device-side building blocks of the record kernel (gfx950).
+//
+// The whole library is compiled with -ffp-contract=off: the FP32 decision
+// formulas below (direction rounding, ray/triangle test, shadow-ray origins,
+// ring distances, quad diagonals) must round exactly as written, because the
+// same published formulas decide the same discrete events on the CPU
+// reference.  Where fused multiply-adds are wanted (box slab tests), they are
+// written explicitly with fmaf.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#define RC_DEV __device__ __forceinline__
+
+namespace rc {
+
+constexpr double kPi = 3.14159265358979323846;
+constexpr float kPiF = 3.14159265358979323846f;
+constexpr int kWave = 64;
+
+// ---------------------------------------------------------------------------
+// Counter-based random numbers: splitmix64 (Steele, Lea, Flood 2014) used as
+// a hash of (seed, record, sample index, dimension).
+// ---------------------------------------------------------------------------
+RC_DEV uint64_t splitmix64(uint64_t x) {
+  uint64_t z = x + 0x9E3779B97F4A7C15ull;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+RC_DEV uint64_t record_key(uint64_t seed, uint64_t rec) { return splitmix64(splitmix64(seed) ^ rec); }
+RC_DEV float uniform24(uint64_t key, uint64_t idx, uint64_t dim) {
+  return (float)(splitmix64(splitmix64(key ^ idx) ^ dim) >> 40) * 0x1p-24f;
+}
+constexpr uint64_t kRingIdx = 0xFFFFFFFFull;
+
+// Jittered sample of stratum (a, b) of the equal-solid-angle (z, phi) grid,
+// evaluated in FP64 and rounded once to FP32 (Sec. 6, Implementation).
+RC_DEV float3 stratum_direction(uint64_t key, int a, int b, int nth, int nph) {
+  uint64_t idx = (uint64_t)a * (uint64_t)nph + (uint64_t)b;
+  double xi0 = uniform24(key, idx, 0), xi1 = uniform24(key, idx, 1);
+  double u = ((double)a + xi0) / (double)nth;
+  double v = ((double)b + xi1) / (double)nph;
+  double z = 1.0 - 2.0 * u;
+  double phi = (2.0 * kPi) * v;
+  double zz = z * z;
+  double st = sqrt(fmax(0.0, 1.0 - zz));
+  return make_float3((float)(st * cos(phi)), (float)(st * sin(phi)), (float)z);
+}
+
+RC_DEV float ring_distance(int i, float xi, float step) { return ((float)i + xi) * step; }
+
+// ---------------------------------------------------------------------------
+// FP32 vector helpers (decision formulas: no fused operations)
+// ---------------------------------------------------------------------------
+RC_DEV float3 sub3(float3 a, float3 b) { return make_float3(a.x - b.x, a.y - b.y, a.z - b.z); }
+RC_DEV float3 cross3(float3 a, float3 b) {
+  return make_float3(a.y * b.z - a.z * b.y, a.z * b.x - a.x * b.z, a.x * b.y - a.y * b.x);
+}
+RC_DEV float dot3(float3 a, float3 b) { return (a.x * b.x + a.y * b.y) + a.z * b.z; }
+RC_DEV float3 axpy3(float t, float3 w, float3 x) { return make_float3(x.x + t * w.x, x.y + t * w.y, x.z + t * w.z); }
+RC_DEV float det3(float3 a, float3 b, float3 c) { return dot3(a, cross3(b, c)); }
+
+// Moller-Trumbore in FP32 on (v0, e1, e2); rejects rays within ~0.6 degrees
+// of the triangle plane; hit iff tmin < t < tmax.  front: the ray travels
+// against e1 x e2.
+RC_DEV bool hit_triangle(float3 o, float3 d, float dd, float4 A, float4 B, float4 C, float tmin, float tmax,
+                         float& tout, bool& front) {
+  float3 e1 = make_float3(B.x, B.y, B.z), e2 = make_float3(C.x, C.y, C.z);
+  float3 p = cross3(d, e2);
+  float det = dot3(e1, p);
+  if (!(det * det > 1e-4f * (dd * B.w))) return false;
+  float3 s = sub3(o, make_float3(A.x, A.y, A.z));
+  float u = dot3(s, p);
+  float3 q = cross3(s, e1);
+  float v = dot3(d, q);
+  float tn = dot3(e2, q);
+  bool fr = true;
+  if (det < 0.0f) { det = -det; u = -u; v = -v; tn = -tn; fr = false; }
+  if (u < 0.0f || v < 0.0f || u + v > det) return false;
+  float t = tn / det;
+  if (!(t > tmin && t < tmax)) return false;
+  tout = t;
+  front = fr;
+  return true;
+}
+
+// FP32 distance to the exit of the medium box (rays that hit nothing).
+RC_DEV float box_exit(float3 o, float3 d, float3 lo, float3 hi) {
+  float t = __builtin_huge_valf();
+  if (d.x > 0.0f) t = fminf(t, (hi.x - o.x) / d.x); else if (d.x < 0.0f) t = fminf(t, (lo.x - o.x) / d.x);
+  if (d.y > 0.0f) t = fminf(t, (hi.y - o.y) / d.y); else if (d.y < 0.0f) t = fminf(t, (lo.y - o.y) / d.y);
+  if (d.z > 0.0f) t = fminf(t, (hi.z - o.z) / d.z); else if (d.z < 0.0f) t = fminf(t, (lo.z - o.z) / d.z);
+  return t > 0.0f ? t : 0.0f;
+}
+
+// ---------------------------------------------------------------------------
+// BVH traversal.  Boxes are padded by more than the FP32 error of an accepted
+// hit, so pruning never removes a triangle whose hit test would pass: the
+// closest hit (smallest t, ties to the lowest triangle id) and the any-hit
+// answer equal those of testing every triangle.
+// The per-lane stack lives in LDS: entry k of lane l at stk[k * 64] (stk is
+// pre-offset by the lane).
+// ---------------------------------------------------------------------------
+struct TraceCount {
+  uint32_t nodes = 0, tris = 0;
+};
+
+RC_DEV int leaf_first(int code) { return (~code) >> 3; }
+RC_DEV int leaf_count(int code) { return ((~code) & 7) + 1; }
+
+RC_DEV void ray_inv(float3 d, float3 o, float3& inv, float3& oi) {
+  const float eps = 1e-20f;
+  float dx = fabsf(d.x) > eps ? d.x : copysignf(eps, d.x);
+  float dy = fabsf(d.y) > eps ? d.y : copysignf(eps, d.y);
+  float dz = fabsf(d.z) > eps ? d.z : copysignf(eps, d.z);
+  inv = make_float3(1.0f / dx, 1.0f / dy, 1.0f / dz);
+  oi = make_float3(o.x * inv.x, o.y * inv.y, o.z * inv.z);
+}
+
+// slab test of one child box; returns the entry distance or +inf on a miss
+RC_DEV float slab(float lx, float hx, float ly, float hy, float lz, float hz, float3 inv, float3 oi, float t0,
+                  float t1) {
+  float ax = fmaf(lx, inv.x, -oi.x), bx = fmaf(hx, inv.x, -oi.x);
+  float ay = fmaf(ly, inv.y, -oi.y), by = fmaf(hy, inv.y, -oi.y);
+  float az = fmaf(lz, inv.z, -oi.z), bz = fmaf(hz, inv.z, -oi.z);
+  float tn = fmaxf(fmaxf(fminf(ax, bx), fminf(ay, by)), fmaxf(fminf(az, bz), t0));
+  float tf = fminf(fminf(fmaxf(ax, bx), fmaxf(ay, by)), fminf(fmaxf(az, bz), t1));
+  return tn <= tf ? tn : __builtin_huge_valf();
+}
+
+template <bool COUNT>
+RC_DEV void trace_closest(const float4* __restrict__ nodes, const float4* __restrict__ tris, float3 o, float3 d,
+                          int* stk, int& best_id, float& best_t, bool& best_front, TraceCount& cnt) {
+  float dd = dot3(d, d);
+  float3 inv, oi;
+  ray_inv(d, o, inv, oi);
+  best_id = -1;
+  best_t = __builtin_huge_valf();
+  best_front = false;
+  int sp = 0;
+  int node = 0;
+  while (true) {
+    while (node >= 0) {
+      const float4* nd = nodes + 4 * node;
+      float4 w0 = nd[0], w1 = nd[1], w2 = nd[2], w3 = nd[3];
+      if (COUNT) cnt.nodes++;
+      float ta = slab(w0.x, w0.y, w0.z, w0.w, w2.x, w2.y, inv, oi, 0.0f, best_t);
+      float tb = slab(w1.x, w1.y, w1.z, w1.w, w2.z, w2.w, inv, oi, 0.0f, best_t);
+      int ca = __float_as_int(w3.x), cb = __float_as_int(w3.y);
+      bool ha = ta <= best_t, hb = tb <= best_t;
+      if (ha && hb) {
+        int nearc = ta <= tb ? ca : cb, farc = ta <= tb ? cb : ca;
+        stk[sp * kWave] = farc;
+        sp++;
+        node = nearc;
+      } else if (ha) {
+        node = ca;
+      } else if (hb) {
+        node = cb;
+      } else {
+        if (sp == 0) return;
+        sp--;
+        node = stk[sp * kWave];
+      }
+    }
+    // leaf
+    int first = leaf_first(node), n = leaf_count(node);
+    for (int k = 0; k < n; k++) {
+      const float4* tr = tris + 3 * (first + k);
+      float4 A = tr[0], B = tr[1], C = tr[2];
+      if (COUNT) cnt.tris++;
+      float t;
+      bool fr;
+      if (hit_triangle(o, d, dd, A, B, C, 0.0f, __builtin_huge_valf(), t, fr)) {
+        int id = __float_as_int(A.w);
+        if (t < best_t || (t == best_t && id < best_id)) {
+          best_t = t;
+          best_id = id;
+          best_front = fr;
+        }
+      }
+    }
+    if (sp == 0) return;
+    sp--;
+    node = stk[sp * kWave];
+  }
+}
+
+// Shadow segment o -> o + d: blocked iff some triangle other than `skip` is
+// hit with 1e-4 < t < 1.
+template <bool COUNT>
+RC_DEV bool occluded(const float4* __restrict__ nodes, const float4* __restrict__ tris, float3 o, float3 d,
+                     int skip, int* stk, TraceCount& cnt) {
+  float dd = dot3(d, d);
+  float3 inv, oi;
+  ray_inv(d, o, inv, oi);
+  int sp = 0;
+  int node = 0;
+  while (true) {
+    while (node >= 0) {
+      const float4* nd = nodes + 4 * node;
+      float4 w0 = nd[0], w1 = nd[1], w2 = nd[2], w3 = nd[3];
+      if (COUNT) cnt.nodes++;
+      float ta = slab(w0.x, w0.y, w0.z, w0.w, w2.x, w2.y, inv, oi, 0.0f, 1.0f);
+      float tb = slab(w1.x, w1.y, w1.z, w1.w, w2.z, w2.w, inv, oi, 0.0f, 1.0f);
+      int ca = __float_as_int(w3.x), cb = __float_as_int(w3.y);
+      bool ha = ta <= 1.0f, hb = tb <= 1.0f;
+      if (ha && hb) {
+        int nearc = ta <= tb ? ca : cb, farc = ta <= tb ? cb : ca;
+        stk[sp * kWave] = farc;
+        sp++;
+        node = nearc;
+      } else if (ha) {
+        node = ca;
+      } else if (hb) {
+        node = cb;
+      } else {
+        if (sp == 0) return false;
+        sp--;
+        node = stk[sp * kWave];
+      }
+    }
+    int first = leaf_first(node), n = leaf_count(node);
+    for (int k = 0; k < n; k++) {
+      const float4* tr = tris + 3 * (first + k);
+      float4 A = tr[0], B = tr[1], C = tr[2];
+      if (COUNT) cnt.tris++;
+      float t;
+      bool fr;
+      if (__float_as_int(A.w) != skip && hit_triangle(o, d, dd, A, B, C, 1e-4f, 1.0f, t, fr)) return true;
+    }
+    if (sp == 0) return false;
+    sp--;
+    node = stk[sp * kWave];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// One triangle's contribution to the gradient and Hessian
+// (Eqs. SSSegALGradientSimp / SSSegALHessianSimp):
+//   g = wL (T grad F + F grad T)
+//   H = wL (T HF + grad T grad F^T + grad F grad T^T + F HT)
+// with the triangle's solid angle Omega = 2 atan2(|A|, B), F = Omega/(4 pi)
+// (App. C), its gradient (B grad|A| - |A| grad B) / (2 pi D), D = A^2 + B^2,
+// and its Hessian written in symmetric form
+//   HF = [ -|A| J(grad B) / D
+//          + ((A^2 - B^2)(a b^T + b a^T) - 2 |A| B (a a^T - b b^T)) / D^2 ] / (2 pi)
+// where a = grad|A| (J(grad A) = 0, App. C) and b = grad B.  Transmittance
+// T = exp(-mu r) to the far vertex and its derivatives (App. A).
+// Vertices are given relative to x (r_k = y_k - x); `far` indexes the far
+// vertex.  Outputs g[3] and h[6] (xx, xy, xz, yy, yz, zz).
+// ---------------------------------------------------------------------------
+template <typename R>
+struct V3 {
+  R x, y, z;
+};
+template <typename R>
+RC_DEV V3<R> mk(R x, R y, R z) { return V3<R>{x, y, z}; }
+template <typename R>
+RC_DEV V3<R> operator+(V3<R> a, V3<R> b) { return mk(a.x + b.x, a.y + b.y, a.z + b.z); }
+template <typename R>
+RC_DEV V3<R> operator-(V3<R> a, V3<R> b) { return mk(a.x - b.x, a.y - b.y, a.z - b.z); }
+template <typename R>
+RC_DEV V3<R> operator*(R s, V3<R> a) { return mk(s * a.x, s * a.y, s * a.z); }
+template <typename R>
+RC_DEV R dotv(V3<R> a, V3<R> b) { return a.x * b.x + a.y * b.y + a.z * b.z; }
+template <typename R>
+RC_DEV V3<R> crossv(V3<R> a, V3<R> b) { return mk(a.y * b.z - a.z * b.y, a.z * b.x - a.x * b.z, a.x * b.y - a.y * b.x); }
+
+// symmetric outer-product helpers on 6-vectors (xx, xy, xz, yy, yz, zz)
+template <typename R>
+RC_DEV void sym_add_outer2(R* h, R s, V3<R> a, V3<R> b) {  // h += s (a b^T + b a^T)
+  h[0] += s * (2 * a.x * b.x);
+  h[1] += s * (a.x * b.y + a.y * b.x);
+  h[2] += s * (a.x * b.z + a.z * b.x);
+  h[3] += s * (2 * a.y * b.y);
+  h[4] += s * (a.y * b.z + a.z * b.y);
+  h[5] += s * (2 * a.z * b.z);
+}
+template <typename R>
+RC_DEV void sym_add_outer(R* h, R s, V3<R> a) {  // h += s a a^T
+  h[0] += s * a.x * a.x;
+  h[1] += s * a.x * a.y;
+  h[2] += s * a.x * a.z;
+  h[3] += s * a.y * a.y;
+  h[4] += s * a.y * a.z;
+  h[5] += s * a.z * a.z;
+}
+
+template <typename R>
+RC_DEV R r_atan2(R y, R x);
+template <>
+RC_DEV float r_atan2<float>(float y, float x) { return atan2f(y, x); }
+template <>
+RC_DEV double r_atan2<double>(double y, double x) { return atan2(y, x); }
+template <typename R>
+RC_DEV R r_sqrt(R v);
+template <>
+RC_DEV float r_sqrt<float>(float v) { return sqrtf(v); }
+template <>
+RC_DEV double r_sqrt<double>(double v) { return sqrt(v); }
+template <typename R>
+RC_DEV R r_exp(R v);
+template <>
+RC_DEV float r_exp<float>(float v) { return expf(v); }
+template <>
+RC_DEV double r_exp<double>(double v) { return exp(v); }
+
+// Returns false if the triangle is degenerate for this precision (caller
+// retries in FP64 or drops a term of zero measure).
+// q_k = t_k w_k: vertex k at ray distance t_k along direction w_k.
+// detw = w1 . (w2 x w3), supplied by the caller in FP64 precision: for thin
+// (near-zero-area) triangles it is the one quantity FP32 cannot resolve, and
+// A = q1 . (q2 x q3) = t1 t2 t3 detw exactly.
+//
+// F is invariant under scaling of the vertices about x, grad F scales as 1/s
+// and HF as 1/s^2: the form factor is evaluated on vertices divided by
+// s = max_k |r_k| and rescaled, which keeps B ~ |r|^3 and 1/D^2 ~ |r|^-12 inside
+// the FP32 range for vertices arbitrarily close to x.
+template <typename R>
+RC_DEV bool triangle_term(V3<R> q1, V3<R> q2, V3<R> q3, R t1, R t2, R t3, R detw, int far, R wL, R mu, R* g,
+                          R* h) {
+  const R inv2pi = (R)(1.0 / (2.0 * kPi));
+  R m1 = r_sqrt(dotv(q1, q1)), m2 = r_sqrt(dotv(q2, q2)), m3 = r_sqrt(dotv(q3, q3));
+  R sc = m1 > m2 ? (m1 > m3 ? m1 : m3) : (m2 > m3 ? m2 : m3);
+  if (!(sc > (R)0)) return false;
+  R isc = (R)1 / sc;
+  V3<R> r1 = isc * q1, r2 = isc * q2, r3 = isc * q3;
+  R l1 = m1 * isc, l2 = m2 * isc, l3 = m3 * isc;
+  V3<R> c12 = crossv(r1, r2), c23 = crossv(r2, r3), c31 = crossv(r3, r1);
+  R A = ((t1 * isc) * (t2 * isc) * (t3 * isc)) * detw;
+  R d12 = dotv(r1, r2), d23 = dotv(r2, r3), d13 = dotv(r1, r3);
+  R B = l1 * l2 * l3 + d12 * l3 + d23 * l1 + d13 * l2;
+  R absA = A < 0 ? -A : A;
+  R sg = A < 0 ? (R)-1 : (R)1;
+  if (A == (R)0) return false;
+  V3<R> u1 = ((R)1 / l1) * r1, u2 = ((R)1 / l2) * r2, u3 = ((R)1 / l3) * r3;
+  V3<R> a = (-sg) * (c12 + c23 + c31);
+  // b = grad B, with grad l_k = -u_k
+  V3<R> b = (-(l2 * l3 + d23)) * u1 + (-(l1 * l3 + d13)) * u2 + (-(l1 * l2 + d12)) * u3;
+  b = b - l3 * (r1 + r2) - l1 * (r2 + r3) - l2 * (r1 + r3);
+  R D = absA * absA + B * B;
+  R iD = (R)1 / D;
+  R F = r_atan2(absA, B) * inv2pi;  // Omega / (4 pi) with Omega = 2 atan2(|A|, B)
+  V3<R> gF = (inv2pi * iD * isc) * (B * a - absA * b);
+  // J(grad B), symmetric
+  R JB[6] = {0, 0, 0, 0, 0, 0};
+  R k1 = (l2 * l3 + d23) / l1, k2 = (l1 * l3 + d13) / l2, k3 = (l1 * l2 + d12) / l3;
+  R diag = k1 + k2 + k3 + (R)2 * (l1 + l2 + l3);
+  JB[0] = diag;
+  JB[3] = diag;
+  JB[5] = diag;
+  sym_add_outer(JB, -k1, u1);
+  sym_add_outer(JB, -k2, u2);
+  sym_add_outer(JB, -k3, u3);
+  sym_add_outer2(JB, l1, u2, u3);
+  sym_add_outer2(JB, l2, u1, u3);
+  sym_add_outer2(JB, l3, u1, u2);
+  sym_add_outer2(JB, (R)1, u3, r1 + r2);
+  sym_add_outer2(JB, (R)1, u1, r2 + r3);
+  sym_add_outer2(JB, (R)1, u2, r1 + r3);
+  R HF[6];
+  R c0 = -absA * iD * inv2pi;
+  R iD2 = iD * iD * inv2pi;
+  for (int k = 0; k < 6; k++) HF[k] = c0 * JB[k];
+  sym_add_outer2(HF, (A * A - B * B) * iD2, a, b);
+  sym_add_outer(HF, (R)-2 * absA * B * iD2, a);
+  sym_add_outer(HF, (R)2 * absA * B * iD2, b);
+  const R isc2 = isc * isc;
+  for (int k = 0; k < 6; k++) HF[k] *= isc2;
+  // transmittance to the far vertex (true distances), u = x - y_far = -r_far
+  V3<R> rf = far == 0 ? r1 : (far == 1 ? r2 : r3);
+  R lf = (far == 0 ? l1 : (far == 1 ? l2 : l3)) * sc;
+  V3<R> uf = (sc / lf) * rf;
+  R T = r_exp(-mu * lf);
+  V3<R> gT = (mu * T) * uf;
+  // HT = -(mu T / r)(I - (1 + mu r) uf uf^T)
+  R cH = -mu * T / lf;
+  R HT[6] = {cH, 0, 0, cH, 0, cH};
+  sym_add_outer(HT, -cH * ((R)1 + mu * lf), uf);
+  g[0] = wL * (T * gF.x + F * gT.x);
+  g[1] = wL * (T * gF.y + F * gT.y);
+  g[2] = wL * (T * gF.z + F * gT.z);
+  R hh[6];
+  for (int k = 0; k < 6; k++) hh[k] = T * HF[k] + F * HT[k];
+  sym_add_outer2(hh, (R)1, gT, gF);
+  for (int k = 0; k < 6; k++) h[k] = wL * hh[k];
+  return true;
+}
+
+// Neumaier compensated accumulation in FP32
+RC_DEV void kadd(float& s, float& c, float x) {
+  float t = s + x;
+  if (fabsf(s) >= fabsf(x)) c += (s - t) + x;
+  else c += (x - t) + s;
+  s = t;
+}
+
+}  // namespace rc

@@ -1,0 +1,40 @@
+// internal.hpp -- shared between the host API and the kernels of librc.
+#pragma once
+#include <cstddef>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/rc.h"
+
+namespace rc {
+
+// Node layout (64 bytes, four 16-byte words), a binary BVH whose nodes store
+// both children's padded boxes so one fetch decides both:
+//   w0 = (c0.lo.x, c0.hi.x, c0.lo.y, c0.hi.y)
+//   w1 = (c1.lo.x, c1.hi.x, c1.lo.y, c1.hi.y)
+//   w2 = (c0.lo.z, c0.hi.z, c1.lo.z, c1.hi.z)
+//   w3 = (child0, child1, 0, 0) as int bits: >= 0 internal node index,
+//        < 0 leaf ~((first << 3) | (count - 1)).
+// Triangle layout (48 bytes): (v0.xyz, id bits), (e1.xyz, |e1 x e2|^2),
+// (e2.xyz, 0) with e1 = v1 - v0, e2 = v2 - v0 rounded in FP32.
+constexpr int kLeafMax = 4;
+constexpr int kMaxDepth = 60;
+
+struct HostBvh {
+  std::vector<float> nodes;   // [n_nodes * 16]
+  std::vector<float> tris;    // [T * 12]
+  int depth = 0;
+  float pad = 0.f;
+};
+
+// Build on the host. pad = scene coordinate scale (bvh_pad_for).
+int build_bvh(const float* tri, int64_t T, float pad, HostBvh& out, std::string& err);
+
+// Scene coordinate scale (largest |coordinate| or box side) that sets the
+// FP32 error of an accepted ray/triangle hit.
+float bvh_pad_for(const float* tri, int64_t T, const float* lo, const float* hi);
+// Box padding of one triangle (FP32 hit error bound x 5, see bvh.cpp).
+float triangle_pad(const float* t, float scale);
+
+}  // namespace rc

@@ -1,0 +1,619 @@
+// kernels.hip -- HIP kernels of librc for gfx950 (AMD Instinct MI355X).
+//
+// record_kernel: one wavefront computes one whole radiance-cache record
+// (Sec. 4 and Sec. 6 of Marco et al. 2018).  The grid is persistent: each
+// wavefront pops record indices from a queue counter until the queue is
+// empty.  Per record the wave walks the strata rows from the north pole to
+// the south pole, keeping two rows on chip (LDS):
+//   1. trace the row's directions (closest hit over the BVH) and count the
+//      medium rings in front of each hit;
+//   2. shade every surface vertex and ring vertex of the row with one shadow
+//      ray per point light; the (vertex, light) tasks of the row are
+//      compacted across the 64 lanes;
+//   3. accumulate the Monte Carlo value of the row's strata;
+//   4. form the triangles between the previous row and this one (polar fans
+//      at the ends, two triangles per quad elsewhere) and evaluate every
+//      (triangle, ring) term, again compacted across lanes, into per-lane
+//      compensated FP32 sums (FP64 for near-degenerate terms);
+// and finally reduces the 64 lanes in FP64 with cross-lane shuffles.
+#include <hip/hip_runtime.h>
+
+#include "device.hpp"
+#include "kernels.hpp"
+
+namespace rc {
+
+namespace {
+
+struct Row {
+  float *wx, *wy, *wz, *t, *Ls, *Lm;
+  int *code, *M;
+};
+
+RC_DEV Row row_view(float* base, int cap, int mr) {
+  Row r;
+  r.wx = base;
+  r.wy = base + cap;
+  r.wz = base + 2 * cap;
+  r.t = base + 3 * cap;
+  r.code = (int*)(base + 4 * cap);
+  r.M = (int*)(base + 5 * cap);
+  r.Ls = base + 6 * cap;
+  r.Lm = base + 7 * cap;  // [mr][cap]
+  (void)mr;
+  return r;
+}
+
+RC_DEV int wave_inclusive_scan(int v, int lane) {
+#pragma unroll
+  for (int s = 1; s < kWave; s <<= 1) {
+    int o = __shfl_up(v, s, kWave);
+    if (lane >= s) v += o;
+  }
+  return v;
+}
+
+// largest j in [0, n) with off[j] <= x (off non-decreasing, off[0] = 0)
+RC_DEV int find_slot(const int* off, int n, int x) {
+  int lo = 0, hi = n - 1;
+  while (lo < hi) {
+    int mid = (lo + hi + 1) >> 1;
+    if (off[mid] <= x) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
+}
+
+RC_DEV double wave_sum(double v) {
+#pragma unroll
+  for (int s = 32; s >= 1; s >>= 1) v += __shfl_xor(v, s, kWave);
+  return v;
+}
+
+}  // namespace
+
+template <int STACK, bool COUNT, bool F64>
+__global__ __launch_bounds__(64) void record_kernel(RecordArgs g) {
+  extern __shared__ float lds[];
+  const int lane = threadIdx.x;
+  const int cap = g.max_n_phi;
+  const int MR = g.max_rings;
+  int* stk = reinterpret_cast<int*>(lds) + lane;
+  float* rows = lds + STACK * kWave;
+  const int row_words = cap * (7 + MR);
+  int* off = reinterpret_cast<int*>(rows + 2 * row_words);  // [2 * cap + 1]
+  // per-record FP64 accumulators (lane 0 writes): 2 values + 2 x 9 derivatives
+  double* racc = reinterpret_cast<double*>(off + ((2 * cap + 2) & ~1));
+
+  const float mu = g.sigma_s + g.sigma_a;
+  const float ms_scale = g.sigma_s * (float)(1.0 / (4.0 * kPi));
+  TraceCount tc;
+  uint32_t n_rays = 0, n_terms = 0;
+
+  while (true) {
+    int q = 0;
+    if (lane == 0) q = (int)atomicAdd(&g.queue[0], 1u);
+    q = __shfl(q, 0, kWave);
+    if (q >= g.P) break;
+    const int rec = g.order ? g.order[q] : q;
+    if (rec < 0 || rec >= g.P) {  // corrupt queue entry: count it, touch nothing
+      if (lane == 0) atomicAdd(&g.queue[1], 1u);
+      continue;
+    }
+    const float3 x = make_float3(g.pos[3 * rec], g.pos[3 * rec + 1], g.pos[3 * rec + 2]);
+    const int nth = g.n_theta[rec], nph = g.n_phi[rec];
+    const bool bad = !(nth >= 2 && nph >= 5 && nph <= cap) || !(x.x >= g.box_lo.x && x.x <= g.box_hi.x) ||
+                     !(x.y >= g.box_lo.y && x.y <= g.box_hi.y) || !(x.z >= g.box_lo.z && x.z <= g.box_hi.z);
+    if (bad) {
+      if (lane < 2) {
+        g.value[2 * rec + lane] = __builtin_nan("");
+        for (int k = 0; k < 3; k++) g.grad[6 * rec + 3 * lane + k] = __builtin_nan("");
+        for (int k = 0; k < 6; k++) g.hess[12 * rec + 6 * lane + k] = __builtin_nan("");
+      }
+      if (lane == 0) atomicAdd(&g.queue[1], 1u);
+      continue;
+    }
+    const int N = nth * nph;
+    const uint64_t key = record_key(g.seed, (uint64_t)(g.rec_base + rec));
+    const float xr = uniform24(key, kRingIdx, 0);
+
+    if (lane < 20) racc[lane] = 0.0;
+
+    // rows: -1 north pole, 0..nth-1 strata rows, nth south pole
+    for (int a = -1; a <= nth; a++) {
+      float* const baseR = rows + ((a + 1) & 1) * row_words;
+      float* const baseP = rows + (a & 1) * row_words;
+      const Row R = row_view(baseR, cap, MR);
+      const Row P = row_view(baseP, cap, MR);
+      const bool pole = (a < 0 || a == nth);
+      const int n = pole ? 1 : nph;
+      // ---- 1. primary rays ------------------------------------------------
+      for (int base = 0; base < n; base += kWave) {
+        int j = base + lane;
+        if (j < n) {
+          float3 w;
+          if (a < 0) w = make_float3(0.f, 0.f, 1.f);
+          else if (a == nth) w = make_float3(0.f, 0.f, -1.f);
+          else w = stratum_direction(key, a, j, nth, nph);
+          int id;
+          float t;
+          bool fr;
+          trace_closest<COUNT>(g.nodes, g.tris, x, w, stk, id, t, fr, tc);
+          if (id < 0) t = box_exit(x, w, g.box_lo, g.box_hi);
+          int M = 0;
+          while (M < MR && ring_distance(M, xr, g.ring_step) < t) M++;
+          R.wx[j] = w.x;
+          R.wy[j] = w.y;
+          R.wz[j] = w.z;
+          R.t[j] = t;
+          R.code[j] = id >= 0 ? ((id << 1) | (fr ? 1 : 0)) : -1;
+          R.M[j] = M;
+          R.Ls[j] = id >= 0 ? g.emission[id] : 0.f;
+          for (int i = 0; i < M; i++) R.Lm[i * cap + j] = 0.f;
+          if (COUNT) n_rays++;
+        }
+      }
+      __syncthreads();
+      // ---- 2. shadow rays: tasks (vertex, light), compacted ----------------
+      if (g.n_lights > 0) {
+        int carry = 0;
+        for (int base = 0; base < n; base += kWave) {
+          int j = base + lane;
+          int c = (j < n) ? ((R.code[j] >= 0 ? 1 : 0) + R.M[j]) : 0;
+          int inc = wave_inclusive_scan(c, lane);
+          if (j < n) off[j] = carry + inc - c;
+          carry += __shfl(inc, kWave - 1, kWave);
+        }
+        const int total = carry;
+        __syncthreads();
+        for (int l = 0; l < g.n_lights; l++) {
+          const float4 L = g.lights[l];
+          for (int base = 0; base < total; base += kWave) {
+            int task = base + lane;
+            if (task < total) {
+              int j = find_slot(off, n, task);
+              int v = task - off[j];
+              int code = R.code[j];
+              float3 w = make_float3(R.wx[j], R.wy[j], R.wz[j]);
+              if (code >= 0 && v == 0) {
+                // surface vertex: Lambertian, lit side facing x
+                int id = code >> 1;
+                float3 y = axpy3(R.t[j], w, x);
+                float3 seg = make_float3(L.x - y.x, L.y - y.y, L.z - y.z);
+                float4 sh = g.shade[id];
+                float nsign = (code & 1) ? 1.f : -1.f;
+                float dist = sqrtf(dot3(seg, seg));
+                float c = nsign * dot3(make_float3(sh.x, sh.y, sh.z), seg) / dist;
+                if (c > 0.f && !occluded<COUNT>(g.nodes, g.tris, y, seg, id, stk, tc))
+                  R.Ls[j] += sh.w * (float)(1.0 / kPi) * L.w * c * expf(-mu * dist) / (dist * dist);
+              } else {
+                int i = v - (code >= 0 ? 1 : 0);
+                float3 y = axpy3(ring_distance(i, xr, g.ring_step), w, x);
+                float3 seg = make_float3(L.x - y.x, L.y - y.y, L.z - y.z);
+                if (!occluded<COUNT>(g.nodes, g.tris, y, seg, -1, stk, tc)) {
+                  float dist2 = dot3(seg, seg);
+                  float dist = sqrtf(dist2);
+                  R.Lm[i * cap + j] += ms_scale * L.w * expf(-mu * dist) / dist2;
+                }
+              }
+              if (COUNT) n_rays++;
+            }
+          }
+          __syncthreads();
+        }
+      }
+      // ---- 3. Monte Carlo value of the strata in this row -----------------
+      if (!pole) {
+        float vs = 0.f, vsc = 0.f, vm = 0.f, vmc = 0.f;
+        for (int base = 0; base < n; base += kWave) {
+          int j = base + lane;
+          if (j < n) {
+            float3 w = make_float3(R.wx[j], R.wy[j], R.wz[j]);
+            float wn = sqrtf(dot3(w, w));
+            kadd(vs, vsc, expf(-mu * R.t[j] * wn) * R.Ls[j]);
+            for (int i = 0; i < R.M[j]; i++)
+              kadd(vm, vmc, g.ring_step * expf(-mu * ring_distance(i, xr, g.ring_step) * wn) * R.Lm[i * cap + j]);
+          }
+        }
+        double s0 = wave_sum((double)vs + (double)vsc);
+        double s1 = wave_sum((double)vm + (double)vmc);
+        if (lane == 0) {
+          racc[0] += s0;
+          racc[1] += s1;
+        }
+      }
+      // ---- 4. triangles between the previous row and this one -------------
+      if (a >= 0) {
+        // kind 0: north fan (P = pole, R = row 0); 1: band; 2: south fan
+        const int kind = (a == 0) ? 0 : (a == nth ? 2 : 1);
+        const int ntri = (kind == 1) ? 2 * nph : nph;
+        const int prow = a - 1;  // strata row index of P (for vertex ids)
+        int carry = 0;
+        for (int base = 0; base < ntri; base += kWave) {
+          int tI = base + lane;
+          int c = 0;
+          if (tI < ntri) {
+            int m0, m1, m2;
+            int b = (kind == 1) ? (tI >> 1) : tI;
+            int b1 = (b + 1 == nph) ? 0 : b + 1;
+            if (kind == 0) { m0 = P.M[0]; m1 = R.M[b]; m2 = R.M[b1]; }
+            else if (kind == 2) { m0 = R.M[0]; m1 = P.M[b1]; m2 = P.M[b]; }
+            else { m0 = max(P.M[b], P.M[b1]); m1 = R.M[b]; m2 = R.M[b1]; }
+            c = 1 + max(m0, max(m1, m2));
+          }
+          int inc = wave_inclusive_scan(c, lane);
+          if (tI < ntri) off[tI] = carry + inc - c;
+          carry += __shfl(inc, kWave - 1, kWave);
+        }
+        const int total = carry;
+        __syncthreads();
+        float acc[18], accc[18];
+#pragma unroll
+        for (int k = 0; k < 18; k++) { acc[k] = 0.f; accc[k] = 0.f; }
+        for (int base = 0; base < total; base += kWave) {
+          int item = base + lane;
+          if (item >= total) continue;
+          int tI = find_slot(off, ntri, item);
+          int ring = item - off[tI] - 1;  // -1: surface ring
+          // the triangle's three vertices: (row pointer, column, global id)
+          const float* vb[3];  // row base of each vertex
+          int col[3], gid[3];
+          if (kind == 0) {
+            int b = tI, b1 = (b + 1 == nph) ? 0 : b + 1;
+            vb[0] = baseP; col[0] = 0; gid[0] = 0;
+            vb[1] = baseR; col[1] = b; gid[1] = 1 + b;
+            vb[2] = baseR; col[2] = b1; gid[2] = 1 + b1;
+          } else if (kind == 2) {
+            int b = tI, b1 = (b + 1 == nph) ? 0 : b + 1;
+            vb[0] = baseR; col[0] = 0; gid[0] = N + 1;
+            vb[1] = baseP; col[1] = b1; gid[1] = 1 + prow * nph + b1;
+            vb[2] = baseP; col[2] = b; gid[2] = 1 + prow * nph + b;
+          } else {
+            int b = tI >> 1, b1 = (b + 1 == nph) ? 0 : b + 1;
+            float3 wP = make_float3(P.wx[b], P.wy[b], P.wz[b]);
+            float3 wQ = make_float3(P.wx[b1], P.wy[b1], P.wz[b1]);
+            float3 wR = make_float3(R.wx[b], R.wy[b], R.wz[b]);
+            float3 wS = make_float3(R.wx[b1], R.wy[b1], R.wz[b1]);
+            bool d1 = det3(wP, wR, wS) > 0.f && det3(wP, wS, wQ) > 0.f;
+            int gP = 1 + prow * nph + b, gQ = 1 + prow * nph + b1, gR = 1 + a * nph + b, gS = 1 + a * nph + b1;
+            bool second = tI & 1;
+            if (d1) {
+              if (!second) { vb[0] = baseP; col[0] = b; gid[0] = gP; vb[1] = baseR; col[1] = b; gid[1] = gR; vb[2] = baseR; col[2] = b1; gid[2] = gS; }
+              else { vb[0] = baseP; col[0] = b; gid[0] = gP; vb[1] = baseR; col[1] = b1; gid[1] = gS; vb[2] = baseP; col[2] = b1; gid[2] = gQ; }
+            } else {
+              if (!second) { vb[0] = baseP; col[0] = b; gid[0] = gP; vb[1] = baseR; col[1] = b; gid[1] = gR; vb[2] = baseP; col[2] = b1; gid[2] = gQ; }
+              else { vb[0] = baseP; col[0] = b1; gid[0] = gQ; vb[1] = baseR; col[1] = b; gid[1] = gR; vb[2] = baseR; col[2] = b1; gid[2] = gS; }
+            }
+          }
+          float tau[3], Lv[3];
+          float3 wv[3];
+          const float rr = ring >= 0 ? ring_distance(ring, xr, g.ring_step) : 0.f;
+#pragma unroll
+          for (int k = 0; k < 3; k++) {
+            const float* b = vb[k];
+            int c = col[k];
+            // field offsets as laid out by row_view
+            wv[k] = make_float3(b[c], b[cap + c], b[2 * cap + c]);
+            float tk = b[3 * cap + c];
+            if (ring < 0) {
+              tau[k] = tk;
+              Lv[k] = b[6 * cap + c];
+            } else {
+              bool front = ring < reinterpret_cast<const int*>(b)[5 * cap + c];
+              tau[k] = front ? rr : tk;
+              Lv[k] = front ? b[(7 + ring) * cap + c] : 0.f;
+            }
+          }
+          int far = 0;
+#pragma unroll
+          for (int k = 1; k < 3; k++)
+            if (tau[k] > tau[far] || (tau[k] == tau[far] && gid[k] < gid[far])) far = k;
+          float Lf = Lv[far];
+          if (Lf == 0.f) continue;
+          // direction determinant in FP64 (thin triangles); A = tau1 tau2 tau3 detw
+          double dw = (double)wv[0].x * ((double)wv[1].y * wv[2].z - (double)wv[1].z * wv[2].y) +
+                      (double)wv[0].y * ((double)wv[1].z * wv[2].x - (double)wv[1].x * wv[2].z) +
+                      (double)wv[0].z * ((double)wv[1].x * wv[2].y - (double)wv[1].y * wv[2].x);
+          const int ch = ring < 0 ? 0 : 9;
+          if (!F64) {
+            float wL = ring < 0 ? Lf : g.ring_step * Lf;
+            float gg[3], hh[6];
+            V3<float> r1 = mk(tau[0] * wv[0].x, tau[0] * wv[0].y, tau[0] * wv[0].z);
+            V3<float> r2 = mk(tau[1] * wv[1].x, tau[1] * wv[1].y, tau[1] * wv[1].z);
+            V3<float> r3 = mk(tau[2] * wv[2].x, tau[2] * wv[2].y, tau[2] * wv[2].z);
+            if (triangle_term<float>(r1, r2, r3, tau[0], tau[1], tau[2], (float)dw, far, wL, mu, gg, hh)) {
+#pragma unroll
+              for (int k = 0; k < 3; k++) kadd(acc[ch + k], accc[ch + k], gg[k]);
+#pragma unroll
+              for (int k = 0; k < 6; k++) kadd(acc[ch + 3 + k], accc[ch + 3 + k], hh[k]);
+            }
+          } else {
+            // study mode: the whole term in FP64, folded into the compensated
+            // pair as a (hi, lo) split
+            double dtau[3] = {tau[0], tau[1], tau[2]};
+            if (ring >= 0) {
+              double r64 = ((double)ring + (double)xr) * (double)g.ring_step;
+#pragma unroll
+              for (int k = 0; k < 3; k++)
+                if (tau[k] == rr) dtau[k] = r64;
+            }
+            V3<double> r1 = mk(dtau[0] * wv[0].x, dtau[0] * wv[0].y, dtau[0] * wv[0].z);
+            V3<double> r2 = mk(dtau[1] * wv[1].x, dtau[1] * wv[1].y, dtau[1] * wv[1].z);
+            V3<double> r3 = mk(dtau[2] * wv[2].x, dtau[2] * wv[2].y, dtau[2] * wv[2].z);
+            double g64[3], h64[6];
+            double wL64 = ring < 0 ? (double)Lf : (double)g.ring_step * (double)Lf;
+            if (triangle_term<double>(r1, r2, r3, dtau[0], dtau[1], dtau[2], dw, far, wL64, (double)mu, g64, h64)) {
+#pragma unroll
+              for (int k = 0; k < 3; k++) {
+                float hi = (float)g64[k];
+                kadd(acc[ch + k], accc[ch + k], hi);
+                kadd(acc[ch + k], accc[ch + k], (float)(g64[k] - (double)hi));
+              }
+#pragma unroll
+              for (int k = 0; k < 6; k++) {
+                float hi = (float)h64[k];
+                kadd(acc[ch + 3 + k], accc[ch + 3 + k], hi);
+                kadd(acc[ch + 3 + k], accc[ch + 3 + k], (float)(h64[k] - (double)hi));
+              }
+            }
+          }
+          if (COUNT) n_terms++;
+        }
+        // band partial sums: lanes -> FP64 across the wave -> record accumulator
+#pragma unroll
+        for (int k = 0; k < 18; k++) {
+          double sk = wave_sum((double)acc[k] + (double)accc[k]);
+          if (lane == 0) racc[2 + k] += sk;
+        }
+      }
+      __syncthreads();
+    }
+    // ---- store ------------------------------------------------------------
+    if (lane < 2) g.value[2 * rec + lane] = racc[lane] / (double)N;
+    if (lane < 18) {
+      int c = lane / 9, k = lane % 9;
+      if (k < 3) g.grad[6 * rec + 3 * c + k] = racc[2 + lane];
+      else g.hess[12 * rec + 6 * c + (k - 3)] = racc[2 + lane];
+    }
+    __syncthreads();
+  }
+  if (COUNT) {
+    // wave-level totals, one atomic per wave
+    double r = wave_sum((double)n_rays), nd = wave_sum((double)tc.nodes), tr = wave_sum((double)tc.tris),
+           te = wave_sum((double)n_terms);
+    if (lane == 0) {
+      atomicAdd(&g.counters[0], (unsigned long long)r);
+      atomicAdd(&g.counters[1], (unsigned long long)nd);
+      atomicAdd(&g.counters[2], (unsigned long long)tr);
+      atomicAdd(&g.counters[3], (unsigned long long)te);
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// small kernels
+// ---------------------------------------------------------------------------
+__global__ void reset_queue_kernel(unsigned int* q) {
+  if (threadIdx.x < 2) q[threadIdx.x] = 0u;
+}
+
+// Queue of records ordered by decreasing cost N = n_theta * n_phi (coarse
+// buckets of 1/8 octave); ties in any order (records do not interact).
+__global__ void order_hist_kernel(const int* nth, const int* nph, int P, unsigned int* hist) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= P) return;
+  float n = fmaxf((float)nth[i] * (float)nph[i], 1.f);
+  int b = min(max((int)(log2f(n) * 8.f), 0), kOrderBuckets - 1);
+  atomicAdd(&hist[kOrderBuckets - 1 - b], 1u);
+}
+__global__ void order_scan_kernel(unsigned int* hist, unsigned int* cursor) {
+  if (threadIdx.x == 0) {
+    unsigned int s = 0;
+    for (int b = 0; b < kOrderBuckets; b++) {
+      cursor[b] = s;
+      s += hist[b];
+    }
+  }
+}
+__global__ void order_scatter_kernel(const int* nth, const int* nph, int P, unsigned int* cursor, int* order) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= P) return;
+  float n = fmaxf((float)nth[i] * (float)nph[i], 1.f);
+  int b = min(max((int)(log2f(n) * 8.f), 0), kOrderBuckets - 1);
+  unsigned int p = atomicAdd(&cursor[kOrderBuckets - 1 - b], 1u);
+  order[p] = i;
+}
+__global__ void zero_u32_kernel(unsigned int* p, int n) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = 0u;
+}
+
+// ---------------------------------------------------------------------------
+// validity radius: Jacobi eigen-decomposition of the summed 3x3 Hessian (FP64)
+// ---------------------------------------------------------------------------
+__global__ void radius_kernel(const double* __restrict__ value, const double* __restrict__ hess, int P, float eps,
+                              float r_min, float r_max, float* __restrict__ R, float* __restrict__ axes) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= P) return;
+  double L = value[2 * i] + value[2 * i + 1];
+  const double* h0 = hess + 12 * i;
+  double h[6];
+  for (int k = 0; k < 6; k++) h[k] = h0[k] + h0[6 + k];
+  double a[3][3] = {{h[0], h[1], h[2]}, {h[1], h[3], h[4]}, {h[2], h[4], h[5]}};
+  double v[3][3] = {{1, 0, 0}, {0, 1, 0}, {0, 0, 1}};
+  for (int sweep = 0; sweep < 12; sweep++) {
+    double off = a[0][1] * a[0][1] + a[0][2] * a[0][2] + a[1][2] * a[1][2];
+    double dg = a[0][0] * a[0][0] + a[1][1] * a[1][1] + a[2][2] * a[2][2];
+    if (!(off > 1e-30 * dg) || off == 0.0) break;
+    for (int p = 0; p < 2; p++)
+      for (int q = p + 1; q < 3; q++) {
+        if (a[p][q] == 0.0) continue;
+        double theta = (a[q][q] - a[p][p]) / (2.0 * a[p][q]);
+        double t = (theta >= 0 ? 1.0 : -1.0) / (fabs(theta) + sqrt(theta * theta + 1.0));
+        double c = 1.0 / sqrt(t * t + 1.0), s = t * c;
+        for (int k = 0; k < 3; k++) {  // A <- A J (columns p, q)
+          double akp = a[k][p], akq = a[k][q];
+          a[k][p] = c * akp - s * akq;
+          a[k][q] = s * akp + c * akq;
+        }
+        for (int k = 0; k < 3; k++) {  // A <- J^T A (rows p, q)
+          double apk = a[p][k], aqk = a[q][k];
+          a[p][k] = c * apk - s * aqk;
+          a[q][k] = s * apk + c * aqk;
+        }
+        for (int k = 0; k < 3; k++) {
+          double vkp = v[k][p], vkq = v[k][q];
+          v[k][p] = c * vkp - s * vkq;
+          v[k][q] = s * vkp + c * vkq;
+        }
+      }
+  }
+  double lam[3] = {a[0][0], a[1][1], a[2][2]};
+  double Ri[3];
+  for (int k = 0; k < 3; k++) {
+    double al = fabs(lam[k]);
+    double r;
+    if (!(L > 0.0)) r = r_min;
+    else if (al == 0.0) r = r_max;
+    else r = pow(15.0 * L * (double)eps / (4.0 * kPi * al), 0.2);
+    if (!(r >= (double)r_min)) r = r_min;  // also catches NaN
+    if (r > (double)r_max) r = r_max;
+    Ri[k] = r;
+  }
+  R[i] = (float)fmin(Ri[0], fmin(Ri[1], Ri[2]));
+  if (axes) {
+    for (int k = 0; k < 3; k++) axes[12 * i + k] = (float)Ri[k];
+    for (int k = 0; k < 3; k++)
+      for (int c = 0; c < 3; c++) axes[12 * i + 3 + 3 * k + c] = (float)v[c][k];  // row k = eigenvector k
+  }
+}
+
+// ---------------------------------------------------------------------------
+// host launchers
+// ---------------------------------------------------------------------------
+size_t record_lds_bytes(int stack, int max_n_phi, int max_rings) {
+  size_t words = (size_t)stack * kWave + 2 * (size_t)max_n_phi * (7 + max_rings) + ((2 * (size_t)max_n_phi + 2) & ~size_t(1));
+  return words * 4 + 20 * sizeof(double);
+}
+
+template <int S, bool C, bool D>
+static const void* kernel_ptr() {
+  return reinterpret_cast<const void*>(&record_kernel<S, C, D>);
+}
+
+// kernel variants: stack depth {32, 48, 64} x counting x FP64 study mode
+static const void* select_kernel(int stack, bool count, bool f64) {
+  const int s = stack <= 32 ? 0 : (stack <= 48 ? 1 : 2);
+  static const void* const table[3][2][2] = {
+      {{kernel_ptr<32, false, false>(), kernel_ptr<32, false, true>()},
+       {kernel_ptr<32, true, false>(), kernel_ptr<32, true, true>()}},
+      {{kernel_ptr<48, false, false>(), kernel_ptr<48, false, true>()},
+       {kernel_ptr<48, true, false>(), kernel_ptr<48, true, true>()}},
+      {{kernel_ptr<64, false, false>(), kernel_ptr<64, false, true>()},
+       {kernel_ptr<64, true, false>(), kernel_ptr<64, true, true>()}}};
+  return table[s][count ? 1 : 0][f64 ? 1 : 0];
+}
+
+int stack_variant(int depth) { return depth <= 32 ? 32 : (depth <= 48 ? 48 : 64); }
+
+int record_occupancy(int stack, bool count, bool f64, size_t lds) {
+  int n = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, select_kernel(stack, count, f64), kWave, lds) != hipSuccess)
+    return 0;
+  return n;
+}
+
+hipError_t prepare_record(int stack, bool count, bool f64, size_t lds) {
+  return hipFuncSetAttribute(select_kernel(stack, count, f64), hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+}
+
+hipError_t launch_record(const RecordArgs& a, int stack, bool count, bool f64, int grid, size_t lds, hipStream_t s) {
+  void* args[] = {const_cast<RecordArgs*>(&a)};
+  return hipLaunchKernel(select_kernel(stack, count, f64), dim3(grid), dim3(kWave), args, lds, s);
+}
+
+hipError_t launch_reset(unsigned int* q, hipStream_t s) {
+  hipLaunchKernelGGL(reset_queue_kernel, dim3(1), dim3(64), 0, s, q);
+  return hipGetLastError();
+}
+
+hipError_t launch_order(const int* nth, const int* nph, int P, unsigned int* hist, unsigned int* cursor, int* order,
+                        hipStream_t s) {
+  hipLaunchKernelGGL(zero_u32_kernel, dim3(1), dim3(kOrderBuckets), 0, s, hist, kOrderBuckets);
+  int blocks = (P + 255) / 256;
+  if (blocks > 0) hipLaunchKernelGGL(order_hist_kernel, dim3(blocks), dim3(256), 0, s, nth, nph, P, hist);
+  hipLaunchKernelGGL(order_scan_kernel, dim3(1), dim3(64), 0, s, hist, cursor);
+  if (blocks > 0) hipLaunchKernelGGL(order_scatter_kernel, dim3(blocks), dim3(256), 0, s, nth, nph, P, cursor, order);
+  return hipGetLastError();
+}
+
+hipError_t launch_radius(const double* value, const double* hess, int P, float eps, float r_min, float r_max, float* R,
+                         float* axes, hipStream_t s) {
+  int blocks = (P + 127) / 128;
+  if (blocks > 0)
+    hipLaunchKernelGGL(radius_kernel, dim3(blocks), dim3(128), 0, s, value, hess, P, eps, r_min, r_max, R, axes);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// ray queries (traversal checks): one ray per lane
+// ---------------------------------------------------------------------------
+template <int STACK>
+__global__ __launch_bounds__(64) void trace_rays_kernel(const float4* __restrict__ nodes,
+                                                        const float4* __restrict__ tris, const float* __restrict__ o,
+                                                        const float* __restrict__ d, int n, int* __restrict__ hit,
+                                                        float* __restrict__ t, int* __restrict__ front,
+                                                        float3 lo, float3 hi) {
+  __shared__ int stack[STACK * kWave];
+  int i = blockIdx.x * kWave + threadIdx.x;
+  if (i >= n) return;
+  float3 oo = make_float3(o[3 * i], o[3 * i + 1], o[3 * i + 2]);
+  float3 dd = make_float3(d[3 * i], d[3 * i + 1], d[3 * i + 2]);
+  int id;
+  float tt;
+  bool fr;
+  TraceCount tc;
+  trace_closest<false>(nodes, tris, oo, dd, stack + threadIdx.x, id, tt, fr, tc);
+  if (id < 0) tt = box_exit(oo, dd, lo, hi);
+  hit[i] = id;
+  t[i] = tt;
+  front[i] = fr ? 1 : 0;
+}
+
+template <int STACK>
+__global__ __launch_bounds__(64) void occluded_rays_kernel(const float4* __restrict__ nodes,
+                                                           const float4* __restrict__ tris,
+                                                           const float* __restrict__ o, const float* __restrict__ d,
+                                                           const int* __restrict__ skip, int n, int* __restrict__ occ) {
+  __shared__ int stack[STACK * kWave];
+  int i = blockIdx.x * kWave + threadIdx.x;
+  if (i >= n) return;
+  float3 oo = make_float3(o[3 * i], o[3 * i + 1], o[3 * i + 2]);
+  float3 dd = make_float3(d[3 * i], d[3 * i + 1], d[3 * i + 2]);
+  TraceCount tc;
+  occ[i] = occluded<false>(nodes, tris, oo, dd, skip ? skip[i] : -1, stack + threadIdx.x, tc) ? 1 : 0;
+}
+
+hipError_t launch_trace_rays(const float4* nodes, const float4* tris, int depth, const float* o, const float* d, int n,
+                             int* hit, float* t, int* front, float3 lo, float3 hi, hipStream_t s) {
+  int blocks = (n + kWave - 1) / kWave;
+  if (blocks == 0) return hipSuccess;
+  int st = stack_variant(depth);
+  if (st <= 32) hipLaunchKernelGGL(trace_rays_kernel<32>, dim3(blocks), dim3(kWave), 0, s, nodes, tris, o, d, n, hit, t, front, lo, hi);
+  else if (st <= 48) hipLaunchKernelGGL(trace_rays_kernel<48>, dim3(blocks), dim3(kWave), 0, s, nodes, tris, o, d, n, hit, t, front, lo, hi);
+  else hipLaunchKernelGGL(trace_rays_kernel<64>, dim3(blocks), dim3(kWave), 0, s, nodes, tris, o, d, n, hit, t, front, lo, hi);
+  return hipGetLastError();
+}
+
+hipError_t launch_occluded_rays(const float4* nodes, const float4* tris, int depth, const float* o, const float* d,
+                                const int* skip, int n, int* occ, hipStream_t s) {
+  int blocks = (n + kWave - 1) / kWave;
+  if (blocks == 0) return hipSuccess;
+  int st = stack_variant(depth);
+  if (st <= 32) hipLaunchKernelGGL(occluded_rays_kernel<32>, dim3(blocks), dim3(kWave), 0, s, nodes, tris, o, d, skip, n, occ);
+  else if (st <= 48) hipLaunchKernelGGL(occluded_rays_kernel<48>, dim3(blocks), dim3(kWave), 0, s, nodes, tris, o, d, skip, n, occ);
+  else hipLaunchKernelGGL(occluded_rays_kernel<64>, dim3(blocks), dim3(kWave), 0, s, nodes, tris, o, d, skip, n, occ);
+  return hipGetLastError();
+}
+
+}  // namespace rc

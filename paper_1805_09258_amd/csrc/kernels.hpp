@@ -1,0 +1,56 @@
+// kernels.hpp -- launch interface between the host API and the kernels.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include "../../include/rc.h"
+
+namespace rc {
+
+constexpr int kOrderBuckets = 256;
+
+struct RecordArgs {
+  const float4* nodes;
+  const float4* tris;
+  const float4* shade;     // per triangle: unit normal (xyz), albedo (w)
+  const float* emission;   // per triangle
+  float3 box_lo, box_hi;
+  int n_lights;
+  float4 lights[RC_MAX_LIGHTS];
+  float sigma_s, sigma_a;
+  const float* pos;
+  const int* n_theta;
+  const int* n_phi;
+  int P;
+  long long rec_base;
+  float ring_step;
+  int max_rings;
+  int max_n_phi;
+  int precision;
+  unsigned long long seed;
+  double* value;
+  double* grad;
+  double* hess;
+  const int* order;        // queue order or nullptr (identity)
+  unsigned int* queue;     // [0] next queue slot, [1] invalid records
+  unsigned long long* counters;
+};
+
+int stack_variant(int depth);
+size_t record_lds_bytes(int stack, int max_n_phi, int max_rings);
+int record_occupancy(int stack, bool count, bool f64, size_t lds);
+hipError_t prepare_record(int stack, bool count, bool f64, size_t lds);
+hipError_t launch_record(const RecordArgs& a, int stack, bool count, bool f64, int grid, size_t lds, hipStream_t s);
+hipError_t launch_reset(unsigned int* q, hipStream_t s);
+hipError_t launch_order(const int* nth, const int* nph, int P, unsigned int* hist, unsigned int* cursor, int* order,
+                        hipStream_t s);
+hipError_t launch_radius(const double* value, const double* hess, int P, float eps, float r_min, float r_max, float* R,
+                         float* axes, hipStream_t s);
+
+hipError_t launch_trace_rays(const float4* nodes, const float4* tris, int depth, const float* o, const float* d, int n,
+                             int* hit, float* t, int* front, float3 lo, float3 hi, hipStream_t s);
+hipError_t launch_occluded_rays(const float4* nodes, const float4* tris, int depth, const float* o, const float* d,
+                                const int* skip, int n, int* occ, hipStream_t s);
+
+}  // namespace rc

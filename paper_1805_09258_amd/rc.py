@@ -1,0 +1,298 @@
+"""Thin Python binding of librc (the C ABI declared in include/rc.h).
+
+Argument marshalling only: every step of the computation runs in librc's HIP
+kernels.  PyTorch supplies device memory and streams.  The functions keep the
+C names (rc_scene_create, rc_records, ...); `Scene` and `compute_records` are
+conveniences that allocate the outputs as torch tensors.
+
+Loading fails loudly if the library has not been built (run
+``python -c "import __graft_entry__ as g; g.build()"`` or
+``python paper_1805_09258_amd/build.py``); there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+from pathlib import Path
+
+import numpy as np
+
+_PKG = Path(__file__).resolve().parent
+LIB_PATH = _PKG / "librc.so"
+
+RC_OK, RC_EINVAL, RC_ENOMEM, RC_EDEVICE, RC_ENODEV = 0, -1, -2, -3, -4
+RC_MAX_LIGHTS, RC_MAX_RINGS, RC_MAX_NPHI = 16, 64, 256
+
+
+class RCError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"librc error {code}: {msg}")
+        self.code = code
+
+
+class rc_medium(C.Structure):
+    _fields_ = [("sigma_s", C.c_float), ("sigma_a", C.c_float)]
+
+
+class rc_point_light(C.Structure):
+    _fields_ = [("pos", C.c_float * 3), ("intensity", C.c_float)]
+
+
+class rc_params(C.Structure):
+    _fields_ = [("ring_step", C.c_float), ("max_rings", C.c_int32), ("max_n_phi", C.c_int32),
+                ("precision", C.c_int32), ("seed", C.c_uint64), ("rec_base", C.c_int64),
+                ("counters", C.c_void_p)]
+
+
+class rc_scene_stats(C.Structure):
+    _fields_ = [("n_tri", C.c_int64), ("n_nodes", C.c_int64), ("depth", C.c_int32), ("leaf_max", C.c_int32),
+                ("node_bytes", C.c_int64), ("tri_bytes", C.c_int64), ("pad", C.c_float)]
+
+
+EXPORTS = ["rc_scene_create", "rc_scene_destroy", "rc_scene_info", "rc_bvh_build_host", "rc_workspace_size",
+           "rc_workspace_errors", "rc_records", "rc_records_batched", "rc_autotune", "rc_radius",
+           "rc_trace_rays", "rc_occluded_rays", "rc_last_error", "rc_version"]
+
+_LIB = None
+
+
+def lib():
+    global _LIB
+    if _LIB is None:
+        if not LIB_PATH.exists():
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with paper_1805_09258_amd/build.py")
+        L = C.CDLL(str(LIB_PATH))
+        vp, i64, i32, f32, sz = C.c_void_p, C.c_int64, C.c_int, C.c_float, C.c_size_t
+        L.rc_scene_create.argtypes = [vp, vp, vp, i64, vp, vp, C.POINTER(vp)]
+        L.rc_scene_create.restype = i32
+        L.rc_scene_destroy.argtypes = [vp]
+        L.rc_scene_destroy.restype = i32
+        L.rc_scene_info.argtypes = [vp, C.POINTER(rc_scene_stats)]
+        L.rc_scene_info.restype = i32
+        L.rc_bvh_build_host.argtypes = [vp, i64, vp, vp, vp, i64, vp, C.POINTER(rc_scene_stats)]
+        L.rc_bvh_build_host.restype = i64
+        L.rc_workspace_size.argtypes = [i64]
+        L.rc_workspace_size.restype = sz
+        L.rc_workspace_errors.argtypes = [vp, vp]
+        L.rc_workspace_errors.restype = i64
+        rec = [vp, C.POINTER(rc_medium), C.POINTER(rc_point_light), i32, vp, vp, vp, i64, C.POINTER(rc_params)]
+        L.rc_records.argtypes = rec + [vp, vp, vp, vp, vp]
+        L.rc_records.restype = i32
+        L.rc_records_batched.argtypes = rec + [vp, i32, i32, vp, vp, vp, vp, vp]
+        L.rc_records_batched.restype = i32
+        L.rc_autotune.argtypes = rec + [vp, vp, vp, vp, C.c_char_p, C.POINTER(i32), vp, C.POINTER(i32), vp]
+        L.rc_autotune.restype = i32
+        L.rc_radius.argtypes = [vp, vp, i64, f32, f32, f32, vp, vp, vp]
+        L.rc_radius.restype = i32
+        L.rc_trace_rays.argtypes = [vp, vp, vp, i64, vp, vp, vp, vp]
+        L.rc_trace_rays.restype = i32
+        L.rc_occluded_rays.argtypes = [vp, vp, vp, vp, i64, vp, vp]
+        L.rc_occluded_rays.restype = i32
+        L.rc_last_error.restype = C.c_char_p
+        L.rc_version.restype = C.c_char_p
+        _LIB = L
+    return _LIB
+
+
+def _check(code):
+    if code < 0:
+        raise RCError(code, lib().rc_last_error().decode(errors="replace"))
+    return code
+
+
+def _ptr(t):
+    """Raw pointer of a torch tensor or numpy array (None -> NULL)."""
+    if t is None:
+        return None
+    if hasattr(t, "data_ptr"):
+        return C.c_void_p(t.data_ptr())
+    return t.ctypes.data_as(C.c_void_p)
+
+
+def _stream(stream):
+    if stream is None:
+        import torch
+        stream = torch.cuda.current_stream()
+    return C.c_void_p(stream.cuda_stream) if hasattr(stream, "cuda_stream") else C.c_void_p(stream)
+
+
+def _lights(lights):
+    li = np.ascontiguousarray(lights, np.float32).reshape(-1, 4)
+    arr = (rc_point_light * max(len(li), 1))()
+    for i, (x, y, z, I) in enumerate(li):
+        arr[i].pos[0], arr[i].pos[1], arr[i].pos[2], arr[i].intensity = x, y, z, I
+    return arr, len(li)
+
+
+# ---------------------------------------------------------------------------
+# C-named entry points
+# ---------------------------------------------------------------------------
+def rc_scene_create(tri, albedo, emission, box_lo, box_hi):
+    tri = np.ascontiguousarray(tri, np.float32).reshape(-1, 9)
+    alb = np.ascontiguousarray(albedo, np.float32)
+    em = None if emission is None else np.ascontiguousarray(emission, np.float32)
+    lo = np.ascontiguousarray(box_lo, np.float32)
+    hi = np.ascontiguousarray(box_hi, np.float32)
+    h = C.c_void_p()
+    _check(lib().rc_scene_create(_ptr(tri), _ptr(alb), _ptr(em), tri.shape[0], _ptr(lo), _ptr(hi), C.byref(h)))
+    return h
+
+
+def rc_scene_destroy(h):
+    return _check(lib().rc_scene_destroy(h))
+
+
+def rc_scene_info(h):
+    st = rc_scene_stats()
+    _check(lib().rc_scene_info(h, C.byref(st)))
+    return {k: getattr(st, k) for k, _ in rc_scene_stats._fields_}
+
+
+def rc_bvh_build_host(tri, box_lo, box_hi):
+    tri = np.ascontiguousarray(tri, np.float32).reshape(-1, 9)
+    lo = np.ascontiguousarray(box_lo, np.float32)
+    hi = np.ascontiguousarray(box_hi, np.float32)
+    st = rc_scene_stats()
+    n = _check(lib().rc_bvh_build_host(_ptr(tri), tri.shape[0], _ptr(lo), _ptr(hi), None, 0, None, C.byref(st)))
+    nodes = np.zeros((n, 16), np.float32)
+    tris = np.zeros((tri.shape[0], 12), np.float32)
+    _check(lib().rc_bvh_build_host(_ptr(tri), tri.shape[0], _ptr(lo), _ptr(hi), _ptr(nodes), n, _ptr(tris),
+                                   C.byref(st)))
+    return nodes, tris, {k: getattr(st, k) for k, _ in rc_scene_stats._fields_}
+
+
+def rc_workspace_size(P):
+    return int(lib().rc_workspace_size(int(P)))
+
+
+def rc_workspace_errors(ws, stream=None):
+    return _check(lib().rc_workspace_errors(_ptr(ws), _stream(stream)))
+
+
+def make_params(ring_step, max_rings, max_n_phi, seed, rec_base=0, precision=0, counters=None):
+    return rc_params(float(ring_step), int(max_rings), int(max_n_phi), int(precision), int(seed) & (2**64 - 1),
+                     int(rec_base), None if counters is None else counters.data_ptr())
+
+
+def rc_records(scene, sigma_s, sigma_a, lights, pos, n_theta, n_phi, params, value, grad, hess, workspace,
+               stream=None):
+    med = rc_medium(float(sigma_s), float(sigma_a))
+    arr, nl = _lights(lights)
+    P = int(pos.shape[0])
+    return _check(lib().rc_records(scene, C.byref(med), arr, nl, _ptr(pos), _ptr(n_theta), _ptr(n_phi), P,
+                                   C.byref(params), _ptr(value), _ptr(grad), _ptr(hess), _ptr(workspace),
+                                   _stream(stream)))
+
+
+def rc_records_batched(scene, sigma_s, sigma_a, lights, pos, n_theta, n_phi, params, order, use_graph, tile, value,
+                       grad, hess, workspace, stream=None):
+    med = rc_medium(float(sigma_s), float(sigma_a))
+    arr, nl = _lights(lights)
+    P = int(pos.shape[0])
+    return _check(lib().rc_records_batched(scene, C.byref(med), arr, nl, _ptr(pos), _ptr(n_theta), _ptr(n_phi), P,
+                                           C.byref(params), _ptr(order), int(use_graph), int(tile), _ptr(value),
+                                           _ptr(grad), _ptr(hess), _ptr(workspace), _stream(stream)))
+
+
+def rc_autotune(scene, sigma_s, sigma_a, lights, pos, n_theta, n_phi, params, value, grad, hess, workspace,
+                cache_path=None, measure=True, stream=None):
+    med = rc_medium(float(sigma_s), float(sigma_a))
+    arr, nl = _lights(lights)
+    P = int(pos.shape[0])
+    best = C.c_int(0)
+    nt = C.c_int(0)
+    ms = np.zeros(16, np.float32)
+    _check(lib().rc_autotune(scene, C.byref(med), arr, nl, _ptr(pos), _ptr(n_theta), _ptr(n_phi), P,
+                             C.byref(params), _ptr(value), _ptr(grad), _ptr(hess), _ptr(workspace),
+                             None if cache_path is None else str(cache_path).encode(), C.byref(best),
+                             _ptr(ms) if measure else None, C.byref(nt), _stream(stream)))
+    return best.value, (ms[:nt.value].tolist() if measure else None)
+
+
+def rc_radius(value, hess, eps, r_min, r_max, R, axes=None, stream=None):
+    P = int(value.shape[0])
+    return _check(lib().rc_radius(_ptr(value), _ptr(hess), P, float(eps), float(r_min), float(r_max), _ptr(R),
+                                  _ptr(axes), _stream(stream)))
+
+
+def rc_trace_rays(scene, orig, dirs, hit_id, t, front, stream=None):
+    return _check(lib().rc_trace_rays(scene, _ptr(orig), _ptr(dirs), int(orig.shape[0]), _ptr(hit_id), _ptr(t),
+                                      _ptr(front), _stream(stream)))
+
+
+def rc_occluded_rays(scene, orig, seg, skip, occ, stream=None):
+    return _check(lib().rc_occluded_rays(scene, _ptr(orig), _ptr(seg), _ptr(skip), int(orig.shape[0]), _ptr(occ),
+                                         _stream(stream)))
+
+
+def rc_version():
+    return lib().rc_version().decode()
+
+
+# ---------------------------------------------------------------------------
+# conveniences
+# ---------------------------------------------------------------------------
+class Scene:
+    """Device scene handle built from host arrays (owned; freed on close)."""
+
+    def __init__(self, tri, albedo, emission=None, box_lo=(0, 0, 0), box_hi=(1, 1, 1)):
+        self.box_lo = np.asarray(box_lo, np.float32)
+        self.box_hi = np.asarray(box_hi, np.float32)
+        self.handle = rc_scene_create(tri, albedo, emission, self.box_lo, self.box_hi)
+
+    @classmethod
+    def from_workload(cls, w):
+        return cls(w.tri, w.albedo, w.emission, w.box_lo, w.box_hi)
+
+    def info(self):
+        return rc_scene_info(self.handle)
+
+    def close(self):
+        if getattr(self, "handle", None) is not None and self.handle.value:
+            rc_scene_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class DeviceWorkload:
+    """Device copies (torch, cuda:0) of a workload's per-record inputs."""
+
+    def __init__(self, w, device="cuda"):
+        import torch
+        self.w = w
+        self.pos = torch.as_tensor(np.ascontiguousarray(w.pos, np.float32), device=device)
+        self.n_theta = torch.as_tensor(np.ascontiguousarray(w.n_theta, np.int32), device=device)
+        self.n_phi = torch.as_tensor(np.ascontiguousarray(w.n_phi, np.int32), device=device)
+        self.max_n_phi = int(np.max(w.n_phi)) if len(w.n_phi) else 5
+
+    def outputs(self):
+        import torch
+        P = self.pos.shape[0]
+        dev = self.pos.device
+        return (torch.empty((P, 2), dtype=torch.float64, device=dev),
+                torch.empty((P, 2, 3), dtype=torch.float64, device=dev),
+                torch.empty((P, 2, 6), dtype=torch.float64, device=dev))
+
+    def workspace(self):
+        import torch
+        return torch.zeros(rc_workspace_size(self.pos.shape[0]), dtype=torch.uint8, device=self.pos.device)
+
+
+def compute_records(scene: Scene, dw: DeviceWorkload, batched=False, use_graph=False, tile=-1, order=None,
+                    precision=0, counters=None, out=None, workspace=None, stream=None):
+    """Records for every point of a DeviceWorkload; returns (value, grad, hess, workspace)."""
+    w = dw.w
+    value, grad, hess = out if out is not None else dw.outputs()
+    ws = workspace if workspace is not None else dw.workspace()
+    prm = make_params(w.ring_step, w.max_rings, dw.max_n_phi, w.seed, 0, precision, counters)
+    if batched:
+        rc_records_batched(scene.handle, w.sigma_s, w.sigma_a, w.lights, dw.pos, dw.n_theta, dw.n_phi, prm, order,
+                           use_graph, tile, value, grad, hess, ws, stream)
+    else:
+        rc_records(scene.handle, w.sigma_s, w.sigma_a, w.lights, dw.pos, dw.n_theta, dw.n_phi, prm, value, grad,
+                   hess, ws, stream)
+    return value, grad, hess, ws
