@@ -83,9 +83,30 @@ struct Builder {
     return ~(int32_t)((first << 3) | (cnt - 1));
   }
 
+  // Large triangles (room walls, slab faces) whose boxes span most of the
+  // node would inflate every subtree they land in; they are split off into
+  // their own subtree first.  Returns mid or -1 if nothing to separate.
+  int64_t split_large(int64_t b, int64_t e) {
+    Box nb = bounds(b, e);
+    float ext = std::max({nb.hi[0] - nb.lo[0], nb.hi[1] - nb.lo[1], nb.hi[2] - nb.lo[2]});
+    auto big = [&](const Prim& p) {
+      float s = std::max({p.hi[0] - p.lo[0], p.hi[1] - p.lo[1], p.hi[2] - p.lo[2]});
+      return s > 0.5f * ext;
+    };
+    int64_t nbig = 0;
+    for (int64_t i = b; i < e; i++) nbig += big(prims[i]) ? 1 : 0;
+    if (nbig == 0 || nbig == e - b || nbig > (e - b) / 2) return -1;
+    auto it = std::stable_partition(prims.begin() + b, prims.begin() + e, big);
+    return it - prims.begin();
+  }
+
   // Split [b, e) -> mid; returns mid (b < mid < e)
   int64_t split(int64_t b, int64_t e, int depth) {
     int64_t n = e - b;
+    if (n > 2 * kLeafMax) {
+      int64_t m = split_large(b, e);
+      if (m > b && m < e) return m;
+    }
     Box cb;
     for (int64_t i = b; i < e; i++) cb.grow(prims[i].c, prims[i].c);
     int axis = 0;

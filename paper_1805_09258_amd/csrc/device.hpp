@@ -340,10 +340,18 @@ RC_DEV bool triangle_term(V3<R> q1, V3<R> q2, V3<R> q3, R t1, R t2, R t3, R detw
   // b = grad B, with grad l_k = -u_k
   V3<R> b = (-(l2 * l3 + d23)) * u1 + (-(l1 * l3 + d13)) * u2 + (-(l1 * l2 + d12)) * u3;
   b = b - l3 * (r1 + r2) - l1 * (r2 + r3) - l2 * (r1 + r3);
-  R D = absA * absA + B * B;
-  R iD = (R)1 / D;
+  // Work with a/sqrt(D) and b/sqrt(D), D = A^2 + B^2, so that every
+  // coefficient below ((A^2 - B^2)/D, |A| B / D, |A|/sqrt(D), B/sqrt(D)) is
+  // bounded by 1 and no intermediate overflows when two vertices are much
+  // closer to x than the third (B ~ l1 l2 l3 tiny).
+  R rho = absA > (B < 0 ? -B : B) ? absA : (B < 0 ? -B : B);
+  R an = absA / rho, bn = B / rho;
+  R sD = rho * r_sqrt(an * an + bn * bn);  // sqrt(D)
+  R isD = (R)1 / sD;
+  R cA = absA * isD, cB = B * isD;           // |A|/sqrt(D), B/sqrt(D)
+  V3<R> al = isD * a, be = isD * b;          // a/sqrt(D), b/sqrt(D)
   R F = r_atan2(absA, B) * inv2pi;  // Omega / (4 pi) with Omega = 2 atan2(|A|, B)
-  V3<R> gF = (inv2pi * iD * isc) * (B * a - absA * b);
+  V3<R> gF = (inv2pi * isc) * (cB * al - cA * be);
   // J(grad B), symmetric
   R JB[6] = {0, 0, 0, 0, 0, 0};
   R k1 = (l2 * l3 + d23) / l1, k2 = (l1 * l3 + d13) / l2, k3 = (l1 * l2 + d12) / l3;
@@ -360,15 +368,15 @@ RC_DEV bool triangle_term(V3<R> q1, V3<R> q2, V3<R> q3, R t1, R t2, R t3, R detw
   sym_add_outer2(JB, (R)1, u3, r1 + r2);
   sym_add_outer2(JB, (R)1, u1, r2 + r3);
   sym_add_outer2(JB, (R)1, u2, r1 + r3);
+  // HF = [ -|A| J(grad B)/D + ((A^2-B^2)/D)(al be^T + be al^T) - 2(|A| B/D)(al al^T - be be^T) ] / (2 pi)
   R HF[6];
-  R c0 = -absA * iD * inv2pi;
-  R iD2 = iD * iD * inv2pi;
+  R c0 = -cA * isD;
   for (int k = 0; k < 6; k++) HF[k] = c0 * JB[k];
-  sym_add_outer2(HF, (A * A - B * B) * iD2, a, b);
-  sym_add_outer(HF, (R)-2 * absA * B * iD2, a);
-  sym_add_outer(HF, (R)2 * absA * B * iD2, b);
-  const R isc2 = isc * isc;
-  for (int k = 0; k < 6; k++) HF[k] *= isc2;
+  sym_add_outer2(HF, (cA - cB) * (cA + cB), al, be);
+  sym_add_outer(HF, (R)-2 * cA * cB, al);
+  sym_add_outer(HF, (R)2 * cA * cB, be);
+  const R hs = inv2pi * isc * isc;
+  for (int k = 0; k < 6; k++) HF[k] *= hs;
   // transmittance to the far vertex (true distances), u = x - y_far = -r_far
   V3<R> rf = far == 0 ? r1 : (far == 1 ? r2 : r3);
   R lf = (far == 0 ? l1 : (far == 1 ? l2 : l3)) * sc;
