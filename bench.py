@@ -113,12 +113,15 @@ def main():
     eps, r_min, r_max = 1.5e-4, 1e-3, 0.25 * float(np.linalg.norm(w.box_hi - w.box_lo))
 
     # untimed: algorithmic work of one launch (rays, node and triangle fetches)
-    cnt = torch.zeros(4, dtype=torch.int64, device=dev)
+    cnt = torch.zeros(8, dtype=torch.int64, device=dev)
     with torch.cuda.stream(stream):
         rc.compute_records(scene, dw, batched=True, counters=cnt, out=(value, grad, hess), workspace=ws,
                            stream=stream)
     stream.synchronize()
-    rays, nodes, tris, terms = (int(x) for x in cnt.cpu().tolist())
+    rays, nodes, tris, terms, c0, c1, c2, c3 = (int(x) for x in cnt.cpu().tolist())
+    ctot = max(c0 + c1 + c2 + c3, 1)
+    phase_frac = {"primary_rays": c0 / ctot, "shadow_rays": c1 / ctot, "mc_value": c2 / ctot,
+                  "triangle_terms": c3 / ctot}
     alg_bytes = nodes * NODE_BYTES + tris * TRI_BYTES + w.n_rec * (12 + 8 + 16 + 48 + 96 + 4)
     log(f"per launch: {rays} rays, {nodes} node fetches, {tris} triangle tests, {terms} triangle terms")
 
@@ -175,7 +178,8 @@ def main():
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "kernel": "record_kernel", "kernel_ms": kern_ms,
                      "alg_bytes_per_launch": alg_bytes,
-                     "alg_bytes_per_ray": (nodes * NODE_BYTES + tris * TRI_BYTES) / max(rays, 1)},
+                     "alg_bytes_per_ray": (nodes * NODE_BYTES + tris * TRI_BYTES) / max(rays, 1),
+                     "phase_clock_fraction": phase_frac},
     }
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle) ...")

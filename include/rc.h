@@ -76,9 +76,12 @@ typedef struct {
  *   precision : 0 = FP32 terms, compensated FP32 sums, FP64 for
  *               near-degenerate triangle terms and the final reduction
  *               (default); 1 = every triangle term in FP64 (study mode).
- *   counters  : device uint64_t[4] or NULL.  If set, the launch also counts
+ *   counters  : device uint64_t[8] or NULL.  If set, the launch also counts
  *               (atomically added): rays traced, BVH nodes visited,
- *               ray/triangle tests, triangle terms evaluated. */
+ *               ray/triangle tests, triangle terms evaluated, and the shader
+ *               clocks each wavefront spent in primary rays, shadow rays, the
+ *               Monte Carlo value and the triangle terms (summed over
+ *               wavefronts). */
 typedef struct {
   float ring_step;
   int32_t max_rings;

@@ -113,7 +113,8 @@ int check_inputs(const rc_scene* s, const rc_medium* m, const rc_point_light* li
 rc::RecordArgs make_args(const rc_scene* s, const rc_medium* m, const rc_point_light* lights, int n_lights,
                          const float* pos, const int32_t* nth, const int32_t* nph, int64_t P, const rc_params* p,
                          double* value, double* grad, double* hess, void* ws, const int32_t* order) {
-  rc::RecordArgs a{};
+  rc::RecordArgs a;
+  std::memset(&a, 0, sizeof a);  // padding too: the graph cache compares whole structs
   a.nodes = s->nodes;
   a.tris = s->tris;
   a.shade = s->shade;
@@ -243,6 +244,7 @@ int rc_scene_create(const float* tri, const float* albedo, const float* emission
       return fail(RC_EDEVICE, "hipMemcpy");
     return RC_OK;
   };
+  bvh.tris.resize(bvh.tris.size() + 4, 0.f);  // one padding word after the last triangle
   int r = up((void**)&s->nodes, bvh.nodes.data(), bvh.nodes.size() * 4);
   if (!r) r = up((void**)&s->tris, bvh.tris.data(), bvh.tris.size() * 4);
   if (!r) r = up((void**)&s->shade, shade.data(), shade.size() * 4);

@@ -114,7 +114,8 @@ RC_DEV void ray_inv(float3 d, float3 o, float3& inv, float3& oi) {
   float dx = fabsf(d.x) > eps ? d.x : copysignf(eps, d.x);
   float dy = fabsf(d.y) > eps ? d.y : copysignf(eps, d.y);
   float dz = fabsf(d.z) > eps ? d.z : copysignf(eps, d.z);
-  inv = make_float3(1.0f / dx, 1.0f / dy, 1.0f / dz);
+  // hardware reciprocal (1 ulp): only the padded-box slab tests use it
+  inv = make_float3(__builtin_amdgcn_rcpf(dx), __builtin_amdgcn_rcpf(dy), __builtin_amdgcn_rcpf(dz));
   oi = make_float3(o.x * inv.x, o.y * inv.y, o.z * inv.z);
 }
 

@@ -5,7 +5,7 @@
 #include <string>
 #include <vector>
 
-#include "../../include/rc.h"
+#include "rc.h"
 
 namespace rc {
 

@@ -25,12 +25,19 @@ namespace rc {
 
 namespace {
 
+// One strata row in LDS, structure of arrays over the row's columns:
+// direction, hit distance, hit code ((triangle << 1) | front, or -1), rings
+// in front of the hit, surface radiance, surface light-visibility bits, and
+// ring radiance [ring][column] (holding light-visibility bits until shaded).
+constexpr int kRowFields = 8;
+// idle lanes that trigger a refill of the shadow-ray loop
+constexpr int kRefillMin = 16;
 struct Row {
   float *wx, *wy, *wz, *t, *Ls, *Lm;
-  int *code, *M;
+  int *code, *M, *visS;
 };
 
-RC_DEV Row row_view(float* base, int cap, int mr) {
+RC_DEV Row row_view(float* base, int cap) {
   Row r;
   r.wx = base;
   r.wy = base + cap;
@@ -39,8 +46,8 @@ RC_DEV Row row_view(float* base, int cap, int mr) {
   r.code = (int*)(base + 4 * cap);
   r.M = (int*)(base + 5 * cap);
   r.Ls = base + 6 * cap;
-  r.Lm = base + 7 * cap;  // [mr][cap]
-  (void)mr;
+  r.visS = (int*)(base + 7 * cap);
+  r.Lm = base + kRowFields * cap;  // [max_rings][cap]
   return r;
 }
 
@@ -80,7 +87,7 @@ __global__ __launch_bounds__(64) void record_kernel(RecordArgs g) {
   const int MR = g.max_rings;
   int* stk = reinterpret_cast<int*>(lds) + lane;
   float* rows = lds + STACK * kWave;
-  const int row_words = cap * (7 + MR);
+  const int row_words = cap * (kRowFields + MR);
   int* off = reinterpret_cast<int*>(rows + 2 * row_words);  // [2 * cap + 1]
   // per-record FP64 accumulators (lane 0 writes): 2 values + 2 x 9 derivatives
   double* racc = reinterpret_cast<double*>(off + ((2 * cap + 2) & ~1));
@@ -89,6 +96,8 @@ __global__ __launch_bounds__(64) void record_kernel(RecordArgs g) {
   const float ms_scale = g.sigma_s * (float)(1.0 / (4.0 * kPi));
   TraceCount tc;
   uint32_t n_rays = 0, n_terms = 0;
+  uint64_t cyc[4] = {0, 0, 0, 0};  // counting variant: shader clocks per phase
+  uint64_t t_mark = 0;
 
   while (true) {
     int q = 0;
@@ -123,11 +132,12 @@ __global__ __launch_bounds__(64) void record_kernel(RecordArgs g) {
     for (int a = -1; a <= nth; a++) {
       float* const baseR = rows + ((a + 1) & 1) * row_words;
       float* const baseP = rows + (a & 1) * row_words;
-      const Row R = row_view(baseR, cap, MR);
-      const Row P = row_view(baseP, cap, MR);
+      const Row R = row_view(baseR, cap);
+      const Row P = row_view(baseP, cap);
       const bool pole = (a < 0 || a == nth);
       const int n = pole ? 1 : nph;
       // ---- 1. primary rays ------------------------------------------------
+      if (COUNT) t_mark = clock64();
       for (int base = 0; base < n; base += kWave) {
         int j = base + lane;
         if (j < n) {
@@ -149,12 +159,19 @@ __global__ __launch_bounds__(64) void record_kernel(RecordArgs g) {
           R.code[j] = id >= 0 ? ((id << 1) | (fr ? 1 : 0)) : -1;
           R.M[j] = M;
           R.Ls[j] = id >= 0 ? g.emission[id] : 0.f;
-          for (int i = 0; i < M; i++) R.Lm[i * cap + j] = 0.f;
+          R.visS[j] = 0;
+          for (int i = 0; i < M; i++) reinterpret_cast<int*>(R.Lm)[i * cap + j] = 0;
           if (COUNT) n_rays++;
         }
       }
       __syncthreads();
-      // ---- 2. shadow rays: tasks (vertex, light), compacted ----------------
+      if (COUNT) { uint64_t t = clock64(); cyc[0] += t - t_mark; t_mark = t; }
+      // ---- 2. shadow rays ---------------------------------------------------
+      // One work list of (vertex, light) tasks for the row, light-major so
+      // neighbouring lanes trace coherent segments.  Each loop iteration
+      // advances every active lane by one traversal step (one node or one
+      // triangle); a lane whose segment is resolved takes the next task at
+      // once.  Unblocked segments set the light's bit on the vertex.
       if (g.n_lights > 0) {
         int carry = 0;
         for (int base = 0; base < n; base += kWave) {
@@ -164,44 +181,168 @@ __global__ __launch_bounds__(64) void record_kernel(RecordArgs g) {
           if (j < n) off[j] = carry + inc - c;
           carry += __shfl(inc, kWave - 1, kWave);
         }
-        const int total = carry;
+        const int nvert = carry;
+        const int total = nvert * g.n_lights;
         __syncthreads();
-        for (int l = 0; l < g.n_lights; l++) {
-          const float4 L = g.lights[l];
-          for (int base = 0; base < total; base += kWave) {
-            int task = base + lane;
+        int next = 0;          // next unassigned task (wave-uniform)
+        bool active = false;
+        int task = 0, node = 0, sp = 0, lf = 0, ln = 0, skip = -1, slot = 0;
+        float3 o = make_float3(0.f, 0.f, 0.f), d = o, inv = o, oi = o;
+        float dd = 0.f;
+        while (true) {
+          // refill idle lanes in lane order, once enough of them are idle
+          const uint64_t idle = __ballot(!active);
+          const bool refill = next < total && (__popcll(idle) >= kRefillMin || idle == ~0ull);
+          const bool need = refill && !active;
+          const uint64_t want = refill ? idle : 0ull;
+          if (need) {
+            int rank = __popcll(want & __lanemask_lt());
+            task = next + rank;
             if (task < total) {
-              int j = find_slot(off, n, task);
-              int v = task - off[j];
-              int code = R.code[j];
-              float3 w = make_float3(R.wx[j], R.wy[j], R.wz[j]);
-              if (code >= 0 && v == 0) {
-                // surface vertex: Lambertian, lit side facing x
-                int id = code >> 1;
-                float3 y = axpy3(R.t[j], w, x);
-                float3 seg = make_float3(L.x - y.x, L.y - y.y, L.z - y.z);
-                float4 sh = g.shade[id];
-                float nsign = (code & 1) ? 1.f : -1.f;
-                float dist = sqrtf(dot3(seg, seg));
-                float c = nsign * dot3(make_float3(sh.x, sh.y, sh.z), seg) / dist;
-                if (c > 0.f && !occluded<COUNT>(g.nodes, g.tris, y, seg, id, stk, tc))
-                  R.Ls[j] += sh.w * (float)(1.0 / kPi) * L.w * c * expf(-mu * dist) / (dist * dist);
+              active = true;
+              const int l = task / nvert, v = task - l * nvert;
+              const int j = find_slot(off, n, v);
+              const int k = v - off[j];
+              const int code = R.code[j];
+              const float4 L = g.lights[l];
+              const float3 w = make_float3(R.wx[j], R.wy[j], R.wz[j]);
+              if (code >= 0 && k == 0) {
+                skip = code >> 1;
+                o = axpy3(R.t[j], w, x);
+                slot = -1 - j;  // surface vertex of column j
+                d = make_float3(L.x - o.x, L.y - o.y, L.z - o.z);
+                const float4 sh = g.shade[skip];
+                const float nsign = (code & 1) ? 1.f : -1.f;
+                // light behind the lit side: nothing to trace
+                if (!(nsign * dot3(make_float3(sh.x, sh.y, sh.z), d) > 0.f)) active = false;
               } else {
-                int i = v - (code >= 0 ? 1 : 0);
-                float3 y = axpy3(ring_distance(i, xr, g.ring_step), w, x);
-                float3 seg = make_float3(L.x - y.x, L.y - y.y, L.z - y.z);
-                if (!occluded<COUNT>(g.nodes, g.tris, y, seg, -1, stk, tc)) {
-                  float dist2 = dot3(seg, seg);
-                  float dist = sqrtf(dist2);
-                  R.Lm[i * cap + j] += ms_scale * L.w * expf(-mu * dist) / dist2;
-                }
+                const int i = k - (code >= 0 ? 1 : 0);
+                skip = -1;
+                o = axpy3(ring_distance(i, xr, g.ring_step), w, x);
+                slot = i * cap + j;
+                d = make_float3(L.x - o.x, L.y - o.y, L.z - o.z);
               }
+              dd = dot3(d, d);
+              ray_inv(d, o, inv, oi);
+              node = 0;
+              sp = 0;
+              ln = 0;
               if (COUNT) n_rays++;
             }
           }
-          __syncthreads();
+          next += __popcll(want);
+          if (__ballot(active) == 0ull) {
+            if (next >= total) break;
+            continue;
+          }
+          if (active) {
+            bool done = false, blocked = false;
+            // one fetch per lane per iteration: the next triangle of the current
+            // leaf, or the current node (the triangle array carries one word of
+            // padding so the fourth load of the last triangle stays in bounds)
+            const float4* src = (ln > 0) ? (g.tris + 3 * lf) : (g.nodes + 4 * node);
+            const float4 q0 = src[0], q1 = src[1], q2 = src[2], q3 = src[3];
+            if (ln > 0) {
+              if (COUNT) tc.tris++;
+              float t;
+              bool fr;
+              if (__float_as_int(q0.w) != skip && hit_triangle(o, d, dd, q0, q1, q2, 1e-4f, 1.0f, t, fr)) {
+                done = true;
+                blocked = true;
+              } else {
+                lf++;
+                ln--;
+                if (ln == 0) {
+                  if (sp == 0) {
+                    done = true;
+                  } else {
+                    const int c = stk[--sp * kWave];
+                    if (c < 0) {  // a postponed leaf
+                      lf = leaf_first(c);
+                      ln = leaf_count(c);
+                    } else {
+                      node = c;
+                    }
+                  }
+                }
+              }
+            } else {
+              if (COUNT) tc.nodes++;
+              const float ta = slab(q0.x, q0.y, q0.z, q0.w, q2.x, q2.y, inv, oi, 0.0f, 1.0f);
+              const float tb = slab(q1.x, q1.y, q1.z, q1.w, q2.z, q2.w, inv, oi, 0.0f, 1.0f);
+              const int ca = __float_as_int(q3.x), cb = __float_as_int(q3.y);
+              const bool ha = ta <= 1.0f, hb = tb <= 1.0f;
+              int nx;
+              if (ha && hb) {
+                nx = ta <= tb ? ca : cb;
+                stk[sp++ * kWave] = ta <= tb ? cb : ca;
+              } else if (ha || hb) {
+                nx = ha ? ca : cb;
+              } else {
+                nx = sp == 0 ? 0x7fffffff : stk[--sp * kWave];
+              }
+              if (nx == 0x7fffffff) {
+                done = true;
+              } else if (nx < 0) {
+                lf = leaf_first(nx);
+                ln = leaf_count(nx);
+              } else {
+                node = nx;
+              }
+            }
+            if (done) {
+              active = false;
+              if (!blocked) {
+                const int bit = 1 << (task / nvert);
+                if (slot < 0) atomicOr(&R.visS[-1 - slot], bit);
+                else atomicOr(reinterpret_cast<int*>(R.Lm) + slot, bit);
+              }
+            }
+          }
         }
+        __syncthreads();
+        // radiance from the visibility bits, lights summed in order
+        for (int v = lane; v < nvert; v += kWave) {
+          const int j = find_slot(off, n, v);
+          const int k = v - off[j];
+          const int code = R.code[j];
+          const float3 w = make_float3(R.wx[j], R.wy[j], R.wz[j]);
+          if (code >= 0 && k == 0) {
+            const int bits = R.visS[j];
+            const int id = code >> 1;
+            const float3 y = axpy3(R.t[j], w, x);
+            const float4 sh = g.shade[id];
+            const float nsign = (code & 1) ? 1.f : -1.f;
+            float Lsum = R.Ls[j];
+            for (int l = 0; l < g.n_lights; l++) {
+              if (!((bits >> l) & 1)) continue;
+              const float4 L = g.lights[l];
+              const float3 seg = make_float3(L.x - y.x, L.y - y.y, L.z - y.z);
+              const float dist = sqrtf(dot3(seg, seg));
+              const float c = nsign * dot3(make_float3(sh.x, sh.y, sh.z), seg) / dist;
+              Lsum += sh.w * (float)(1.0 / kPi) * L.w * c * expf(-mu * dist) / (dist * dist);
+            }
+            R.Ls[j] = Lsum;
+          } else {
+            const int i = k - (code >= 0 ? 1 : 0);
+            const int bits = reinterpret_cast<int*>(R.Lm)[i * cap + j];
+            const float3 y = axpy3(ring_distance(i, xr, g.ring_step), w, x);
+            float Lsum = 0.f;
+            for (int l = 0; l < g.n_lights; l++) {
+              if (!((bits >> l) & 1)) continue;
+              const float4 L = g.lights[l];
+              const float3 seg = make_float3(L.x - y.x, L.y - y.y, L.z - y.z);
+              const float dist2 = dot3(seg, seg);
+              Lsum += ms_scale * L.w * expf(-mu * sqrtf(dist2)) / dist2;
+            }
+            R.Lm[i * cap + j] = Lsum;
+          }
+        }
+        __syncthreads();
+      } else {
+        // no lights: ring radiance is zero (slots were cleared as ints)
       }
+      if (COUNT) { uint64_t t = clock64(); cyc[1] += t - t_mark; t_mark = t; }
       // ---- 3. Monte Carlo value of the strata in this row -----------------
       if (!pole) {
         float vs = 0.f, vsc = 0.f, vm = 0.f, vmc = 0.f;
@@ -222,6 +363,7 @@ __global__ __launch_bounds__(64) void record_kernel(RecordArgs g) {
           racc[1] += s1;
         }
       }
+      if (COUNT) { uint64_t t = clock64(); cyc[2] += t - t_mark; t_mark = t; }
       // ---- 4. triangles between the previous row and this one -------------
       if (a >= 0) {
         // kind 0: north fan (P = pole, R = row 0); 1: band; 2: south fan
@@ -301,7 +443,7 @@ __global__ __launch_bounds__(64) void record_kernel(RecordArgs g) {
             } else {
               bool front = ring < reinterpret_cast<const int*>(b)[5 * cap + c];
               tau[k] = front ? rr : tk;
-              Lv[k] = front ? b[(7 + ring) * cap + c] : 0.f;
+              Lv[k] = front ? b[(kRowFields + ring) * cap + c] : 0.f;
             }
           }
           int far = 0;
@@ -367,6 +509,7 @@ __global__ __launch_bounds__(64) void record_kernel(RecordArgs g) {
         }
       }
       __syncthreads();
+      if (COUNT) { uint64_t t = clock64(); cyc[3] += t - t_mark; t_mark = t; }
     }
     // ---- store ------------------------------------------------------------
     if (lane < 2) g.value[2 * rec + lane] = racc[lane] / (double)N;
@@ -386,6 +529,7 @@ __global__ __launch_bounds__(64) void record_kernel(RecordArgs g) {
       atomicAdd(&g.counters[1], (unsigned long long)nd);
       atomicAdd(&g.counters[2], (unsigned long long)tr);
       atomicAdd(&g.counters[3], (unsigned long long)te);
+      for (int k = 0; k < 4; k++) atomicAdd(&g.counters[4 + k], (unsigned long long)cyc[k]);
     }
   }
 }
@@ -492,7 +636,7 @@ __global__ void radius_kernel(const double* __restrict__ value, const double* __
 // host launchers
 // ---------------------------------------------------------------------------
 size_t record_lds_bytes(int stack, int max_n_phi, int max_rings) {
-  size_t words = (size_t)stack * kWave + 2 * (size_t)max_n_phi * (7 + max_rings) + ((2 * (size_t)max_n_phi + 2) & ~size_t(1));
+  size_t words = (size_t)stack * kWave + 2 * (size_t)max_n_phi * (kRowFields + max_rings) + ((2 * (size_t)max_n_phi + 2) & ~size_t(1));
   return words * 4 + 20 * sizeof(double);
 }
 
@@ -501,20 +645,20 @@ static const void* kernel_ptr() {
   return reinterpret_cast<const void*>(&record_kernel<S, C, D>);
 }
 
-// kernel variants: stack depth {32, 48, 64} x counting x FP64 study mode
+// kernel variants: stack depth {16, 24, 32, 48, 64} x counting x FP64 study mode
+static int stack_index(int stack) {
+  return stack <= 16 ? 0 : (stack <= 24 ? 1 : (stack <= 32 ? 2 : (stack <= 48 ? 3 : 4)));
+}
+#define RC_KVARIANTS(S) \
+  {{kernel_ptr<S, false, false>(), kernel_ptr<S, false, true>()}, {kernel_ptr<S, true, false>(), kernel_ptr<S, true, true>()}}
 static const void* select_kernel(int stack, bool count, bool f64) {
-  const int s = stack <= 32 ? 0 : (stack <= 48 ? 1 : 2);
-  static const void* const table[3][2][2] = {
-      {{kernel_ptr<32, false, false>(), kernel_ptr<32, false, true>()},
-       {kernel_ptr<32, true, false>(), kernel_ptr<32, true, true>()}},
-      {{kernel_ptr<48, false, false>(), kernel_ptr<48, false, true>()},
-       {kernel_ptr<48, true, false>(), kernel_ptr<48, true, true>()}},
-      {{kernel_ptr<64, false, false>(), kernel_ptr<64, false, true>()},
-       {kernel_ptr<64, true, false>(), kernel_ptr<64, true, true>()}}};
-  return table[s][count ? 1 : 0][f64 ? 1 : 0];
+  static const void* const table[5][2][2] = {RC_KVARIANTS(16), RC_KVARIANTS(24), RC_KVARIANTS(32), RC_KVARIANTS(48),
+                                             RC_KVARIANTS(64)};
+  return table[stack_index(stack)][count ? 1 : 0][f64 ? 1 : 0];
 }
 
-int stack_variant(int depth) { return depth <= 32 ? 32 : (depth <= 48 ? 48 : 64); }
+// the stack holds at most (depth - 1) postponed children on one root-to-leaf path
+int stack_variant(int depth) { return depth <= 16 ? 16 : (depth <= 24 ? 24 : (depth <= 32 ? 32 : (depth <= 48 ? 48 : 64))); }
 
 int record_occupancy(int stack, bool count, bool f64, size_t lds) {
   int n = 0;
@@ -599,7 +743,8 @@ hipError_t launch_trace_rays(const float4* nodes, const float4* tris, int depth,
   int blocks = (n + kWave - 1) / kWave;
   if (blocks == 0) return hipSuccess;
   int st = stack_variant(depth);
-  if (st <= 32) hipLaunchKernelGGL(trace_rays_kernel<32>, dim3(blocks), dim3(kWave), 0, s, nodes, tris, o, d, n, hit, t, front, lo, hi);
+  if (st <= 16) hipLaunchKernelGGL(trace_rays_kernel<16>, dim3(blocks), dim3(kWave), 0, s, nodes, tris, o, d, n, hit, t, front, lo, hi);
+  else if (st <= 32) hipLaunchKernelGGL(trace_rays_kernel<32>, dim3(blocks), dim3(kWave), 0, s, nodes, tris, o, d, n, hit, t, front, lo, hi);
   else if (st <= 48) hipLaunchKernelGGL(trace_rays_kernel<48>, dim3(blocks), dim3(kWave), 0, s, nodes, tris, o, d, n, hit, t, front, lo, hi);
   else hipLaunchKernelGGL(trace_rays_kernel<64>, dim3(blocks), dim3(kWave), 0, s, nodes, tris, o, d, n, hit, t, front, lo, hi);
   return hipGetLastError();
@@ -610,7 +755,8 @@ hipError_t launch_occluded_rays(const float4* nodes, const float4* tris, int dep
   int blocks = (n + kWave - 1) / kWave;
   if (blocks == 0) return hipSuccess;
   int st = stack_variant(depth);
-  if (st <= 32) hipLaunchKernelGGL(occluded_rays_kernel<32>, dim3(blocks), dim3(kWave), 0, s, nodes, tris, o, d, skip, n, occ);
+  if (st <= 16) hipLaunchKernelGGL(occluded_rays_kernel<16>, dim3(blocks), dim3(kWave), 0, s, nodes, tris, o, d, skip, n, occ);
+  else if (st <= 32) hipLaunchKernelGGL(occluded_rays_kernel<32>, dim3(blocks), dim3(kWave), 0, s, nodes, tris, o, d, skip, n, occ);
   else if (st <= 48) hipLaunchKernelGGL(occluded_rays_kernel<48>, dim3(blocks), dim3(kWave), 0, s, nodes, tris, o, d, skip, n, occ);
   else hipLaunchKernelGGL(occluded_rays_kernel<64>, dim3(blocks), dim3(kWave), 0, s, nodes, tris, o, d, skip, n, occ);
   return hipGetLastError();

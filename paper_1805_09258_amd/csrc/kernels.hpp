@@ -4,7 +4,7 @@
 #include <stddef.h>
 #include <stdint.h>
 
-#include "../../include/rc.h"
+#include "rc.h"
 
 namespace rc {
 

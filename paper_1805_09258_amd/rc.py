@@ -12,12 +12,13 @@ Loading fails loudly if the library has not been built (run
 from __future__ import annotations
 
 import ctypes as C
+import os
 from pathlib import Path
 
 import numpy as np
 
 _PKG = Path(__file__).resolve().parent
-LIB_PATH = _PKG / "librc.so"
+LIB_PATH = Path(os.environ.get("RC_LIBRARY", str(_PKG / "librc.so")))
 
 RC_OK, RC_EINVAL, RC_ENOMEM, RC_EDEVICE, RC_ENODEV = 0, -1, -2, -3, -4
 RC_MAX_LIGHTS, RC_MAX_RINGS, RC_MAX_NPHI = 16, 64, 256
