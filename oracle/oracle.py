@@ -59,6 +59,8 @@ def lib():
         L.rco_splitmix64.argtypes = [u64]
         L.rco_splitmix64.restype = u64
         L.rco_nstat.restype = i32
+        L.rco_probe.argtypes = [vp, f32, f32, vp, i32, vp, i64, u64, vp, vp]
+        L.rco_probe.restype = i32
         _LIB = L
     return _LIB
 
@@ -156,6 +158,45 @@ def records_for(w, idx=None, xeval=None, nthreads=0, scene=None):
                    ring_step=w.ring_step, max_rings=w.max_rings, seed=w.seed, xeval=xeval, nthreads=nthreads)
 
 
+def probe(scene: Scene, sigma_s, sigma_a, lights, cand, seed, ids=None):
+    """32 probe features per candidate (FP64 values, FP32 decisions)."""
+    cand = _c(cand, np.float32).reshape(-1, 3)
+    n = cand.shape[0]
+    ids = _c(np.arange(n) if ids is None else ids, np.uint64)
+    li = _c(lights, np.float32).reshape(-1, 4)
+    feat = np.zeros((n, 32))
+    rc = lib().rco_probe(scene._h, float(sigma_s), float(sigma_a), _p(li), li.shape[0], _p(cand), n,
+                         int(seed) & (2**64 - 1), _p(ids), _p(feat))
+    if rc != 0:
+        raise ValueError(f"rco_probe failed ({rc})")
+    return feat
+
+
+def _within32(q, p, R):
+    """|q - p|^2 < R^2 taken in FP32 as ((dx*dx + dy*dy) + dz*dz) < R*R: the one
+    discrete decision of cover and interpolation, made in single precision so
+    that both implementations decide alike."""
+    d = np.asarray(q, np.float32) - np.asarray(p, np.float32)
+    d2 = (d[..., 0] * d[..., 0] + d[..., 1] * d[..., 1]) + d[..., 2] * d[..., 2]
+    R = np.asarray(R, np.float32)
+    return d2 < R * R
+
+
+def greedy_cover(cand, radius):
+    """Sequential greedy cover (Sec. 6 insertion rule applied to a candidate
+    list): visit the candidates in index order and accept one unless an already
+    accepted point p lies closer to it than p's radius.  Returns the accepted
+    indices in acceptance order."""
+    cand = np.asarray(cand, np.float32)
+    radius = np.asarray(radius, np.float32)
+    acc = []
+    for i in range(len(cand)):
+        if acc and np.any(_within32(cand[i], cand[acc], radius[acc])):
+            continue
+        acc.append(i)
+    return np.array(acc, np.int64)
+
+
 def formfactor(r1, r2, r3):
     """App. C: F, grad F, Hessian F for vertices r_i = y_i - x (FP64)."""
     a = [_c(r, np.float64) for r in (r1, r2, r3)]
@@ -241,18 +282,21 @@ def radius(value, hess6, eps, r_min, r_max, anisotropic=False):
 def interpolate(cache_pos, cache_val, cache_grad, cache_R, query):
     """L(x') = sum_k [L_k + grad L_k . (x' - x_k)] w_k / sum_k w_k over the
     cache points whose radius contains x', with w = 3d^2 - 2d^3,
-    d = 1 - |x' - x_k| / R_k.  Returns (L [Q], covered [Q])."""
+    d = 1 - |x' - x_k| / R_k.  Returns (L [Q], covered [Q]).
+    The membership test |x' - x_k| < R_k is taken in FP32 (see _within32);
+    everything else is FP64."""
     cp = np.asarray(cache_pos, np.float64)
     cv = np.asarray(cache_val, np.float64)
     cg = np.asarray(cache_grad, np.float64)
     cR = np.asarray(cache_R, np.float64)
     q = np.asarray(query, np.float64)
+    q32, cp32, cR32 = (np.asarray(a, np.float32) for a in (query, cache_pos, cache_R))
     out = np.zeros(len(q))
     cov = np.zeros(len(q), bool)
     for i, x in enumerate(q):
         dx = x[None, :] - cp
         dist = np.sqrt((dx * dx).sum(1))
-        m = dist < cR
+        m = _within32(q32[i][None, :], cp32, cR32)
         if not m.any():
             continue
         d = 1.0 - dist[m] / cR[m]

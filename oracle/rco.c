@@ -885,3 +885,115 @@ int rco_triangles(const float* dirs, int nth, int nph, int32_t* out) {
 /* uniform float of the counter-based generator (for tests of the generator) */
 float rco_unif(uint64_t seed, uint64_t rec, uint64_t idx, uint64_t dim) { return unif(rec_key(seed, rec), idx, dim); }
 uint64_t rco_splitmix64(uint64_t x) { return sm64(x); }
+
+/* ------------------------------------------------------------------ */
+/* Probe features for learned placement (project-defined, not in the   */
+/* paper).  A 4 x 16 jittered strata grid from the same sampler; per     */
+/* direction: distance to the first hit (or box exit), Lambertian        */
+/* radiance of the hit with shadow rays, attenuated to x; plus the        */
+/* visibility of lights 0..3 from x.  32 features, each defined below.    */
+/* ------------------------------------------------------------------ */
+int rco_probe(const rco_scene* s, float sigma_s, float sigma_a, const float* lights, int L, const float* cand,
+              int64_t C, uint64_t seed, const uint64_t* ids, double* feat) {
+  if (!s || C < 0 || (C > 0 && (!cand || !ids || !feat)) || L < 0 || (L > 0 && !lights)) return RCO_EINVAL;
+  rco_params p = {sigma_s, sigma_a, lights, L, 0.1f, 0, seed};
+  const double mu = (double)sigma_s + (double)sigma_a;
+#pragma omp parallel for schedule(dynamic, 16)
+  for (int64_t c = 0; c < C; c++) {
+    const float* xin = cand + 3 * c;
+    f3 x32 = {xin[0], xin[1], xin[2]};
+    double x64[3] = {xin[0], xin[1], xin[2]};
+    uint64_t key = rec_key(seed, ids[c]);
+    double dist[64], Lt[64], wv[64][3];
+    int hitk[64];
+    int64_t dummy = 0;
+    for (int k = 0; k < 64; k++) {
+      int a = k / 16, b = k % 16;
+      f3 w = stratum_dir(key, a, b, 4, 16);
+      double w64[3] = {w.x, w.y, w.z};
+      hit32 h = trace_closest(s, x32, w);
+      double t64;
+      float t32;
+      if (h.hit) {
+        const double* n = s->n64 + 3 * h.id;
+        const double* a0 = s->v064 + 3 * h.id;
+        double num = (a0[0] - x64[0]) * n[0] + (a0[1] - x64[1]) * n[1] + (a0[2] - x64[2]) * n[2];
+        t64 = num / d3_dot(w64, n);
+        t32 = h.t;
+      } else {
+        t32 = box_exit32(s, x32, w);
+        t64 = box_exit64(s, x64, w64);
+      }
+      double Ls = h.hit ? shade_surface(s, &p, x32, x64, w, t32, t64, h.id, h.front, &dummy) : 0.0;
+      double wn = sqrt(d3_dot(w64, w64));
+      double dd = t64 * wn;
+      if (dd < 1e-6) dd = 1e-6;
+      dist[k] = dd;
+      Lt[k] = exp(-mu * dd) * Ls;
+      hitk[k] = h.hit;
+      for (int q = 0; q < 3; q++) wv[k][q] = w64[q];
+    }
+    double* f = feat + 32 * c;
+    double mn = 1e300, mx = -1e300, sl = 0, sinv = 0, sL = 0, maxL = -1e300, esc = 0;
+    for (int k = 0; k < 64; k++) {
+      double ld = log(dist[k]);
+      mn = fmin(mn, ld);
+      mx = fmax(mx, ld);
+      sl += ld;
+      sinv += 1.0 / dist[k];
+      sL += Lt[k];
+      maxL = fmax(maxL, Lt[k]);
+      esc += hitk[k] ? 0.0 : 1.0;
+    }
+    double ml = sl / 64, mL = sL / 64, vl = 0, vL = 0;
+    for (int k = 0; k < 64; k++) {
+      vl += (log(dist[k]) - ml) * (log(dist[k]) - ml);
+      vL += (Lt[k] - mL) * (Lt[k] - mL);
+    }
+    f[0] = mn;                                   /* min log distance */
+    f[1] = ml;                                   /* mean log distance */
+    f[2] = sqrt(vl / 64);                        /* std of log distance */
+    f[3] = mx;                                   /* max log distance */
+    f[4] = esc / 64;                             /* escaped fraction */
+    f[5] = log(sinv / 64);                       /* log mean inverse distance */
+    f[6] = log(mL + 1e-6);                       /* log mean radiance */
+    f[7] = sqrt(vL / 64) / (mL + 1e-6);          /* coefficient of variation */
+    f[8] = log(maxL + 1e-6);                     /* log max radiance */
+    for (int l = 0; l < 4; l++) {                /* lights seen from x, unshadowed irradiance */
+      if (l < L) {
+        const float* lp = lights + 4 * l;
+        f3 seg = {lp[0] - x32.x, lp[1] - x32.y, lp[2] - x32.z};
+        f[9 + l] = occluded(s, x32, seg, -1) ? 0.0 : 1.0;
+        double d[3] = {(double)lp[0] - x64[0], (double)lp[1] - x64[1], (double)lp[2] - x64[2]};
+        double d2 = d3_dot(d, d);
+        f[13 + l] = log((double)lp[3] * exp(-mu * sqrt(d2)) / d2 + 1e-6);
+      } else {
+        f[9 + l] = 0.0;
+        f[13 + l] = 0.0;
+      }
+    }
+    double sLt = sL + 1e-12;
+    for (int q = 0; q < 3; q++) {
+      double aL = 0, aI = 0;
+      for (int k = 0; k < 64; k++) {
+        aL += Lt[k] * wv[k][q];
+        aI += wv[k][q] / dist[k];
+      }
+      f[17 + q] = aL / sLt;                      /* radiance-weighted mean direction */
+      f[20 + q] = aI / sinv;                     /* inverse-distance-weighted mean direction */
+    }
+    for (int r = 0; r < 4; r++) {                /* per strata row: mean log distance, mean log radiance */
+      double a1 = 0, a2 = 0;
+      for (int b = 0; b < 16; b++) {
+        a1 += log(dist[16 * r + b]);
+        a2 += log(Lt[16 * r + b] + 1e-6);
+      }
+      f[23 + r] = a1 / 16;
+      f[27 + r] = a2 / 16;
+    }
+    double con = 0;                              /* contrast with the next column of the same row */
+    for (int k = 0; k < 64; k++) con += fabs(Lt[k] - Lt[16 * (k / 16) + (k % 16 + 1) % 16]);
+    f[31] = con / sLt;
+  }
+  return RCO_OK;
+}
