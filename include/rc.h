@@ -73,6 +73,11 @@ typedef struct {
  *   rec_base  : record id of pos[0]; record i draws its random numbers with
  *               id rec_base + i (so a subset of a large batch can be
  *               recomputed exactly).
+ *   common_random : 0 (default) as above; 1 = every record of the call uses
+ *               id rec_base, i.e. the same directions and ring jitter at
+ *               every point (common random numbers: records then differ
+ *               only through the scene, which makes a cache's interpolation
+ *               error measurable apart from Monte Carlo noise).
  *   precision : 0 = FP32 terms, compensated FP32 sums, FP64 for
  *               near-degenerate triangle terms and the final reduction
  *               (default); 1 = every triangle term in FP64 (study mode).
@@ -87,6 +92,7 @@ typedef struct {
   int32_t max_rings;
   int32_t max_n_phi;
   int32_t precision;
+  int32_t common_random;
   uint64_t seed;
   int64_t rec_base;
   uint64_t* counters;
@@ -219,6 +225,115 @@ int rc_trace_rays(const rc_scene* scene, const float* orig, const float* dir, in
  * is hit with 1e-4 < t < 1.  skip device int32[n] or NULL (none). */
 int rc_occluded_rays(const rc_scene* scene, const float* orig, const float* seg, const int32_t* skip, int64_t n,
                      int32_t* occ, void* stream);
+
+/* ------------------------------------------------------------------ */
+/* Learned placement (project-defined; predicts the validity radius of  */
+/* Sec. 5, Eq. radiusAniso3D, from a cheap probe)                       */
+/* ------------------------------------------------------------------ */
+/* 64-ray probe of candidate points: a 4 x 16 jittered strata grid (same
+ * sampler as the records, record id = id_base + i, or id_base for every
+ * candidate if common_random = 1; `seed`), closest hits,
+ * Lambertian shading of the hits with shadow rays, attenuation to x, and the
+ * visibility of the first four lights from x; reduced to 32 features per
+ * candidate:
+ *   0-3  min, mean, std, max of log hit distance      4 escaped fraction
+ *   5    log mean inverse distance   6 log mean radiance   7 radiance CV
+ *   8    log max radiance            9-12 light visible from x (lights 0-3)
+ *   13-16 log unshadowed irradiance from lights 0-3
+ *   17-19 radiance-weighted mean direction  20-22 inverse-distance-weighted
+ *   23-26 mean log distance per strata row  27-30 mean log radiance per row
+ *   31   neighbour contrast of radiance along phi.
+ * cand device float[C][3]; feat32 device float[C][32] and/or feat_bf16 device
+ * bfloat16[C][32] (either may be NULL, not both). */
+int rc_probe(const rc_scene* scene, const rc_medium* medium, const rc_point_light* lights, int n_lights,
+             const float* cand, int64_t C, uint64_t seed, int64_t id_base, int common_random, float* feat32,
+             uint16_t* feat_bf16, void* stream);
+
+/* MLP 32 -> 128 -> 128 -> 1 with tanh-GELU, predicting log R.  Parameter
+ * block (device, rc_mlp_param_bytes() bytes): float shift[32], scale[32]
+ * (feature standardisation x' = (x - shift) * scale), b1[128], b2[128],
+ * w3[128], b3, padding to 464 floats; then bfloat16 W1[128][32],
+ * W2[128][128], W2^T[128][128].  Training state (device float,
+ * 3 * rc_mlp_n_params()): FP32 master parameters, Adam first and second
+ * moments, each laid out as W1[128][32], b1[128], W2[128][128], b2[128],
+ * w3[128], b3, loss slot. */
+size_t rc_mlp_param_bytes(void);
+int64_t rc_mlp_n_params(void);
+/* Glorot-uniform initialisation from the counter-based generator. */
+int rc_mlp_init(void* params, float* state, uint64_t seed, void* stream);
+/* Rebuild the parameter block's FP32/BF16 copies from master parameters. */
+int rc_mlp_load(void* params, const float* state, void* stream);
+/* Set the feature standardisation from n samples X (device float[n][32]);
+ * workspace device, >= 256 * 64 floats. */
+int rc_mlp_fit_features(void* params, const float* X, int64_t n, void* workspace, void* stream);
+/* out[i] = MLP(X[i]) (device float[n]); BF16 MFMA (16x16x32), FP32
+ * accumulation; layer-1 activations rounded to BF16, layer 2 output FP32. */
+int rc_mlp_forward(const void* params, const float* X, int64_t n, float* out, void* stream);
+/* Predicted validity radius: R[i] = clamp(safety * exp(MLP(X[i])), r_min,
+ * r_max) (device float[n]); safety > 0, 0 < r_min <= r_max. */
+int rc_mlp_radius(const void* params, const float* X, int64_t n, float safety, float r_min, float r_max, float* R,
+                  void* stream);
+/* One Adam step (lr, bias correction for `step` >= 1, betas 0.9/0.999,
+ * eps 1e-8) on the mean squared error over the n samples (X, target device
+ * float[n]).  workspace: rc_mlp_train_workspace_bytes(n) bytes.  loss (device
+ * float[1], sum of squared errors) and grad (device float[n_params], the
+ * gradient) are optional outputs. */
+size_t rc_mlp_train_workspace_bytes(int64_t n);
+int rc_mlp_train_step(void* params, float* state, const float* X, const float* target, int64_t n, float lr,
+                      int64_t step, void* workspace, float* loss, float* grad, void* stream);
+
+/* Greedy cover placement over candidates cand device float[C][3], exactly the
+ * sequential rule "visit the candidates in order and accept one unless an
+ * accepted point lies closer than that point's radius", run in rounds (Sec. 6
+ * inserts a cache point where no cached point is valid).  The distance test is
+ * ((dx*dx + dy*dy) + dz*dz) < R*R in FP32, dx = candidate - accepted point.
+ * order device int32[C] (a permutation: the visiting order) or NULL (index
+ * order).  state device int32[5] (zero to start): cursor, accepted count,
+ * first/count accepted in the last round, gathered batch size.  covered
+ * device uint8[C] (zero to start; 1 = decided or covered).
+ *   gather: the next `batch` (1..4096) undecided candidates after the cursor
+ *           in visiting order: indices batch_idx, positions batch_pos
+ *           (device float[batch][3]), and radii batch_R from `radius`
+ *           (device float[C]) if given; state[4] = how many were gathered;
+ *   accept: decide the gathered batch in order with radii batch_R (all
+ *           members become decided); append the accepted ones' indices and
+ *           radii to accepted / accepted_R (device, capacity >= C), their
+ *           positions to accepted_pos (device float[.][3]) if not NULL, and,
+ *           if batch_value/batch_grad (records of the batch slots, device
+ *           double [batch][2], [batch][2][3]) are given, copy those records
+ *           to cache_value / cache_grad at the appended positions;
+ *   cover : mark candidates within the radius of accepted[first ..
+ *           first+count) (or of the last round's points if first < 0) as
+ *           covered, testing every candidate;
+ *   cover_grid : the same for grid candidates, visiting only nearby cells.
+ *           Candidate (ix, iy, iz) (index (ix * dims[1] + iy) * dims[2] + iz)
+ *           must lie in cell lo + [i, i+1) * cell (host float[3] each) up to
+ *           rounding; dims host int32[3], product < 2^31; cand and covered
+ *           hold exactly dims[0] * dims[1] * dims[2] candidates.
+ * Errors: EINVAL for NULL pointers, sizes out of range, a bad batch size or a
+ * bad grid; the kernels themselves only read indices the state holds. */
+int rc_place_gather(const float* cand, const float* radius, const int32_t* order, int64_t C, const uint8_t* covered,
+                    int32_t* state, int32_t* batch_idx, float* batch_pos, float* batch_R, int batch, void* stream);
+int rc_place_accept(const float* cand, const int32_t* batch_idx, const float* batch_R, uint8_t* covered,
+                    int32_t* state, int32_t* accepted, float* accepted_R, float* accepted_pos,
+                    const double* batch_value, const double* batch_grad, double* cache_value, double* cache_grad,
+                    void* stream);
+int rc_place_cover(const float* cand, int64_t C, uint8_t* covered, const int32_t* state, const int32_t* accepted,
+                   const float* accepted_R, int64_t first, int64_t count, void* stream);
+int rc_place_cover_grid(const float* cand, const int32_t dims[3], const float lo[3], const float cell[3],
+                        uint8_t* covered, const int32_t* state, const int32_t* accepted, const float* accepted_R,
+                        int64_t first, int64_t count, void* stream);
+
+/* Radiance from a cache (Sec. 5, Eq. radianceTaylor): weighted first-order
+ * Taylor expansions of every cache point whose radius contains the query,
+ * cubic kernel w = 3d^2 - 2d^3, d = 1 - |x' - x_k|/R_k, FP64.  cache_value
+ * [K][2] and cache_grad [K][2][3] are records (channels summed).  out device
+ * double[Q] (0 where uncovered), hits device int32[Q] or NULL.  With
+ * ref_value (device double[Q][2]) each block of 256 queries writes the sums
+ * of (out - ref)^2 and ref^2 over its covered queries to err_partial[2b..]. */
+int rc_interp(const float* cache_pos, const double* cache_value, const double* cache_grad, const float* cache_R,
+              int64_t K, const float* query, int64_t Q, double* out, int32_t* hits, const double* ref_value,
+              double* err_partial, void* stream);
 
 /* ------------------------------------------------------------------ */
 /* Diagnostics                                                          */

@@ -15,6 +15,7 @@
 
 #include "internal.hpp"
 #include "kernels.hpp"
+#include "learned.hpp"
 
 namespace {
 
@@ -103,6 +104,7 @@ int check_inputs(const rc_scene* s, const rc_medium* m, const rc_point_light* li
   if (p->max_rings < 1 || p->max_rings > RC_MAX_RINGS) return fail(RC_EINVAL, "max_rings must be in [1, %d]", RC_MAX_RINGS);
   if (p->max_n_phi < 5 || p->max_n_phi > RC_MAX_NPHI) return fail(RC_EINVAL, "max_n_phi must be in [5, %d]", RC_MAX_NPHI);
   if (p->precision != 0 && p->precision != 1) return fail(RC_EINVAL, "precision must be 0 or 1");
+  if (p->common_random != 0 && p->common_random != 1) return fail(RC_EINVAL, "common_random must be 0 or 1");
   if (p->rec_base < 0) return fail(RC_EINVAL, "rec_base must be >= 0");
   if (P > 0 && (!pos || !nth || !nph || !value || !grad || !hess))
     return fail(RC_EINVAL, "NULL input or output pointer");
@@ -131,6 +133,7 @@ rc::RecordArgs make_args(const rc_scene* s, const rc_medium* m, const rc_point_l
   a.n_phi = nph;
   a.P = (int)P;
   a.rec_base = p->rec_base;
+  a.common_random = p->common_random;
   a.ring_step = p->ring_step;
   a.max_rings = p->max_rings;
   a.max_n_phi = p->max_n_phi;
@@ -477,6 +480,173 @@ int rc_occluded_rays(const rc_scene* s, const float* orig, const float* seg, con
   if (n > 0 && (!orig || !seg || !occ)) return fail(RC_EINVAL, "NULL pointer");
   RC_HIP(rc::launch_occluded_rays(s->nodes, s->tris, s->depth, orig, seg, skip, (int)n, occ,
                                   static_cast<hipStream_t>(stream)));
+  return RC_OK;
+}
+
+/* ------------------------------------------------------------------ */
+/* Learned placement                                                    */
+/* ------------------------------------------------------------------ */
+int rc_probe(const rc_scene* s, const rc_medium* m, const rc_point_light* lights, int n_lights, const float* cand,
+             int64_t C, uint64_t seed, int64_t id_base, int common_random, float* feat32, uint16_t* feat_bf16,
+             void* stream) {
+  if (!s) return fail(RC_EINVAL, "scene is NULL");
+  if (!m || !std::isfinite(m->sigma_s) || !std::isfinite(m->sigma_a) || m->sigma_s < 0 || m->sigma_a < 0)
+    return fail(RC_EINVAL, "medium coefficients must be finite and >= 0");
+  if (n_lights < 0 || n_lights > RC_MAX_LIGHTS || (n_lights > 0 && !lights)) return fail(RC_EINVAL, "bad lights");
+  if (C < 0 || C > 0x7fffffff || id_base < 0) return fail(RC_EINVAL, "C or id_base out of range");
+  if (common_random != 0 && common_random != 1) return fail(RC_EINVAL, "common_random must be 0 or 1");
+  if (C > 0 && (!cand || (!feat32 && !feat_bf16))) return fail(RC_EINVAL, "NULL candidate or feature pointer");
+  if (C == 0) return RC_OK;
+  rc::ProbeArgs a;
+  std::memset(&a, 0, sizeof a);
+  a.nodes = s->nodes;
+  a.tris = s->tris;
+  a.shade = s->shade;
+  a.emission = s->emission;
+  a.box_lo = make_float3(s->box_lo[0], s->box_lo[1], s->box_lo[2]);
+  a.box_hi = make_float3(s->box_hi[0], s->box_hi[1], s->box_hi[2]);
+  a.n_lights = n_lights;
+  for (int l = 0; l < n_lights; l++)
+    a.lights[l] = make_float4(lights[l].pos[0], lights[l].pos[1], lights[l].pos[2], lights[l].intensity);
+  a.sigma_s = m->sigma_s;
+  a.sigma_a = m->sigma_a;
+  a.cand = cand;
+  a.C = (int)C;
+  a.seed = seed;
+  a.id_base = id_base;
+  a.common_random = common_random;
+  a.feat32 = feat32;
+  a.feat16 = reinterpret_cast<__bf16*>(feat_bf16);
+  RC_HIP(rc::launch_probe(a, s->depth, static_cast<hipStream_t>(stream)));
+  return RC_OK;
+}
+
+size_t rc_mlp_param_bytes(void) { return rc::kMlpParamBytes; }
+int64_t rc_mlp_n_params(void) { return rc::kMlpGradFloats; }
+size_t rc_mlp_train_workspace_bytes(int64_t n) {
+  const int64_t tiles = (std::max<int64_t>(n, 1) + 63) / 64;
+  return (size_t)tiles * rc::kMlpGradFloats * sizeof(float);
+}
+
+int rc_mlp_init(void* params, float* state, uint64_t seed, void* stream) {
+  if (!params || !state) return fail(RC_EINVAL, "NULL pointer");
+  RC_HIP(rc::launch_mlp_init(params, state, seed, static_cast<hipStream_t>(stream)));
+  return RC_OK;
+}
+
+int rc_mlp_load(void* params, const float* state, void* stream) {
+  if (!params || !state) return fail(RC_EINVAL, "NULL pointer");
+  RC_HIP(rc::launch_mlp_sync(params, state, static_cast<hipStream_t>(stream)));
+  return RC_OK;
+}
+
+int rc_mlp_fit_features(void* params, const float* X, int64_t n, void* workspace, void* stream) {
+  if (!params || (n > 0 && (!X || !workspace))) return fail(RC_EINVAL, "NULL pointer");
+  if (n < 2 || n > 0x7fffffff) return fail(RC_EINVAL, "need 2 <= n < 2^31 samples");
+  RC_HIP(rc::launch_feature_stats(X, (int)n, static_cast<float*>(workspace), 256, params,
+                                  static_cast<hipStream_t>(stream)));
+  return RC_OK;
+}
+
+int rc_mlp_forward(const void* params, const float* X, int64_t n, float* out, void* stream) {
+  if (!params || n < 0 || n > 0x7fffffff || (n > 0 && (!X || !out))) return fail(RC_EINVAL, "invalid arguments");
+  RC_HIP(rc::launch_mlp_forward(params, X, (int)n, out, static_cast<hipStream_t>(stream)));
+  return RC_OK;
+}
+
+int rc_mlp_radius(const void* params, const float* X, int64_t n, float safety, float r_min, float r_max, float* R,
+                  void* stream) {
+  if (!params || n < 0 || n > 0x7fffffff || (n > 0 && (!X || !R))) return fail(RC_EINVAL, "invalid arguments");
+  if (!(safety > 0.f) || !std::isfinite(safety) || !(r_min > 0.f) || !(r_max >= r_min) || !std::isfinite(r_max))
+    return fail(RC_EINVAL, "need safety > 0 and 0 < r_min <= r_max finite");
+  RC_HIP(rc::launch_mlp_radius(params, X, (int)n, safety, r_min, r_max, R, static_cast<hipStream_t>(stream)));
+  return RC_OK;
+}
+
+int rc_mlp_train_step(void* params, float* state, const float* X, const float* target, int64_t n, float lr,
+                      int64_t step, void* workspace, float* loss, float* grad, void* stream) {
+  if (!params || !state || !X || !target || !workspace) return fail(RC_EINVAL, "NULL pointer");
+  if (n < 1 || n > 0x7fffffff || !(lr >= 0.f) || step < 1) return fail(RC_EINVAL, "need n >= 1, lr >= 0, step >= 1");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const int tiles = (int)((n + 63) / 64);
+  float* partial = static_cast<float*>(workspace);
+  RC_HIP(rc::launch_mlp_grad(params, X, target, (int)n, partial, st));
+  const float b1c = (float)(1.0 - std::pow(0.9, (double)step));
+  const float b2c = (float)(1.0 - std::pow(0.999, (double)step));
+  RC_HIP(rc::launch_mlp_adam(params, state, state + rc::kMlpGradFloats, state + 2 * rc::kMlpGradFloats, partial,
+                             tiles, lr, b1c, b2c, grad, loss, st));
+  return RC_OK;
+}
+
+int rc_place_gather(const float* cand, const float* radius, const int32_t* order, int64_t C, const uint8_t* covered,
+                    int32_t* state, int32_t* batch_idx, float* batch_pos, float* batch_R, int batch, void* stream) {
+  if (C < 0 || C > 0x7fffffff || batch < 1 || batch > rc::kPlaceMaxBatch)
+    return fail(RC_EINVAL, "C out of range or batch not in [1, %d]", rc::kPlaceMaxBatch);
+  if (!cand || !covered || !state || !batch_idx || !batch_pos || (radius && !batch_R))
+    return fail(RC_EINVAL, "NULL pointer");
+  RC_HIP(rc::launch_place_gather(cand, radius, order, (int)C, covered, state, batch_idx, batch_pos, batch_R, batch,
+                                 static_cast<hipStream_t>(stream)));
+  return RC_OK;
+}
+
+int rc_place_accept(const float* cand, const int32_t* batch_idx, const float* batch_R, uint8_t* covered,
+                    int32_t* state, int32_t* accepted, float* accepted_R, float* accepted_pos,
+                    const double* batch_value, const double* batch_grad, double* cache_value, double* cache_grad,
+                    void* stream) {
+  if (!cand || !batch_idx || !batch_R || !covered || !state || !accepted || !accepted_R)
+    return fail(RC_EINVAL, "NULL pointer");
+  const bool any = batch_value || batch_grad || cache_value || cache_grad;
+  const bool all = batch_value && batch_grad && cache_value && cache_grad;
+  if (any && !all) return fail(RC_EINVAL, "batch_value, batch_grad, cache_value, cache_grad: all or none");
+  RC_HIP(rc::launch_place_accept(cand, batch_idx, batch_R, covered, state, accepted, accepted_R, accepted_pos,
+                                 batch_value, batch_grad, cache_value, cache_grad, static_cast<hipStream_t>(stream)));
+  return RC_OK;
+}
+
+int rc_place_cover(const float* cand, int64_t C, uint8_t* covered, const int32_t* state, const int32_t* accepted,
+                   const float* accepted_R, int64_t first, int64_t count, void* stream) {
+  if (C < 0 || C > 0x7fffffff || !cand || !covered || !accepted || !accepted_R || (first < 0 && !state))
+    return fail(RC_EINVAL, "invalid arguments");
+  if (first > 0x7fffffff || count < 0 || count > 0x7fffffff) return fail(RC_EINVAL, "first/count out of range");
+  RC_HIP(rc::launch_place_cover(cand, (int)C, covered, state, accepted, accepted_R, (int)first, (int)count,
+                                static_cast<hipStream_t>(stream)));
+  return RC_OK;
+}
+
+int rc_place_cover_grid(const float* cand, const int32_t dims[3], const float lo[3], const float cell[3],
+                        uint8_t* covered, const int32_t* state, const int32_t* accepted, const float* accepted_R,
+                        int64_t first, int64_t count, void* stream) {
+  if (!cand || !dims || !lo || !cell || !covered || !accepted || !accepted_R || (first < 0 && !state))
+    return fail(RC_EINVAL, "NULL pointer");
+  if (first > 0x7fffffff || count < 0 || count > 0x7fffffff) return fail(RC_EINVAL, "first/count out of range");
+  int64_t cells = 1;
+  for (int d = 0; d < 3; d++) {
+    if (dims[d] < 1) return fail(RC_EINVAL, "grid dimensions must be >= 1");
+    if (!(cell[d] > 0.f) || !std::isfinite(cell[d]) || !std::isfinite(lo[d]))
+      return fail(RC_EINVAL, "grid origin and cell size must be finite, cell > 0");
+    cells *= dims[d];
+  }
+  if (cells > 0x7fffffff) return fail(RC_EINVAL, "grid has more than 2^31 - 1 cells");
+  rc::PlaceGrid g;
+  g.nx = dims[0];
+  g.ny = dims[1];
+  g.nz = dims[2];
+  g.lo = make_float3(lo[0], lo[1], lo[2]);
+  g.inv_h = make_float3(1.f / cell[0], 1.f / cell[1], 1.f / cell[2]);
+  RC_HIP(rc::launch_place_cover_grid(cand, g, covered, state, accepted, accepted_R, (int)first, (int)count,
+                                     rc::kPlaceMaxBatch, static_cast<hipStream_t>(stream)));
+  return RC_OK;
+}
+
+int rc_interp(const float* cache_pos, const double* cache_value, const double* cache_grad, const float* cache_R,
+              int64_t K, const float* query, int64_t Q, double* out, int32_t* hits, const double* ref_value,
+              double* err_partial, void* stream) {
+  if (K < 0 || K > 0x7fffffff || Q < 0 || Q > 0x7fffffff) return fail(RC_EINVAL, "K or Q out of range");
+  if ((K > 0 && (!cache_pos || !cache_value || !cache_grad || !cache_R)) || (Q > 0 && (!query || !out)) ||
+      (ref_value && !err_partial))
+    return fail(RC_EINVAL, "NULL pointer");
+  RC_HIP(rc::launch_interp(cache_pos, cache_value, cache_grad, cache_R, (int)K, query, (int)Q, out, hits, ref_value,
+                           err_partial, static_cast<hipStream_t>(stream)));
   return RC_OK;
 }
 

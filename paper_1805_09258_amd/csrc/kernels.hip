@@ -123,7 +123,7 @@ __global__ __launch_bounds__(64) void record_kernel(RecordArgs g) {
       continue;
     }
     const int N = nth * nph;
-    const uint64_t key = record_key(g.seed, (uint64_t)(g.rec_base + rec));
+    const uint64_t key = record_key(g.seed, (uint64_t)(g.rec_base + (g.common_random ? 0 : rec)));
     const float xr = uniform24(key, kRingIdx, 0);
 
     if (lane < 20) racc[lane] = 0.0;

@@ -24,6 +24,7 @@ struct RecordArgs {
   const int* n_phi;
   int P;
   long long rec_base;
+  int common_random;       // 1: every record draws with id rec_base
   float ring_step;
   int max_rings;
   int max_n_phi;

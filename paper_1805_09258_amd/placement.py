@@ -1,0 +1,319 @@
+"""Cache placement on the GPU: the plain pipeline and the learned one.
+
+Both build a radiance cache over a set of candidate points such that every
+candidate lies inside the validity radius (Sec. 5, Eq. radiusAniso3D) of some
+cached record, inserting records greedily in a fixed visiting order (the
+insertion rule of Sec. 6).
+
+* plain: rounds of "gather the next undecided candidates -> full records ->
+  radii -> accept in order -> cover".  Every gathered candidate costs a full
+  record, including those an earlier member of the same round turns out to
+  cover.
+* learned: the same rounds decided by a 64-ray probe and the MLP's predicted
+  radius (cheap), then full records at the accepted points in one launch.
+  The records are the judge: with their true radii the candidates are covered
+  again, and whatever is left uncovered goes through plain rounds (the
+  fallback), so the final cache meets the same validity rule as the plain
+  one.
+
+Every step runs in the library's kernels (rc.*); this module only sequences
+calls and holds device buffers.  All records of a placement use common random
+numbers (one record id), so a cache's interpolation error can be told apart
+from Monte Carlo noise.
+"""
+from __future__ import annotations
+
+import time
+from dataclasses import dataclass, field
+
+import numpy as np
+
+from . import rc
+from . import workloads as W
+
+
+@dataclass
+class CacheConfig:
+    eps: float = 1.5e-4          # error threshold of the validity radius
+    r_min: float = 1e-3
+    r_max: float = 0.25 * float(np.sqrt(3.0))
+    n_theta: int = 16            # record directions (16 x 64 = 1024)
+    n_phi: int = 64
+    rec_id: int = 7_000_003      # the one record id of the cache (common random numbers)
+    probe_id: int = 9_000_011    # the one probe id
+    batch: int = 4096            # candidates per round (plain and learned)
+
+
+class SceneContext:
+    """A device scene plus the medium, lights and ring settings of a workload."""
+
+    def __init__(self, w: W.Workload):
+        self.w = w
+        self.scene = rc.Scene.from_workload(w)
+
+    def close(self):
+        self.scene.close()
+
+    def params(self, cfg: CacheConfig):
+        w = self.w
+        return rc.make_params(w.ring_step, w.max_rings, max(cfg.n_phi, 5), w.seed, rec_base=cfg.rec_id,
+                              common_random=True)
+
+    def records(self, pos, value, grad, hess, ws, cfg: CacheConfig, nth, nph):
+        """Full records at pos (device float[P][3]) into value/grad/hess."""
+        w = self.w
+        P = pos.shape[0]
+        if P == 0:
+            return
+        rc.rc_records_batched(self.scene.handle, w.sigma_s, w.sigma_a, w.lights, pos, nth[:P], nph[:P],
+                              self.params(cfg), None, False, -1, value[:P], grad[:P], hess[:P], ws)
+
+    def probe(self, pos, feat, cfg: CacheConfig):
+        w = self.w
+        if pos.shape[0] == 0:
+            return
+        rc.rc_probe(self.scene.handle, w.sigma_s, w.sigma_a, w.lights, pos, w.seed, cfg.probe_id, feat32=feat,
+                    common_random=True)
+
+
+@dataclass
+class Mlp:
+    """Device parameter block and training state of the radius MLP."""
+    params: object
+    state: object
+
+    @classmethod
+    def new(cls, device, seed=1):
+        import torch
+        p = torch.zeros(rc.rc_mlp_param_bytes(), dtype=torch.uint8, device=device)
+        s = torch.zeros(3 * rc.rc_mlp_n_params(), dtype=torch.float32, device=device)
+        rc.rc_mlp_init(p, s, seed)
+        return cls(p, s)
+
+
+@dataclass
+class PlacementResult:
+    pos: object                  # device float[K][3]
+    value: object                # device double[K][2]
+    grad: object                 # device double[K][2][3]
+    R: object                    # device float[K] (true radii)
+    K: int
+    stats: dict = field(default_factory=dict)
+
+
+class Placer:
+    """Device buffers for placing caches over one candidate set."""
+
+    def __init__(self, ctx: SceneContext, cands: W.GridCandidates, cfg: CacheConfig, device):
+        import torch
+        self.ctx, self.cands, self.cfg, self.dev = ctx, cands, cfg, device
+        C, B = cands.n, cfg.batch
+        t = lambda a: torch.as_tensor(a, device=device)  # noqa: E731
+        self.cand = t(cands.pos)
+        self.order = t(cands.order)
+        self.covered = torch.zeros(C, dtype=torch.uint8, device=device)
+        self.state = torch.zeros(5, dtype=torch.int32, device=device)
+        self.bidx = torch.zeros(B, dtype=torch.int32, device=device)
+        self.bpos = torch.zeros((B, 3), dtype=torch.float32, device=device)
+        self.bR = torch.zeros(B, dtype=torch.float32, device=device)
+        self.feat = torch.zeros((B, 32), dtype=torch.float32, device=device)
+        self.bval = torch.zeros((B, 2), dtype=torch.float64, device=device)
+        self.bgrad = torch.zeros((B, 2, 3), dtype=torch.float64, device=device)
+        self.bhess = torch.zeros((B, 2, 6), dtype=torch.float64, device=device)
+        self.bws = torch.zeros(rc.rc_workspace_size(B), dtype=torch.uint8, device=device)
+        self.acc = torch.zeros(C, dtype=torch.int32, device=device)
+        self.accR = torch.zeros(C, dtype=torch.float32, device=device)
+        self.accpos = torch.zeros((C, 3), dtype=torch.float32, device=device)
+        self.cval = torch.zeros((C, 2), dtype=torch.float64, device=device)
+        self.cgrad = torch.zeros((C, 2, 3), dtype=torch.float64, device=device)
+        n = max(B, 1)
+        self.nth = torch.full((n,), cfg.n_theta, dtype=torch.int32, device=device)
+        self.nph = torch.full((n,), cfg.n_phi, dtype=torch.int32, device=device)
+        self._big = None  # records of the learned points (allocated on first use)
+
+    # -- pieces ---------------------------------------------------------------
+    def _reset(self):
+        self.covered.zero_()
+        self.state.zero_()
+
+    def _gather(self):
+        rc.rc_place_gather(self.cand, None, self.covered, self.state, self.bidx, self.bpos, self.bR, self.cfg.batch,
+                           order=self.order)
+        return int(self.state[4].item())
+
+    def _cover_last_round(self):
+        c = self.cands
+        rc.rc_place_cover_grid(self.cand, c.dims, c.lo, c.cell, self.covered, self.state, self.acc, self.accR)
+
+    def _plain_rounds(self):
+        """Rounds with full records until every candidate is decided."""
+        cfg = self.cfg
+        rounds = records = 0
+        while True:
+            m = self._gather()
+            if m == 0:
+                break
+            self.ctx.records(self.bpos[:m], self.bval, self.bgrad, self.bhess, self.bws, cfg, self.nth, self.nph)
+            rc.rc_radius(self.bval[:m], self.bhess[:m], cfg.eps, cfg.r_min, cfg.r_max, self.bR[:m])
+            rc.rc_place_accept(self.cand, self.bidx, self.bR, self.covered, self.state, self.acc, self.accR,
+                               self.accpos, self.bval, self.bgrad, self.cval, self.cgrad)
+            self._cover_last_round()
+            rounds += 1
+            records += m
+        return rounds, records
+
+    def _result(self, stats):
+        K = int(self.state[1].item())
+        return PlacementResult(self.accpos[:K], self.cval[:K], self.cgrad[:K], self.accR[:K], K, stats)
+
+    # -- pipelines ------------------------------------------------------------
+    def plain(self):
+        import torch
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        self._reset()
+        rounds, records = self._plain_rounds()
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        res = self._result({"seconds": dt, "rounds": rounds, "records": records})
+        res.stats["accepted"] = res.K
+        return res
+
+    def learned(self, mlp: Mlp, safety: float):
+        import torch
+        cfg, c = self.cfg, self.cands
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        self._reset()
+        rounds = probes = 0
+        while True:
+            m = self._gather()
+            if m == 0:
+                break
+            self.ctx.probe(self.bpos[:m], self.feat[:m], cfg)
+            rc.rc_mlp_radius(mlp.params, self.feat[:m], safety, cfg.r_min, cfg.r_max, self.bR[:m])
+            rc.rc_place_accept(self.cand, self.bidx, self.bR, self.covered, self.state, self.acc, self.accR,
+                               self.accpos)
+            self._cover_last_round()
+            rounds += 1
+            probes += m
+        K1 = int(self.state[1].item())
+        t1 = time.perf_counter()
+        # full records at the predicted placement, in one launch
+        if self._big is None or self._big[0].shape[0] < K1:
+            n = max(K1, 1)
+            self._big = (torch.zeros((n, 2, 6), dtype=torch.float64, device=self.dev),
+                         torch.zeros(rc.rc_workspace_size(n), dtype=torch.uint8, device=self.dev),
+                         torch.full((n,), cfg.n_theta, dtype=torch.int32, device=self.dev),
+                         torch.full((n,), cfg.n_phi, dtype=torch.int32, device=self.dev))
+        hess, ws, nth, nph = self._big
+        self.ctx.records(self.accpos[:K1], self.cval, self.cgrad, hess, ws, cfg, nth, nph)
+        # the judge: true radii replace the predicted ones, the candidates are covered again
+        rc.rc_radius(self.cval[:K1], hess[:K1], cfg.eps, cfg.r_min, cfg.r_max, self.accR[:K1])
+        self.covered.zero_()
+        rc.rc_place_cover_grid(self.cand, c.dims, c.lo, c.cell, self.covered, None, self.acc, self.accR, 0, K1)
+        self.state[0] = 0
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        uncovered = int((self.covered == 0).sum().item())
+        # fallback: plain rounds over whatever the true radii leave uncovered
+        f_rounds, f_records = self._plain_rounds()
+        torch.cuda.synchronize()
+        t3 = time.perf_counter()
+        res = self._result({"seconds": t3 - t0, "seconds_rounds": t1 - t0, "seconds_records_judge": t2 - t1,
+                            "seconds_fallback": t3 - t2, "rounds": rounds, "probes": probes,
+                            "records_learned": K1, "uncovered_after_judge": uncovered,
+                            "fallback_rounds": f_rounds, "fallback_records": f_records})
+        res.stats["records"] = K1 + f_records
+        res.stats["accepted"] = res.K
+        return res
+
+
+def direct_records(ctx: SceneContext, pts, cfg: CacheConfig, device, chunk=65536):
+    """Records at arbitrary points with the cache's directions: the reference a
+    cache is compared against.  Returns device (value [Q][2], hess [Q][2][6])."""
+    import torch
+    Q = pts.shape[0]
+    value = torch.zeros((Q, 2), dtype=torch.float64, device=device)
+    grad = torch.zeros((Q, 2, 3), dtype=torch.float64, device=device)
+    hess = torch.zeros((Q, 2, 6), dtype=torch.float64, device=device)
+    n = min(Q, chunk)
+    ws = torch.zeros(rc.rc_workspace_size(max(n, 1)), dtype=torch.uint8, device=device)
+    nth = torch.full((max(n, 1),), cfg.n_theta, dtype=torch.int32, device=device)
+    nph = torch.full((max(n, 1),), cfg.n_phi, dtype=torch.int32, device=device)
+    for s in range(0, Q, chunk):
+        e = min(Q, s + chunk)
+        ctx.records(pts[s:e], value[s:e], grad[s:e], hess[s:e], ws, cfg, nth, nph)
+    return value, grad, hess
+
+
+def cache_error(res: PlacementResult, query, ref_value, device):
+    """Relative L2 error of the cache's interpolation (Eq. radianceTaylor) at
+    the query points against reference values, over the covered queries."""
+    import torch
+    Q = query.shape[0]
+    out = torch.zeros(Q, dtype=torch.float64, device=device)
+    hits = torch.zeros(Q, dtype=torch.int32, device=device)
+    nb = (Q + 255) // 256
+    err = torch.zeros(2 * max(nb, 1), dtype=torch.float64, device=device)
+    rc.rc_interp(res.pos, res.value, res.grad, res.R, query, out, hits, ref_value, err)
+    e = err.view(-1, 2).sum(0).cpu().numpy()
+    covered = float((hits > 0).double().mean().item()) if Q else 0.0
+    return {"rel_l2": float(np.sqrt(e[0] / e[1])) if e[1] > 0 else float("nan"), "covered": covered,
+            "mean_hits": float(hits.double().mean().item()) if Q else 0.0}
+
+
+# ---------------------------------------------------------------------------
+# training data and training
+# ---------------------------------------------------------------------------
+def labels_and_features(ctx: SceneContext, pts, cfg: CacheConfig, device):
+    """(features [P][32], log R [P]) at points of a scene: probe features and
+    the log of the true validity radius from full records."""
+    import torch
+    value, grad, hess = direct_records(ctx, pts, cfg, device)
+    P = pts.shape[0]
+    R = torch.zeros(P, dtype=torch.float32, device=device)
+    rc.rc_radius(value, hess, cfg.eps, cfg.r_min, cfg.r_max, R)
+    feat = torch.zeros((P, 32), dtype=torch.float32, device=device)
+    for s in range(0, P, 65536):
+        e = min(P, s + 65536)
+        ctx.probe(pts[s:e], feat[s:e], cfg)
+    return feat, torch.log(R)
+
+
+def train(mlp: Mlp, X, y, epochs=30, batch=1024, lr=2e-3, seed=0, log=None):
+    """Adam on the mean squared error of log R; the learning rate decays
+    linearly to 10 % over the run.  Returns the per-epoch mean loss."""
+    import torch
+    n = X.shape[0]
+    ws = torch.zeros(rc.rc_mlp_train_workspace_bytes(batch), dtype=torch.uint8, device=X.device)
+    rc.rc_mlp_fit_features(mlp.params, X, ws)
+    loss = torch.zeros(1, dtype=torch.float32, device=X.device)
+    g = torch.Generator(device=X.device)
+    g.manual_seed(seed)
+    steps_per_epoch = n // batch
+    total = epochs * steps_per_epoch
+    step = 0
+    hist = []
+    for ep in range(epochs):
+        perm = torch.randperm(n, device=X.device, generator=g)
+        acc = torch.zeros(1, dtype=torch.float64, device=X.device)
+        for b in range(steps_per_epoch):
+            idx = perm[b * batch:(b + 1) * batch]
+            Xb = X.index_select(0, idx).contiguous()
+            yb = y.index_select(0, idx).contiguous()
+            step += 1
+            lr_t = lr * (1.0 - 0.9 * (step - 1) / max(total - 1, 1))
+            rc.rc_mlp_train_step(mlp.params, mlp.state, Xb, yb, lr_t, step, ws, loss)
+            acc += loss
+        hist.append(float(acc.item()) / (steps_per_epoch * batch))
+        if log:
+            log(f"epoch {ep + 1}/{epochs}: mse {hist[-1]:.4f}")
+    return hist
+
+
+def predict_log_radius(mlp: Mlp, X):
+    import torch
+    out = torch.zeros(X.shape[0], dtype=torch.float32, device=X.device)
+    rc.rc_mlp_forward(mlp.params, X, out)
+    return out

@@ -40,7 +40,8 @@ class rc_point_light(C.Structure):
 
 class rc_params(C.Structure):
     _fields_ = [("ring_step", C.c_float), ("max_rings", C.c_int32), ("max_n_phi", C.c_int32),
-                ("precision", C.c_int32), ("seed", C.c_uint64), ("rec_base", C.c_int64),
+                ("precision", C.c_int32), ("common_random", C.c_int32), ("seed", C.c_uint64),
+                ("rec_base", C.c_int64),
                 ("counters", C.c_void_p)]
 
 
@@ -51,7 +52,11 @@ class rc_scene_stats(C.Structure):
 
 EXPORTS = ["rc_scene_create", "rc_scene_destroy", "rc_scene_info", "rc_bvh_build_host", "rc_workspace_size",
            "rc_workspace_errors", "rc_records", "rc_records_batched", "rc_autotune", "rc_radius",
-           "rc_trace_rays", "rc_occluded_rays", "rc_last_error", "rc_version"]
+           "rc_trace_rays", "rc_occluded_rays", "rc_probe", "rc_mlp_param_bytes", "rc_mlp_n_params", "rc_mlp_init",
+           "rc_mlp_load", "rc_mlp_fit_features", "rc_mlp_forward", "rc_mlp_radius", "rc_mlp_train_workspace_bytes",
+           "rc_mlp_train_step", "rc_place_gather", "rc_place_accept", "rc_place_cover", "rc_place_cover_grid",
+           "rc_interp",
+           "rc_last_error", "rc_version"]
 
 _LIB = None
 
@@ -88,6 +93,36 @@ def lib():
         L.rc_trace_rays.restype = i32
         L.rc_occluded_rays.argtypes = [vp, vp, vp, vp, i64, vp, vp]
         L.rc_occluded_rays.restype = i32
+        u64 = C.c_uint64
+        L.rc_probe.argtypes = [vp, C.POINTER(rc_medium), C.POINTER(rc_point_light), i32, vp, i64, u64, i64, i32, vp,
+                               vp, vp]
+        L.rc_probe.restype = i32
+        L.rc_mlp_param_bytes.restype = sz
+        L.rc_mlp_n_params.restype = i64
+        L.rc_mlp_init.argtypes = [vp, vp, u64, vp]
+        L.rc_mlp_init.restype = i32
+        L.rc_mlp_load.argtypes = [vp, vp, vp]
+        L.rc_mlp_load.restype = i32
+        L.rc_mlp_fit_features.argtypes = [vp, vp, i64, vp, vp]
+        L.rc_mlp_fit_features.restype = i32
+        L.rc_mlp_forward.argtypes = [vp, vp, i64, vp, vp]
+        L.rc_mlp_forward.restype = i32
+        L.rc_mlp_radius.argtypes = [vp, vp, i64, f32, f32, f32, vp, vp]
+        L.rc_mlp_radius.restype = i32
+        L.rc_mlp_train_workspace_bytes.argtypes = [i64]
+        L.rc_mlp_train_workspace_bytes.restype = sz
+        L.rc_mlp_train_step.argtypes = [vp, vp, vp, vp, i64, f32, i64, vp, vp, vp, vp]
+        L.rc_mlp_train_step.restype = i32
+        L.rc_place_gather.argtypes = [vp, vp, vp, i64, vp, vp, vp, vp, vp, i32, vp]
+        L.rc_place_gather.restype = i32
+        L.rc_place_accept.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp]
+        L.rc_place_accept.restype = i32
+        L.rc_place_cover.argtypes = [vp, i64, vp, vp, vp, vp, i64, i64, vp]
+        L.rc_place_cover.restype = i32
+        L.rc_place_cover_grid.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, i64, i64, vp]
+        L.rc_place_cover_grid.restype = i32
+        L.rc_interp.argtypes = [vp, vp, vp, vp, i64, vp, i64, vp, vp, vp, vp, vp]
+        L.rc_interp.restype = i32
         L.rc_last_error.restype = C.c_char_p
         L.rc_version.restype = C.c_char_p
         _LIB = L
@@ -169,9 +204,9 @@ def rc_workspace_errors(ws, stream=None):
     return _check(lib().rc_workspace_errors(_ptr(ws), _stream(stream)))
 
 
-def make_params(ring_step, max_rings, max_n_phi, seed, rec_base=0, precision=0, counters=None):
-    return rc_params(float(ring_step), int(max_rings), int(max_n_phi), int(precision), int(seed) & (2**64 - 1),
-                     int(rec_base), None if counters is None else counters.data_ptr())
+def make_params(ring_step, max_rings, max_n_phi, seed, rec_base=0, precision=0, counters=None, common_random=False):
+    return rc_params(float(ring_step), int(max_rings), int(max_n_phi), int(precision), int(bool(common_random)),
+                     int(seed) & (2**64 - 1), int(rec_base), None if counters is None else counters.data_ptr())
 
 
 def rc_records(scene, sigma_s, sigma_a, lights, pos, n_theta, n_phi, params, value, grad, hess, workspace,
@@ -223,6 +258,88 @@ def rc_trace_rays(scene, orig, dirs, hit_id, t, front, stream=None):
 def rc_occluded_rays(scene, orig, seg, skip, occ, stream=None):
     return _check(lib().rc_occluded_rays(scene, _ptr(orig), _ptr(seg), _ptr(skip), int(orig.shape[0]), _ptr(occ),
                                          _stream(stream)))
+
+
+def rc_probe(scene, sigma_s, sigma_a, lights, cand, seed, id_base, feat32=None, feat_bf16=None, stream=None,
+             common_random=False):
+    med = rc_medium(float(sigma_s), float(sigma_a))
+    arr, nl = _lights(lights)
+    return _check(lib().rc_probe(scene, C.byref(med), arr, nl, _ptr(cand), int(cand.shape[0]), int(seed) & (2**64 - 1),
+                                 int(id_base), int(bool(common_random)), _ptr(feat32), _ptr(feat_bf16),
+                                 _stream(stream)))
+
+
+def rc_mlp_param_bytes():
+    return int(lib().rc_mlp_param_bytes())
+
+
+def rc_mlp_n_params():
+    return int(lib().rc_mlp_n_params())
+
+
+def rc_mlp_init(params, state, seed, stream=None):
+    return _check(lib().rc_mlp_init(_ptr(params), _ptr(state), int(seed), _stream(stream)))
+
+
+def rc_mlp_load(params, state, stream=None):
+    return _check(lib().rc_mlp_load(_ptr(params), _ptr(state), _stream(stream)))
+
+
+def rc_mlp_fit_features(params, X, workspace, stream=None):
+    return _check(lib().rc_mlp_fit_features(_ptr(params), _ptr(X), int(X.shape[0]), _ptr(workspace), _stream(stream)))
+
+
+def rc_mlp_forward(params, X, out, stream=None):
+    return _check(lib().rc_mlp_forward(_ptr(params), _ptr(X), int(X.shape[0]), _ptr(out), _stream(stream)))
+
+
+def rc_mlp_radius(params, X, safety, r_min, r_max, R, stream=None):
+    return _check(lib().rc_mlp_radius(_ptr(params), _ptr(X), int(X.shape[0]), float(safety), float(r_min),
+                                      float(r_max), _ptr(R), _stream(stream)))
+
+
+def rc_mlp_train_workspace_bytes(n):
+    return int(lib().rc_mlp_train_workspace_bytes(int(n)))
+
+
+def rc_mlp_train_step(params, state, X, target, lr, step, workspace, loss=None, grad=None, stream=None):
+    return _check(lib().rc_mlp_train_step(_ptr(params), _ptr(state), _ptr(X), _ptr(target), int(X.shape[0]),
+                                          float(lr), int(step), _ptr(workspace), _ptr(loss), _ptr(grad),
+                                          _stream(stream)))
+
+
+def rc_place_gather(cand, radius, covered, state, batch_idx, batch_pos, batch_R, batch, order=None, stream=None):
+    return _check(lib().rc_place_gather(_ptr(cand), _ptr(radius), _ptr(order), int(cand.shape[0]), _ptr(covered),
+                                        _ptr(state), _ptr(batch_idx), _ptr(batch_pos), _ptr(batch_R), int(batch),
+                                        _stream(stream)))
+
+
+def rc_place_accept(cand, batch_idx, batch_R, covered, state, accepted, accepted_R, accepted_pos=None,
+                    batch_value=None, batch_grad=None, cache_value=None, cache_grad=None, stream=None):
+    return _check(lib().rc_place_accept(_ptr(cand), _ptr(batch_idx), _ptr(batch_R), _ptr(covered), _ptr(state),
+                                        _ptr(accepted), _ptr(accepted_R), _ptr(accepted_pos), _ptr(batch_value),
+                                        _ptr(batch_grad), _ptr(cache_value), _ptr(cache_grad), _stream(stream)))
+
+
+def rc_place_cover(cand, covered, state, accepted, accepted_R, first=-1, count=0, stream=None):
+    return _check(lib().rc_place_cover(_ptr(cand), int(cand.shape[0]), _ptr(covered), _ptr(state), _ptr(accepted),
+                                       _ptr(accepted_R), int(first), int(count), _stream(stream)))
+
+
+def rc_place_cover_grid(cand, dims, lo, cell, covered, state, accepted, accepted_R, first=-1, count=0, stream=None):
+    d = np.ascontiguousarray(dims, np.int32)
+    l0 = np.ascontiguousarray(lo, np.float32)
+    ce = np.ascontiguousarray(cell, np.float32)
+    return _check(lib().rc_place_cover_grid(_ptr(cand), _ptr(d), _ptr(l0), _ptr(ce), _ptr(covered), _ptr(state),
+                                            _ptr(accepted), _ptr(accepted_R), int(first), int(count),
+                                            _stream(stream)))
+
+
+def rc_interp(cache_pos, cache_value, cache_grad, cache_R, query, out, hits=None, ref_value=None, err_partial=None,
+              stream=None):
+    return _check(lib().rc_interp(_ptr(cache_pos), _ptr(cache_value), _ptr(cache_grad), _ptr(cache_R),
+                                  int(cache_pos.shape[0]), _ptr(query), int(query.shape[0]), _ptr(out), _ptr(hits),
+                                  _ptr(ref_value), _ptr(err_partial), _stream(stream)))
 
 
 def rc_version():

@@ -36,6 +36,8 @@ __all__ = [
     "make_c5",
     "make",
     "default_max_rings",
+    "GridCandidates",
+    "uniform_points",
 ]
 
 
@@ -284,3 +286,36 @@ def make_c5(seed: int = 5, P: int = 1_000_000, n_tri: int = 1_000_000, n_dirs: i
 
 def make(name: str, **kw) -> Workload:
     return {"C1": make_c1, "C2": make_c2, "C3": make_c3, "C5": make_c5}[name.upper()](**kw)
+
+
+class GridCandidates:
+    """Candidate cache points for placement: one point per cell of an
+    n x n x n grid over the medium box, jittered inside its cell (kept 1e-3
+    of a cell away from the faces so FP32 rounding cannot move it out), and
+    a seeded random visiting order.  Index (ix * n + iy) * n + iz."""
+
+    def __init__(self, n: int, box_lo, box_hi, seed: int):
+        rng = np.random.default_rng(seed)
+        lo = np.asarray(box_lo, np.float64)
+        hi = np.asarray(box_hi, np.float64)
+        h = (hi - lo) / n
+        ix, iy, iz = np.meshgrid(np.arange(n), np.arange(n), np.arange(n), indexing="ij")
+        cell = np.stack([ix.ravel(), iy.ravel(), iz.ravel()], 1).astype(np.float64)
+        u = rng.uniform(1e-3, 1.0 - 1e-3, size=cell.shape)
+        self.pos = (lo + (cell + u) * h).astype(np.float32)
+        self.order = rng.permutation(n ** 3).astype(np.int32)
+        self.dims = np.array([n, n, n], np.int32)
+        self.lo = lo.astype(np.float32)
+        self.cell = h.astype(np.float32)
+
+    @property
+    def n(self) -> int:
+        return self.pos.shape[0]
+
+
+def uniform_points(n: int, box_lo, box_hi, seed: int) -> np.ndarray:
+    """n points uniform in the box (test points for cache error)."""
+    rng = np.random.default_rng(seed)
+    lo = np.asarray(box_lo, np.float64)
+    hi = np.asarray(box_hi, np.float64)
+    return (lo + rng.uniform(0, 1, (n, 3)) * (hi - lo)).astype(np.float32)
