@@ -12,8 +12,10 @@ triangulation, per-triangle derivative terms, reductions) followed by the
 validity-radius kernel.
 
 Prints one JSON line.  Extra fields: Mrays/s (counted rays), the roofline of
-the dominant kernel (record_kernel) and the FP64 CPU oracle's rate on a
-bounded sample of the same workload.
+the dominant kernel (record_kernel), the FP64 CPU oracle's rate on a bounded
+sample of the same workload, and the learned-vs-plain placement comparison
+(candidates resolved per second by each pipeline on a held-out scene of the
+same family, with each cache's error against 16384-direction references).
 """
 import argparse
 import hashlib
@@ -80,12 +82,39 @@ def cpu_baseline(w, budget_s=15.0):
             "cpu": O.cpu_info()["model"]}
 
 
+def learned_vs_plain(dev, safety=1.0):
+    """Train the radius MLP on 20 C2-family scenes (200k records), then place
+    caches over 128^3 = 2,097,152 candidates of a held-out scene with both
+    pipelines; the learned pipeline runs with safety factor 1 (fixed a priori,
+    the judge and fallback keep the cache valid)."""
+    from paper_1805_09258_amd import placement as PL
+    r = PL.compare(dev, safeties=(safety,), log=log)
+    lp, pl = r[f"learned_s{safety}"], r["plain"]
+    keep = ("seconds", "rounds", "records", "accepted", "rel_l2", "median_rel", "rel_l2_far_from_lights",
+            "covered", "mean_hits")
+    res = {"candidates": r["candidates"],
+           "plain": {k: pl[k] for k in keep if k in pl},
+           "learned": {k: lp[k] for k in keep + ("probes", "records_learned", "uncovered_after_judge",
+                                                 "fallback_rounds", "fallback_records", "seconds_rounds",
+                                                 "seconds_records_judge", "seconds_fallback", "safety") if k in lp},
+           "reference_noise": r["reference_noise"], "no_cache_error": r["no_cache"],
+           "training": {k: r[k] for k in ("train_samples", "train_data_seconds", "train_seconds", "train_mse",
+                                          "heldout_mse_net", "heldout_mse_constant")}}
+    res["plain"]["candidates_per_s"] = r["candidates"] / pl["seconds"]
+    res["learned"]["candidates_per_s"] = r["candidates"] / lp["seconds"]
+    res["speedup"] = pl["seconds"] / lp["seconds"]
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-learned", action="store_true", help="skip the learned-vs-plain placement comparison")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only copy a 1 GiB float32 buffer three times (scales the HBM byte counters)")
     ap.add_argument("--profile-steps", type=int, default=None, help=argparse.SUPPRESS)
     args = ap.parse_args()
     if args.gpus != 1:
@@ -94,6 +123,14 @@ def main():
         sys.exit(2)
 
     import torch
+    if args.copy_calibration:
+        a = torch.ones(1 << 28, dtype=torch.float32, device="cuda:0")
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        log("copied 3 x 1 GiB")
+        return
     from paper_1805_09258_amd import rc
     from paper_1805_09258_amd import workloads as W
 
@@ -181,6 +218,9 @@ def main():
                      "alg_bytes_per_ray": (nodes * NODE_BYTES + tris * TRI_BYTES) / max(rays, 1),
                      "phase_clock_fraction": phase_frac},
     }
+    if not args.no_learned:
+        log("learned vs plain placement ...")
+        out["learned_vs_plain"] = learned_vs_plain(dev)
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle) ...")
         out["cpu_baseline"] = cpu_baseline(w)

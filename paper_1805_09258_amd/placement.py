@@ -17,9 +17,10 @@ insertion rule of Sec. 6).
   one.
 
 Every step runs in the library's kernels (rc.*); this module only sequences
-calls and holds device buffers.  All records of a placement use common random
-numbers (one record id), so a cache's interpolation error can be told apart
-from Monte Carlo noise.
+calls and holds device buffers.  Records draw independent random numbers
+(record ids count up through a placement); probes all use one id (common
+random numbers), which makes the features a deterministic function of
+position for a given scene and seed.
 """
 from __future__ import annotations
 
@@ -39,7 +40,8 @@ class CacheConfig:
     r_max: float = 0.25 * float(np.sqrt(3.0))
     n_theta: int = 16            # record directions (16 x 64 = 1024)
     n_phi: int = 64
-    rec_id: int = 7_000_003      # the one record id of the cache (common random numbers)
+    ref_n_theta: int = 64        # reference records at test points (64 x 256 = 16384)
+    ref_n_phi: int = 256
     probe_id: int = 9_000_011    # the one probe id
     batch: int = 4096            # candidates per round (plain and learned)
 
@@ -54,19 +56,18 @@ class SceneContext:
     def close(self):
         self.scene.close()
 
-    def params(self, cfg: CacheConfig):
-        w = self.w
-        return rc.make_params(w.ring_step, w.max_rings, max(cfg.n_phi, 5), w.seed, rec_base=cfg.rec_id,
-                              common_random=True)
-
-    def records(self, pos, value, grad, hess, ws, cfg: CacheConfig, nth, nph):
-        """Full records at pos (device float[P][3]) into value/grad/hess."""
+    def records(self, pos, value, grad, hess, ws, nth, nph, max_n_phi, rec_base, seed=None):
+        """Full records at pos (device float[P][3]) into value/grad/hess; record
+        i draws with id rec_base + i.  Returns P."""
         w = self.w
         P = pos.shape[0]
         if P == 0:
-            return
-        rc.rc_records_batched(self.scene.handle, w.sigma_s, w.sigma_a, w.lights, pos, nth[:P], nph[:P],
-                              self.params(cfg), None, False, -1, value[:P], grad[:P], hess[:P], ws)
+            return 0
+        prm = rc.make_params(w.ring_step, w.max_rings, max(int(max_n_phi), 5), w.seed if seed is None else seed,
+                             rec_base=rec_base)
+        rc.rc_records_batched(self.scene.handle, w.sigma_s, w.sigma_a, w.lights, pos, nth[:P], nph[:P], prm, None,
+                              False, -1, value[:P], grad[:P], hess[:P], ws)
+        return P
 
     def probe(self, pos, feat, cfg: CacheConfig):
         w = self.w
@@ -130,11 +131,17 @@ class Placer:
         self.nth = torch.full((n,), cfg.n_theta, dtype=torch.int32, device=device)
         self.nph = torch.full((n,), cfg.n_phi, dtype=torch.int32, device=device)
         self._big = None  # records of the learned points (allocated on first use)
+        self._next_id = 0  # record ids count up through a placement
 
     # -- pieces ---------------------------------------------------------------
     def _reset(self):
         self.covered.zero_()
         self.state.zero_()
+        self._next_id = 0
+
+    def _records(self, pos, value, grad, hess, ws, nth, nph):
+        n = self.ctx.records(pos, value, grad, hess, ws, nth, nph, self.cfg.n_phi, self._next_id)
+        self._next_id += n
 
     def _gather(self):
         rc.rc_place_gather(self.cand, None, self.covered, self.state, self.bidx, self.bpos, self.bR, self.cfg.batch,
@@ -153,7 +160,7 @@ class Placer:
             m = self._gather()
             if m == 0:
                 break
-            self.ctx.records(self.bpos[:m], self.bval, self.bgrad, self.bhess, self.bws, cfg, self.nth, self.nph)
+            self._records(self.bpos[:m], self.bval, self.bgrad, self.bhess, self.bws, self.nth, self.nph)
             rc.rc_radius(self.bval[:m], self.bhess[:m], cfg.eps, cfg.r_min, cfg.r_max, self.bR[:m])
             rc.rc_place_accept(self.cand, self.bidx, self.bR, self.covered, self.state, self.acc, self.accR,
                                self.accpos, self.bval, self.bgrad, self.cval, self.cgrad)
@@ -207,7 +214,7 @@ class Placer:
                          torch.full((n,), cfg.n_theta, dtype=torch.int32, device=self.dev),
                          torch.full((n,), cfg.n_phi, dtype=torch.int32, device=self.dev))
         hess, ws, nth, nph = self._big
-        self.ctx.records(self.accpos[:K1], self.cval, self.cgrad, hess, ws, cfg, nth, nph)
+        self._records(self.accpos[:K1], self.cval, self.cgrad, hess, ws, nth, nph)
         # the judge: true radii replace the predicted ones, the candidates are covered again
         rc.rc_radius(self.cval[:K1], hess[:K1], cfg.eps, cfg.r_min, cfg.r_max, self.accR[:K1])
         self.covered.zero_()
@@ -229,27 +236,32 @@ class Placer:
         return res
 
 
-def direct_records(ctx: SceneContext, pts, cfg: CacheConfig, device, chunk=65536):
-    """Records at arbitrary points with the cache's directions: the reference a
-    cache is compared against.  Returns device (value [Q][2], hess [Q][2][6])."""
+def direct_records(ctx: SceneContext, pts, n_theta, n_phi, rec_base, device, seed=None, chunk=65536):
+    """Records at arbitrary points (ids rec_base + i): the no-cache estimate and
+    the high-sample reference a cache is compared against.  Returns device
+    (value [Q][2], grad [Q][2][3], hess [Q][2][6])."""
     import torch
     Q = pts.shape[0]
     value = torch.zeros((Q, 2), dtype=torch.float64, device=device)
     grad = torch.zeros((Q, 2, 3), dtype=torch.float64, device=device)
     hess = torch.zeros((Q, 2, 6), dtype=torch.float64, device=device)
-    n = min(Q, chunk)
-    ws = torch.zeros(rc.rc_workspace_size(max(n, 1)), dtype=torch.uint8, device=device)
-    nth = torch.full((max(n, 1),), cfg.n_theta, dtype=torch.int32, device=device)
-    nph = torch.full((max(n, 1),), cfg.n_phi, dtype=torch.int32, device=device)
+    n = max(min(Q, chunk), 1)
+    ws = torch.zeros(rc.rc_workspace_size(n), dtype=torch.uint8, device=device)
+    nth = torch.full((n,), n_theta, dtype=torch.int32, device=device)
+    nph = torch.full((n,), n_phi, dtype=torch.int32, device=device)
     for s in range(0, Q, chunk):
         e = min(Q, s + chunk)
-        ctx.records(pts[s:e], value[s:e], grad[s:e], hess[s:e], ws, cfg, nth, nph)
+        ctx.records(pts[s:e], value[s:e], grad[s:e], hess[s:e], ws, nth, nph, n_phi, rec_base + s, seed)
     return value, grad, hess
 
 
-def cache_error(res: PlacementResult, query, ref_value, device):
-    """Relative L2 error of the cache's interpolation (Eq. radianceTaylor) at
-    the query points against reference values, over the covered queries."""
+def cache_error(res: PlacementResult, query, ref_value, device, lights=None, light_margin=0.15):
+    """Error of the cache's interpolation (Eq. radianceTaylor) at the query
+    points against reference values, over the covered queries: relative L2
+    (from the interpolation kernel's partial sums), median relative error,
+    and relative L2 over queries at least light_margin from every point
+    light (point lights make the in-scattered radiance singular, and its
+    estimates heavy-tailed, near them)."""
     import torch
     Q = query.shape[0]
     out = torch.zeros(Q, dtype=torch.float64, device=device)
@@ -258,9 +270,34 @@ def cache_error(res: PlacementResult, query, ref_value, device):
     err = torch.zeros(2 * max(nb, 1), dtype=torch.float64, device=device)
     rc.rc_interp(res.pos, res.value, res.grad, res.R, query, out, hits, ref_value, err)
     e = err.view(-1, 2).sum(0).cpu().numpy()
-    covered = float((hits > 0).double().mean().item()) if Q else 0.0
-    return {"rel_l2": float(np.sqrt(e[0] / e[1])) if e[1] > 0 else float("nan"), "covered": covered,
-            "mean_hits": float(hits.double().mean().item()) if Q else 0.0}
+    cov = hits > 0
+    ref = ref_value.sum(1)
+    d = {"rel_l2": float(np.sqrt(e[0] / e[1])) if e[1] > 0 else float("nan"),
+         "covered": float(cov.double().mean().item()) if Q else 0.0,
+         "mean_hits": float(hits.double().mean().item()) if Q else 0.0}
+    if Q:
+        relerr = ((out - ref).abs() / ref.abs().clamp_min(1e-30))[cov]
+        d["median_rel"] = float(relerr.median().item()) if relerr.numel() else float("nan")
+        if lights is not None:
+            lp = torch.as_tensor(np.asarray(lights, np.float32)[:, :3], device=device)
+            far = (torch.cdist(query, lp).min(1).values >= light_margin) & cov
+            num = ((out - ref)[far] ** 2).sum()
+            den = (ref[far] ** 2).sum()
+            d["rel_l2_far_from_lights"] = float(torch.sqrt(num / den).item())
+    return d
+
+
+def estimate_error(est, ref, query, lights=None, light_margin=0.15):
+    """The same error measures for per-point estimates est [Q][2] (no cache)."""
+    import torch
+    a, b = est.sum(1), ref.sum(1)
+    d = {"rel_l2": float(torch.sqrt(((a - b) ** 2).sum() / (b ** 2).sum()).item()),
+         "median_rel": float(((a - b).abs() / b.abs().clamp_min(1e-30)).median().item())}
+    if lights is not None:
+        lp = torch.as_tensor(np.asarray(lights, np.float32)[:, :3], device=query.device)
+        far = torch.cdist(query, lp).min(1).values >= light_margin
+        d["rel_l2_far_from_lights"] = float(torch.sqrt(((a - b)[far] ** 2).sum() / (b[far] ** 2).sum()).item())
+    return d
 
 
 # ---------------------------------------------------------------------------
@@ -270,7 +307,7 @@ def labels_and_features(ctx: SceneContext, pts, cfg: CacheConfig, device):
     """(features [P][32], log R [P]) at points of a scene: probe features and
     the log of the true validity radius from full records."""
     import torch
-    value, grad, hess = direct_records(ctx, pts, cfg, device)
+    value, grad, hess = direct_records(ctx, pts, cfg.n_theta, cfg.n_phi, 0, device)
     P = pts.shape[0]
     R = torch.zeros(P, dtype=torch.float32, device=device)
     rc.rc_radius(value, hess, cfg.eps, cfg.r_min, cfg.r_max, R)
@@ -316,4 +353,75 @@ def predict_log_radius(mlp: Mlp, X):
     import torch
     out = torch.zeros(X.shape[0], dtype=torch.float32, device=X.device)
     rc.rc_mlp_forward(mlp.params, X, out)
+    return out
+
+
+# ---------------------------------------------------------------------------
+# learned vs plain on one held-out scene
+# ---------------------------------------------------------------------------
+def training_set(seeds, P, cfg: CacheConfig, device):
+    """Probe features and log true radii at P seeded points in each C2-family
+    scene (the records the method itself generates)."""
+    import torch
+    Xs, ys = [], []
+    for sd in seeds:
+        w = W.make_c4_scene(sd, P=P)
+        ctx = SceneContext(w)
+        X, y = labels_and_features(ctx, torch.as_tensor(w.pos, device=device), cfg, device)
+        Xs.append(X)
+        ys.append(y)
+        ctx.close()
+    return torch.cat(Xs), torch.cat(ys)
+
+
+def compare(device, train_seeds=range(1000, 1020), P_train=10_000, val_seed=1099, eval_seed=4242, grid_n=128,
+            n_test=20_000, safeties=(1.0, 0.8), epochs=20, cfg: CacheConfig | None = None, log=None):
+    """Train the radius MLP, then place caches over grid_n^3 candidates of a
+    held-out scene with the plain and the learned pipeline (each timed after
+    one untimed run) and measure their interpolation error at n_test uniform
+    points against 16384-direction reference records."""
+    import torch
+    cfg = cfg or CacheConfig()
+    out = {}
+    t0 = time.perf_counter()
+    X, y = training_set(train_seeds, P_train, cfg, device)
+    torch.cuda.synchronize()
+    out["train_samples"] = int(X.shape[0])
+    out["train_data_seconds"] = time.perf_counter() - t0
+    mlp = Mlp.new(device, seed=1)
+    t0 = time.perf_counter()
+    hist = train(mlp, X, y, epochs=epochs, log=log)
+    torch.cuda.synchronize()
+    out["train_seconds"] = time.perf_counter() - t0
+    out["train_mse"] = hist[-1]
+    Xv, yv = training_set([val_seed], P_train, cfg, device)
+    pv = predict_log_radius(mlp, Xv)
+    out["heldout_mse_net"] = float(((pv - yv) ** 2).mean().item())
+    out["heldout_mse_constant"] = float(((yv - y.mean()) ** 2).mean().item())
+    del X, y, Xv, yv
+    # evaluation scene
+    we = W.make_c4_scene(eval_seed, P=1)
+    ctx = SceneContext(we)
+    cands = W.GridCandidates(grid_n, we.box_lo, we.box_hi, seed=eval_seed + 1)
+    placer = Placer(ctx, cands, cfg, device)
+    q = torch.as_tensor(W.uniform_points(n_test, we.box_lo, we.box_hi, eval_seed + 2), device=device)
+    ref, _, _ = direct_records(ctx, q, cfg.ref_n_theta, cfg.ref_n_phi, 50_000_000, device, seed=eval_seed + 3)
+    ref2, _, _ = direct_records(ctx, q, cfg.ref_n_theta, cfg.ref_n_phi, 60_000_000, device, seed=eval_seed + 4)
+    direct, _, _ = direct_records(ctx, q, cfg.n_theta, cfg.n_phi, 70_000_000, device, seed=eval_seed + 5)
+
+    out["reference_noise"] = estimate_error(ref2, ref, q, we.lights)   # two 16384-direction references
+    out["no_cache"] = estimate_error(direct, ref, q, we.lights)        # a 1024-direction record per test point
+    out["candidates"] = cands.n
+    placer.plain()
+    r = placer.plain()
+    out["plain"] = dict(r.stats, **cache_error(r, q, ref, device, we.lights))
+    if log:
+        log("plain", out["plain"])
+    for s in safeties:
+        placer.learned(mlp, s)
+        r = placer.learned(mlp, s)
+        out[f"learned_s{s}"] = dict(r.stats, safety=s, **cache_error(r, q, ref, device, we.lights))
+        if log:
+            log(f"learned s={s}", out[f"learned_s{s}"])
+    ctx.close()
     return out
