@@ -31,6 +31,14 @@ ROOT = Path(__file__).resolve().parent
 sys.path.insert(0, str(ROOT))
 
 HBM_PEAK_GBS = 8000.0
+WORKLOAD_TEXT = {
+    "c2": "C2: 10k points, closed unit room + 10k-triangle soup (edge 0.02), 1024 directions (16x64), "
+          "sigma_s=1.0 sigma_a=0.2, 4 point lights, ring step 0.1",
+    "c3": "C3: 200k points, room + 20 slabs + soup (100k triangles), directions log-uniform in [256, 4096], "
+          "sigma_s=1.0 sigma_a=0.2, 4 point lights, ring step 0.1",
+    "c5": "C5: 1M points, room + 20 slabs + soup (1M triangles), 2048 directions (32x64), sigma_s=2.0 "
+          "sigma_a=0.5, 4 point lights, ring step 0.1",
+}
 NODE_BYTES, TRI_BYTES = 64, 48
 
 
@@ -78,7 +86,7 @@ def cpu_baseline(w, budget_s=15.0):
     cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
     cores = min(cores, os.cpu_count() or cores)
     return {"value": n / dt, "unit": "records/s", "cores": cores, "kind": "oracle",
-            "sample": f"{n} of {w.n_rec} records (seeded), same scene, 1024 directions each, {dt:.1f} s",
+            "sample": f"{n} of {w.n_rec} records (seeded), same scene and sample counts, {dt:.1f} s",
             "cpu": O.cpu_info()["model"]}
 
 
@@ -113,6 +121,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-vs-plain placement comparison")
+    ap.add_argument("--workload", default="c2", choices=["c2", "c3", "c5"],
+                    help="c2 (default, the headline line); c3 = 200k points with mixed sample counts over "
+                         "100k triangles; c5 = 1M points over 1M triangles")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only copy a 1 GiB float32 buffer three times (scales the HBM byte counters)")
     ap.add_argument("--profile-steps", type=int, default=None, help=argparse.SUPPRESS)
@@ -138,8 +149,10 @@ def main():
         print("bench.py: no GPU visible", file=sys.stderr)
         sys.exit(1)
     dev = torch.device("cuda:0")
-    w = W.make_c2()
-    log(f"workload C2: {w.n_rec} records, {w.n_tri} triangles, N={int(w.n_theta[0] * w.n_phi[0])}")
+    w = W.make(args.workload)
+    ndir = (w.n_theta.astype(np.int64) * w.n_phi).astype(np.float64)
+    log(f"workload {w.name}: {w.n_rec} records, {w.n_tri} triangles, N mean {ndir.mean():.0f} "
+        f"[{ndir.min():.0f}, {ndir.max():.0f}]")
     scene = rc.Scene.from_workload(w)
     info = scene.info()
     dw = rc.DeviceWorkload(w, device=dev)
@@ -161,13 +174,21 @@ def main():
                   "triangle_terms": c3 / ctot}
     alg_bytes = nodes * NODE_BYTES + tris * TRI_BYTES + w.n_rec * (12 + 8 + 16 + 48 + 96 + 4)
     log(f"per launch: {rays} rays, {nodes} node fetches, {tris} triangle tests, {terms} triangle terms")
+    # untimed: the launch configuration, chosen by the autotuner over the persistent-grid tiles
+    # (measured on the first 20k records)
+    prm = rc.make_params(w.ring_step, w.max_rings, dw.max_n_phi, w.seed)
+    nt = min(w.n_rec, 20_000)
+    tile, tile_ms = rc.rc_autotune(scene.handle, w.sigma_s, w.sigma_a, w.lights, dw.pos[:nt], dw.n_theta[:nt],
+                                   dw.n_phi[:nt], prm, value[:nt], grad[:nt], hess[:nt], ws, stream=stream)
+    stream.synchronize()
+    log(f"autotune: tile {tile} ({', '.join(f'{t:.1f}' for t in tile_ms)} ms)")
 
     def step(ev=None):
         with torch.cuda.stream(stream):
             if ev is not None:
                 ev[0].record(stream)
-            rc.compute_records(scene, dw, batched=True, use_graph=True, out=(value, grad, hess), workspace=ws,
-                               stream=stream)
+            rc.compute_records(scene, dw, batched=True, use_graph=True, tile=tile, out=(value, grad, hess),
+                               workspace=ws, stream=stream)
             if ev is not None:
                 ev[1].record(stream)
             rc.rc_radius(value, hess, eps, r_min, r_max, R, None, stream=stream)
@@ -191,7 +212,7 @@ def main():
     log(f"timed {args.steps} steps: {ms_step:.3f} ms/step, record kernel {kern_ms:.3f} ms")
 
     achieved = alg_bytes / (kern_ms * 1e-3) / 1e9
-    traffic = traffic_from_profile(alg_bytes)
+    traffic = traffic_from_profile(alg_bytes) if args.workload == "c2" else None
     out = {
         "metric": "cache records/s (value+grad+Hessian) & Mrays/s; learned vs plain at equal error",
         "value": rec_s,
@@ -205,10 +226,10 @@ def main():
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": "C2: 10k points, closed unit room + 10k-triangle soup (edge 0.02), 1024 directions "
-                               "(16x64), sigma_s=1.0 sigma_a=0.2, 4 point lights, ring step 0.1",
-                   "records_per_step": w.n_rec, "n_triangles": w.n_tri, "directions": 1024,
-                   "bvh_nodes": info["n_nodes"], "bvh_depth": info["depth"]},
+        "config": {"workload": WORKLOAD_TEXT[args.workload],
+                   "records_per_step": w.n_rec, "n_triangles": w.n_tri, "directions_mean": float(ndir.mean()),
+                   "bvh_nodes": info["n_nodes"], "bvh_depth": info["depth"], "tile": tile,
+                   "tile_ms": tile_ms},
         "mrays_per_s": rays * args.steps / dt / 1e6,
         "rays_per_record": rays / w.n_rec,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
@@ -218,7 +239,7 @@ def main():
                      "alg_bytes_per_ray": (nodes * NODE_BYTES + tris * TRI_BYTES) / max(rays, 1),
                      "phase_clock_fraction": phase_frac},
     }
-    if not args.no_learned:
+    if not args.no_learned and args.workload == "c2":
         log("learned vs plain placement ...")
         out["learned_vs_plain"] = learned_vs_plain(dev)
     if not args.no_cpu_baseline:
