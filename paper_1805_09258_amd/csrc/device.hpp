@@ -149,7 +149,8 @@ RC_DEV void trace_closest(const float4* __restrict__ nodes, const float4* __rest
       float ta = slab(w0.x, w0.y, w0.z, w0.w, w2.x, w2.y, inv, oi, 0.0f, best_t);
       float tb = slab(w1.x, w1.y, w1.z, w1.w, w2.z, w2.w, inv, oi, 0.0f, best_t);
       int ca = __float_as_int(w3.x), cb = __float_as_int(w3.y);
-      bool ha = ta <= best_t, hb = tb <= best_t;
+      // slab() clamps to best_t and returns +inf on a miss
+      bool ha = ta < __builtin_huge_valf(), hb = tb < __builtin_huge_valf();
       if (ha && hb) {
         int nearc = ta <= tb ? ca : cb, farc = ta <= tb ? cb : ca;
         stk[sp * kWave] = farc;
@@ -206,7 +207,7 @@ RC_DEV bool occluded(const float4* __restrict__ nodes, const float4* __restrict_
       float ta = slab(w0.x, w0.y, w0.z, w0.w, w2.x, w2.y, inv, oi, 0.0f, 1.0f);
       float tb = slab(w1.x, w1.y, w1.z, w1.w, w2.z, w2.w, inv, oi, 0.0f, 1.0f);
       int ca = __float_as_int(w3.x), cb = __float_as_int(w3.y);
-      bool ha = ta <= 1.0f, hb = tb <= 1.0f;
+      bool ha = ta < __builtin_huge_valf(), hb = tb < __builtin_huge_valf();
       if (ha && hb) {
         int nearc = ta <= tb ? ca : cb, farc = ta <= tb ? cb : ca;
         stk[sp * kWave] = farc;

@@ -271,7 +271,7 @@ __global__ __launch_bounds__(64) void record_kernel(RecordArgs g) {
               const float ta = slab(q0.x, q0.y, q0.z, q0.w, q2.x, q2.y, inv, oi, 0.0f, 1.0f);
               const float tb = slab(q1.x, q1.y, q1.z, q1.w, q2.z, q2.w, inv, oi, 0.0f, 1.0f);
               const int ca = __float_as_int(q3.x), cb = __float_as_int(q3.y);
-              const bool ha = ta <= 1.0f, hb = tb <= 1.0f;
+              const bool ha = ta < __builtin_huge_valf(), hb = tb < __builtin_huge_valf();
               int nx;
               if (ha && hb) {
                 nx = ta <= tb ? ca : cb;
