@@ -78,6 +78,14 @@ typedef struct {
  *               every point (common random numbers: records then differ
  *               only through the scene, which makes a cache's interpolation
  *               error measurable apart from Monte Carlo noise).
+ *   splits    : wavefronts per record, 0 = automatic (batches of up to 16384
+ *               records split each record's strata rows over 1..8
+ *               wavefronts, each recomputing one boundary row, as a model of
+ *               the launch's makespan suggests: small batches finish sooner);
+ *               1..8 forces a count (more than 1 needs P <= 16384).  Parts
+ *               leave FP64 partial sums that the last one adds in part order,
+ *               so results are deterministic for a given count and differ
+ *               from an unsplit record only in FP64 rounding.
  *   precision : 0 = FP32 terms, compensated FP32 sums, FP64 for
  *               near-degenerate triangle terms and the final reduction
  *               (default); 1 = every triangle term in FP64 (study mode).
@@ -93,6 +101,7 @@ typedef struct {
   int32_t max_n_phi;
   int32_t precision;
   int32_t common_random;
+  int32_t splits;
   uint64_t seed;
   int64_t rec_base;
   uint64_t* counters;

@@ -86,6 +86,9 @@ namespace {
 
 constexpr size_t kWsQueue = 0, kWsHist = 256, kWsCursor = 256 + 4 * rc::kOrderBuckets,
                  kWsOrder = 256 + 8 * rc::kOrderBuckets;
+// after the queue order: per-record part counters, then per-part partial sums
+size_t ws_split_offset(int64_t P) { return (kWsOrder + 4 * (size_t)std::max<int64_t>(P, 0) + 255) & ~size_t(255); }
+size_t ws_partial_offset(int64_t Pm) { return (4 * (size_t)Pm + 255) & ~size_t(255); }
 
 int check_inputs(const rc_scene* s, const rc_medium* m, const rc_point_light* lights, int n_lights, const float* pos,
                  const int32_t* nth, const int32_t* nph, int64_t P, const rc_params* p, double* value, double* grad,
@@ -105,6 +108,9 @@ int check_inputs(const rc_scene* s, const rc_medium* m, const rc_point_light* li
   if (p->max_n_phi < 5 || p->max_n_phi > RC_MAX_NPHI) return fail(RC_EINVAL, "max_n_phi must be in [5, %d]", RC_MAX_NPHI);
   if (p->precision != 0 && p->precision != 1) return fail(RC_EINVAL, "precision must be 0 or 1");
   if (p->common_random != 0 && p->common_random != 1) return fail(RC_EINVAL, "common_random must be 0 or 1");
+  if (p->splits < 0 || p->splits > rc::kMaxSplits) return fail(RC_EINVAL, "splits must be in [0, %d]", rc::kMaxSplits);
+  if (p->splits > 1 && P > rc::kSplitMaxRecords)
+    return fail(RC_EINVAL, "splits > 1 needs P <= %d", rc::kSplitMaxRecords);
   if (p->rec_base < 0) return fail(RC_EINVAL, "rec_base must be >= 0");
   if (P > 0 && (!pos || !nth || !nph || !value || !grad || !hess))
     return fail(RC_EINVAL, "NULL input or output pointer");
@@ -145,7 +151,36 @@ rc::RecordArgs make_args(const rc_scene* s, const rc_medium* m, const rc_point_l
   a.order = order;
   a.queue = reinterpret_cast<unsigned int*>(static_cast<char*>(ws) + kWsQueue);
   a.counters = reinterpret_cast<unsigned long long*>(p->counters);
+  a.splits = 1;
   return a;
+}
+
+// Wavefronts per record: explicit (params->splits) or chosen to minimise a
+// makespan model of the persistent launch: the work spread over the resident
+// wavefronts, P (1 + (S - 1) / rows) / resident record-times (each extra part
+// recomputes one of ~16 rows), plus the tail of one part, 1 / S.
+void set_splits(rc::RecordArgs& a, const rc_params* p, int64_t P, int64_t resident, void* ws) {
+  int S = p->splits;
+  if (S == 0) {
+    S = 1;
+    if (P <= rc::kSplitMaxRecords && P > 0) {
+      const double rows = 16.0;
+      double best = 1e300;
+      for (int k = 1; k <= rc::kMaxSplits; k++) {
+        const double t = (double)P * (1.0 + (k - 1) / rows) / (double)resident + 1.0 / k;
+        if (t < best - 1e-9) {
+          best = t;
+          S = k;
+        }
+      }
+    }
+  }
+  a.splits = S;
+  if (S > 1) {
+    char* base = static_cast<char*>(ws) + ws_split_offset(P);
+    a.done = reinterpret_cast<unsigned int*>(base);
+    a.partial = reinterpret_cast<double*>(base + ws_partial_offset(std::min<int64_t>(P, rc::kSplitMaxRecords)));
+  }
 }
 
 // launch configurations ("tiles"): persistent grid as a multiple of the
@@ -153,7 +188,8 @@ rc::RecordArgs make_args(const rc_scene* s, const rc_medium* m, const rc_point_l
 constexpr int kNTiles = 4;
 constexpr float kTileGrid[kNTiles] = {1.0f, 2.0f, 0.5f, 4.0f};
 
-int plan(const rc_scene* s, const rc_params* p, int64_t P, int tile, int& stack, size_t& lds, int& grid) {
+int plan(const rc_scene* s, const rc_params* p, int64_t P, int tile, int& stack, size_t& lds, int& grid,
+         int64_t* resident_out = nullptr) {
   stack = rc::stack_variant(s->depth);
   lds = rc::record_lds_bytes(stack, p->max_n_phi, p->max_rings);
   if (lds > 160 * 1024) return fail(RC_EINVAL, "max_n_phi x max_rings needs %zu bytes of LDS (> 160 KiB)", lds);
@@ -163,14 +199,16 @@ int plan(const rc_scene* s, const rc_params* p, int64_t P, int tile, int& stack,
   if (occ < 1) occ = 1;
   int t = (tile >= 0 && tile < kNTiles) ? tile : 0;
   int64_t resident = (int64_t)occ * s->n_cu;
+  if (resident_out) *resident_out = resident;
   int64_t gsz = (int64_t)std::llround((double)resident * kTileGrid[t]);
-  gsz = std::max<int64_t>(1, std::min<int64_t>(gsz, P));
+  gsz = std::max<int64_t>(1, std::min<int64_t>(gsz, P * (int64_t)rc::kMaxSplits));
   grid = (int)gsz;
   return RC_OK;
 }
 
 int launch_direct(rc_scene* s, const rc::RecordArgs& a, int stack, size_t lds, int grid, hipStream_t st) {
   RC_HIP(rc::launch_reset(a.queue, st));
+  if (a.splits > 1) RC_HIP(rc::launch_zero_u32(a.done, a.P, st));
   RC_HIP(rc::launch_record(a, stack, a.counters != nullptr, a.precision == 1, grid, lds, st));
   return RC_OK;
 }
@@ -305,8 +343,8 @@ int64_t rc_bvh_build_host(const float* tri, int64_t T, const float box_lo[3], co
 }
 
 size_t rc_workspace_size(int64_t P) {
-  size_t b = kWsOrder + 4 * (size_t)std::max<int64_t>(P, 0);
-  return (b + 255) & ~size_t(255);
+  const int64_t Pm = std::min<int64_t>(std::max<int64_t>(P, 0), rc::kSplitMaxRecords);
+  return ws_split_offset(P) + ws_partial_offset(Pm) + (size_t)Pm * rc::kMaxSplits * 20 * sizeof(double);
 }
 
 int64_t rc_workspace_errors(const void* ws, void* stream) {
@@ -327,9 +365,12 @@ int rc_records(const rc_scene* scene, const rc_medium* medium, const rc_point_li
   rc_scene* s = const_cast<rc_scene*>(scene);
   int stack, grid;
   size_t lds;
-  if ((r = plan(s, params, P, 0, stack, lds, grid))) return r;
+  int64_t resident = 0;
+  if ((r = plan(s, params, P, 0, stack, lds, grid, &resident))) return r;
   rc::RecordArgs a = make_args(s, medium, lights, n_lights, pos, n_theta, n_phi, P, params, value, grad, hess,
                                workspace, nullptr);
+  set_splits(a, params, P, resident, workspace);
+  grid = (int)std::min<int64_t>(grid, P * (int64_t)a.splits);
   return launch_direct(s, a, stack, lds, grid, static_cast<hipStream_t>(stream));
 }
 
@@ -345,7 +386,8 @@ int rc_records_batched(const rc_scene* scene, const rc_medium* medium, const rc_
   hipStream_t st = static_cast<hipStream_t>(stream);
   int stack, grid;
   size_t lds;
-  if ((r = plan(s, params, P, tile, stack, lds, grid))) return r;
+  int64_t resident = 0;
+  if ((r = plan(s, params, P, tile, stack, lds, grid, &resident))) return r;
   char* ws = static_cast<char*>(workspace);
   const int32_t* ord = order;
   if (!ord) {
@@ -356,6 +398,8 @@ int rc_records_batched(const rc_scene* scene, const rc_medium* medium, const rc_
   }
   rc::RecordArgs a = make_args(s, medium, lights, n_lights, pos, n_theta, n_phi, P, params, value, grad, hess,
                                workspace, ord);
+  set_splits(a, params, P, resident, workspace);
+  grid = (int)std::min<int64_t>(grid, P * (int64_t)a.splits);
   if (!use_graph || st == nullptr) return launch_direct(s, a, stack, lds, grid, st);
   std::lock_guard<std::mutex> lk(s->mu);
   GraphCache& gc = s->graph;
@@ -365,6 +409,7 @@ int rc_records_batched(const rc_scene* scene, const rc_medium* medium, const rc_
     gc.clear();
     RC_HIP(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
     hipError_t e1 = rc::launch_reset(a.queue, st);
+    if (e1 == hipSuccess && a.splits > 1) e1 = rc::launch_zero_u32(a.done, a.P, st);
     hipError_t e2 = e1 == hipSuccess ? rc::launch_record(a, stack, a.counters != nullptr, a.precision == 1, grid, lds, st) : e1;
     hipGraph_t g = nullptr;
     hipError_t e3 = hipStreamEndCapture(st, &g);

@@ -99,14 +99,16 @@ __global__ __launch_bounds__(64) void record_kernel(RecordArgs g) {
   uint64_t cyc[4] = {0, 0, 0, 0};  // counting variant: shader clocks per phase
   uint64_t t_mark = 0;
 
+  const int S = g.splits;  // wavefronts per record (row ranges); 1 for large batches
   while (true) {
     int q = 0;
     if (lane == 0) q = (int)atomicAdd(&g.queue[0], 1u);
     q = __shfl(q, 0, kWave);
-    if (q >= g.P) break;
-    const int rec = g.order ? g.order[q] : q;
+    if (q >= g.P * S) break;
+    const int qr = q / S, part = q - qr * S;
+    const int rec = g.order ? g.order[qr] : qr;
     if (rec < 0 || rec >= g.P) {  // corrupt queue entry: count it, touch nothing
-      if (lane == 0) atomicAdd(&g.queue[1], 1u);
+      if (lane == 0 && part == 0) atomicAdd(&g.queue[1], 1u);
       continue;
     }
     const float3 x = make_float3(g.pos[3 * rec], g.pos[3 * rec + 1], g.pos[3 * rec + 2]);
@@ -114,6 +116,7 @@ __global__ __launch_bounds__(64) void record_kernel(RecordArgs g) {
     const bool bad = !(nth >= 2 && nph >= 5 && nph <= cap) || !(x.x >= g.box_lo.x && x.x <= g.box_hi.x) ||
                      !(x.y >= g.box_lo.y && x.y <= g.box_hi.y) || !(x.z >= g.box_lo.z && x.z <= g.box_hi.z);
     if (bad) {
+      if (part != 0) continue;  // the first part reports it
       if (lane < 2) {
         g.value[2 * rec + lane] = __builtin_nan("");
         for (int k = 0; k < 3; k++) g.grad[6 * rec + 3 * lane + k] = __builtin_nan("");
@@ -128,8 +131,15 @@ __global__ __launch_bounds__(64) void record_kernel(RecordArgs g) {
 
     if (lane < 20) racc[lane] = 0.0;
 
-    // rows: -1 north pole, 0..nth-1 strata rows, nth south pole
-    for (int a = -1; a <= nth; a++) {
+    // rows: -1 north pole, 0..nth-1 strata rows, nth south pole.  Part k of S
+    // owns rows a_own..a_hi (values and the bands ending at them); a later
+    // part also recomputes the row before a_own, which its first band needs.
+    const int nr = nth + 2;
+    const int r0 = (int)(((long long)part * nr) / S), r1 = (int)(((long long)(part + 1) * nr) / S);
+    const int a_own = r0 - 1, a_hi = r1 - 2;
+    const int a_lo = (part > 0 && r1 > r0) ? a_own - 1 : a_own;
+    for (int a = a_lo; a <= a_hi; a++) {
+      const bool own = a >= a_own;
       float* const baseR = rows + ((a + 1) & 1) * row_words;
       float* const baseP = rows + (a & 1) * row_words;
       const Row R = row_view(baseR, cap);
@@ -161,7 +171,7 @@ __global__ __launch_bounds__(64) void record_kernel(RecordArgs g) {
           R.Ls[j] = id >= 0 ? g.emission[id] : 0.f;
           R.visS[j] = 0;
           for (int i = 0; i < M; i++) reinterpret_cast<int*>(R.Lm)[i * cap + j] = 0;
-          if (COUNT) n_rays++;
+          if (COUNT && own) n_rays++;
         }
       }
       __syncthreads();
@@ -227,7 +237,7 @@ __global__ __launch_bounds__(64) void record_kernel(RecordArgs g) {
               node = 0;
               sp = 0;
               ln = 0;
-              if (COUNT) n_rays++;
+              if (COUNT && own) n_rays++;
             }
           }
           next += __popcll(want);
@@ -344,7 +354,7 @@ __global__ __launch_bounds__(64) void record_kernel(RecordArgs g) {
       }
       if (COUNT) { uint64_t t = clock64(); cyc[1] += t - t_mark; t_mark = t; }
       // ---- 3. Monte Carlo value of the strata in this row -----------------
-      if (!pole) {
+      if (!pole && own) {
         float vs = 0.f, vsc = 0.f, vm = 0.f, vmc = 0.f;
         for (int base = 0; base < n; base += kWave) {
           int j = base + lane;
@@ -365,7 +375,7 @@ __global__ __launch_bounds__(64) void record_kernel(RecordArgs g) {
       }
       if (COUNT) { uint64_t t = clock64(); cyc[2] += t - t_mark; t_mark = t; }
       // ---- 4. triangles between the previous row and this one -------------
-      if (a >= 0) {
+      if (a >= 0 && own) {
         // kind 0: north fan (P = pole, R = row 0); 1: band; 2: south fan
         const int kind = (a == 0) ? 0 : (a == nth ? 2 : 1);
         const int ntri = (kind == 1) ? 2 * nph : nph;
@@ -512,6 +522,26 @@ __global__ __launch_bounds__(64) void record_kernel(RecordArgs g) {
       if (COUNT) { uint64_t t = clock64(); cyc[3] += t - t_mark; t_mark = t; }
     }
     // ---- store ------------------------------------------------------------
+    if (S > 1) {
+      // parts leave FP64 partial sums; the last part to finish adds them in
+      // part order (deterministic) and stores the record
+      double* pp = g.partial + ((size_t)rec * S + part) * 20;
+      if (lane < 20) pp[lane] = racc[lane];
+      __threadfence();
+      unsigned int old = 0;
+      if (lane == 0) old = atomicAdd(&g.done[rec], 1u);
+      old = __shfl(old, 0, kWave);
+      if (old != (unsigned int)(S - 1)) continue;
+      __threadfence();
+      if (lane < 20) {
+        double sum = 0.0;
+        for (int k = 0; k < S; k++)
+          sum += __hip_atomic_load(g.partial + ((size_t)rec * S + k) * 20 + lane, __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_AGENT);
+        racc[lane] = sum;
+      }
+      __syncthreads();
+    }
     if (lane < 2) g.value[2 * rec + lane] = racc[lane] / (double)N;
     if (lane < 18) {
       int c = lane / 9, k = lane % 9;
@@ -678,6 +708,11 @@ hipError_t launch_record(const RecordArgs& a, int stack, bool count, bool f64, i
 
 hipError_t launch_reset(unsigned int* q, hipStream_t s) {
   hipLaunchKernelGGL(reset_queue_kernel, dim3(1), dim3(64), 0, s, q);
+  return hipGetLastError();
+}
+
+hipError_t launch_zero_u32(unsigned int* p, int n, hipStream_t s) {
+  if (n > 0) hipLaunchKernelGGL(zero_u32_kernel, dim3((n + 255) / 256), dim3(256), 0, s, p, n);
   return hipGetLastError();
 }
 

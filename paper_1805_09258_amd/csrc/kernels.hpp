@@ -35,6 +35,9 @@ struct RecordArgs {
   double* hess;
   const int* order;        // queue order or nullptr (identity)
   unsigned int* queue;     // [0] next queue slot, [1] invalid records
+  int splits;              // wavefronts per record (each owns a range of rows)
+  double* partial;         // [P][splits][20] partial sums (splits > 1)
+  unsigned int* done;      // [P] parts finished (splits > 1; zero before launch)
   unsigned long long* counters;
 };
 
@@ -44,6 +47,9 @@ int record_occupancy(int stack, bool count, bool f64, size_t lds);
 hipError_t prepare_record(int stack, bool count, bool f64, size_t lds);
 hipError_t launch_record(const RecordArgs& a, int stack, bool count, bool f64, int grid, size_t lds, hipStream_t s);
 hipError_t launch_reset(unsigned int* q, hipStream_t s);
+hipError_t launch_zero_u32(unsigned int* p, int n, hipStream_t s);
+constexpr int kMaxSplits = 8;        // wavefronts per record at most
+constexpr int kSplitMaxRecords = 16384;  // batches up to this size may split records
 hipError_t launch_order(const int* nth, const int* nph, int P, unsigned int* hist, unsigned int* cursor, int* order,
                         hipStream_t s);
 hipError_t launch_radius(const double* value, const double* hess, int P, float eps, float r_min, float r_max, float* R,

@@ -12,7 +12,8 @@ insertion rule of Sec. 6).
 * learned: the same rounds decided by a 64-ray probe and the MLP's predicted
   radius (cheap), then full records at the accepted points in one launch.
   The records are the judge: with their true radii the candidates are covered
-  again, and whatever is left uncovered goes through plain rounds (the
+  again; the candidates left uncovered go through another learned pass with a
+  smaller safety factor, and the last few through plain rounds (the
   fallback), so the final cache meets the same validity rule as the plain
   one.
 
@@ -143,8 +144,9 @@ class Placer:
         n = self.ctx.records(pos, value, grad, hess, ws, nth, nph, self.cfg.n_phi, self._next_id)
         self._next_id += n
 
-    def _gather(self):
-        rc.rc_place_gather(self.cand, None, self.covered, self.state, self.bidx, self.bpos, self.bR, self.cfg.batch,
+    def _gather(self, batch=None):
+        b = self.cfg.batch if batch is None else min(int(batch), self.cfg.batch)
+        rc.rc_place_gather(self.cand, None, self.covered, self.state, self.bidx, self.bpos, self.bR, b,
                            order=self.order)
         return int(self.state[4].item())
 
@@ -152,12 +154,12 @@ class Placer:
         c = self.cands
         rc.rc_place_cover_grid(self.cand, c.dims, c.lo, c.cell, self.covered, self.state, self.acc, self.accR)
 
-    def _plain_rounds(self):
+    def _plain_rounds(self, batch=None):
         """Rounds with full records until every candidate is decided."""
         cfg = self.cfg
         rounds = records = 0
         while True:
-            m = self._gather()
+            m = self._gather(batch)
             if m == 0:
                 break
             self._records(self.bpos[:m], self.bval, self.bgrad, self.bhess, self.bws, self.nth, self.nph)
@@ -174,24 +176,22 @@ class Placer:
         return PlacementResult(self.accpos[:K], self.cval[:K], self.cgrad[:K], self.accR[:K], K, stats)
 
     # -- pipelines ------------------------------------------------------------
-    def plain(self):
+    def plain(self, batch=None):
         import torch
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         self._reset()
-        rounds, records = self._plain_rounds()
+        rounds, records = self._plain_rounds(batch)
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
-        res = self._result({"seconds": dt, "rounds": rounds, "records": records})
+        res = self._result({"seconds": dt, "rounds": rounds, "records": records,
+                            "batch": self.cfg.batch if batch is None else min(int(batch), self.cfg.batch)})
         res.stats["accepted"] = res.K
         return res
 
-    def learned(self, mlp: Mlp, safety: float):
-        import torch
-        cfg, c = self.cfg, self.cands
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        self._reset()
+    def _learned_rounds(self, mlp: Mlp, safety: float):
+        """Rounds decided by the probe and the predicted radius (no records)."""
+        cfg = self.cfg
         rounds = probes = 0
         while True:
             m = self._gather()
@@ -204,34 +204,70 @@ class Placer:
             self._cover_last_round()
             rounds += 1
             probes += m
-        K1 = int(self.state[1].item())
-        t1 = time.perf_counter()
-        # full records at the predicted placement, in one launch
-        if self._big is None or self._big[0].shape[0] < K1:
-            n = max(K1, 1)
-            self._big = (torch.zeros((n, 2, 6), dtype=torch.float64, device=self.dev),
-                         torch.zeros(rc.rc_workspace_size(n), dtype=torch.uint8, device=self.dev),
-                         torch.full((n,), cfg.n_theta, dtype=torch.int32, device=self.dev),
-                         torch.full((n,), cfg.n_phi, dtype=torch.int32, device=self.dev))
+        return rounds, probes
+
+    def _judge(self, k0, k1):
+        """Full records at accepted points k0..k1 in one launch, their true radii
+        in place of the predicted ones, and every candidate covered again by
+        the whole cache.  Returns the number of candidates left uncovered."""
+        import torch
+        cfg, c = self.cfg, self.cands
+        n = k1 - k0
+        if self._big is None or self._big[0].shape[0] < n:
+            m = max(n, 1)
+            self._big = (torch.zeros((m, 2, 6), dtype=torch.float64, device=self.dev),
+                         torch.zeros(rc.rc_workspace_size(m), dtype=torch.uint8, device=self.dev),
+                         torch.full((m,), cfg.n_theta, dtype=torch.int32, device=self.dev),
+                         torch.full((m,), cfg.n_phi, dtype=torch.int32, device=self.dev))
         hess, ws, nth, nph = self._big
-        self._records(self.accpos[:K1], self.cval, self.cgrad, hess, ws, nth, nph)
-        # the judge: true radii replace the predicted ones, the candidates are covered again
-        rc.rc_radius(self.cval[:K1], hess[:K1], cfg.eps, cfg.r_min, cfg.r_max, self.accR[:K1])
+        self._records(self.accpos[k0:k1], self.cval[k0:k1], self.cgrad[k0:k1], hess, ws, nth, nph)
+        rc.rc_radius(self.cval[k0:k1], hess[:n], cfg.eps, cfg.r_min, cfg.r_max, self.accR[k0:k1])
         self.covered.zero_()
-        rc.rc_place_cover_grid(self.cand, c.dims, c.lo, c.cell, self.covered, None, self.acc, self.accR, 0, K1)
+        rc.rc_place_cover_grid(self.cand, c.dims, c.lo, c.cell, self.covered, None, self.acc, self.accR, 0, k1)
         self.state[0] = 0
+        return int((self.covered == 0).sum().item())
+
+    def learned(self, mlp: Mlp, safety: float, passes: int = 3, shrink: float = 0.5, plain_below: int = 64):
+        """Learned placement: probe-decided rounds, records at the accepted
+        points, the judge; while candidates stay uncovered (and passes remain),
+        another learned pass over them with the safety factor shrunk; plain
+        rounds for whatever is left (fewer than plain_below candidates, or
+        after the last pass)."""
+        import torch
         torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        self._reset()
+        s = safety
+        rounds = probes = 0
+        k0 = 0
+        history = []
+        t_rounds = t_records = 0.0
+        uncovered = self.cands.n
+        for p in range(passes):
+            ta = time.perf_counter()
+            r, pr = self._learned_rounds(mlp, s)
+            k1 = int(self.state[1].item())
+            tb = time.perf_counter()
+            uncovered = self._judge(k0, k1)
+            tc = time.perf_counter()
+            t_rounds += tb - ta
+            t_records += tc - tb
+            rounds += r
+            probes += pr
+            history.append({"safety": s, "records": k1 - k0, "uncovered_after": uncovered})
+            k0 = k1
+            s *= shrink
+            if uncovered < plain_below:
+                break
         t2 = time.perf_counter()
-        uncovered = int((self.covered == 0).sum().item())
-        # fallback: plain rounds over whatever the true radii leave uncovered
         f_rounds, f_records = self._plain_rounds()
         torch.cuda.synchronize()
         t3 = time.perf_counter()
-        res = self._result({"seconds": t3 - t0, "seconds_rounds": t1 - t0, "seconds_records_judge": t2 - t1,
+        res = self._result({"seconds": t3 - t0, "seconds_rounds": t_rounds, "seconds_records_judge": t_records,
                             "seconds_fallback": t3 - t2, "rounds": rounds, "probes": probes,
-                            "records_learned": K1, "uncovered_after_judge": uncovered,
+                            "records_learned": k0, "passes": history, "uncovered_after_judge": uncovered,
                             "fallback_rounds": f_rounds, "fallback_records": f_records})
-        res.stats["records"] = K1 + f_records
+        res.stats["records"] = k0 + f_records
         res.stats["accepted"] = res.K
         return res
 
@@ -375,11 +411,14 @@ def training_set(seeds, P, cfg: CacheConfig, device):
 
 
 def compare(device, train_seeds=range(1000, 1020), P_train=10_000, val_seed=1099, eval_seed=4242, grid_n=128,
-            n_test=20_000, safeties=(1.0, 0.8), epochs=20, cfg: CacheConfig | None = None, log=None):
-    """Train the radius MLP, then place caches over grid_n^3 candidates of a
-    held-out scene with the plain and the learned pipeline (each timed after
-    one untimed run) and measure their interpolation error at n_test uniform
-    points against 16384-direction reference records."""
+            n_test=20_000, safeties=(0.8, 1.0, 1.25, 1.5), epochs=20, cfg: CacheConfig | None = None, log=None,
+            plain_batches=(512, 1024, 2048, 4096)):
+    """Train the radius MLP; pick the learned pipeline's safety factor on a
+    validation scene; then place caches over grid_n^3 candidates of a held-out
+    scene with the plain pipeline (at its fastest round size) and the learned
+    pipeline (each timed after one untimed run) and measure their
+    interpolation error at n_test uniform points against 16384-direction
+    reference records."""
     import torch
     cfg = cfg or CacheConfig()
     out = {}
@@ -399,6 +438,21 @@ def compare(device, train_seeds=range(1000, 1020), P_train=10_000, val_seed=1099
     out["heldout_mse_net"] = float(((pv - yv) ** 2).mean().item())
     out["heldout_mse_constant"] = float(((yv - y.mean()) ** 2).mean().item())
     del X, y, Xv, yv
+    # safety factor: the fastest learned placement on the validation scene
+    wv = W.make_c4_scene(val_seed, P=1)
+    cv = SceneContext(wv)
+    pv_ = Placer(cv, W.GridCandidates(grid_n // 2, wv.box_lo, wv.box_hi, seed=val_seed + 1), cfg, device)
+    times = {}
+    for sf in safeties:
+        pv_.learned(mlp, sf)
+        times[sf] = pv_.learned(mlp, sf).stats["seconds"]
+    cv.close()
+    del pv_
+    safety = min(times, key=times.get)
+    out["safety_validation_seconds"] = {str(k): v for k, v in times.items()}
+    out["safety"] = safety
+    if log:
+        log("validation placement seconds by safety factor", times, "-> safety", safety)
     # evaluation scene
     we = W.make_c4_scene(eval_seed, P=1)
     ctx = SceneContext(we)
@@ -412,16 +466,20 @@ def compare(device, train_seeds=range(1000, 1020), P_train=10_000, val_seed=1099
     out["reference_noise"] = estimate_error(ref2, ref, q, we.lights)   # two 16384-direction references
     out["no_cache"] = estimate_error(direct, ref, q, we.lights)        # a 1024-direction record per test point
     out["candidates"] = cands.n
-    placer.plain()
-    r = placer.plain()
-    out["plain"] = dict(r.stats, **cache_error(r, q, ref, device, we.lights))
-    if log:
-        log("plain", out["plain"])
-    for s in safeties:
-        placer.learned(mlp, s)
-        r = placer.learned(mlp, s)
-        out[f"learned_s{s}"] = dict(r.stats, safety=s, **cache_error(r, q, ref, device, we.lights))
+    best = None
+    for b in plain_batches:  # the plain pipeline at its best round size
+        placer.plain(b)
+        r = placer.plain(b)
+        st = dict(r.stats, **cache_error(r, q, ref, device, we.lights))
         if log:
-            log(f"learned s={s}", out[f"learned_s{s}"])
+            log(f"plain batch {b}", st)
+        if best is None or st["seconds"] < best["seconds"]:
+            best = st
+    out["plain"] = best
+    placer.learned(mlp, safety)
+    r = placer.learned(mlp, safety)
+    out["learned"] = dict(r.stats, safety=safety, **cache_error(r, q, ref, device, we.lights))
+    if log:
+        log(f"learned s={safety}", out["learned"])
     ctx.close()
     return out

@@ -40,7 +40,8 @@ class rc_point_light(C.Structure):
 
 class rc_params(C.Structure):
     _fields_ = [("ring_step", C.c_float), ("max_rings", C.c_int32), ("max_n_phi", C.c_int32),
-                ("precision", C.c_int32), ("common_random", C.c_int32), ("seed", C.c_uint64),
+                ("precision", C.c_int32), ("common_random", C.c_int32), ("splits", C.c_int32),
+                ("seed", C.c_uint64),
                 ("rec_base", C.c_int64),
                 ("counters", C.c_void_p)]
 
@@ -204,9 +205,11 @@ def rc_workspace_errors(ws, stream=None):
     return _check(lib().rc_workspace_errors(_ptr(ws), _stream(stream)))
 
 
-def make_params(ring_step, max_rings, max_n_phi, seed, rec_base=0, precision=0, counters=None, common_random=False):
+def make_params(ring_step, max_rings, max_n_phi, seed, rec_base=0, precision=0, counters=None, common_random=False,
+                splits=0):
     return rc_params(float(ring_step), int(max_rings), int(max_n_phi), int(precision), int(bool(common_random)),
-                     int(seed) & (2**64 - 1), int(rec_base), None if counters is None else counters.data_ptr())
+                     int(splits), int(seed) & (2**64 - 1), int(rec_base),
+                     None if counters is None else counters.data_ptr())
 
 
 def rc_records(scene, sigma_s, sigma_a, lights, pos, n_theta, n_phi, params, value, grad, hess, workspace,
@@ -401,12 +404,12 @@ class DeviceWorkload:
 
 
 def compute_records(scene: Scene, dw: DeviceWorkload, batched=False, use_graph=False, tile=-1, order=None,
-                    precision=0, counters=None, out=None, workspace=None, stream=None):
+                    precision=0, counters=None, out=None, workspace=None, stream=None, splits=0):
     """Records for every point of a DeviceWorkload; returns (value, grad, hess, workspace)."""
     w = dw.w
     value, grad, hess = out if out is not None else dw.outputs()
     ws = workspace if workspace is not None else dw.workspace()
-    prm = make_params(w.ring_step, w.max_rings, dw.max_n_phi, w.seed, 0, precision, counters)
+    prm = make_params(w.ring_step, w.max_rings, dw.max_n_phi, w.seed, 0, precision, counters, splits=splits)
     if batched:
         rc_records_batched(scene.handle, w.sigma_s, w.sigma_a, w.lights, dw.pos, dw.n_theta, dw.n_phi, prm, order,
                            use_graph, tile, value, grad, hess, ws, stream)

@@ -91,6 +91,46 @@ def test_c1_all_records_match_oracle(dev):
     assert int(cnt[3].item()) == int(ref["stats"][:, 1].sum() + ref["stats"][:, 2].sum())
 
 
+@pytest.mark.parametrize("splits", [1, 2, 3, 8])
+def test_records_split_over_wavefronts_match_oracle(dev, splits):
+    """A record's strata rows split over several wavefronts (each recomputing
+    its boundary row) give the oracle's record, with the same traced rays and
+    terms, and agree with the unsplit record to FP64 rounding."""
+    w = W.make_c1(P=40)
+    sc = rc.Scene.from_workload(w)
+    dw = rc.DeviceWorkload(w)
+    cnt = torch.zeros(8, dtype=torch.int64, device=dev)
+    v, g, h, ws = rc.compute_records(sc, dw, batched=True, counters=cnt, splits=splits)
+    v1, g1, h1, _ = rc.compute_records(sc, dw, batched=True, splits=1)
+    torch.cuda.synchronize()
+    assert rc.rc_workspace_errors(ws) == 0
+    ref = O.records_for(w)
+    a = (v.cpu().numpy(), g.cpu().numpy(), h.cpu().numpy())
+    assert_parity(*a, ref, f"C1, {splits} parts")
+    assert int(cnt[0].item()) == int(ref["stats"][:, 0].sum())
+    assert int(cnt[3].item()) == int(ref["stats"][:, 1].sum() + ref["stats"][:, 2].sum())
+    for x, y in zip(a, (v1.cpu().numpy(), g1.cpu().numpy(), h1.cpu().numpy())):
+        np.testing.assert_allclose(x, y, rtol=1e-12, atol=1e-12 * np.abs(y).max())
+    sc.close()
+
+
+def test_small_batches_split_automatically_on_the_c2_scene(dev):
+    w = W.make_c2().subset(np.arange(37))
+    sc = rc.Scene.from_workload(w)
+    dw = rc.DeviceWorkload(w)
+    v, g, h, ws = rc.compute_records(sc, dw, batched=True, use_graph=False)
+    torch.cuda.synchronize()
+    assert rc.rc_workspace_errors(ws) == 0
+    idx = np.arange(0, 37, 3)
+    ref = O.records_for(w, idx)
+    assert_parity(v.cpu().numpy()[idx], g.cpu().numpy()[idx], h.cpu().numpy()[idx], ref, "C2 scene, 37 records")
+    with pytest.raises(rc.RCError):
+        big = W.make_c1(P=16385)
+        dwb = rc.DeviceWorkload(big)
+        rc.compute_records(rc.Scene.from_workload(big), dwb, splits=2)
+    sc.close()
+
+
 def test_c2_full_size_sampled_records_match_oracle(dev):
     """C2 at its full size (10k records, 1024 directions, 10k-triangle soup in a
     closed room, 4 lights) in the benchmark's launch configuration (batched

@@ -74,10 +74,10 @@ def test_both_pipelines_build_valid_caches_and_learned_needs_fewer_record_rounds
     assert rl.K > 0 and _all_covered(cands, rl).all()
     Rl = rl.R.cpu().numpy()
     assert np.all((Rl >= cfg.r_min) & (Rl <= cfg.r_max))
-    # the network decides the rounds; full records run in one launch plus at
-    # most a few fallback rounds, against one record launch per plain round
+    # the network decides the rounds: probes pick the points, and fewer full
+    # records are computed than the plain rounds compute
     assert rl.stats["probes"] >= rl.stats["records_learned"]
-    assert 1 + rl.stats["fallback_rounds"] < rp.stats["rounds"]
+    assert rl.stats["records"] < rp.stats["records"]
     ctx.close()
 
 
