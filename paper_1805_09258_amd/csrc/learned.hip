@@ -65,10 +65,14 @@ template <int STACK>
 __global__ __launch_bounds__(64) void probe_kernel(ProbeArgs g) {
   __shared__ int stack[STACK * kWave];
   __shared__ float Ls_row[kWave];
+  __shared__ float sw[3][kWave], st_[kWave];  // each direction and its hit distance
+  __shared__ int scode[kWave];                  // (triangle << 1) | front, or -1
+  __shared__ int vbits[kWave + 1];              // unblocked lights per hit; [64]: from x
   const int lane = threadIdx.x;
   int* stk = stack + lane;
   TraceCount tc;
   const float mu = g.sigma_s + g.sigma_a;
+  const int nx = g.n_lights < 4 ? g.n_lights : 4;  // lights whose visibility from x is a feature
   for (int c = blockIdx.x; c < g.C; c += gridDim.x) {
     const float3 x = make_float3(g.cand[3 * c], g.cand[3 * c + 1], g.cand[3 * c + 2]);
     const uint64_t key = record_key(g.seed, (uint64_t)(g.id_base + (g.common_random ? 0 : c)));
@@ -80,8 +84,136 @@ __global__ __launch_bounds__(64) void probe_kernel(ProbeArgs g) {
     trace_closest<false>(g.nodes, g.tris, x, w, stk, id, t, fr, tc);
     const bool hit = id >= 0;
     if (!hit) t = box_exit(x, w, g.box_lo, g.box_hi);
+    sw[0][lane] = w.x;
+    sw[1][lane] = w.y;
+    sw[2][lane] = w.z;
+    st_[lane] = t;
+    scode[lane] = hit ? ((id << 1) | (fr ? 1 : 0)) : -1;
+    vbits[lane] = 0;
+    if (lane == 0) vbits[kWave] = 0;
+    __syncthreads();
+    // Shadow segments, as a list of tasks: (direction k, light l) for
+    // k + 64 l < 64 L (hit point to light l, skipped when the hit's lit side
+    // faces away), then (x, light l) for l < min(L, 4).  Each loop iteration
+    // advances every busy lane by one node or one triangle; a lane whose
+    // segment is resolved takes the next task, so lanes stay busy while
+    // segments of different lengths finish.
+    {
+      const int total = kWave * g.n_lights + nx;
+      int next = 0;
+      bool active = false;
+      int node = 0, sp = 0, lf = 0, ln = 0, skip = -1, dst = 0, bit = 0;
+      float3 o = make_float3(0.f, 0.f, 0.f), d = o, inv = o, oi = o;
+      float dd = 0.f;
+      while (true) {
+        const uint64_t idle = __ballot(!active);
+        if (next < total && (__popcll(idle) >= 8 || idle == ~0ull)) {
+          if (!active) {
+            const int task = next + __popcll(idle & __lanemask_lt());
+            if (task < total) {
+              active = true;
+              if (task < kWave * g.n_lights) {
+                const int k = task & (kWave - 1), l = task >> 6;
+                const int code = scode[k];
+                const float4 L = g.lights[l];
+                if (code < 0) {
+                  active = false;
+                } else {
+                  const float3 wk = make_float3(sw[0][k], sw[1][k], sw[2][k]);
+                  o = axpy3(st_[k], wk, x);
+                  d = make_float3(L.x - o.x, L.y - o.y, L.z - o.z);
+                  skip = code >> 1;
+                  const float4 sh = g.shade[skip];
+                  const float nsign = (code & 1) ? 1.f : -1.f;
+                  const float cs = nsign * dot3(make_float3(sh.x, sh.y, sh.z), d) / sqrtf(dot3(d, d));
+                  if (!(cs > 0.f)) active = false;
+                  dst = k;
+                  bit = 1 << l;
+                }
+              } else {
+                const int l = task - kWave * g.n_lights;
+                const float4 L = g.lights[l];
+                o = x;
+                d = make_float3(L.x - x.x, L.y - x.y, L.z - x.z);
+                skip = -1;
+                dst = kWave;
+                bit = 1 << l;
+              }
+              dd = dot3(d, d);
+              ray_inv(d, o, inv, oi);
+              node = 0;
+              sp = 0;
+              ln = 0;
+            }
+          }
+          next += __popcll(idle);
+        }
+        if (__ballot(active) == 0ull) {
+          if (next >= total) break;
+          continue;
+        }
+        if (active) {
+          bool done = false, blocked = false;
+          const float4* src = (ln > 0) ? (g.tris + 3 * lf) : (g.nodes + 4 * node);
+          const float4 q0 = src[0], q1 = src[1], q2 = src[2], q3 = src[3];
+          if (ln > 0) {
+            float th;
+            bool fh;
+            if (__float_as_int(q0.w) != skip && hit_triangle(o, d, dd, q0, q1, q2, 1e-4f, 1.0f, th, fh)) {
+              done = true;
+              blocked = true;
+            } else {
+              lf++;
+              ln--;
+              if (ln == 0) {
+                if (sp == 0) {
+                  done = true;
+                } else {
+                  const int cc = stk[--sp * kWave];
+                  if (cc < 0) {
+                    lf = leaf_first(cc);
+                    ln = leaf_count(cc);
+                  } else {
+                    node = cc;
+                  }
+                }
+              }
+            }
+          } else {
+            const float ta = slab(q0.x, q0.y, q0.z, q0.w, q2.x, q2.y, inv, oi, 0.0f, 1.0f);
+            const float tb = slab(q1.x, q1.y, q1.z, q1.w, q2.z, q2.w, inv, oi, 0.0f, 1.0f);
+            const int ca = __float_as_int(q3.x), cb = __float_as_int(q3.y);
+            const bool ha = ta < __builtin_huge_valf(), hb = tb < __builtin_huge_valf();
+            int nxn;
+            if (ha && hb) {
+              nxn = ta <= tb ? ca : cb;
+              stk[sp++ * kWave] = ta <= tb ? cb : ca;
+            } else if (ha || hb) {
+              nxn = ha ? ca : cb;
+            } else {
+              nxn = sp == 0 ? 0x7fffffff : stk[--sp * kWave];
+            }
+            if (nxn == 0x7fffffff) {
+              done = true;
+            } else if (nxn < 0) {
+              lf = leaf_first(nxn);
+              ln = leaf_count(nxn);
+            } else {
+              node = nxn;
+            }
+          }
+          if (done) {
+            active = false;
+            if (!blocked) atomicOr(&vbits[dst], bit);
+          }
+        }
+      }
+    }
+    __syncthreads();
+    // radiance of each hit: emission plus the unblocked lights, in order
     float Ls = hit ? g.emission[id] : 0.f;
     if (hit) {
+      const int bits = vbits[lane];
       const float3 y = axpy3(t, w, x);
       const float4 sh = g.shade[id];
       const float nsign = fr ? 1.f : -1.f;
@@ -90,7 +222,7 @@ __global__ __launch_bounds__(64) void probe_kernel(ProbeArgs g) {
         const float3 seg = make_float3(L.x - y.x, L.y - y.y, L.z - y.z);
         const float dist = sqrtf(dot3(seg, seg));
         const float cs = nsign * dot3(make_float3(sh.x, sh.y, sh.z), seg) / dist;
-        if (cs > 0.f && !occluded<false>(g.nodes, g.tris, y, seg, id, stk, tc))
+        if (cs > 0.f && ((bits >> l) & 1))
           Ls += sh.w * (float)(1.0 / kPi) * L.w * cs * expf(-mu * dist) / (dist * dist);
       }
     }
@@ -99,11 +231,11 @@ __global__ __launch_bounds__(64) void probe_kernel(ProbeArgs g) {
     const float Lt = expf(-mu * dist) * Ls;          // radiance arriving at x
     // direct light from x: visibility and unshadowed irradiance proxy
     float vis = 0.f, dirl = 0.f;
-    if (lane < g.n_lights && lane < 4) {
+    if (lane < nx) {
       const float4 L = g.lights[lane];
       const float3 seg = make_float3(L.x - x.x, L.y - x.y, L.z - x.z);
       const float d2 = dot3(seg, seg);
-      vis = occluded<false>(g.nodes, g.tris, x, seg, -1, stk, tc) ? 0.f : 1.f;
+      vis = ((vbits[kWave] >> lane) & 1) ? 1.f : 0.f;
       dirl = logf(L.w * expf(-mu * sqrtf(d2)) / d2 + 1e-6f);
     }
     // neighbour contrast along phi within the strata row
