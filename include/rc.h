@@ -43,6 +43,8 @@ extern "C" {
 #define RC_MAX_LIGHTS 16
 #define RC_MAX_RINGS 64
 #define RC_MAX_NPHI 256
+/* int32 words of the placement state (5 counters + 4096 batch status words) */
+#define RC_PLACE_STATE_INTS 4101
 
 typedef struct rc_scene rc_scene;
 
@@ -297,8 +299,9 @@ int rc_mlp_train_step(void* params, float* state, const float* X, const float* t
  * inserts a cache point where no cached point is valid).  The distance test is
  * ((dx*dx + dy*dy) + dz*dz) < R*R in FP32, dx = candidate - accepted point.
  * order device int32[C] (a permutation: the visiting order) or NULL (index
- * order).  state device int32[5] (zero to start): cursor, accepted count,
- * first/count accepted in the last round, gathered batch size.  covered
+ * order).  state device int32[RC_PLACE_STATE_INTS] (zero to start): cursor,
+ * accepted count, first/count accepted in the last round, gathered batch
+ * size, then one status word per gathered candidate.  covered
  * device uint8[C] (zero to start; 1 = decided or covered).
  *   gather: the next `batch` (1..4096) undecided candidates after the cursor
  *           in visiting order: indices batch_idx, positions batch_pos

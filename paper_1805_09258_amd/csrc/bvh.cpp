@@ -1,5 +1,5 @@
 // bvh.cpp -- host builder of the flat binary BVH traversed by the record
-// kernel.  Binned surface-area heuristic (16 bins per axis over centroid
+// kernel.  Binned surface-area heuristic (32 bins per axis over centroid
 // bounds), leaves of at most kLeafMax triangles, object-median fallback when
 // the heuristic finds no split or the tree gets deep.  The paper relies on
 // Embree for tracing (Sec. 6) and describes no acceleration structure; this
@@ -120,7 +120,7 @@ struct Builder {
       return mid;
     };
     if (!(ext > 0.f) || depth > 40) return median(axis);
-    constexpr int NB = 16;
+    constexpr int NB = 32;
     double best = std::numeric_limits<double>::infinity();
     int best_axis = -1, best_bin = -1;
     for (int ax = 0; ax < 3; ax++) {

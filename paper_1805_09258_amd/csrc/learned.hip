@@ -729,6 +729,7 @@ __global__ __launch_bounds__(kPlaceThreads) void place_gather_kernel(const float
   __shared__ int wtot[kPlaceThreads / kWave];
   __shared__ int s_stop;
   const int t = threadIdx.x, lane = t & (kWave - 1), wv = t / kWave;
+  for (int j = t; j < kPlaceMaxBatch; j += kPlaceThreads) state[kPlaceStatus + j] = 0;  // all undecided
   int cursor = state[0];
   int have = 0;
   while (cursor < C && have < batch) {
@@ -776,6 +777,45 @@ __global__ __launch_bounds__(kPlaceThreads) void place_gather_kernel(const float
   }
 }
 
+// One pass of the fixed point below, spread over many workgroups: every
+// undecided entry j scans the entries i < j (positions staged in LDS) and is
+// rejected by an accepted coverer, accepted when all its coverers are
+// rejected, else left undecided.  Status words (state[kPlaceStatus + j]) only
+// ever go from undecided to decided, so passes racing with each other are
+// harmless.
+__global__ __launch_bounds__(256) void place_resolve_kernel(const float* __restrict__ cand,
+                                                            const int* __restrict__ batch_idx,
+                                                            const float* __restrict__ batch_R,
+                                                            int* __restrict__ state) {
+  __shared__ float4 ps[kPlaceMaxBatch];
+  const int m = min(state[4], kPlaceMaxBatch);
+  const int j0 = blockIdx.x * 256;
+  if (j0 >= m) return;
+  const int jn = min(m, j0 + 256);  // entries i < jn are read
+  for (int i = threadIdx.x; i < jn; i += 256) {
+    const int c = batch_idx[i];
+    ps[i] = make_float4(cand[3 * c], cand[3 * c + 1], cand[3 * c + 2], batch_R[i]);
+  }
+  __syncthreads();
+  const int j = j0 + threadIdx.x;
+  volatile int* stv = state + kPlaceStatus;
+  if (j >= m || stv[j] != 0) return;
+  const float4 pj = ps[j];
+  int verdict = 1;
+  for (int i = 0; i < j; i++) {
+    const float4 pi = ps[i];
+    if (within(pj.x, pj.y, pj.z, pi.x, pi.y, pi.z, pi.w)) {
+      const int si = stv[i];
+      if (si == 1) {
+        verdict = 2;
+        break;
+      }
+      if (si == 0) verdict = 0;
+    }
+  }
+  if (verdict != 0) stv[j] = verdict;
+}
+
 // Batch entry j is accepted iff no accepted entry i < j covers it.  Each pass
 // decides every entry whose covering predecessors are all decided: rejected
 // as soon as one accepted predecessor covers it, accepted once every covering
@@ -797,7 +837,7 @@ __global__ __launch_bounds__(kPlaceThreads) void place_accept_kernel(
   for (int j = t; j < m; j += kPlaceThreads) {
     const int c = batch_idx[j];
     ps[j] = make_float4(cand[3 * c], cand[3 * c + 1], cand[3 * c + 2], batch_R[j]);
-    st[j] = 0;
+    st[j] = (unsigned char)state[kPlaceStatus + j];  // decided by the resolve passes, or 0
   }
   for (;;) {
     __syncthreads();
@@ -1070,6 +1110,11 @@ hipError_t launch_place_gather(const float* cand, const float* radius, const int
 hipError_t launch_place_accept(const float* cand, const int* batch_idx, const float* batch_R, unsigned char* covered,
                                int* state, int* accepted, float* accepted_R, float* accepted_pos, const double* bval,
                                const double* bgrad, double* cval, double* cgrad, hipStream_t s) {
+  // a few wide passes decide almost every entry; the one-workgroup kernel
+  // finishes whatever chains of coverers remain and appends the result
+  for (int pass = 0; pass < kPlacePasses; pass++)
+    hipLaunchKernelGGL(place_resolve_kernel, dim3(kPlaceMaxBatch / 256), dim3(256), 0, s, cand, batch_idx, batch_R,
+                       state);
   hipLaunchKernelGGL(place_accept_kernel, dim3(1), dim3(kPlaceThreads), 0, s, cand, batch_idx, batch_R, covered, state,
                      accepted, accepted_R, accepted_pos, bval, bgrad, cval, cgrad);
   return hipGetLastError();

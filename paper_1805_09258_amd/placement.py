@@ -114,7 +114,7 @@ class Placer:
         self.cand = t(cands.pos)
         self.order = t(cands.order)
         self.covered = torch.zeros(C, dtype=torch.uint8, device=device)
-        self.state = torch.zeros(5, dtype=torch.int32, device=device)
+        self.state = torch.zeros(rc.RC_PLACE_STATE_INTS, dtype=torch.int32, device=device)
         self.bidx = torch.zeros(B, dtype=torch.int32, device=device)
         self.bpos = torch.zeros((B, 3), dtype=torch.float32, device=device)
         self.bR = torch.zeros(B, dtype=torch.float32, device=device)

@@ -22,6 +22,7 @@ LIB_PATH = Path(os.environ.get("RC_LIBRARY", str(_PKG / "librc.so")))
 
 RC_OK, RC_EINVAL, RC_ENOMEM, RC_EDEVICE, RC_ENODEV = 0, -1, -2, -3, -4
 RC_MAX_LIGHTS, RC_MAX_RINGS, RC_MAX_NPHI = 16, 64, 256
+RC_PLACE_STATE_INTS = 4101  # placement state: 5 counters + one status word per gathered candidate
 
 
 class RCError(RuntimeError):

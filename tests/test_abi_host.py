@@ -194,3 +194,12 @@ def test_bvh_padding_covers_fp32_hit_error():
         worst = max(worst, max(h, out) * sinb)
     assert hit.sum() > 10000
     assert worst < 2e-4 / 5, worst
+
+
+def test_binding_constants_match_header():
+    import re
+    text = (Path(__file__).resolve().parent.parent / "include" / "rc.h").read_text()
+    defs = dict(re.findall(r"#define (RC_[A-Z_]+) (-?\d+)", text))
+    assert int(defs["RC_PLACE_STATE_INTS"]) == rc.RC_PLACE_STATE_INTS
+    assert (int(defs["RC_MAX_LIGHTS"]), int(defs["RC_MAX_RINGS"]), int(defs["RC_MAX_NPHI"])) == (
+        rc.RC_MAX_LIGHTS, rc.RC_MAX_RINGS, rc.RC_MAX_NPHI)

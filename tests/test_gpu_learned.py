@@ -277,7 +277,7 @@ def gpu_greedy(cand, R, batch, dev):
     tc = torch.as_tensor(cand, device=dev)
     tR = torch.as_tensor(R, device=dev)
     covered = torch.zeros(C, dtype=torch.uint8, device=dev)
-    state = torch.zeros(5, dtype=torch.int32, device=dev)
+    state = torch.zeros(rc.RC_PLACE_STATE_INTS, dtype=torch.int32, device=dev)
     bi = torch.zeros(batch, dtype=torch.int32, device=dev)
     bp = torch.zeros((batch, 3), device=dev)
     bR = torch.zeros(batch, device=dev)
@@ -314,7 +314,7 @@ def test_greedy_cover_rejects_bad_batch(dev):
     t = torch.zeros((4, 3), device=dev)
     with pytest.raises(rc.RCError):
         rc.rc_place_gather(t, None, torch.zeros(4, dtype=torch.uint8, device=dev),
-                           torch.zeros(5, dtype=torch.int32, device=dev), torch.zeros(5000, dtype=torch.int32,
+                           torch.zeros(rc.RC_PLACE_STATE_INTS, dtype=torch.int32, device=dev), torch.zeros(5000, dtype=torch.int32,
                                                                                       device=dev),
                            torch.zeros((5000, 3), device=dev), torch.zeros(5000, device=dev), 5000)
 
@@ -354,7 +354,7 @@ def test_greedy_cover_in_visiting_order_equals_oracle(dev, C, batch, seed):
     order = rng.permutation(C).astype(np.int32)
     tc, tR, to = (torch.as_tensor(a, device=dev) for a in (cand, R, order))
     covered = torch.zeros(C, dtype=torch.uint8, device=dev)
-    state = torch.zeros(5, dtype=torch.int32, device=dev)
+    state = torch.zeros(rc.RC_PLACE_STATE_INTS, dtype=torch.int32, device=dev)
     bi = torch.zeros(batch, dtype=torch.int32, device=dev)
     bp = torch.zeros((batch, 3), device=dev)
     bR = torch.zeros(batch, device=dev)
@@ -384,7 +384,7 @@ def test_accept_copies_records_of_accepted_slots(dev):
     R = np.full(C, 0.15, np.float32)
     tc, tR = torch.as_tensor(cand, device=dev), torch.as_tensor(R, device=dev)
     covered = torch.zeros(C, dtype=torch.uint8, device=dev)
-    state = torch.zeros(5, dtype=torch.int32, device=dev)
+    state = torch.zeros(rc.RC_PLACE_STATE_INTS, dtype=torch.int32, device=dev)
     bi = torch.zeros(B, dtype=torch.int32, device=dev)
     bp = torch.zeros((B, 3), device=dev)
     bR = torch.zeros(B, device=dev)
