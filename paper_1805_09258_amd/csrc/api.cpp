@@ -39,11 +39,17 @@ int fail(int code, const char* fmt, ...) {
 
 bool finite3(const float* v) { return std::isfinite(v[0]) && std::isfinite(v[1]) && std::isfinite(v[2]); }
 
+// One record-kernel launch of a batched call.
+struct Launch {
+  rc::RecordArgs args;
+  int grid;
+  size_t lds;
+};
+
 struct GraphCache {
   bool valid = false;
-  rc::RecordArgs args{};
-  int grid = 0, stack = 0;
-  size_t lds = 0;
+  std::vector<Launch> plan;
+  int stack = 0;
   hipStream_t stream = nullptr;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
@@ -84,8 +90,11 @@ struct rc_scene {
 
 namespace {
 
+// queue area (256 bytes): [0] next item, [1] invalid records, [2..6] next item
+// of each n_phi class launch, [16..25] class ranges [lo, hi)
 constexpr size_t kWsQueue = 0, kWsHist = 256, kWsCursor = 256 + 4 * rc::kOrderBuckets,
                  kWsOrder = 256 + 8 * rc::kOrderBuckets;
+constexpr int kQClassNext = 2, kQClassRange = 16;
 // after the queue order: per-record part counters, then per-part partial sums
 size_t ws_split_offset(int64_t P) { return (kWsOrder + 4 * (size_t)std::max<int64_t>(P, 0) + 255) & ~size_t(255); }
 size_t ws_partial_offset(int64_t Pm) { return (4 * (size_t)Pm + 255) & ~size_t(255); }
@@ -206,10 +215,22 @@ int plan(const rc_scene* s, const rc_params* p, int64_t P, int tile, int& stack,
   return RC_OK;
 }
 
+hipError_t run_plan(const std::vector<Launch>& plan, int stack, hipStream_t st) {
+  const rc::RecordArgs& a0 = plan.front().args;
+  hipError_t e = rc::launch_reset(a0.queue, st);
+  if (e == hipSuccess && plan.size() > 1) e = rc::launch_zero_u32(a0.queue + kQClassNext, rc::kOrderClasses, st);
+  if (e == hipSuccess && a0.splits > 1) e = rc::launch_zero_u32(a0.done, a0.P, st);
+  for (const Launch& l : plan) {
+    if (e != hipSuccess) break;
+    e = rc::launch_record(l.args, stack, l.args.counters != nullptr, l.args.precision == 1, l.grid, l.lds, st);
+  }
+  return e;
+}
+
 int launch_direct(rc_scene* s, const rc::RecordArgs& a, int stack, size_t lds, int grid, hipStream_t st) {
-  RC_HIP(rc::launch_reset(a.queue, st));
-  if (a.splits > 1) RC_HIP(rc::launch_zero_u32(a.done, a.P, st));
-  RC_HIP(rc::launch_record(a, stack, a.counters != nullptr, a.precision == 1, grid, lds, st));
+  (void)s;
+  std::vector<Launch> plan{Launch{a, grid, lds}};
+  RC_HIP(run_plan(plan, stack, st));
   return RC_OK;
 }
 
@@ -390,27 +411,58 @@ int rc_records_batched(const rc_scene* scene, const rc_medium* medium, const rc_
   if ((r = plan(s, params, P, tile, stack, lds, grid, &resident))) return r;
   char* ws = static_cast<char*>(workspace);
   const int32_t* ord = order;
+  unsigned int* q = reinterpret_cast<unsigned int*>(ws + kWsQueue);
   if (!ord) {
     int32_t* o = reinterpret_cast<int32_t*>(ws + kWsOrder);
     RC_HIP(rc::launch_order(n_theta, n_phi, (int)P, reinterpret_cast<unsigned int*>(ws + kWsHist),
-                            reinterpret_cast<unsigned int*>(ws + kWsCursor), o, st));
+                            reinterpret_cast<unsigned int*>(ws + kWsCursor), o, q + kQClassRange, st));
     ord = o;
   }
   rc::RecordArgs a = make_args(s, medium, lights, n_lights, pos, n_theta, n_phi, P, params, value, grad, hess,
                                workspace, ord);
   set_splits(a, params, P, resident, workspace);
-  grid = (int)std::min<int64_t>(grid, P * (int64_t)a.splits);
-  if (!use_graph || st == nullptr) return launch_direct(s, a, stack, lds, grid, st);
+  std::vector<Launch> launches;
+  if (!order && a.splits == 1 && P > rc::kSplitMaxRecords) {
+    // Large batches from the internal queue: one launch per n_phi class, each
+    // with the LDS (and so the occupancy) its rows need; a class's launch
+    // takes only its queue range and exits at once if the class is empty.
+    int prev_cap = 0;
+    size_t lds_max = 0;
+    for (int k = 0; k < rc::kOrderClasses && prev_cap < params->max_n_phi; k++) {
+      const int cap = std::min(rc::kClassCap[k], params->max_n_phi);
+      rc_params pk = *params;
+      pk.max_n_phi = cap;
+      int sk, gk;
+      size_t lk;
+      int64_t rk = 0;
+      if ((r = plan(s, &pk, P, tile, sk, lk, gk, &rk))) return r;
+      rc::RecordArgs ak = a;
+      ak.max_n_phi = cap;
+      ak.range = q + kQClassRange + 2 * k;
+      ak.next = q + kQClassNext + k;
+      launches.push_back(Launch{ak, gk, lk});
+      lds_max = std::max(lds_max, lk);
+      prev_cap = rc::kClassCap[k];
+    }
+    if (hipError_t e = rc::prepare_record(stack, a.counters != nullptr, a.precision == 1, lds_max))
+      return fail(RC_EDEVICE, "kernel attribute: %s", hipGetErrorString(e));
+  } else {
+    launches.push_back(Launch{a, (int)std::min<int64_t>(grid, P * (int64_t)a.splits), lds});
+  }
+  if (!use_graph || st == nullptr) {
+    RC_HIP(run_plan(launches, stack, st));
+    return RC_OK;
+  }
   std::lock_guard<std::mutex> lk(s->mu);
   GraphCache& gc = s->graph;
-  bool same = gc.valid && gc.grid == grid && gc.stack == stack && gc.lds == lds && gc.stream == st &&
-              std::memcmp(&gc.args, &a, sizeof a) == 0;
+  bool same = gc.valid && gc.stack == stack && gc.stream == st && gc.plan.size() == launches.size();
+  for (size_t i = 0; same && i < launches.size(); i++)
+    same = gc.plan[i].grid == launches[i].grid && gc.plan[i].lds == launches[i].lds &&
+           std::memcmp(&gc.plan[i].args, &launches[i].args, sizeof(rc::RecordArgs)) == 0;
   if (!same) {
     gc.clear();
     RC_HIP(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
-    hipError_t e1 = rc::launch_reset(a.queue, st);
-    if (e1 == hipSuccess && a.splits > 1) e1 = rc::launch_zero_u32(a.done, a.P, st);
-    hipError_t e2 = e1 == hipSuccess ? rc::launch_record(a, stack, a.counters != nullptr, a.precision == 1, grid, lds, st) : e1;
+    hipError_t e2 = run_plan(launches, stack, st);
     hipGraph_t g = nullptr;
     hipError_t e3 = hipStreamEndCapture(st, &g);
     if (e2 != hipSuccess || e3 != hipSuccess) {
@@ -425,10 +477,8 @@ int rc_records_batched(const rc_scene* scene, const rc_medium* medium, const rc_
     }
     gc.graph = g;
     gc.exec = ex;
-    gc.args = a;
-    gc.grid = grid;
+    gc.plan = launches;
     gc.stack = stack;
-    gc.lds = lds;
     gc.stream = st;
     gc.valid = true;
   }

@@ -100,12 +100,16 @@ __global__ __launch_bounds__(64) void record_kernel(RecordArgs g) {
   uint64_t t_mark = 0;
 
   const int S = g.splits;  // wavefronts per record (row ranges); 1 for large batches
+  // queue slots [lo, hi) of this launch: all of them, or one class of records
+  const int q_lo = g.range ? (int)g.range[0] : 0;
+  const int q_n = g.range ? (int)g.range[1] - q_lo : g.P;
+  unsigned int* const next = g.next ? g.next : &g.queue[0];
   while (true) {
     int q = 0;
-    if (lane == 0) q = (int)atomicAdd(&g.queue[0], 1u);
+    if (lane == 0) q = (int)atomicAdd(next, 1u);
     q = __shfl(q, 0, kWave);
-    if (q >= g.P * S) break;
-    const int qr = q / S, part = q - qr * S;
+    if (q >= q_n * S) break;
+    const int qr = q_lo + q / S, part = q - (q / S) * S;
     const int rec = g.order ? g.order[qr] : qr;
     if (rec < 0 || rec >= g.P) {  // corrupt queue entry: count it, touch nothing
       if (lane == 0 && part == 0) atomicAdd(&g.queue[1], 1u);
@@ -571,30 +575,38 @@ __global__ void reset_queue_kernel(unsigned int* q) {
   if (threadIdx.x < 2) q[threadIdx.x] = 0u;
 }
 
-// Queue of records ordered by decreasing cost N = n_theta * n_phi (coarse
-// buckets of 1/8 octave); ties in any order (records do not interact).
+// Queue of records grouped by n_phi class (the LDS a record's rows need:
+// n_phi <= 16, 32, 64, 128, 256), the largest class first, and within a
+// class ordered by decreasing cost N = n_theta * n_phi (buckets of 1/4
+// octave); ties in any order (records do not interact).  The scan also
+// writes each class's queue range [lo, hi) to class_range[2 * class].
+RC_DEV int order_class(int nph) { return nph <= 16 ? 0 : (nph <= 32 ? 1 : (nph <= 64 ? 2 : (nph <= 128 ? 3 : 4))); }
+RC_DEV int order_bucket(int nth, int nph) {
+  const float n = fmaxf((float)nth * (float)nph, 1.f);
+  const int cb = min(max((int)(log2f(n) * 4.f), 0), kOrderPerClass - 1);
+  return (kOrderClasses - 1 - order_class(nph)) * kOrderPerClass + (kOrderPerClass - 1 - cb);
+}
 __global__ void order_hist_kernel(const int* nth, const int* nph, int P, unsigned int* hist) {
   int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= P) return;
-  float n = fmaxf((float)nth[i] * (float)nph[i], 1.f);
-  int b = min(max((int)(log2f(n) * 8.f), 0), kOrderBuckets - 1);
-  atomicAdd(&hist[kOrderBuckets - 1 - b], 1u);
+  atomicAdd(&hist[order_bucket(nth[i], nph[i])], 1u);
 }
-__global__ void order_scan_kernel(unsigned int* hist, unsigned int* cursor) {
+__global__ void order_scan_kernel(unsigned int* hist, unsigned int* cursor, unsigned int* class_range) {
   if (threadIdx.x == 0) {
     unsigned int s = 0;
     for (int b = 0; b < kOrderBuckets; b++) {
+      const int blk = b / kOrderPerClass, cls = kOrderClasses - 1 - blk;
+      if (b % kOrderPerClass == 0 && blk < kOrderClasses) class_range[2 * cls] = s;
       cursor[b] = s;
       s += hist[b];
+      if (b % kOrderPerClass == kOrderPerClass - 1 && blk < kOrderClasses) class_range[2 * cls + 1] = s;
     }
   }
 }
 __global__ void order_scatter_kernel(const int* nth, const int* nph, int P, unsigned int* cursor, int* order) {
   int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= P) return;
-  float n = fmaxf((float)nth[i] * (float)nph[i], 1.f);
-  int b = min(max((int)(log2f(n) * 8.f), 0), kOrderBuckets - 1);
-  unsigned int p = atomicAdd(&cursor[kOrderBuckets - 1 - b], 1u);
+  unsigned int p = atomicAdd(&cursor[order_bucket(nth[i], nph[i])], 1u);
   order[p] = i;
 }
 __global__ void zero_u32_kernel(unsigned int* p, int n) {
@@ -717,11 +729,11 @@ hipError_t launch_zero_u32(unsigned int* p, int n, hipStream_t s) {
 }
 
 hipError_t launch_order(const int* nth, const int* nph, int P, unsigned int* hist, unsigned int* cursor, int* order,
-                        hipStream_t s) {
+                        unsigned int* class_range, hipStream_t s) {
   hipLaunchKernelGGL(zero_u32_kernel, dim3(1), dim3(kOrderBuckets), 0, s, hist, kOrderBuckets);
   int blocks = (P + 255) / 256;
   if (blocks > 0) hipLaunchKernelGGL(order_hist_kernel, dim3(blocks), dim3(256), 0, s, nth, nph, P, hist);
-  hipLaunchKernelGGL(order_scan_kernel, dim3(1), dim3(64), 0, s, hist, cursor);
+  hipLaunchKernelGGL(order_scan_kernel, dim3(1), dim3(64), 0, s, hist, cursor, class_range);
   if (blocks > 0) hipLaunchKernelGGL(order_scatter_kernel, dim3(blocks), dim3(256), 0, s, nth, nph, P, cursor, order);
   return hipGetLastError();
 }

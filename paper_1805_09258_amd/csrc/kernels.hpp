@@ -9,6 +9,10 @@
 namespace rc {
 
 constexpr int kOrderBuckets = 256;
+constexpr int kOrderClasses = 5;    // n_phi classes: <= 16, 32, 64, 128, 256
+constexpr int kOrderPerClass = 48;  // cost buckets per class (1/4 octave of N)
+constexpr int kClassCap[kOrderClasses] = {16, 32, 64, 128, 256};
+static_assert(kOrderClasses * kOrderPerClass <= kOrderBuckets, "order buckets");
 
 struct RecordArgs {
   const float4* nodes;
@@ -38,6 +42,8 @@ struct RecordArgs {
   int splits;              // wavefronts per record (each owns a range of rows)
   double* partial;         // [P][splits][20] partial sums (splits > 1)
   unsigned int* done;      // [P] parts finished (splits > 1; zero before launch)
+  const unsigned int* range;  // device [lo, hi): queue slots of this launch, or nullptr (all)
+  unsigned int* next;         // item counter of this launch, or nullptr (queue[0])
   unsigned long long* counters;
 };
 
@@ -51,7 +57,7 @@ hipError_t launch_zero_u32(unsigned int* p, int n, hipStream_t s);
 constexpr int kMaxSplits = 8;        // wavefronts per record at most
 constexpr int kSplitMaxRecords = 16384;  // batches up to this size may split records
 hipError_t launch_order(const int* nth, const int* nph, int P, unsigned int* hist, unsigned int* cursor, int* order,
-                        hipStream_t s);
+                        unsigned int* class_range, hipStream_t s);
 hipError_t launch_radius(const double* value, const double* hess, int P, float eps, float r_min, float r_max, float* R,
                          float* axes, hipStream_t s);
 

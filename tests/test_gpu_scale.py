@@ -53,9 +53,12 @@ def _run(w, dev, precision=0, autotune=False, graph=False):
     return out
 
 
-def test_c3_batched_mixed_sample_counts_sampled_parity(dev):
+@pytest.mark.parametrize("P", [3000, 20000])
+def test_c3_batched_mixed_sample_counts_sampled_parity(dev, P):
+    """3000 records run as one launch (records split over wavefronts); 20000
+    as one launch per n_phi class (each with its own LDS size)."""
     full = W.make_c3()
-    w = full.subset(np.arange(3000))
+    w = full.subset(np.arange(P))
     _say("C3 scene:", w.n_tri, "triangles; N in", int((w.n_theta * w.n_phi).min()), "..",
          int((w.n_theta * w.n_phi).max()))
     v, g, h = _run(w, dev, autotune=True, graph=True)
