@@ -164,11 +164,12 @@ def main():
     stream = torch.cuda.Stream()
     eps, r_min, r_max = 1.5e-4, 1e-3, 0.25 * float(np.linalg.norm(w.box_hi - w.box_lo))
 
-    # untimed: algorithmic work of one launch (rays, node and triangle fetches)
+    # untimed: algorithmic work of one launch (rays, node and triangle fetches), counted with one
+    # wavefront per record so that rows recomputed by split records are not counted
     cnt = torch.zeros(8, dtype=torch.int64, device=dev)
     with torch.cuda.stream(stream):
         rc.compute_records(scene, dw, batched=True, counters=cnt, out=(value, grad, hess), workspace=ws,
-                           stream=stream)
+                           stream=stream, splits=1 if w.n_rec <= 16384 else 0)
     stream.synchronize()
     rays, nodes, tris, terms, c0, c1, c2, c3 = (int(x) for x in cnt.cpu().tolist())
     ctot = max(c0 + c1 + c2 + c3, 1)
