@@ -151,7 +151,9 @@ int64_t rc_bvh_build_host(const float* tri, int64_t T, const float box_lo[3], co
 /* Workspace                                                            */
 /* ------------------------------------------------------------------ */
 /* Every launch needs a device workspace owned by the caller (queue
- * counters, error counter).  Size in bytes for up to P records: */
+ * counters, error counter, the device-built queue, and for batches of up to
+ * 16384 records the per-record part counters and FP64 partial sums of split
+ * records).  Size in bytes for up to P records: */
 size_t rc_workspace_size(int64_t P);
 /* Copy the workspace's invalid-record counter to the host (synchronises
  * `stream`).  Returns the count (>= 0) or a negative error code. */
@@ -176,8 +178,9 @@ int64_t rc_workspace_errors(const void* workspace, void* stream);
  *             yz, zz) (Eq. SegmentRadianceHessian with SSSegALHessianSimp;
  *             form factor derivatives of App. C, transmittance of App. A).
  *   workspace: device, at least rc_workspace_size(P) bytes.
- * The launch is one persistent kernel: each wavefront pops records from a
- * queue in `workspace` and computes its whole record on chip. */
+ * The launch is one persistent kernel: each wavefront pops a record (or one
+ * part of a split record, see rc_params.splits) from a queue in `workspace`
+ * and computes it on chip. */
 int rc_records(const rc_scene* scene, const rc_medium* medium, const rc_point_light* lights, int n_lights,
                const float* pos, const int32_t* n_theta, const int32_t* n_phi, int64_t P,
                const rc_params* params, double* value, double* grad, double* hess,
@@ -186,13 +189,18 @@ int rc_records(const rc_scene* scene, const rc_medium* medium, const rc_point_li
 /* Same records, scheduled from a caller-supplied queue.
  *   order     : device int32[P] permutation of 0..P-1, the order in which
  *               records are popped (e.g. most expensive first), or NULL to
- *               build one on the device (records sorted by n_theta * n_phi,
- *               largest first).
- *   use_graph : nonzero = capture the queue reset and the persistent launch in
- *               a hipGraph on first use for this (scene, P, tile) and replay
- *               it afterwards (the graph is cached in the scene handle).
+ *               build one on the device: records grouped by n_phi class
+ *               (<= 16, 32, 64, 128, 256; widest first), largest
+ *               n_theta * n_phi first within a class.  With the device-built
+ *               queue, batches of more than 16384 records are launched once
+ *               per class, each launch sized (LDS, occupancy) for its class.
+ *   use_graph : nonzero = capture the queue reset and the persistent
+ *               launch(es) in a hipGraph on first use for these arguments and
+ *               replay it afterwards (the graph is cached in the scene
+ *               handle).
  *   tile      : launch configuration index from rc_autotune, or -1 = default.
- * Outputs are identical (bitwise) to rc_records for the same inputs. */
+ * Outputs are identical (bitwise) to rc_records for the same inputs and
+ * params (the same number of parts per record is chosen for both). */
 int rc_records_batched(const rc_scene* scene, const rc_medium* medium, const rc_point_light* lights,
                        int n_lights, const float* pos, const int32_t* n_theta, const int32_t* n_phi, int64_t P,
                        const rc_params* params, const int32_t* order, int use_graph, int tile,
