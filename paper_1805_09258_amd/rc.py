@@ -6,7 +6,6 @@ C names (rc_scene_create, rc_records, ...); `Scene` and `compute_records` are
 conveniences that allocate the outputs as torch tensors.
 
 Loading fails loudly if the library has not been built (run
-``python -c "import __graft_entry__ as g; g.build()"`` or
 ``python paper_1805_09258_amd/build.py``); there is no CPU fallback.
 """
 from __future__ import annotations
