@@ -127,6 +127,11 @@ int check_inputs(const rc_scene* s, const rc_medium* m, const rc_point_light* li
   return RC_OK;
 }
 
+// LDS row width: rows of up to 64 columns are held whole; wider rows are done
+// in sectors of 64 columns (plus one), which keeps two rows within ~20 KB and
+// the record kernel at 7-8 wavefronts per CU instead of 4 or fewer.
+int lds_cols_for(int max_n_phi) { return max_n_phi > 64 ? 65 : max_n_phi; }
+
 rc::RecordArgs make_args(const rc_scene* s, const rc_medium* m, const rc_point_light* lights, int n_lights,
                          const float* pos, const int32_t* nth, const int32_t* nph, int64_t P, const rc_params* p,
                          double* value, double* grad, double* hess, void* ws, const int32_t* order) {
@@ -152,6 +157,7 @@ rc::RecordArgs make_args(const rc_scene* s, const rc_medium* m, const rc_point_l
   a.ring_step = p->ring_step;
   a.max_rings = p->max_rings;
   a.max_n_phi = p->max_n_phi;
+  a.lds_cols = lds_cols_for(p->max_n_phi);
   a.precision = p->precision;
   a.seed = p->seed;
   a.value = value;
@@ -200,7 +206,7 @@ constexpr float kTileGrid[kNTiles] = {1.0f, 2.0f, 0.5f, 4.0f};
 int plan(const rc_scene* s, const rc_params* p, int64_t P, int tile, int& stack, size_t& lds, int& grid,
          int64_t* resident_out = nullptr) {
   stack = rc::stack_variant(s->depth);
-  lds = rc::record_lds_bytes(stack, p->max_n_phi, p->max_rings);
+  lds = rc::record_lds_bytes(stack, lds_cols_for(p->max_n_phi), p->max_rings);
   if (lds > 160 * 1024) return fail(RC_EINVAL, "max_n_phi x max_rings needs %zu bytes of LDS (> 160 KiB)", lds);
   hipError_t e = rc::prepare_record(stack, p->counters != nullptr, p->precision == 1, lds);
   if (e != hipSuccess) return fail(RC_EDEVICE, "kernel attribute: %s", hipGetErrorString(e));
@@ -438,6 +444,7 @@ int rc_records_batched(const rc_scene* scene, const rc_medium* medium, const rc_
       if ((r = plan(s, &pk, P, tile, sk, lk, gk, &rk))) return r;
       rc::RecordArgs ak = a;
       ak.max_n_phi = cap;
+      ak.lds_cols = lds_cols_for(cap);
       ak.range = q + kQClassRange + 2 * k;
       ak.next = q + kQClassNext + k;
       launches.push_back(Launch{ak, gk, lk});

@@ -83,7 +83,7 @@ template <int STACK, bool COUNT, bool F64>
 __global__ __launch_bounds__(64) void record_kernel(RecordArgs g) {
   extern __shared__ float lds[];
   const int lane = threadIdx.x;
-  const int cap = g.max_n_phi;
+  const int cap = g.lds_cols;  // columns of an LDS row
   const int MR = g.max_rings;
   int* stk = reinterpret_cast<int*>(lds) + lane;
   float* rows = lds + STACK * kWave;
@@ -117,7 +117,7 @@ __global__ __launch_bounds__(64) void record_kernel(RecordArgs g) {
     }
     const float3 x = make_float3(g.pos[3 * rec], g.pos[3 * rec + 1], g.pos[3 * rec + 2]);
     const int nth = g.n_theta[rec], nph = g.n_phi[rec];
-    const bool bad = !(nth >= 2 && nph >= 5 && nph <= cap) || !(x.x >= g.box_lo.x && x.x <= g.box_hi.x) ||
+    const bool bad = !(nth >= 2 && nph >= 5 && nph <= g.max_n_phi) || !(x.x >= g.box_lo.x && x.x <= g.box_hi.x) ||
                      !(x.y >= g.box_lo.y && x.y <= g.box_hi.y) || !(x.z >= g.box_lo.z && x.z <= g.box_hi.z);
     if (bad) {
       if (part != 0) continue;  // the first part reports it
@@ -142,6 +142,17 @@ __global__ __launch_bounds__(64) void record_kernel(RecordArgs g) {
     const int r0 = (int)(((long long)part * nr) / S), r1 = (int)(((long long)(part + 1) * nr) / S);
     const int a_own = r0 - 1, a_hi = r1 - 2;
     const int a_lo = (part > 0 && r1 > r0) ? a_own - 1 : a_own;
+    // Columns: a row wider than the LDS rows is done in sectors of cap - 1
+    // owned columns plus the next sector's first column (the quads between
+    // them need it); each sector walks the rows again (poles included).
+    // Local column j of sector s is global column (b0 + j) mod n_phi.
+    const bool sectored = nph > cap;
+    const int wsec = sectored ? cap - 1 : nph;
+    const int nsec = (nph + wsec - 1) / wsec;
+    for (int sec = 0; sec < nsec; sec++) {
+    const int b0 = sec * wsec;
+    const int nown = min(wsec, nph - b0);           // owned columns (strata, quads)
+    const int ncol = sectored ? nown + 1 : nph;      // columns held
     for (int a = a_lo; a <= a_hi; a++) {
       const bool own = a >= a_own;
       float* const baseR = rows + ((a + 1) & 1) * row_words;
@@ -149,7 +160,9 @@ __global__ __launch_bounds__(64) void record_kernel(RecordArgs g) {
       const Row R = row_view(baseR, cap);
       const Row P = row_view(baseP, cap);
       const bool pole = (a < 0 || a == nth);
-      const int n = pole ? 1 : nph;
+      const int n = pole ? 1 : ncol;
+      // counted once per record: owned columns, and the poles in the first sector
+      const int n_cnt = pole ? (sec == 0 ? 1 : 0) : nown;
       // ---- 1. primary rays ------------------------------------------------
       if (COUNT) t_mark = clock64();
       for (int base = 0; base < n; base += kWave) {
@@ -158,7 +171,7 @@ __global__ __launch_bounds__(64) void record_kernel(RecordArgs g) {
           float3 w;
           if (a < 0) w = make_float3(0.f, 0.f, 1.f);
           else if (a == nth) w = make_float3(0.f, 0.f, -1.f);
-          else w = stratum_direction(key, a, j, nth, nph);
+          else w = stratum_direction(key, a, sectored ? (b0 + j) % nph : j, nth, nph);
           int id;
           float t;
           bool fr;
@@ -175,7 +188,7 @@ __global__ __launch_bounds__(64) void record_kernel(RecordArgs g) {
           R.Ls[j] = id >= 0 ? g.emission[id] : 0.f;
           R.visS[j] = 0;
           for (int i = 0; i < M; i++) reinterpret_cast<int*>(R.Lm)[i * cap + j] = 0;
-          if (COUNT && own) n_rays++;
+          if (COUNT && own && j < n_cnt) n_rays++;
         }
       }
       __syncthreads();
@@ -241,7 +254,7 @@ __global__ __launch_bounds__(64) void record_kernel(RecordArgs g) {
               node = 0;
               sp = 0;
               ln = 0;
-              if (COUNT && own) n_rays++;
+              if (COUNT && own && j < n_cnt) n_rays++;
             }
           }
           next += __popcll(want);
@@ -360,9 +373,9 @@ __global__ __launch_bounds__(64) void record_kernel(RecordArgs g) {
       // ---- 3. Monte Carlo value of the strata in this row -----------------
       if (!pole && own) {
         float vs = 0.f, vsc = 0.f, vm = 0.f, vmc = 0.f;
-        for (int base = 0; base < n; base += kWave) {
+        for (int base = 0; base < nown; base += kWave) {
           int j = base + lane;
-          if (j < n) {
+          if (j < nown) {
             float3 w = make_float3(R.wx[j], R.wy[j], R.wz[j]);
             float wn = sqrtf(dot3(w, w));
             kadd(vs, vsc, expf(-mu * R.t[j] * wn) * R.Ls[j]);
@@ -382,7 +395,7 @@ __global__ __launch_bounds__(64) void record_kernel(RecordArgs g) {
       if (a >= 0 && own) {
         // kind 0: north fan (P = pole, R = row 0); 1: band; 2: south fan
         const int kind = (a == 0) ? 0 : (a == nth ? 2 : 1);
-        const int ntri = (kind == 1) ? 2 * nph : nph;
+        const int ntri = (kind == 1) ? 2 * nown : nown;
         const int prow = a - 1;  // strata row index of P (for vertex ids)
         int carry = 0;
         for (int base = 0; base < ntri; base += kWave) {
@@ -391,7 +404,7 @@ __global__ __launch_bounds__(64) void record_kernel(RecordArgs g) {
           if (tI < ntri) {
             int m0, m1, m2;
             int b = (kind == 1) ? (tI >> 1) : tI;
-            int b1 = (b + 1 == nph) ? 0 : b + 1;
+            int b1 = (b + 1 == ncol) ? 0 : b + 1;
             if (kind == 0) { m0 = P.M[0]; m1 = R.M[b]; m2 = R.M[b1]; }
             else if (kind == 2) { m0 = R.M[0]; m1 = P.M[b1]; m2 = P.M[b]; }
             else { m0 = max(P.M[b], P.M[b1]); m1 = R.M[b]; m2 = R.M[b1]; }
@@ -414,24 +427,28 @@ __global__ __launch_bounds__(64) void record_kernel(RecordArgs g) {
           // the triangle's three vertices: (row pointer, column, global id)
           const float* vb[3];  // row base of each vertex
           int col[3], gid[3];
+          // local columns b, b1 of the quad; global columns gb, gb1 (vertex ids)
           if (kind == 0) {
-            int b = tI, b1 = (b + 1 == nph) ? 0 : b + 1;
+            int b = tI, b1 = (b + 1 == ncol) ? 0 : b + 1;
+            const int gb = (b0 + b) % nph, gb1 = (b0 + b1) % nph;
             vb[0] = baseP; col[0] = 0; gid[0] = 0;
-            vb[1] = baseR; col[1] = b; gid[1] = 1 + b;
-            vb[2] = baseR; col[2] = b1; gid[2] = 1 + b1;
+            vb[1] = baseR; col[1] = b; gid[1] = 1 + gb;
+            vb[2] = baseR; col[2] = b1; gid[2] = 1 + gb1;
           } else if (kind == 2) {
-            int b = tI, b1 = (b + 1 == nph) ? 0 : b + 1;
+            int b = tI, b1 = (b + 1 == ncol) ? 0 : b + 1;
+            const int gb = (b0 + b) % nph, gb1 = (b0 + b1) % nph;
             vb[0] = baseR; col[0] = 0; gid[0] = N + 1;
-            vb[1] = baseP; col[1] = b1; gid[1] = 1 + prow * nph + b1;
-            vb[2] = baseP; col[2] = b; gid[2] = 1 + prow * nph + b;
+            vb[1] = baseP; col[1] = b1; gid[1] = 1 + prow * nph + gb1;
+            vb[2] = baseP; col[2] = b; gid[2] = 1 + prow * nph + gb;
           } else {
-            int b = tI >> 1, b1 = (b + 1 == nph) ? 0 : b + 1;
+            int b = tI >> 1, b1 = (b + 1 == ncol) ? 0 : b + 1;
+            const int gb = (b0 + b) % nph, gb1 = (b0 + b1) % nph;
             float3 wP = make_float3(P.wx[b], P.wy[b], P.wz[b]);
             float3 wQ = make_float3(P.wx[b1], P.wy[b1], P.wz[b1]);
             float3 wR = make_float3(R.wx[b], R.wy[b], R.wz[b]);
             float3 wS = make_float3(R.wx[b1], R.wy[b1], R.wz[b1]);
             bool d1 = det3(wP, wR, wS) > 0.f && det3(wP, wS, wQ) > 0.f;
-            int gP = 1 + prow * nph + b, gQ = 1 + prow * nph + b1, gR = 1 + a * nph + b, gS = 1 + a * nph + b1;
+            int gP = 1 + prow * nph + gb, gQ = 1 + prow * nph + gb1, gR = 1 + a * nph + gb, gS = 1 + a * nph + gb1;
             bool second = tI & 1;
             if (d1) {
               if (!second) { vb[0] = baseP; col[0] = b; gid[0] = gP; vb[1] = baseR; col[1] = b; gid[1] = gR; vb[2] = baseR; col[2] = b1; gid[2] = gS; }
@@ -525,6 +542,7 @@ __global__ __launch_bounds__(64) void record_kernel(RecordArgs g) {
       __syncthreads();
       if (COUNT) { uint64_t t = clock64(); cyc[3] += t - t_mark; t_mark = t; }
     }
+    }  // sectors
     // ---- store ------------------------------------------------------------
     if (S > 1) {
       // parts leave FP64 partial sums; the last part to finish adds them in

@@ -31,7 +31,8 @@ struct RecordArgs {
   int common_random;       // 1: every record draws with id rec_base
   float ring_step;
   int max_rings;
-  int max_n_phi;
+  int max_n_phi;           // largest n_phi accepted (records above it are invalid)
+  int lds_cols;            // columns of an LDS row (wider rows are done in sectors)
   int precision;
   unsigned long long seed;
   double* value;

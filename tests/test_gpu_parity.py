@@ -114,6 +114,27 @@ def test_records_split_over_wavefronts_match_oracle(dev, splits):
     sc.close()
 
 
+@pytest.mark.parametrize("nth,nph,splits", [(4, 100, 1), (3, 129, 1), (2, 256, 1), (6, 100, 3)])
+def test_wide_rows_done_in_column_sectors_match_oracle(dev, nth, nph, splits):
+    """Rows wider than 64 columns are traced and triangulated in sectors of 64
+    columns (plus the next sector's first); records, ray and term counts equal
+    the oracle's, also combined with row parts."""
+    w = W.make_c1(P=24)
+    w.n_theta = np.full(w.n_rec, nth, np.int32)
+    w.n_phi = np.full(w.n_rec, nph, np.int32)
+    sc = rc.Scene.from_workload(w)
+    dw = rc.DeviceWorkload(w)
+    cnt = torch.zeros(8, dtype=torch.int64, device=dev)
+    v, g, h, ws = rc.compute_records(sc, dw, batched=True, counters=cnt, splits=splits)
+    torch.cuda.synchronize()
+    assert rc.rc_workspace_errors(ws) == 0
+    ref = O.records_for(w)
+    assert_parity(v.cpu().numpy(), g.cpu().numpy(), h.cpu().numpy(), ref, f"{nth}x{nph}, {splits} parts")
+    assert int(cnt[0].item()) == int(ref["stats"][:, 0].sum())
+    assert int(cnt[3].item()) == int(ref["stats"][:, 1].sum() + ref["stats"][:, 2].sum())
+    sc.close()
+
+
 def test_small_batches_split_automatically_on_the_c2_scene(dev):
     w = W.make_c2().subset(np.arange(37))
     sc = rc.Scene.from_workload(w)
