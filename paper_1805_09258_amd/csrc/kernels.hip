@@ -80,7 +80,10 @@ RC_DEV double wave_sum(double v) {
 }  // namespace
 
 template <int STACK, bool COUNT, bool F64>
-__global__ __launch_bounds__(64) void record_kernel(RecordArgs g) {
+// Register budget for 3 wavefronts per SIMD (168 VGPRs; the compiler spills
+// a few values of the cooler phases): traversal is latency-bound, so more
+// resident wavefronts beat the spills.
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3, 3))) void record_kernel(RecordArgs g) {
   extern __shared__ float lds[];
   const int lane = threadIdx.x;
   const int cap = g.lds_cols;  // columns of an LDS row
