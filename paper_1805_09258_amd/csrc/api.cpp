@@ -127,11 +127,19 @@ int check_inputs(const rc_scene* s, const rc_medium* m, const rc_point_light* li
   return RC_OK;
 }
 
-// LDS row width: rows of up to 32 columns are held whole; wider rows are done
-// in sectors of 32 columns (plus one).  Two rows then take ~7 KB, so LDS
-// allows 10-13 wavefronts per CU and the register budget (3 per SIMD, 168
-// VGPRs) sets 12: 1.27x the records/s of whole 64-column rows at 8 per CU.
-int lds_cols_for(int max_n_phi) { return max_n_phi > 32 ? 33 : max_n_phi; }
+// LDS row width.  The record kernel's register budget allows 12 wavefronts per
+// CU (3 per SIMD); rows are held whole when that fits the LDS, else in
+// sectors of w columns (plus one) with the widest w <= 32 for which a
+// wavefront's LDS (stack, two rows, offsets) stays within 1/12 of the CU's
+// 160 KB.  Whole 64-column rows at 8 wavefronts per CU gave 0.79x the
+// records/s of 32-column sectors at 12.
+int lds_cols_for(int max_n_phi, int stack, int max_rings) {
+  const size_t budget = (size_t)160 * 1024 / 12;
+  if (rc::record_lds_bytes(stack, max_n_phi, max_rings) <= budget) return max_n_phi;
+  for (int w = std::min(32, max_n_phi - 1); w >= 8; w--)
+    if (rc::record_lds_bytes(stack, w + 1, max_rings) <= budget) return w + 1;
+  return std::min(max_n_phi, 33);  // deep stacks or many rings: fewer wavefronts
+}
 
 rc::RecordArgs make_args(const rc_scene* s, const rc_medium* m, const rc_point_light* lights, int n_lights,
                          const float* pos, const int32_t* nth, const int32_t* nph, int64_t P, const rc_params* p,
@@ -158,7 +166,7 @@ rc::RecordArgs make_args(const rc_scene* s, const rc_medium* m, const rc_point_l
   a.ring_step = p->ring_step;
   a.max_rings = p->max_rings;
   a.max_n_phi = p->max_n_phi;
-  a.lds_cols = lds_cols_for(p->max_n_phi);
+  a.lds_cols = lds_cols_for(p->max_n_phi, rc::stack_variant(s->depth), p->max_rings);
   a.precision = p->precision;
   a.seed = p->seed;
   a.value = value;
@@ -207,7 +215,7 @@ constexpr float kTileGrid[kNTiles] = {1.0f, 2.0f, 0.5f, 4.0f};
 int plan(const rc_scene* s, const rc_params* p, int64_t P, int tile, int& stack, size_t& lds, int& grid,
          int64_t* resident_out = nullptr) {
   stack = rc::stack_variant(s->depth);
-  lds = rc::record_lds_bytes(stack, lds_cols_for(p->max_n_phi), p->max_rings);
+  lds = rc::record_lds_bytes(stack, lds_cols_for(p->max_n_phi, stack, p->max_rings), p->max_rings);
   if (lds > 160 * 1024) return fail(RC_EINVAL, "max_n_phi x max_rings needs %zu bytes of LDS (> 160 KiB)", lds);
   hipError_t e = rc::prepare_record(stack, p->counters != nullptr, p->precision == 1, lds);
   if (e != hipSuccess) return fail(RC_EDEVICE, "kernel attribute: %s", hipGetErrorString(e));
@@ -445,7 +453,7 @@ int rc_records_batched(const rc_scene* scene, const rc_medium* medium, const rc_
       if ((r = plan(s, &pk, P, tile, sk, lk, gk, &rk))) return r;
       rc::RecordArgs ak = a;
       ak.max_n_phi = cap;
-      ak.lds_cols = lds_cols_for(cap);
+      ak.lds_cols = lds_cols_for(cap, stack, params->max_rings);
       ak.range = q + kQClassRange + 2 * k;
       ak.next = q + kQClassNext + k;
       launches.push_back(Launch{ak, gk, lk});

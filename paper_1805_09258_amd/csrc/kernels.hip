@@ -145,13 +145,13 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3, 3))) void
     const int r0 = (int)(((long long)part * nr) / S), r1 = (int)(((long long)(part + 1) * nr) / S);
     const int a_own = r0 - 1, a_hi = r1 - 2;
     const int a_lo = (part > 0 && r1 > r0) ? a_own - 1 : a_own;
-    // Columns: a row wider than the LDS rows is done in sectors of cap - 1
-    // owned columns plus the next sector's first column (the quads between
-    // them need it); each sector walks the rows again (poles included).
+    // Columns: a row wider than the LDS rows is done in sectors of at most
+    // cap - 1 owned columns plus the next sector's first column (the quads
+    // between them need it); each sector walks the rows again (poles included).
     // Local column j of sector s is global column (b0 + j) mod n_phi.
     const bool sectored = nph > cap;
-    const int wsec = sectored ? cap - 1 : nph;
-    const int nsec = (nph + wsec - 1) / wsec;
+    const int nsec = sectored ? (nph + cap - 2) / (cap - 1) : 1;  // sectors of at most cap - 1 columns,
+    const int wsec = (nph + nsec - 1) / nsec;                     // balanced
     for (int sec = 0; sec < nsec; sec++) {
     const int b0 = sec * wsec;
     const int nown = min(wsec, nph - b0);           // owned columns (strata, quads)
