@@ -278,6 +278,7 @@ int rc_probe(const rc_scene* scene, const rc_medium* medium, const rc_point_ligh
  * w3[128], b3, loss slot. */
 size_t rc_mlp_param_bytes(void);
 int64_t rc_mlp_n_params(void);
+/* Every MLP call below takes at most 2^30 samples (RC_EINVAL beyond). */
 /* Glorot-uniform initialisation from the counter-based generator. */
 int rc_mlp_init(void* params, float* state, uint64_t seed, void* stream);
 /* Rebuild the parameter block's FP32/BF16 copies from master parameters. */

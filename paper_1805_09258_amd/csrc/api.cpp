@@ -632,6 +632,9 @@ int rc_probe(const rc_scene* s, const rc_medium* m, const rc_point_light* lights
   return RC_OK;
 }
 
+// sample counts of the MLP calls (grid-stride loops index samples with int)
+constexpr int64_t kMlpMaxSamples = int64_t(1) << 30;
+
 size_t rc_mlp_param_bytes(void) { return rc::kMlpParamBytes; }
 int64_t rc_mlp_n_params(void) { return rc::kMlpGradFloats; }
 size_t rc_mlp_train_workspace_bytes(int64_t n) {
@@ -653,21 +656,21 @@ int rc_mlp_load(void* params, const float* state, void* stream) {
 
 int rc_mlp_fit_features(void* params, const float* X, int64_t n, void* workspace, void* stream) {
   if (!params || (n > 0 && (!X || !workspace))) return fail(RC_EINVAL, "NULL pointer");
-  if (n < 2 || n > 0x7fffffff) return fail(RC_EINVAL, "need 2 <= n < 2^31 samples");
+  if (n < 2 || n > kMlpMaxSamples) return fail(RC_EINVAL, "need 2 <= n <= 2^30 samples");
   RC_HIP(rc::launch_feature_stats(X, (int)n, static_cast<float*>(workspace), 256, params,
                                   static_cast<hipStream_t>(stream)));
   return RC_OK;
 }
 
 int rc_mlp_forward(const void* params, const float* X, int64_t n, float* out, void* stream) {
-  if (!params || n < 0 || n > 0x7fffffff || (n > 0 && (!X || !out))) return fail(RC_EINVAL, "invalid arguments");
+  if (!params || n < 0 || n > kMlpMaxSamples || (n > 0 && (!X || !out))) return fail(RC_EINVAL, "invalid arguments");
   RC_HIP(rc::launch_mlp_forward(params, X, (int)n, out, static_cast<hipStream_t>(stream)));
   return RC_OK;
 }
 
 int rc_mlp_radius(const void* params, const float* X, int64_t n, float safety, float r_min, float r_max, float* R,
                   void* stream) {
-  if (!params || n < 0 || n > 0x7fffffff || (n > 0 && (!X || !R))) return fail(RC_EINVAL, "invalid arguments");
+  if (!params || n < 0 || n > kMlpMaxSamples || (n > 0 && (!X || !R))) return fail(RC_EINVAL, "invalid arguments");
   if (!(safety > 0.f) || !std::isfinite(safety) || !(r_min > 0.f) || !(r_max >= r_min) || !std::isfinite(r_max))
     return fail(RC_EINVAL, "need safety > 0 and 0 < r_min <= r_max finite");
   RC_HIP(rc::launch_mlp_radius(params, X, (int)n, safety, r_min, r_max, R, static_cast<hipStream_t>(stream)));
@@ -677,7 +680,8 @@ int rc_mlp_radius(const void* params, const float* X, int64_t n, float safety, f
 int rc_mlp_train_step(void* params, float* state, const float* X, const float* target, int64_t n, float lr,
                       int64_t step, void* workspace, float* loss, float* grad, void* stream) {
   if (!params || !state || !X || !target || !workspace) return fail(RC_EINVAL, "NULL pointer");
-  if (n < 1 || n > 0x7fffffff || !(lr >= 0.f) || step < 1) return fail(RC_EINVAL, "need n >= 1, lr >= 0, step >= 1");
+  if (n < 1 || n > kMlpMaxSamples || !(lr >= 0.f) || step < 1)
+    return fail(RC_EINVAL, "need 1 <= n <= 2^30, lr >= 0, step >= 1");
   hipStream_t st = static_cast<hipStream_t>(stream);
   const int tiles = (int)((n + 63) / 64);
   float* partial = static_cast<float*>(workspace);
