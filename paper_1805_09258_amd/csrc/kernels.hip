@@ -77,6 +77,26 @@ RC_DEV double wave_sum(double v) {
   return v;
 }
 
+// Add one term's 9 outputs (gradient 3, Hessian 6) to the compensated pairs of
+// channel OFF (0 surface, 9 medium).  The channel is a template argument so the
+// 18 accumulators keep compile-time indices and stay in registers.
+template <int OFF>
+RC_DEV void add_term(float* acc, float* accc, const float* t) {
+#pragma unroll
+  for (int k = 0; k < 9; k++) kadd(acc[OFF + k], accc[OFF + k], t[k]);
+}
+
+// The same with each output given as an FP32 (hi, lo) split of an FP64 value:
+// hi then lo, per output.
+template <int OFF>
+RC_DEV void add_term2(float* acc, float* accc, const float* hi, const float* lo) {
+#pragma unroll
+  for (int k = 0; k < 9; k++) {
+    kadd(acc[OFF + k], accc[OFF + k], hi[k]);
+    kadd(acc[OFF + k], accc[OFF + k], lo[k]);
+  }
+}
+
 }  // namespace
 
 template <int STACK, bool COUNT, bool F64>
@@ -480,17 +500,20 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3, 3))) void
               Lv[k] = front ? b[(kRowFields + ring) * cap + c] : 0.f;
             }
           }
+          // far vertex: largest distance, ties to the smaller vertex id (the
+          // running maximum is kept in scalars so nothing is indexed at run time)
           int far = 0;
+          float tf = tau[0];
+          int gf = gid[0];
 #pragma unroll
           for (int k = 1; k < 3; k++)
-            if (tau[k] > tau[far] || (tau[k] == tau[far] && gid[k] < gid[far])) far = k;
-          float Lf = Lv[far];
+            if (tau[k] > tf || (tau[k] == tf && gid[k] < gf)) { far = k; tf = tau[k]; gf = gid[k]; }
+          float Lf = far == 0 ? Lv[0] : (far == 1 ? Lv[1] : Lv[2]);
           if (Lf == 0.f) continue;
           // direction determinant in FP64 (thin triangles); A = tau1 tau2 tau3 detw
           double dw = (double)wv[0].x * ((double)wv[1].y * wv[2].z - (double)wv[1].z * wv[2].y) +
                       (double)wv[0].y * ((double)wv[1].z * wv[2].x - (double)wv[1].x * wv[2].z) +
                       (double)wv[0].z * ((double)wv[1].x * wv[2].y - (double)wv[1].y * wv[2].x);
-          const int ch = ring < 0 ? 0 : 9;
           if (!F64) {
             float wL = ring < 0 ? Lf : g.ring_step * Lf;
             float gg[3], hh[6];
@@ -498,10 +521,9 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3, 3))) void
             V3<float> r2 = mk(tau[1] * wv[1].x, tau[1] * wv[1].y, tau[1] * wv[1].z);
             V3<float> r3 = mk(tau[2] * wv[2].x, tau[2] * wv[2].y, tau[2] * wv[2].z);
             if (triangle_term<float>(r1, r2, r3, tau[0], tau[1], tau[2], (float)dw, far, wL, mu, gg, hh)) {
-#pragma unroll
-              for (int k = 0; k < 3; k++) kadd(acc[ch + k], accc[ch + k], gg[k]);
-#pragma unroll
-              for (int k = 0; k < 6; k++) kadd(acc[ch + 3 + k], accc[ch + 3 + k], hh[k]);
+              const float t9[9] = {gg[0], gg[1], gg[2], hh[0], hh[1], hh[2], hh[3], hh[4], hh[5]};
+              if (ring < 0) add_term<0>(acc, accc, t9);
+              else add_term<9>(acc, accc, t9);
             }
           } else {
             // study mode: the whole term in FP64, folded into the compensated
@@ -519,18 +541,15 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3, 3))) void
             double g64[3], h64[6];
             double wL64 = ring < 0 ? (double)Lf : (double)g.ring_step * (double)Lf;
             if (triangle_term<double>(r1, r2, r3, dtau[0], dtau[1], dtau[2], dw, far, wL64, (double)mu, g64, h64)) {
+              float hi[9], lo[9];
 #pragma unroll
-              for (int k = 0; k < 3; k++) {
-                float hi = (float)g64[k];
-                kadd(acc[ch + k], accc[ch + k], hi);
-                kadd(acc[ch + k], accc[ch + k], (float)(g64[k] - (double)hi));
+              for (int k = 0; k < 9; k++) {
+                const double x = k < 3 ? g64[k] : h64[k - 3];
+                hi[k] = (float)x;
+                lo[k] = (float)(x - (double)hi[k]);
               }
-#pragma unroll
-              for (int k = 0; k < 6; k++) {
-                float hi = (float)h64[k];
-                kadd(acc[ch + 3 + k], accc[ch + 3 + k], hi);
-                kadd(acc[ch + 3 + k], accc[ch + 3 + k], (float)(h64[k] - (double)hi));
-              }
+              if (ring < 0) add_term2<0>(acc, accc, hi, lo);
+              else add_term2<9>(acc, accc, hi, lo);
             }
           }
           if (COUNT) n_terms++;
