@@ -71,6 +71,14 @@ RC_DEV int find_slot(const int* off, int n, int x) {
   return lo;
 }
 
+// Direction of column `col` of row a: row -1 is the north pole, row nth the
+// south pole, rows 0..nth-1 the strata rows.
+RC_DEV float3 row_direction(uint64_t key, int a, int col, int nth, int nph) {
+  if (a < 0) return make_float3(0.f, 0.f, 1.f);
+  if (a == nth) return make_float3(0.f, 0.f, -1.f);
+  return stratum_direction(key, a, col, nth, nph);
+}
+
 RC_DEV double wave_sum(double v) {
 #pragma unroll
   for (int s = 32; s >= 1; s >>= 1) v += __shfl_xor(v, s, kWave);
@@ -176,6 +184,11 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3, 3))) void
     const int b0 = sec * wsec;
     const int nown = min(wsec, nph - b0);           // owned columns (strata, quads)
     const int ncol = sectored ? nown + 1 : nph;      // columns held
+    // rows g_lo..g_hi had their primary rays traced in one pass; with more
+    // than one row, lane k holds the closest hit of ray k of the pass
+    int g_lo = a_lo, g_hi = a_lo - 1;
+    float held_t = 0.f;
+    int held_code = -1;
     for (int a = a_lo; a <= a_hi; a++) {
       const bool own = a >= a_own;
       float* const baseR = rows + ((a + 1) & 1) * row_words;
@@ -187,28 +200,72 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3, 3))) void
       // counted once per record: owned columns, and the poles in the first sector
       const int n_cnt = pole ? (sec == 0 ? 1 : 0) : nown;
       // ---- 1. primary rays ------------------------------------------------
+      // Narrow rows leave lanes idle, so the closest hits of this row and of
+      // as many following rows as fit in the wavefront are traced in one pass
+      // (a pole row has one column).  A row traced alone keeps its hits in
+      // its LDS row; a pass over several rows keeps them in registers.
       if (COUNT) t_mark = clock64();
+      if (a > g_hi) {
+        g_lo = a;
+        g_hi = a;
+        int tot = n;
+        while (g_hi < a_hi) {
+          const int nn = (g_hi + 1 == nth) ? 1 : ncol;
+          if (tot + nn > kWave) break;
+          g_hi++;
+          tot += nn;
+        }
+        for (int base = 0; base < tot; base += kWave) {
+          int c = base + lane;
+          if (c < tot) {
+            int r = a;
+            for (int m = (r < 0 || r == nth) ? 1 : ncol; c >= m; m = (r < 0 || r == nth) ? 1 : ncol) {
+              c -= m;
+              r++;
+            }
+            const float3 w = row_direction(key, r, sectored ? (b0 + c) % nph : c, nth, nph);
+            int id;
+            float t;
+            bool fr;
+            trace_closest<COUNT>(g.nodes, g.tris, x, w, stk, id, t, fr, tc);
+            const int code = id >= 0 ? ((id << 1) | (fr ? 1 : 0)) : -1;
+            if (g_hi == a) {
+              R.t[c] = t;
+              R.code[c] = code;
+            } else {
+              held_t = t;
+              held_code = code;
+            }
+          }
+        }
+      }
+      // this row's hits: from the LDS row, or from the lanes of the pass
+      const bool grouped = g_hi > g_lo;
+      float gt = 0.f;
+      int gcode = -1;
+      if (grouped) {
+        int o = 0;  // first ray of row a in the pass
+        for (int r = g_lo; r < a; r++) o += (r < 0 || r == nth) ? 1 : ncol;
+        const int src = min(o + lane, kWave - 1);
+        gt = __shfl(held_t, src, kWave);
+        gcode = __shfl(held_code, src, kWave);
+      }
       for (int base = 0; base < n; base += kWave) {
         int j = base + lane;
         if (j < n) {
-          float3 w;
-          if (a < 0) w = make_float3(0.f, 0.f, 1.f);
-          else if (a == nth) w = make_float3(0.f, 0.f, -1.f);
-          else w = stratum_direction(key, a, sectored ? (b0 + j) % nph : j, nth, nph);
-          int id;
-          float t;
-          bool fr;
-          trace_closest<COUNT>(g.nodes, g.tris, x, w, stk, id, t, fr, tc);
-          if (id < 0) t = box_exit(x, w, g.box_lo, g.box_hi);
+          const float3 w = row_direction(key, a, sectored ? (b0 + j) % nph : j, nth, nph);
+          float t = grouped ? gt : R.t[j];
+          const int code = grouped ? gcode : R.code[j];
+          if (code < 0) t = box_exit(x, w, g.box_lo, g.box_hi);
           int M = 0;
           while (M < MR && ring_distance(M, xr, g.ring_step) < t) M++;
           R.wx[j] = w.x;
           R.wy[j] = w.y;
           R.wz[j] = w.z;
           R.t[j] = t;
-          R.code[j] = id >= 0 ? ((id << 1) | (fr ? 1 : 0)) : -1;
+          R.code[j] = code;
           R.M[j] = M;
-          R.Ls[j] = id >= 0 ? g.emission[id] : 0.f;
+          R.Ls[j] = code >= 0 ? g.emission[code >> 1] : 0.f;
           R.visS[j] = 0;
           for (int i = 0; i < M; i++) reinterpret_cast<int*>(R.Lm)[i * cap + j] = 0;
           if (COUNT && own && j < n_cnt) n_rays++;
