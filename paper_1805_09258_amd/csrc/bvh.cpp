@@ -1,7 +1,12 @@
 // bvh.cpp -- host builder of the flat binary BVH traversed by the record
 // kernel.  Binned surface-area heuristic (32 bins per axis over centroid
 // bounds), leaves of at most kLeafMax triangles, object-median fallback when
-// the heuristic finds no split or the tree gets deep.  The paper relies on
+// the heuristic finds no split or the tree gets deep.  A node of at most
+// kLeafMax triangles is split further when the heuristic prices the split
+// below testing every triangle, with one traversal step and one triangle test
+// costing the same (each is one iteration of the kernel's traversal loop);
+// such splits stop at the depth that keeps the traversal stack of the plain
+// build, so a tighter tree never costs the kernel LDS.  The paper relies on
 // Embree for tracing (Sec. 6) and describes no acceleration structure; this
 // one is laid out for the GPU: both children's boxes in one 64-byte node, and
 // the triangles of a leaf contiguous in the order the leaf lists them.
@@ -100,9 +105,14 @@ struct Builder {
     return it - prims.begin();
   }
 
-  // Split [b, e) -> mid; returns mid (b < mid < e)
-  int64_t split(int64_t b, int64_t e, int depth) {
+  // depth below which nodes of at most kLeafMax triangles may still be split
+  int leaf_split_depth = 0;
+
+  // Split [b, e) -> mid; returns mid (b < mid < e).  leaf_cheaper (if given):
+  // the heuristic's best split costs no less than testing all triangles.
+  int64_t split(int64_t b, int64_t e, int depth, bool* leaf_cheaper = nullptr) {
     int64_t n = e - b;
+    if (leaf_cheaper) *leaf_cheaper = true;
     if (n > 2 * kLeafMax) {
       int64_t m = split_large(b, e);
       if (m > b && m < e) return m;
@@ -154,6 +164,12 @@ struct Builder {
         if (cost < best) { best = cost; best_axis = ax; best_bin = k; }
       }
     }
+    if (leaf_cheaper && best_axis >= 0) {
+      // cost of the split in triangle tests: one step for the node, then the
+      // children's triangles weighted by the chance of entering each child
+      const double A = bounds(b, e).area();
+      *leaf_cheaper = !(A > 0.0) || 1.0 + best / A >= (double)n;
+    }
     if (best_axis < 0) return median(axis);
     float lo = cb.lo[best_axis], w = cb.hi[best_axis] - cb.lo[best_axis];
     auto mid_it = std::partition(prims.begin() + b, prims.begin() + e, [&](const Prim& p) {
@@ -170,8 +186,10 @@ struct Builder {
   int32_t build(int64_t b, int64_t e, int depth) {
     max_depth_seen = std::max(max_depth_seen, depth);
     int64_t n = e - b;
-    if (n <= kLeafMax) return make_leaf(b, e);
-    int64_t mid = split(b, e, depth);
+    if (n <= kLeafMax && (n == 1 || depth + 1 >= leaf_split_depth)) return make_leaf(b, e);
+    bool leaf_cheaper = false;
+    int64_t mid = split(b, e, depth, n <= kLeafMax ? &leaf_cheaper : nullptr);
+    if (n <= kLeafMax && leaf_cheaper) return make_leaf(b, e);
     int64_t idx = (int64_t)nodes.size() / 16;
     nodes.resize(nodes.size() + 16, 0.f);
     Box l = bounds(b, mid), r = bounds(mid, e);
@@ -244,7 +262,22 @@ int build_bvh(const float* tri, int64_t T, float pad, HostBvh& out, std::string&
     }
     p.id = (int32_t)i;
   }
+  // plain build first (no splits below kLeafMax triangles) for its depth;
+  // the final build may split small nodes down to that depth's stack size
+  std::vector<Prim> prims0 = prims;
+  int leaf_split_depth = 0;
+  if (T > kLeafMax) {
+    std::vector<float> n0, t0;
+    Builder b0{prims, tri, 0.0f, n0, t0};
+    n0.resize(16, 0.f);
+    int64_t m0 = b0.split(0, T, 0);
+    b0.build(0, m0, 1);
+    b0.build(m0, T, 1);
+    leaf_split_depth = stack_variant(b0.max_depth_seen + 1);
+    prims = prims0;
+  }
   Builder bd{prims, tri, 0.0f, out.nodes, out.tris};
+  bd.leaf_split_depth = leaf_split_depth;
   // The root is always an internal node (the traversal starts by testing
   // both of its children).
   out.nodes.resize(16, 0.f);

@@ -28,6 +28,10 @@ struct HostBvh {
   float pad = 0.f;
 };
 
+// Traversal stack entries of the record kernel variant for a BVH of this
+// depth (16, 24, 32, 48 or 64; kernels.hip).
+int stack_variant(int depth);
+
 // Build on the host. pad = scene coordinate scale (bvh_pad_for).
 int build_bvh(const float* tri, int64_t T, float pad, HostBvh& out, std::string& err);
 
