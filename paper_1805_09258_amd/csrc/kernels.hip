@@ -108,10 +108,13 @@ RC_DEV void add_term2(float* acc, float* accc, const float* hi, const float* lo)
 }  // namespace
 
 template <int STACK, bool COUNT, bool F64>
-// Register budget for 3 wavefronts per SIMD (168 VGPRs; the compiler spills
-// a few values of the cooler phases): traversal is latency-bound, so more
-// resident wavefronts beat the spills.
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3, 3))) void record_kernel(RecordArgs g) {
+// Register budget for record_waves_per_simd(STACK) wavefronts per SIMD (the
+// compiler spills values of the cooler phases, none inside the traversal
+// loops): traversal is latency-bound, so more resident wavefronts beat the
+// spills.
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(record_waves_per_simd(STACK),
+                                                                     record_waves_per_simd(STACK)))) void
+record_kernel(RecordArgs g) {
   extern __shared__ float lds[];
   const int lane = threadIdx.x;
   const int cap = g.lds_cols;  // columns of an LDS row

@@ -50,6 +50,11 @@ struct RecordArgs {
 
 int stack_variant(int depth);
 size_t record_lds_bytes(int stack, int max_n_phi, int max_rings);
+// Resident wavefronts per SIMD the record kernel is compiled for: 4 (128
+// VGPRs) with a traversal stack of up to 24 entries, else 3 (168 VGPRs; a
+// deeper stack takes too much LDS for 16 wavefronts per CU to keep useful
+// row widths).  The LDS row width is chosen for the same occupancy.
+constexpr int record_waves_per_simd(int stack) { return stack <= 24 ? 4 : 3; }
 int record_occupancy(int stack, bool count, bool f64, size_t lds);
 hipError_t prepare_record(int stack, bool count, bool f64, size_t lds);
 hipError_t launch_record(const RecordArgs& a, int stack, bool count, bool f64, int grid, size_t lds, hipStream_t s);
