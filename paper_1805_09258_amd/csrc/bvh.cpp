@@ -6,7 +6,11 @@
 // below testing every triangle, with one traversal step and one triangle test
 // costing the same (each is one iteration of the kernel's traversal loop);
 // such splits stop at the depth that keeps the traversal stack of the plain
-// build, so a tighter tree never costs the kernel LDS.  The paper relies on
+// build, so a tighter tree never costs the kernel LDS.  When a tree bounded
+// to the next smaller stack (median splits wherever the heuristic's split
+// could not be finished as a balanced tree within the bound) prices within
+// 3 % of the unbounded one, the bounded tree is kept: its smaller stack lets
+// more wavefronts share a CU.  The paper relies on
 // Embree for tracing (Sec. 6) and describes no acceleration structure; this
 // one is laid out for the GPU: both children's boxes in one 64-byte node, and
 // the triangles of a leaf contiguous in the order the leaf lists them.
@@ -107,6 +111,20 @@ struct Builder {
 
   // depth below which nodes of at most kLeafMax triangles may still be split
   int leaf_split_depth = 0;
+  // bound on the final depth (0: none)
+  int depth_bound = 0;
+  // surface-area cost of the tree built so far: box area per node visit plus
+  // box area x triangles per leaf (one traversal step = one triangle test)
+  double sah = 0.0;
+
+  // a child of n triangles at depth d can still be finished as a balanced
+  // tree (leaves of kLeafMax) within depth_bound
+  bool fits(int64_t n, int d) const {
+    if (depth_bound <= 0) return true;
+    int64_t cap = kLeafMax;
+    for (int l = d; l < depth_bound - 1 && cap < (int64_t(1) << 40); l++) cap *= 2;
+    return n <= cap;
+  }
 
   // Split [b, e) -> mid; returns mid (b < mid < e).  leaf_cheaper (if given):
   // the heuristic's best split costs no less than testing all triangles.
@@ -115,7 +133,7 @@ struct Builder {
     if (leaf_cheaper) *leaf_cheaper = true;
     if (n > 2 * kLeafMax) {
       int64_t m = split_large(b, e);
-      if (m > b && m < e) return m;
+      if (m > b && m < e && fits(m - b, depth + 1) && fits(e - m, depth + 1)) return m;
     }
     Box cb;
     for (int64_t i = b; i < e; i++) cb.grow(prims[i].c, prims[i].c);
@@ -179,6 +197,7 @@ struct Builder {
     });
     int64_t mid = mid_it - prims.begin();
     if (mid <= b || mid >= e) return median(axis);
+    if (!fits(mid - b, depth + 1) || !fits(e - mid, depth + 1)) return median(best_axis);
     return mid;
   }
 
@@ -186,13 +205,23 @@ struct Builder {
   int32_t build(int64_t b, int64_t e, int depth) {
     max_depth_seen = std::max(max_depth_seen, depth);
     int64_t n = e - b;
-    if (n <= kLeafMax && (n == 1 || depth + 1 >= leaf_split_depth)) return make_leaf(b, e);
-    bool leaf_cheaper = false;
-    int64_t mid = split(b, e, depth, n <= kLeafMax ? &leaf_cheaper : nullptr);
-    if (n <= kLeafMax && leaf_cheaper) return make_leaf(b, e);
+    bool leaf = n <= kLeafMax && (n == 1 || depth + 1 >= leaf_split_depth);
+    int64_t mid = 0;
+    if (!leaf) {
+      bool leaf_cheaper = false;
+      mid = split(b, e, depth, n <= kLeafMax ? &leaf_cheaper : nullptr);
+      leaf = n <= kLeafMax && leaf_cheaper;
+    }
+    if (leaf) {
+      sah += bounds(b, e).area() * (double)n;
+      return make_leaf(b, e);
+    }
     int64_t idx = (int64_t)nodes.size() / 16;
     nodes.resize(nodes.size() + 16, 0.f);
     Box l = bounds(b, mid), r = bounds(mid, e);
+    Box lr = l;
+    lr.grow(r);
+    sah += lr.area();
     int32_t c0 = build(b, mid, depth + 1);
     int32_t c1 = build(mid, e, depth + 1);
     write_node(idx, l, r, c0, c1);
@@ -262,27 +291,32 @@ int build_bvh(const float* tri, int64_t T, float pad, HostBvh& out, std::string&
     }
     p.id = (int32_t)i;
   }
-  // plain build first (no splits below kLeafMax triangles) for its depth;
-  // the final build may split small nodes down to that depth's stack size
   std::vector<Prim> prims0 = prims;
-  int leaf_split_depth = 0;
-  if (T > kLeafMax) {
-    std::vector<float> n0, t0;
-    Builder b0{prims, tri, 0.0f, n0, t0};
-    n0.resize(16, 0.f);
-    int64_t m0 = b0.split(0, T, 0);
-    b0.build(0, m0, 1);
-    b0.build(m0, T, 1);
-    leaf_split_depth = stack_variant(b0.max_depth_seen + 1);
+  // One build of the whole tree (root always internal: the traversal starts
+  // by testing both of its children); returns its depth.
+  auto build_tree = [&](int leaf_split_depth, int depth_bound, std::vector<float>& nodes,
+                        std::vector<float>& tris, double& sah) {
     prims = prims0;
-  }
-  Builder bd{prims, tri, 0.0f, out.nodes, out.tris};
-  bd.leaf_split_depth = leaf_split_depth;
-  // The root is always an internal node (the traversal starts by testing
-  // both of its children).
-  out.nodes.resize(16, 0.f);
-  Box empty;  // inverted box: never hit
+    nodes.assign(16, 0.f);
+    tris.clear();
+    Builder bd{prims, tri, 0.0f, nodes, tris};
+    bd.leaf_split_depth = leaf_split_depth;
+    bd.depth_bound = depth_bound;
+    int64_t mid = bd.split(0, T, 0);
+    Box l = bd.bounds(0, mid), r = bd.bounds(mid, T);
+    Box lr = l;
+    lr.grow(r);
+    bd.sah = lr.area();
+    int32_t c0 = bd.build(0, mid, 1);
+    int32_t c1 = bd.build(mid, T, 1);
+    bd.write_node(0, l, r, c0, c1);
+    sah = bd.sah;
+    return bd.max_depth_seen + 1;
+  };
   if (T <= kLeafMax) {
+    Builder bd{prims, tri, 0.0f, out.nodes, out.tris};
+    out.nodes.resize(16, 0.f);
+    Box empty;  // inverted box: never hit
     int32_t c0 = T > 0 ? bd.make_leaf(0, T) : ~0;
     Box l = T > 0 ? bd.bounds(0, T) : empty;
     bd.write_node(0, l, empty, c0, ~0);
@@ -299,12 +333,24 @@ int build_bvh(const float* tri, int64_t T, float pad, HostBvh& out, std::string&
     out.depth = 1;
     return RC_OK;
   }
-  int64_t mid = bd.split(0, T, 0);
-  Box l = bd.bounds(0, mid), r = bd.bounds(mid, T);
-  int32_t c0 = bd.build(0, mid, 1);
-  int32_t c1 = bd.build(mid, T, 1);
-  bd.write_node(0, l, r, c0, c1);
-  out.depth = bd.max_depth_seen + 1;
+  // plain build (no splits below kLeafMax triangles): its depth sets the stack
+  double sah = 0.0;
+  std::vector<float> nodes_b, tris_b;
+  const int d0 = build_tree(0, 0, nodes_b, tris_b, sah);
+  const int s0 = stack_variant(d0);
+  // the tree the kernel gets: small nodes split down to that stack's depth
+  out.depth = build_tree(s0, 0, out.nodes, out.tris, sah);
+  // or a tree bounded to the next smaller stack, if it prices within 3 %
+  const int sb = s0 == 64 ? 48 : (s0 == 48 ? 32 : (s0 == 32 ? 24 : (s0 == 24 ? 16 : 0)));
+  if (sb > 0) {
+    double sah_b = 0.0;
+    const int db = build_tree(sb, sb, nodes_b, tris_b, sah_b);
+    if (db <= sb && sah_b <= 1.03 * sah) {
+      out.nodes.swap(nodes_b);
+      out.tris.swap(tris_b);
+      out.depth = db;
+    }
+  }
   if (out.depth > kMaxDepth) {
     err = "BVH deeper than the traversal stack";
     return RC_EINVAL;
