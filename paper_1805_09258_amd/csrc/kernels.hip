@@ -71,6 +71,17 @@ RC_DEV int find_slot(const int* off, int n, int x) {
   return lo;
 }
 
+// largest j in [0, n) with off[j] - j <= x (off[j] - j non-decreasing)
+RC_DEV int find_slot_minus(const int* off, int n, int x) {
+  int lo = 0, hi = n - 1;
+  while (lo < hi) {
+    int mid = (lo + hi + 1) >> 1;
+    if (off[mid] - mid <= x) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
+}
+
 // Direction of column `col` of row a: row -1 is the north pole, row nth the
 // south pole, rows 0..nth-1 the strata rows.
 RC_DEV float3 row_direction(uint64_t key, int a, int col, int nth, int nph) {
@@ -85,23 +96,20 @@ RC_DEV double wave_sum(double v) {
   return v;
 }
 
-// Add one term's 9 outputs (gradient 3, Hessian 6) to the compensated pairs of
-// channel OFF (0 surface, 9 medium).  The channel is a template argument so the
-// 18 accumulators keep compile-time indices and stay in registers.
-template <int OFF>
+// Add one term's 9 outputs (gradient 3, Hessian 6) to a channel's
+// compensated pairs.
 RC_DEV void add_term(float* acc, float* accc, const float* t) {
 #pragma unroll
-  for (int k = 0; k < 9; k++) kadd(acc[OFF + k], accc[OFF + k], t[k]);
+  for (int k = 0; k < 9; k++) kadd(acc[k], accc[k], t[k]);
 }
 
 // The same with each output given as an FP32 (hi, lo) split of an FP64 value:
 // hi then lo, per output.
-template <int OFF>
 RC_DEV void add_term2(float* acc, float* accc, const float* hi, const float* lo) {
 #pragma unroll
   for (int k = 0; k < 9; k++) {
-    kadd(acc[OFF + k], accc[OFF + k], hi[k]);
-    kadd(acc[OFF + k], accc[OFF + k], lo[k]);
+    kadd(acc[k], accc[k], hi[k]);
+    kadd(acc[k], accc[k], lo[k]);
   }
 }
 
@@ -499,14 +507,27 @@ record_kernel(RecordArgs g) {
         }
         const int total = carry;
         __syncthreads();
-        float acc[18], accc[18];
+        // Two passes, the surface terms (one per triangle) and then the medium
+        // terms, so each pass keeps only its channel's 9 compensated sums live.
+        // Triangle tI holds items off[tI] .. off[tI+1]-1: its surface term and
+        // then its medium rings, so its rings start at off[tI] - tI among the
+        // medium items.
+        for (int chn = 0; chn < 2; chn++) {
+        float acc[9], accc[9];
 #pragma unroll
-        for (int k = 0; k < 18; k++) { acc[k] = 0.f; accc[k] = 0.f; }
-        for (int base = 0; base < total; base += kWave) {
+        for (int k = 0; k < 9; k++) { acc[k] = 0.f; accc[k] = 0.f; }
+        const int n_items = chn == 0 ? ntri : total - ntri;
+        for (int base = 0; base < n_items; base += kWave) {
           int item = base + lane;
-          if (item >= total) continue;
-          int tI = find_slot(off, ntri, item);
-          int ring = item - off[tI] - 1;  // -1: surface ring
+          if (item >= n_items) continue;
+          int tI, ring;  // ring -1: surface ring
+          if (chn == 0) {
+            tI = item;
+            ring = -1;
+          } else {
+            tI = find_slot_minus(off, ntri, item);
+            ring = item - (off[tI] - tI);
+          }
           // the triangle's three vertices: (row pointer, column, global id)
           const float* vb[3];  // row base of each vertex
           int col[3], gid[3];
@@ -582,8 +603,7 @@ record_kernel(RecordArgs g) {
             V3<float> r3 = mk(tau[2] * wv[2].x, tau[2] * wv[2].y, tau[2] * wv[2].z);
             if (triangle_term<float>(r1, r2, r3, tau[0], tau[1], tau[2], (float)dw, far, wL, mu, gg, hh)) {
               const float t9[9] = {gg[0], gg[1], gg[2], hh[0], hh[1], hh[2], hh[3], hh[4], hh[5]};
-              if (ring < 0) add_term<0>(acc, accc, t9);
-              else add_term<9>(acc, accc, t9);
+              add_term(acc, accc, t9);
             }
           } else {
             // study mode: the whole term in FP64, folded into the compensated
@@ -608,18 +628,18 @@ record_kernel(RecordArgs g) {
                 hi[k] = (float)x;
                 lo[k] = (float)(x - (double)hi[k]);
               }
-              if (ring < 0) add_term2<0>(acc, accc, hi, lo);
-              else add_term2<9>(acc, accc, hi, lo);
+              add_term2(acc, accc, hi, lo);
             }
           }
           if (COUNT) n_terms++;
         }
         // band partial sums: lanes -> FP64 across the wave -> record accumulator
 #pragma unroll
-        for (int k = 0; k < 18; k++) {
+        for (int k = 0; k < 9; k++) {
           double sk = wave_sum((double)acc[k] + (double)accc[k]);
-          if (lane == 0) racc[2 + k] += sk;
+          if (lane == 0) racc[2 + 9 * chn + k] += sk;
         }
+        }  // channels
       }
       __syncthreads();
       if (COUNT) { uint64_t t = clock64(); cyc[3] += t - t_mark; t_mark = t; }
