@@ -240,7 +240,10 @@ def main():
                      "kernel": "record_kernel", "kernel_ms": kern_ms,
                      "alg_bytes_per_launch": alg_bytes,
                      "alg_bytes_per_ray": (nodes * NODE_BYTES + tris * TRI_BYTES) / max(rays, 1),
-                     "phase_clock_fraction": phase_frac},
+                     "phase_clock_fraction": phase_frac,
+                     "note": "achieved counts the algorithmic node and triangle fetches of the traversal; "
+                             "the BVH is served from L2/MALL, so frac can exceed 1 and the HBM bytes are "
+                             "in traffic"},
     }
     if not args.no_learned and args.workload == "c2":
         log("learned vs plain placement ...")
