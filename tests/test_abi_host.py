@@ -149,6 +149,19 @@ def test_bvh_structure_small_and_soup():
     _check_bvh(few, w1.box_lo, w1.box_hi)
 
 
+def test_bvh_structure_of_deeper_scenes():
+    """Scenes whose plain build needs a deeper traversal stack, so the builder
+    also prices a tree bounded to the next smaller stack and keeps one of
+    the two: whichever it keeps holds every triangle once, inside padded boxes,
+    and no deeper than it reports."""
+    w3 = W.make_c3(P=1, n_tri=20_000)
+    st = _check_bvh(w3.tri, w3.box_lo, w3.box_hi)
+    assert st["depth"] <= 24
+    w5 = W.make_c5(P=1, n_tri=60_000)
+    st = _check_bvh(w5.tri, w5.box_lo, w5.box_hi)
+    assert st["depth"] <= 24
+
+
 def test_bvh_padding_covers_fp32_hit_error():
     """The BVH pads each triangle's box by 2e-4 * scale / sin(beta_min).  The
     FP32 hit test (shared decision rule) must accept no point farther than a
