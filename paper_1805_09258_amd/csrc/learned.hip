@@ -718,6 +718,30 @@ RC_DEV bool within(float cx, float cy, float cz, float px, float py, float pz, f
   return dx * dx + dy * dy + dz * dz < R * R;
 }
 
+// Verdict of batch entry j from the entries i < j, one lane per i: 2 if an
+// accepted entry covers j, 0 if an undecided one does (and no accepted one),
+// else 1.  ps: x, y, z, R of the batch; status(i) reads entry i's state
+// (0 undecided, 1 accepted, 2 rejected).  Called by all 64 lanes of a wave.
+template <typename Status>
+RC_DEV int wave_verdict(const float4* ps, int j, Status status, int lane) {
+  const float4 pj = ps[j];
+  bool und = false;
+  for (int i0 = 0; i0 < j; i0 += kWave) {
+    const int i = i0 + lane;
+    bool acc = false;
+    if (i < j) {
+      const float4 pi = ps[i];
+      if (within(pj.x, pj.y, pj.z, pi.x, pi.y, pi.z, pi.w)) {
+        const int si = status(i);
+        acc = si == 1;
+        und = und || si == 0;
+      }
+    }
+    if (__ballot(acc)) return 2;
+  }
+  return __ballot(und) ? 0 : 1;
+}
+
 __global__ __launch_bounds__(kPlaceThreads) void place_gather_kernel(const float* __restrict__ cand,
                                                                      const float* __restrict__ radius,
                                                                      const int* __restrict__ order, int C,
@@ -777,43 +801,33 @@ __global__ __launch_bounds__(kPlaceThreads) void place_gather_kernel(const float
   }
 }
 
-// One pass of the fixed point below, spread over many workgroups: every
-// undecided entry j scans the entries i < j (positions staged in LDS) and is
-// rejected by an accepted coverer, accepted when all its coverers are
-// rejected, else left undecided.  Status words (state[kPlaceStatus + j]) only
-// ever go from undecided to decided, so passes racing with each other are
-// harmless.
-__global__ __launch_bounds__(256) void place_resolve_kernel(const float* __restrict__ cand,
-                                                            const int* __restrict__ batch_idx,
-                                                            const float* __restrict__ batch_R,
-                                                            int* __restrict__ state) {
+// One pass of the fixed point below, spread over many workgroups: each wave
+// takes one undecided entry j, its lanes scan the entries i < j (positions
+// staged in LDS), and j is rejected by an accepted coverer, accepted when all
+// its coverers are rejected, else left undecided.  Status words
+// (state[kPlaceStatus + j]) only ever go from undecided to decided, so passes
+// racing with each other are harmless.
+__global__ __launch_bounds__(kPlaceResolveThreads) void place_resolve_kernel(const float* __restrict__ cand,
+                                                                           const int* __restrict__ batch_idx,
+                                                                           const float* __restrict__ batch_R,
+                                                                           int* __restrict__ state) {
   __shared__ float4 ps[kPlaceMaxBatch];
+  constexpr int kWaves = kPlaceResolveThreads / kWave;
   const int m = min(state[4], kPlaceMaxBatch);
-  const int j0 = blockIdx.x * 256;
+  const int j0 = blockIdx.x * kWaves;
   if (j0 >= m) return;
-  const int jn = min(m, j0 + 256);  // entries i < jn are read
-  for (int i = threadIdx.x; i < jn; i += 256) {
+  const int jn = min(m, j0 + kWaves);  // entries i < jn are read
+  for (int i = threadIdx.x; i < jn; i += kPlaceResolveThreads) {
     const int c = batch_idx[i];
     ps[i] = make_float4(cand[3 * c], cand[3 * c + 1], cand[3 * c + 2], batch_R[i]);
   }
   __syncthreads();
-  const int j = j0 + threadIdx.x;
+  const int lane = threadIdx.x & (kWave - 1);
+  const int j = j0 + threadIdx.x / kWave;
   volatile int* stv = state + kPlaceStatus;
   if (j >= m || stv[j] != 0) return;
-  const float4 pj = ps[j];
-  int verdict = 1;
-  for (int i = 0; i < j; i++) {
-    const float4 pi = ps[i];
-    if (within(pj.x, pj.y, pj.z, pi.x, pi.y, pi.z, pi.w)) {
-      const int si = stv[i];
-      if (si == 1) {
-        verdict = 2;
-        break;
-      }
-      if (si == 0) verdict = 0;
-    }
-  }
-  if (verdict != 0) stv[j] = verdict;
+  const int verdict = wave_verdict(ps, j, [stv](int i) { return stv[i]; }, lane);
+  if (verdict != 0 && lane == 0) stv[j] = verdict;
 }
 
 // Batch entry j is accepted iff no accepted entry i < j covers it.  Each pass
@@ -844,25 +858,17 @@ __global__ __launch_bounds__(kPlaceThreads) void place_accept_kernel(
     if (t == 0) s_und = 0;
     __syncthreads();
     int und = 0;
-    for (int j = t; j < m; j += kPlaceThreads) {
-      if (st[j] != 0) continue;
-      const float4 pj = ps[j];
-      int verdict = 1;
-      for (int i = 0; i < j; i++) {
-        const float4 pi = ps[i];
-        if (within(pj.x, pj.y, pj.z, pi.x, pi.y, pi.z, pi.w)) {
-          const int si = *(volatile unsigned char*)&st[i];
-          if (si == 1) {
-            verdict = 2;
-            break;
-          }
-          if (si == 0) verdict = 0;
-        }
+    for (int j = wv; j < m; j += kPlaceThreads / kWave) {  // one wave per entry
+      if (*(volatile unsigned char*)&st[j] != 0) continue;
+      volatile unsigned char* stv = st;
+      const int verdict = wave_verdict(ps, j, [stv](int i) { return (int)stv[i]; }, lane);
+      if (verdict != 0) {
+        if (lane == 0) *(volatile unsigned char*)&st[j] = (unsigned char)verdict;
+      } else {
+        und++;
       }
-      if (verdict != 0) *(volatile unsigned char*)&st[j] = (unsigned char)verdict;
-      else und++;
     }
-    if (und) atomicAdd(&s_und, und);
+    if (und && lane == 0) atomicAdd(&s_und, und);
     __syncthreads();
     if (s_und == 0) break;
   }
@@ -1113,8 +1119,8 @@ hipError_t launch_place_accept(const float* cand, const int* batch_idx, const fl
   // a few wide passes decide almost every entry; the one-workgroup kernel
   // finishes whatever chains of coverers remain and appends the result
   for (int pass = 0; pass < kPlacePasses; pass++)
-    hipLaunchKernelGGL(place_resolve_kernel, dim3(kPlaceMaxBatch / 256), dim3(256), 0, s, cand, batch_idx, batch_R,
-                       state);
+    hipLaunchKernelGGL(place_resolve_kernel, dim3(kPlaceMaxBatch / (kPlaceResolveThreads / kWave)),
+                       dim3(kPlaceResolveThreads), 0, s, cand, batch_idx, batch_R, state);
   hipLaunchKernelGGL(place_accept_kernel, dim3(1), dim3(kPlaceThreads), 0, s, cand, batch_idx, batch_R, covered, state,
                      accepted, accepted_R, accepted_pos, bval, bgrad, cval, cgrad);
   return hipGetLastError();

@@ -20,6 +20,7 @@ constexpr int kPlaceMaxBatch = 4096;  // candidates gathered / decided per round
 constexpr int kPlaceThreads = 1024;   // one workgroup for gather and accept
 constexpr int kPlaceStatus = 5;       // state[5 + j]: batch entry j undecided (0), accepted (1), rejected (2)
 constexpr int kPlacePasses = 3;       // wide resolve passes before the final one-workgroup pass
+constexpr int kPlaceResolveThreads = 1024;  // 16 waves per resolve workgroup, one batch entry each
 static_assert(RC_PLACE_STATE_INTS == kPlaceStatus + kPlaceMaxBatch, "placement state layout");
 
 // cell grid of grid candidates: index (ix * ny + iy) * nz + iz
