@@ -50,6 +50,12 @@ RC_DEV float3 stratum_direction(uint64_t key, int a, int b, int nth, int nph) {
 
 RC_DEV float ring_distance(int i, float xi, float step) { return ((float)i + xi) * step; }
 
+// Set bits of a wavefront mask below the calling lane (mbcnt: nothing held
+// across loop iterations, unlike a materialised lane mask).
+RC_DEV int mask_rank(uint64_t m) {
+  return (int)__builtin_amdgcn_mbcnt_hi((unsigned)(m >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)m, 0u));
+}
+
 // ---------------------------------------------------------------------------
 // FP32 vector helpers (decision formulas: no fused operations)
 // ---------------------------------------------------------------------------

@@ -314,7 +314,7 @@ record_kernel(RecordArgs g) {
           const bool need = refill && !active;
           const uint64_t want = refill ? idle : 0ull;
           if (need) {
-            int rank = __popcll(want & __lanemask_lt());
+            int rank = mask_rank(want);
             task = next + rank;
             if (task < total) {
               active = true;

@@ -109,7 +109,7 @@ __global__ __launch_bounds__(64) void probe_kernel(ProbeArgs g) {
         const uint64_t idle = __ballot(!active);
         if (next < total && (__popcll(idle) >= 8 || idle == ~0ull)) {
           if (!active) {
-            const int task = next + __popcll(idle & __lanemask_lt());
+            const int task = next + mask_rank(idle);
             if (task < total) {
               active = true;
               if (task < kWave * g.n_lights) {
