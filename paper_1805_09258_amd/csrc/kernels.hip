@@ -300,7 +300,8 @@ record_kernel(RecordArgs g) {
           carry += __shfl(inc, kWave - 1, kWave);
         }
         const int nvert = carry;
-        const int total = nvert * g.n_lights;
+        // wave-uniform counts, kept in scalar registers
+        const int total = __builtin_amdgcn_readfirstlane(nvert * g.n_lights);
         __syncthreads();
         int next = 0;          // next unassigned task (wave-uniform)
         bool active = false;
@@ -348,7 +349,7 @@ record_kernel(RecordArgs g) {
               if (COUNT && own && j < n_cnt) n_rays++;
             }
           }
-          next += __popcll(want);
+          next = __builtin_amdgcn_readfirstlane(next + __popcll(want));
           if (__ballot(active) == 0ull) {
             if (next >= total) break;
             continue;
