@@ -361,6 +361,11 @@ record_kernel(RecordArgs g) {
             // padding so the fourth load of the last triangle stays in bounds)
             const float4* src = (ln > 0) ? (g.tris + 3 * lf) : (g.nodes + 4 * node);
             const float4 q0 = src[0], q1 = src[1], q2 = src[2], q3 = src[3];
+            // next: the code to visit next (a node >= 0, a leaf < 0, kEnd when
+            // the stack is exhausted) or kStay to go on in the current leaf
+            constexpr int kEnd = 0x7fffffff, kStay = 0x7ffffffe;
+            int nx = kStay;
+            bool pop = false;
             if (ln > 0) {
               if (COUNT) tc.tris++;
               float t;
@@ -371,19 +376,7 @@ record_kernel(RecordArgs g) {
               } else {
                 lf++;
                 ln--;
-                if (ln == 0) {
-                  if (sp == 0) {
-                    done = true;
-                  } else {
-                    const int c = stk[--sp * kWave];
-                    if (c < 0) {  // a postponed leaf
-                      lf = leaf_first(c);
-                      ln = leaf_count(c);
-                    } else {
-                      node = c;
-                    }
-                  }
-                }
+                pop = ln == 0;
               }
             } else {
               if (COUNT) tc.nodes++;
@@ -391,18 +384,20 @@ record_kernel(RecordArgs g) {
               const float tb = slab(q1.x, q1.y, q1.z, q1.w, q2.z, q2.w, inv, oi, 0.0f, 1.0f);
               const int ca = __float_as_int(q3.x), cb = __float_as_int(q3.y);
               const bool ha = ta < __builtin_huge_valf(), hb = tb < __builtin_huge_valf();
-              int nx;
               if (ha && hb) {
                 nx = ta <= tb ? ca : cb;
                 stk[sp++ * kWave] = ta <= tb ? cb : ca;
               } else if (ha || hb) {
                 nx = ha ? ca : cb;
               } else {
-                nx = sp == 0 ? 0x7fffffff : stk[--sp * kWave];
+                pop = true;
               }
-              if (nx == 0x7fffffff) {
-                done = true;
-              } else if (nx < 0) {
+            }
+            if (pop) nx = sp == 0 ? kEnd : stk[--sp * kWave];
+            if (nx == kEnd) {
+              done = true;
+            } else if (nx != kStay) {
+              if (nx < 0) {  // a leaf
                 lf = leaf_first(nx);
                 ln = leaf_count(nx);
               } else {
