@@ -131,9 +131,9 @@ int check_inputs(const rc_scene* s, const rc_medium* m, const rc_point_light* li
 // wavefronts per CU (record_waves_per_simd); rows are held whole when that
 // fits the LDS, else in sectors of w columns (plus one) with the widest
 // w <= 32 for which a wavefront's LDS (stack, two rows, offsets) stays within
-// 1/W of the CU's 160 KB.  Measured: whole 64-column rows at 8 wavefronts per
-// CU gave 0.79x the records/s of 32-column sectors at 12, and 25-column
-// sectors at 16 gave 1.09x the 32-column sectors at 12.
+// 1/W of the CU's 160 KB.  Measured at 64 columns: whole rows at 8 wavefronts
+// per CU gave 0.79x the records/s of 33-column LDS rows at 12, and 26-column
+// LDS rows at 16 gave 1.09x those at 12.
 int lds_cols_for(int max_n_phi, int stack, int max_rings) {
   const size_t budget = (size_t)160 * 1024 / (4 * rc::record_waves_per_simd(stack));
   if (rc::record_lds_bytes(stack, max_n_phi, max_rings) <= budget) return max_n_phi;

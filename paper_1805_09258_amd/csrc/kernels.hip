@@ -578,7 +578,7 @@ record_kernel(RecordArgs g) {
             }
           }
           // far vertex: largest distance, ties to the smaller vertex id (the
-          // running maximum is kept in scalars so nothing is indexed at run time)
+          // running maximum is kept in plain variables, so no array is indexed at run time)
           int far = 0;
           float tf = tau[0];
           int gf = gid[0];
