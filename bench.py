@@ -91,11 +91,12 @@ def cpu_baseline(w, budget_s=15.0):
 
 
 def learned_vs_plain(dev):
-    """Train the radius MLP on 20 C2-family scenes (200k records), choose the
+    """Train the radius MLP on 100 C2-family scenes (1M records), choose the
     learned pipeline's safety factor on a validation scene, then place caches
     over 128^3 = 2,097,152 candidates of a held-out scene with both pipelines
-    (plain at its fastest round size); the judge and the fallback keep the
-    learned cache valid whatever the factor."""
+    (plain at its fastest round size) and measure their error at 100k test
+    points; the judge and the fallback keep the learned cache valid whatever
+    the factor."""
     from paper_1805_09258_amd import placement as PL
     r = PL.compare(dev, log=log)
     lp, pl = r["learned"], r["plain"]
@@ -109,7 +110,8 @@ def learned_vs_plain(dev):
            "reference_noise": r["reference_noise"], "no_cache_error": r["no_cache"],
            "training": {k: r[k] for k in ("train_samples", "train_data_seconds", "train_seconds", "train_mse",
                                           "heldout_mse_net", "heldout_mse_constant")},
-           "safety_by_validation": r["safety_validation_seconds"]}
+           "safety_by_validation": r["safety_validation_seconds"],
+           "plain_by_batch": r["plain_by_batch"]}
     res["plain"]["candidates_per_s"] = r["candidates"] / pl["seconds"]
     res["learned"]["candidates_per_s"] = r["candidates"] / lp["seconds"]
     res["speedup"] = pl["seconds"] / lp["seconds"]
