@@ -195,6 +195,69 @@ RC_DEV void trace_closest(const float4* __restrict__ nodes, const float4* __rest
   }
 }
 
+// The same closest hit as trace_closest, one node or one triangle per loop
+// iteration with a single stack pop and dispatch for both kinds of step
+// (fewer divergent branches when the lanes of a wavefront trace different
+// rays in lockstep).
+template <bool COUNT>
+RC_DEV void trace_closest_steps(const float4* __restrict__ nodes, const float4* __restrict__ tris, float3 o, float3 d,
+                                int* stk, int& best_id, float& best_t, bool& best_front, TraceCount& cnt) {
+  constexpr int kEnd = 0x7fffffff, kStay = 0x7ffffffe;
+  const float dd = dot3(d, d);
+  float3 inv, oi;
+  ray_inv(d, o, inv, oi);
+  best_id = -1;
+  best_t = __builtin_huge_valf();
+  best_front = false;
+  int sp = 0, node = 0, lf = 0, ln = 0;
+  while (true) {
+    const float4* src = (ln > 0) ? (tris + 3 * lf) : (nodes + 4 * node);
+    const float4 q0 = src[0], q1 = src[1], q2 = src[2], q3 = src[3];
+    int nx = kStay;
+    bool pop = false;
+    if (ln > 0) {
+      if (COUNT) cnt.tris++;
+      float t;
+      bool fr;
+      if (hit_triangle(o, d, dd, q0, q1, q2, 0.0f, __builtin_huge_valf(), t, fr)) {
+        const int id = __float_as_int(q0.w);
+        if (t < best_t || (t == best_t && id < best_id)) {
+          best_t = t;
+          best_id = id;
+          best_front = fr;
+        }
+      }
+      lf++;
+      ln--;
+      pop = ln == 0;
+    } else {
+      if (COUNT) cnt.nodes++;
+      const float ta = slab(q0.x, q0.y, q0.z, q0.w, q2.x, q2.y, inv, oi, 0.0f, best_t);
+      const float tb = slab(q1.x, q1.y, q1.z, q1.w, q2.z, q2.w, inv, oi, 0.0f, best_t);
+      const int ca = __float_as_int(q3.x), cb = __float_as_int(q3.y);
+      const bool ha = ta < __builtin_huge_valf(), hb = tb < __builtin_huge_valf();
+      if (ha && hb) {
+        nx = ta <= tb ? ca : cb;
+        stk[sp++ * kWave] = ta <= tb ? cb : ca;
+      } else if (ha || hb) {
+        nx = ha ? ca : cb;
+      } else {
+        pop = true;
+      }
+    }
+    if (pop) nx = sp == 0 ? kEnd : stk[--sp * kWave];
+    if (nx == kEnd) return;
+    if (nx != kStay) {
+      if (nx < 0) {
+        lf = leaf_first(nx);
+        ln = leaf_count(nx);
+      } else {
+        node = nx;
+      }
+    }
+  }
+}
+
 // Shadow segment o -> o + d: blocked iff some triangle other than `skip` is
 // hit with 1e-4 < t < 1.
 template <bool COUNT>
