@@ -136,71 +136,12 @@ RC_DEV float slab(float lx, float hx, float ly, float hy, float lz, float hz, fl
   return tn <= tf ? tn : __builtin_huge_valf();
 }
 
+// Closest hit (smallest t, ties to the lowest triangle id): one node or one
+// triangle per loop iteration, with a single stack pop and dispatch for both
+// kinds of step (fewer divergent branches when the lanes of a wavefront trace
+// different rays in lockstep).
 template <bool COUNT>
 RC_DEV void trace_closest(const float4* __restrict__ nodes, const float4* __restrict__ tris, float3 o, float3 d,
-                          int* stk, int& best_id, float& best_t, bool& best_front, TraceCount& cnt) {
-  float dd = dot3(d, d);
-  float3 inv, oi;
-  ray_inv(d, o, inv, oi);
-  best_id = -1;
-  best_t = __builtin_huge_valf();
-  best_front = false;
-  int sp = 0;
-  int node = 0;
-  while (true) {
-    while (node >= 0) {
-      const float4* nd = nodes + 4 * node;
-      float4 w0 = nd[0], w1 = nd[1], w2 = nd[2], w3 = nd[3];
-      if (COUNT) cnt.nodes++;
-      float ta = slab(w0.x, w0.y, w0.z, w0.w, w2.x, w2.y, inv, oi, 0.0f, best_t);
-      float tb = slab(w1.x, w1.y, w1.z, w1.w, w2.z, w2.w, inv, oi, 0.0f, best_t);
-      int ca = __float_as_int(w3.x), cb = __float_as_int(w3.y);
-      // slab() clamps to best_t and returns +inf on a miss
-      bool ha = ta < __builtin_huge_valf(), hb = tb < __builtin_huge_valf();
-      if (ha && hb) {
-        int nearc = ta <= tb ? ca : cb, farc = ta <= tb ? cb : ca;
-        stk[sp * kWave] = farc;
-        sp++;
-        node = nearc;
-      } else if (ha) {
-        node = ca;
-      } else if (hb) {
-        node = cb;
-      } else {
-        if (sp == 0) return;
-        sp--;
-        node = stk[sp * kWave];
-      }
-    }
-    // leaf
-    int first = leaf_first(node), n = leaf_count(node);
-    for (int k = 0; k < n; k++) {
-      const float4* tr = tris + 3 * (first + k);
-      float4 A = tr[0], B = tr[1], C = tr[2];
-      if (COUNT) cnt.tris++;
-      float t;
-      bool fr;
-      if (hit_triangle(o, d, dd, A, B, C, 0.0f, __builtin_huge_valf(), t, fr)) {
-        int id = __float_as_int(A.w);
-        if (t < best_t || (t == best_t && id < best_id)) {
-          best_t = t;
-          best_id = id;
-          best_front = fr;
-        }
-      }
-    }
-    if (sp == 0) return;
-    sp--;
-    node = stk[sp * kWave];
-  }
-}
-
-// The same closest hit as trace_closest, one node or one triangle per loop
-// iteration with a single stack pop and dispatch for both kinds of step
-// (fewer divergent branches when the lanes of a wavefront trace different
-// rays in lockstep).
-template <bool COUNT>
-RC_DEV void trace_closest_steps(const float4* __restrict__ nodes, const float4* __restrict__ tris, float3 o, float3 d,
                                 int* stk, int& best_id, float& best_t, bool& best_front, TraceCount& cnt) {
   constexpr int kEnd = 0x7fffffff, kStay = 0x7ffffffe;
   const float dd = dot3(d, d);

@@ -238,7 +238,7 @@ record_kernel(RecordArgs g) {
             int id;
             float t;
             bool fr;
-            trace_closest_steps<COUNT>(g.nodes, g.tris, x, w, stk, id, t, fr, tc);
+            trace_closest<COUNT>(g.nodes, g.tris, x, w, stk, id, t, fr, tc);
             const int code = id >= 0 ? ((id << 1) | (fr ? 1 : 0)) : -1;
             if (g_hi == a) {
               R.t[c] = t;
