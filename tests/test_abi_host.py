@@ -162,6 +162,23 @@ def test_bvh_structure_of_deeper_scenes():
     assert st["depth"] <= 24
 
 
+def test_bvh_structure_of_degenerate_scenes():
+    """Coincident triangles (zero centroid extent: median splits only) and
+    triangles strung along one line (one useful split axis) still give a valid
+    tree, with the small-node and depth rules in play."""
+    rng = np.random.default_rng(7)
+    lo, hi = np.zeros(3, np.float32), np.ones(3, np.float32)
+    one = np.array([0.4, 0.4, 0.4, 0.45, 0.4, 0.4, 0.4, 0.45, 0.42], np.float32)
+    same = np.tile(one, (300, 1))
+    st = _check_bvh(same, lo, hi)
+    assert st["n_tri"] == 300
+    x = np.sort(rng.uniform(0.05, 0.9, 5000)).astype(np.float32)
+    line = np.stack([x, np.full_like(x, 0.5), np.full_like(x, 0.5), x + 0.01, np.full_like(x, 0.5),
+                     np.full_like(x, 0.5), x, np.full_like(x, 0.51), np.full_like(x, 0.5)], axis=1)
+    st = _check_bvh(line, lo, hi)
+    assert st["depth"] <= 24
+
+
 def test_bvh_padding_covers_fp32_hit_error():
     """The BVH pads each triangle's box by 2e-4 * scale / sin(beta_min).  The
     FP32 hit test (shared decision rule) must accept no point farther than a
