@@ -31,7 +31,7 @@ namespace {
 // ring radiance [ring][column] (holding light-visibility bits until shaded).
 constexpr int kRowFields = 8;
 // idle lanes that trigger a refill of the shadow-ray loop
-constexpr int kRefillMin = 8;
+constexpr int kRefillMin = 12;
 struct Row {
   float *wx, *wy, *wz, *t, *Ls, *Lm;
   int *code, *M, *visS;
