@@ -51,9 +51,12 @@
  * furthest, which quad diagonal is used) are taken here in FP32 with the same
  * published formulas, so that both sides take the same decisions; the FP64
  * values are then recomputed from those decisions.  The decision rules are:
- *   - ray/triangle: Moller-Trumbore (1997) in FP32 on (v0, e1=v1-v0,
- *     e2=v2-v0), no fused multiply-add, rejecting rays within ~0.6 degrees of
- *     the triangle plane (det^2 <= 1e-4 |d|^2 |e1 x e2|^2);
+ *   - ray/triangle: the watertight test of Woop, Benthin and Wald (JCGT
+ *     2013) in a division-free form (see wt32): FP32 projection of the
+ *     vertices along the ray, 2-D edge functions with exact signs (FP64
+ *     from the FP32 points), so every ray that meets a closed mesh hits it,
+ *     at any angle and any distance from a surface (Sec. 4 takes each
+ *     sample at the first surface seen from x);
  *   - closest hit: smallest FP32 t, ties to the lowest triangle index;
  *   - shadow rays: segment y -> light, hit if 1e-4 < t < 1 (t in units of the
  *     unnormalised segment), the surface vertex's own triangle excluded;
@@ -114,8 +117,7 @@ static double d3_norm(const double* a) { return sqrt(d3_dot(a, a)); }
 /* ------------------------------------------------------------------ */
 typedef struct {
   int64_t T;
-  f3 *v0, *e1, *e2;   /* FP32 decision data */
-  float* nn;          /* |e1 x e2|^2 in FP32 */
+  f3 *v0, *v1, *v2;   /* FP32 vertices (decision data) */
   double* n64;        /* unit geometric normal e1 x e2 (FP64 from the FP32 vertices) [T][3] */
   double* v064;       /* v0 in FP64 [T][3] */
   float *albedo, *emission;
@@ -139,20 +141,16 @@ static uint64_t morton_expand(uint64_t v) { /* 21 bits -> every third bit */
   v = (v | v << 2) & 0x1249249249249249ULL;
   return v;
 }
-/* Padding of a triangle's box: the FP32 hit test can accept points about
- * 4e-5 * scale / sin(smallest angle) away from the exact triangle; pad by
- * 50 times that (capped at the scene scale) so culling never removes a
- * triangle the test would accept. */
-static double tri_pad(const float* t, double scale) {
-  double e1[3], e2[3], e3[3];
-  for (int k = 0; k < 3; k++) { e1[k] = (double)t[3 + k] - t[k]; e2[k] = (double)t[6 + k] - t[k]; e3[k] = (double)t[6 + k] - t[3 + k]; }
-  double c[3]; d3_cross(e1, e2, c);
-  double a2 = d3_norm(c), L[3] = {d3_norm(e1), d3_norm(e2), d3_norm(e3)};
-  for (int i = 0; i < 2; i++) for (int j = 0; j < 2 - i; j++) if (L[j] > L[j + 1]) { double x = L[j]; L[j] = L[j + 1]; L[j + 1] = x; }
-  double sinb = (L[1] * L[2] > 0) ? a2 / (L[1] * L[2]) : 0.0;
-  double p = sinb > 0 ? 2e-3 * scale / sinb : scale;
-  return p < scale ? p : scale;
-}
+/* Padding of the triangle boxes.  A hit accepted by wt32 lies at a point
+ * o + t d that is a convex combination of the vertices, each moved by at most
+ * ~8 units of FP32 rounding (2^-24) times the largest vertex-to-origin
+ * coordinate: the FP32 projection and the FP32 rounding of t are the only
+ * inexact steps (the barycentric weights are FP64 with exact signs).  So every
+ * accepted hit point lies within 16 * 2^-24 * scale of the triangle's box
+ * (scale = the medium box's largest side, which bounds every vertex-to-origin
+ * distance); the boxes are padded by 2^-16 * scale, 16 times that bound, so
+ * culling never removes a triangle the test would accept. */
+static double tri_pad(double scale) { return ldexp(scale, -16); }
 typedef struct { uint64_t key; int64_t idx; } kv;
 static int kv_cmp(const void* a, const void* b) {
   const kv* x = (const kv*)a; const kv* y = (const kv*)b;
@@ -163,7 +161,7 @@ static int kv_cmp(const void* a, const void* b) {
 
 void rco_scene_destroy(rco_scene* s) {
   if (!s) return;
-  free(s->v0); free(s->e1); free(s->e2); free(s->nn); free(s->n64); free(s->v064);
+  free(s->v0); free(s->v1); free(s->v2); free(s->n64); free(s->v064);
   free(s->albedo); free(s->emission); free(s->perm);
   if (s->lev_box) for (int l = 0; l < s->nlev; l++) free(s->lev_box[l]);
   free(s->lev_box); free(s->lev_n);
@@ -177,12 +175,12 @@ int rco_scene_create(const float* tri, const float* albedo, const float* emissio
   if (!s) return RCO_ENOMEM;
   s->T = T;
   int64_t Tn = T > 0 ? T : 1;
-  s->v0 = (f3*)malloc(sizeof(f3) * Tn); s->e1 = (f3*)malloc(sizeof(f3) * Tn); s->e2 = (f3*)malloc(sizeof(f3) * Tn);
-  s->nn = (float*)malloc(sizeof(float) * Tn); s->n64 = (double*)malloc(sizeof(double) * 3 * Tn);
+  s->v0 = (f3*)malloc(sizeof(f3) * Tn); s->v1 = (f3*)malloc(sizeof(f3) * Tn); s->v2 = (f3*)malloc(sizeof(f3) * Tn);
+  s->n64 = (double*)malloc(sizeof(double) * 3 * Tn);
   s->v064 = (double*)malloc(sizeof(double) * 3 * Tn);
   s->albedo = (float*)malloc(sizeof(float) * Tn); s->emission = (float*)calloc(Tn, sizeof(float));
   s->perm = (int64_t*)malloc(sizeof(int64_t) * Tn);
-  if (!s->v0 || !s->e1 || !s->e2 || !s->nn || !s->n64 || !s->v064 || !s->albedo || !s->emission || !s->perm) {
+  if (!s->v0 || !s->v1 || !s->v2 || !s->n64 || !s->v064 || !s->albedo || !s->emission || !s->perm) {
     rco_scene_destroy(s); return RCO_ENOMEM;
   }
   s->lo.x = box_lo[0]; s->lo.y = box_lo[1]; s->lo.z = box_lo[2];
@@ -192,9 +190,7 @@ int rco_scene_create(const float* tri, const float* albedo, const float* emissio
   for (int64_t j = 0; j < T; j++) {
     const float* t = tri + 9 * j;
     f3 a = {t[0], t[1], t[2]}, b = {t[3], t[4], t[5]}, c = {t[6], t[7], t[8]};
-    s->v0[j] = a; s->e1[j] = f3_sub(b, a); s->e2[j] = f3_sub(c, a);
-    f3 n = f3_cross(s->e1[j], s->e2[j]);
-    s->nn[j] = f3_dot(n, n);
+    s->v0[j] = a; s->v1[j] = b; s->v2[j] = c;
     double A[3] = {t[0], t[1], t[2]}, B[3] = {t[3], t[4], t[5]}, C[3] = {t[6], t[7], t[8]};
     double E1[3] = {B[0] - A[0], B[1] - A[1], B[2] - A[2]}, E2[3] = {C[0] - A[0], C[1] - A[1], C[2] - A[2]};
     double N[3]; d3_cross(E1, E2, N);
@@ -243,7 +239,7 @@ int rco_scene_create(const float* tri, const float* albedo, const float* emissio
       for (int64_t c = i * RCO_FAN; c < (i + 1) * RCO_FAN && c < nprev; c++) {
         if (l == 0) {
           const float* t = tri + 9 * s->perm[c];
-          double pd = tri_pad(t, s->pad);
+          double pd = tri_pad(s->pad);
           for (int k = 0; k < 9; k++) {
             b[k % 3] = fmin(b[k % 3], (double)t[k] - pd);
             b[3 + k % 3] = fmax(b[3 + k % 3], (double)t[k] + pd);
@@ -262,27 +258,56 @@ int rco_scene_create(const float* tri, const float* albedo, const float* emissio
 }
 
 /* ------------------------------------------------------------------ */
-/* FP32 decision: Moller-Trumbore                                       */
+/* FP32 decision: watertight ray/triangle test                          */
 /* ------------------------------------------------------------------ */
-/* returns 1 on a hit with tmin < t < tmax; *front = 1 if the ray travels
- * against the geometric normal e1 x e2 (origin on the normal's side). */
-static int mt32(const rco_scene* s, int64_t j, f3 o, f3 d, float dd, float tmin, float tmax,
-                float* tout, int* front) {
-  f3 e1 = s->e1[j], e2 = s->e2[j];
-  f3 p = f3_cross(d, e2);
-  float det = f3_dot(e1, p);
-  if (!(det * det > 1e-4f * (dd * s->nn[j]))) return 0;
-  f3 sv = f3_sub(o, s->v0[j]);
-  float u = f3_dot(sv, p);
-  f3 q = f3_cross(sv, e1);
-  float v = f3_dot(d, q);
-  float tn = f3_dot(e2, q);
-  int fr = 1;
-  if (det < 0.0f) { det = -det; u = -u; v = -v; tn = -tn; fr = 0; }
-  if (u < 0.0f || v < 0.0f || u + v > det) return 0;
-  float t = tn / det;
+/* Woop, Benthin and Wald, "Watertight Ray/Triangle Intersection", JCGT 2(1),
+ * 2013, written without divisions.  With kz the axis of the largest |d|
+ * component (ties to the lower axis) and (kx, ky) = (kz+1, kz+2) mod 3, each
+ * vertex v is projected along the ray to the 2-D point
+ *   p(v) = (d_kz a_kx - d_kx a_kz,  d_kz a_ky - d_ky a_kz),  a = v - o,
+ * in FP32 without fused operations (d_kz times the published sheared
+ * coordinates).  The edge functions U = p(v1) x p(v2), V = p(v2) x p(v0),
+ * W = p(v0) x p(v1) are FP64 from the FP32 points: the products are exact
+ * and one rounding keeps every sign exact, so the origin's side of each
+ * projected edge is decided exactly and a ray through an edge shared by two
+ * triangles is never lost.  Hit iff U, V, W are all >= 0 or all <= 0 and
+ * D = U + V + W != 0; then t = (U a_kz(v0) + V a_kz(v1) + W a_kz(v2)) /
+ * (D d_kz) in FP64, rounded once to FP32, and tmin < t < tmax.  D d_kz has the
+ * sign of d . ((v1 - v0) x (v2 - v0)), so front (the ray travels against that
+ * normal) is D d_kz < 0. */
+static int ray_axis(f3 d) {
+  float ax = fabsf(d.x), ay = fabsf(d.y), az = fabsf(d.z);
+  int k = 0;
+  float m = ax;
+  if (ay > m) { k = 1; m = ay; }
+  if (az > m) k = 2;
+  return k;
+}
+static float f3_at(f3 v, int k) { return k == 0 ? v.x : (k == 1 ? v.y : v.z); }
+static int wt32(const rco_scene* s, int64_t j, f3 o, f3 d, int kz, float tmin, float tmax, float* tout, int* front) {
+  const int kx = (kz + 1) % 3, ky = (kz + 2) % 3;
+  const f3 vs[3] = {s->v0[j], s->v1[j], s->v2[j]};
+  const float dx = f3_at(d, kx), dy = f3_at(d, ky), dz = f3_at(d, kz);
+  double px[3], py[3], pz[3];
+  for (int i = 0; i < 3; i++) {
+    f3 a = f3_sub(vs[i], o);
+    float ax = f3_at(a, kx), ay = f3_at(a, ky), az = f3_at(a, kz);
+    float qx = dz * ax - dx * az;
+    float qy = dz * ay - dy * az;
+    px[i] = qx; py[i] = qy; pz[i] = az;
+  }
+  double U = px[1] * py[2] - py[1] * px[2];
+  double V = px[2] * py[0] - py[2] * px[0];
+  double W = px[0] * py[1] - py[0] * px[1];
+  if ((U < 0.0 || V < 0.0 || W < 0.0) && (U > 0.0 || V > 0.0 || W > 0.0)) return 0;
+  double D = (U + V) + W;
+  if (D == 0.0) return 0;
+  double num = (U * pz[0] + V * pz[1]) + W * pz[2];
+  double den = D * (double)dz;
+  float t = (float)(num / den);
   if (!(t > tmin && t < tmax)) return 0;
-  *tout = t; *front = fr;
+  *tout = t;
+  *front = den < 0.0;
   return 1;
 }
 
@@ -308,7 +333,7 @@ typedef struct { int hit; int64_t id; float t; int front; } hit32;
  * t at or below the current best, so the result equals testing every
  * triangle (checked against brute force by the tests). */
 static void closest_rec(const rco_scene* s, int lev, int64_t node, const double* o64, const double* d64,
-                        f3 o, f3 d, float dd, hit32* best) {
+                        f3 o, f3 d, int kz, hit32* best) {
   double tmax = best->hit ? (double)best->t * (1.0 + 1e-6) + 1e-6 : 1e300;
   if (!box_hit(s->lev_box[lev] + 6 * node, o64, d64, 0.0, tmax)) return;
   int64_t nchild = (lev == 0) ? s->T : s->lev_n[lev - 1];
@@ -316,13 +341,13 @@ static void closest_rec(const rco_scene* s, int lev, int64_t node, const double*
     if (lev == 0) {
       int64_t j = s->perm[c];
       float t; int fr;
-      if (mt32(s, j, o, d, dd, 0.0f, INFINITY, &t, &fr)) {
+      if (wt32(s, j, o, d, kz, 0.0f, INFINITY, &t, &fr)) {
         if (!best->hit || t < best->t || (t == best->t && j < best->id)) {
           best->hit = 1; best->id = j; best->t = t; best->front = fr;
         }
       }
     } else {
-      closest_rec(s, lev - 1, c, o64, d64, o, d, dd, best);
+      closest_rec(s, lev - 1, c, o64, d64, o, d, kz, best);
     }
   }
 }
@@ -330,32 +355,32 @@ static hit32 trace_closest(const rco_scene* s, f3 o, f3 d) {
   hit32 best = {0, -1, 0.0f, 0};
   if (s->T == 0) return best;
   double o64[3] = {o.x, o.y, o.z}, d64[3] = {d.x, d.y, d.z};
-  float dd = f3_dot(d, d);
+  int kz = ray_axis(d);
   int top = s->nlev - 1;
-  for (int64_t n = 0; n < s->lev_n[top]; n++) closest_rec(s, top, n, o64, d64, o, d, dd, &best);
+  for (int64_t n = 0; n < s->lev_n[top]; n++) closest_rec(s, top, n, o64, d64, o, d, kz, &best);
   return best;
 }
 static hit32 trace_closest_brute(const rco_scene* s, f3 o, f3 d) {
   hit32 best = {0, -1, 0.0f, 0};
-  float dd = f3_dot(d, d);
+  int kz = ray_axis(d);
   for (int64_t j = 0; j < s->T; j++) {
     float t; int fr;
-    if (mt32(s, j, o, d, dd, 0.0f, INFINITY, &t, &fr))
+    if (wt32(s, j, o, d, kz, 0.0f, INFINITY, &t, &fr))
       if (!best.hit || t < best.t || (t == best.t && j < best.id)) { best.hit = 1; best.id = j; best.t = t; best.front = fr; }
   }
   return best;
 }
 
 static int occluded_rec(const rco_scene* s, int lev, int64_t node, const double* o64, const double* d64,
-                        f3 o, f3 d, float dd, int64_t skip) {
+                        f3 o, f3 d, int kz, int64_t skip) {
   if (!box_hit(s->lev_box[lev] + 6 * node, o64, d64, 0.0, 1.0)) return 0;
   int64_t nchild = (lev == 0) ? s->T : s->lev_n[lev - 1];
   for (int64_t c = node * RCO_FAN; c < (node + 1) * RCO_FAN && c < nchild; c++) {
     if (lev == 0) {
       int64_t j = s->perm[c];
       float t; int fr;
-      if (j != skip && mt32(s, j, o, d, dd, 1e-4f, 1.0f, &t, &fr)) return 1;
-    } else if (occluded_rec(s, lev - 1, c, o64, d64, o, d, dd, skip)) {
+      if (j != skip && wt32(s, j, o, d, kz, 1e-4f, 1.0f, &t, &fr)) return 1;
+    } else if (occluded_rec(s, lev - 1, c, o64, d64, o, d, kz, skip)) {
       return 1;
     }
   }
@@ -365,17 +390,17 @@ static int occluded_rec(const rco_scene* s, int lev, int64_t node, const double*
 static int occluded(const rco_scene* s, f3 o, f3 d, int64_t skip) {
   if (s->T == 0) return 0;
   double o64[3] = {o.x, o.y, o.z}, d64[3] = {d.x, d.y, d.z};
-  float dd = f3_dot(d, d);
+  int kz = ray_axis(d);
   int top = s->nlev - 1;
   for (int64_t n = 0; n < s->lev_n[top]; n++)
-    if (occluded_rec(s, top, n, o64, d64, o, d, dd, skip)) return 1;
+    if (occluded_rec(s, top, n, o64, d64, o, d, kz, skip)) return 1;
   return 0;
 }
 static int occluded_brute(const rco_scene* s, f3 o, f3 d, int64_t skip) {
-  float dd = f3_dot(d, d);
+  int kz = ray_axis(d);
   for (int64_t j = 0; j < s->T; j++) {
     float t; int fr;
-    if (j != skip && mt32(s, j, o, d, dd, 1e-4f, 1.0f, &t, &fr)) return 1;
+    if (j != skip && wt32(s, j, o, d, kz, 1e-4f, 1.0f, &t, &fr)) return 1;
   }
   return 0;
 }

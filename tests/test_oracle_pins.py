@@ -246,6 +246,133 @@ def test_uniform_unoccluded_field_has_zero_derivatives():
     assert np.all(np.linalg.norm(r["hess"][:, 0], axis=1) < 1e-11 * st[:, 4])
 
 
+
+NEAR_SURFACE = [(0.5, 0.5, "h"), (0.3, 0.6, "1-h"), ("h", "h", 0.5), ("1-h", 0.4, "1-h"), ("h", "h", "h"),
+                ("1-h", "1-h", "1-h"), ("h", "1-h", "h")]
+
+
+def _near_point(spec, h):
+    return [h if c == "h" else (1 - h if c == "1-h" else c) for c in spec]
+
+
+@pytest.mark.parametrize("h", [1e-3, 1e-4, 1e-5])
+def test_closed_emitting_box_seen_from_points_next_to_walls_edges_and_corners(h):
+    """Sec. 4 takes each sample at the first surface seen from x.  Inside a
+    closed emitting box in vacuum every direction sees a wall, so V_SS = 1
+    and the triangulated gradient and Hessian vanish (the fan of hit points
+    is a closed star mesh around x) for points arbitrarily close to a wall,
+    an edge or a corner; a ray/triangle test that drops grazing rays loses
+    directions here and the value falls short of 1."""
+    sc = _emitting_box_scene()
+    pts = np.array([_near_point(s_, h) for s_ in NEAR_SURFACE], np.float32)
+    for seed in (5, 6):
+        r = O.records(sc, 0.0, 0.0, NO_LIGHTS, pts, 32, 128, ring_step=0.1, max_rings=20, seed=seed)
+        st = r["stats"]
+        assert np.abs(r["value"][:, 0] - 1.0).max() < 1e-6, r["value"][:, 0]
+        assert np.allclose(r["value"][:, 1], 0.0)
+        assert np.abs(st[:, 7] - 1.0).max() < 1e-9                  # sum of form factors
+        assert np.all(np.linalg.norm(r["grad"][:, 0], axis=1) <= 1e-11 * st[:, 3])
+        assert np.all(np.linalg.norm(r["hess"][:, 0], axis=1) <= 1e-11 * st[:, 4])
+
+
+def _closed_meshes():
+    """Closed triangle meshes around the origin with shared vertices: an
+    octahedron, a cube split along its face diagonals, and a subdivided
+    icosphere-like mesh (random radial perturbation)."""
+    octa_v = np.array([[1, 0, 0], [-1, 0, 0], [0, 1, 0], [0, -1, 0], [0, 0, 1], [0, 0, -1]], np.float64)
+    octa_f = [(0, 2, 4), (2, 1, 4), (1, 3, 4), (3, 0, 4), (2, 0, 5), (1, 2, 5), (3, 1, 5), (0, 3, 5)]
+    cube = W.room_triangles((-1, -1, -1), (1, 1, 1)).reshape(-1, 3, 3).astype(np.float64)
+    rng = np.random.default_rng(11)
+    v, f = octa_v.copy(), list(octa_f)
+    for _ in range(3):   # loop subdivision of the faces (midpoints shared between neighbours)
+        mids, nf = {}, []
+        def mid(a, b):
+            k = (min(a, b), max(a, b))
+            if k not in mids:
+                mids[k] = len(v_list)
+                v_list.append((v_list[a] + v_list[b]) / 2)
+            return mids[k]
+        v_list = list(v)
+        for a, b, c in f:
+            ab, bc, ca = mid(a, b), mid(b, c), mid(c, a)
+            nf += [(a, ab, ca), (ab, b, bc), (ca, bc, c), (ab, bc, ca)]
+        v, f = np.array(v_list), nf
+    v = v / np.linalg.norm(v, axis=1, keepdims=True) * rng.uniform(0.7, 1.3, size=(len(v), 1))
+    sphere = v[np.array(f)]
+    return [octa_v[np.array(octa_f)], cube, sphere]
+
+
+def test_rays_through_shared_edges_and_vertices_of_closed_meshes_always_hit():
+    """Watertightness: rays from inside a closed mesh aimed exactly at its
+    vertices, at points of its edges, and in random directions always hit
+    one of its triangles (brute force and hierarchy agree)."""
+    rng = np.random.default_rng(12)
+    for mesh in _closed_meshes():
+        tri = mesh.reshape(-1, 9).astype(np.float32)
+        sc = O.Scene(tri, np.zeros(len(tri), np.float32), None, (-2, -2, -2), (2, 2, 2))
+        t3 = tri.reshape(-1, 3, 3).astype(np.float64)
+        targets = [t3.reshape(-1, 3)]
+        for a, b in ((0, 1), (1, 2), (2, 0)):
+            for f in (0.5, 0.25, rng.uniform()):
+                targets.append(t3[:, a] + f * (t3[:, b] - t3[:, a]))
+        targets = np.concatenate(targets)
+        for o in (np.zeros(3), rng.uniform(-0.2, 0.2, 3), np.array([0.3, -0.1, 0.05])):
+            o32 = np.broadcast_to(o, targets.shape).astype(np.float32)
+            d = (targets - o32).astype(np.float32)
+            d = np.concatenate([d, rng.normal(size=(3000, 3)).astype(np.float32)])
+            o32 = np.broadcast_to(o, d.shape).astype(np.float32)
+            for brute in (True, False):
+                hid, t, _ = sc.trace(o32, d, brute=brute)
+                assert (hid >= 0).all(), (len(tri), int((hid < 0).sum()))
+
+
+def _grazing_rays(tri, rng, n):
+    """Rays that skim random triangles: origin near the triangle's plane,
+    direction in the plane tilted by 1e-7 .. 1e-2 rad, aimed at the triangle
+    or just past one of its edges."""
+    T = len(tri)
+    t3 = tri.reshape(-1, 3, 3).astype(np.float64)
+    j = rng.integers(0, T, n)
+    v0, v1, v2 = t3[j, 0], t3[j, 1], t3[j, 2]
+    nrm = np.cross(v1 - v0, v2 - v0)
+    nrm /= np.linalg.norm(nrm, axis=1, keepdims=True)
+    bc = rng.dirichlet([1, 1, 1], size=n) * 1.1 - 0.033
+    tgt = bc[:, :1] * v0 + bc[:, 1:2] * v1 + bc[:, 2:] * v2
+    u = rng.normal(size=(n, 3))
+    u -= (u * nrm).sum(1, keepdims=True) * nrm
+    u /= np.linalg.norm(u, axis=1, keepdims=True)
+    ang = 10.0 ** rng.uniform(-7, -2, n) * rng.choice([-1, 1], n)
+    d = u * np.cos(ang)[:, None] + nrm * np.sin(ang)[:, None]
+    dist = rng.uniform(0.01, 0.5, n)
+    o = tgt - d * dist[:, None]
+    return o.astype(np.float32), (d * rng.uniform(0.5, 2.0, (n, 1))).astype(np.float32)
+
+
+def test_grazing_rays_hierarchy_equals_brute_force_and_hits_stay_in_padding():
+    """Rays skimming triangles at 1e-7 .. 1e-2 rad: the hierarchy of padded
+    boxes gives the brute-force closest hit and any-hit answers, and every
+    accepted hit point o + t d lies within 16 * 2^-24 * scale of its
+    triangle's box (the bound the box padding of 2^-16 * scale covers)."""
+    w = W.make_c2(P=4, n_soup=2000)
+    sc = O.Scene.from_workload(w)
+    rng = np.random.default_rng(13)
+    o, d = _grazing_rays(w.tri, rng, 20000)
+    keep = np.all((o > 0.0) & (o < 1.0), axis=1)
+    o, d = o[keep], d[keep]
+    a = sc.trace(o, d, brute=False)
+    b = sc.trace(o, d, brute=True)
+    assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1]) and np.array_equal(a[2], b[2])
+    hit = a[0] >= 0
+    assert hit.mean() > 0.3
+    t3 = w.tri.reshape(-1, 3, 3).astype(np.float64)[a[0][hit]]
+    hp = o[hit].astype(np.float64) + a[1][hit].astype(np.float64)[:, None] * d[hit].astype(np.float64)
+    out = np.maximum(t3.min(1) - hp, hp - t3.max(1)).max(1)
+    scale = float((w.box_hi - w.box_lo).max())
+    assert out.max() <= 16 * 2.0 ** -24 * scale, out.max()
+    seg = d * rng.uniform(0.2, 3.0, (len(d), 1)).astype(np.float32)
+    assert np.array_equal(sc.occluded(o, seg), sc.occluded(o, seg, brute=True))
+
+
 def _rect_omega(p, x1, x2, y1, y2):
     """Solid angle of the rectangle [x1,x2]x[y1,y2] in the plane z = 0 seen
     from p (textbook corner formula)."""
