@@ -232,9 +232,10 @@ int rc_radius(const double* value, const double* hess, int64_t P, float eps, flo
 /* ------------------------------------------------------------------ */
 /* Ray queries (the traversal the record kernel uses, one ray per lane)  */
 /* ------------------------------------------------------------------ */
-/* Closest hit of rays o + t d, t > 0 (Moller-Trumbore in FP32, rays within
- * ~0.6 degrees of a triangle plane rejected, ties to the lowest triangle
- * index).  orig/dir device float[n][3]; hit_id device int32[n] (triangle
+/* Closest hit of rays o + t d, t > 0 (watertight ray/triangle test of Woop,
+ * Benthin and Wald 2013: FP32 projection along the ray, edge functions with
+ * exact signs, t rounded once to FP32; every ray that meets a closed mesh
+ * hits it, at any angle; ties to the lowest triangle index).  orig/dir device float[n][3]; hit_id device int32[n] (triangle
  * index or -1), t device float[n] (hit distance, or the exit distance from
  * the medium box when nothing is hit), front device int32[n] (1 if the ray
  * travels against the triangle normal (v1-v0) x (v2-v0)). */

@@ -76,6 +76,7 @@ struct rc_scene {
   float4* nodes = nullptr;
   float4* tris = nullptr;
   float4* shade = nullptr;
+  double4* plane = nullptr;
   float* emission = nullptr;
   std::mutex mu;
   GraphCache graph;
@@ -84,6 +85,7 @@ struct rc_scene {
     if (nodes) (void)hipFree(nodes);
     if (tris) (void)hipFree(tris);
     if (shade) (void)hipFree(shade);
+    if (plane) (void)hipFree(plane);
     if (emission) (void)hipFree(emission);
   }
 };
@@ -150,6 +152,7 @@ rc::RecordArgs make_args(const rc_scene* s, const rc_medium* m, const rc_point_l
   a.nodes = s->nodes;
   a.tris = s->tris;
   a.shade = s->shade;
+  a.plane = s->plane;
   a.emission = s->emission;
   a.box_lo = make_float3(s->box_lo[0], s->box_lo[1], s->box_lo[2]);
   a.box_hi = make_float3(s->box_hi[0], s->box_hi[1], s->box_hi[2]);
@@ -309,6 +312,10 @@ int rc_scene_create(const float* tri, const float* albedo, const float* emission
   for (int k = 0; k < 3; k++) { s->box_lo[k] = box_lo[k]; s->box_hi[k] = box_hi[k]; }
   // per-triangle shading data
   std::vector<float> shade(4 * std::max<int64_t>(T, 1), 0.f), em(std::max<int64_t>(T, 1), 0.f);
+  // FP64 plane of each triangle (unit normal n from the FP32 vertices, n . v0):
+  // the hit distance the derivative terms use is the exact ray-plane distance
+  // of the decided triangle
+  std::vector<double> plane(4 * std::max<int64_t>(T, 1), 0.0);
   for (int64_t i = 0; i < T; i++) {
     const float* t = tri + 9 * i;
     double e1[3] = {(double)t[3] - t[0], (double)t[4] - t[1], (double)t[5] - t[2]};
@@ -317,6 +324,8 @@ int rc_scene_create(const float* tri, const float* albedo, const float* emission
     double ln = std::sqrt(n[0] * n[0] + n[1] * n[1] + n[2] * n[2]);
     for (int k = 0; k < 3; k++) shade[4 * i + k] = ln > 0 ? (float)(n[k] / ln) : 0.f;
     shade[4 * i + 3] = albedo[i];
+    for (int k = 0; k < 3; k++) plane[4 * i + k] = ln > 0 ? n[k] / ln : 0.0;
+    plane[4 * i + 3] = (plane[4 * i] * t[0] + plane[4 * i + 1] * t[1]) + plane[4 * i + 2] * t[2];
     em[i] = emission ? emission[i] : 0.f;
   }
   auto up = [&](void** dst, const void* src, size_t bytes) -> int {
@@ -329,6 +338,7 @@ int rc_scene_create(const float* tri, const float* albedo, const float* emission
   int r = up((void**)&s->nodes, bvh.nodes.data(), bvh.nodes.size() * 4);
   if (!r) r = up((void**)&s->tris, bvh.tris.data(), bvh.tris.size() * 4);
   if (!r) r = up((void**)&s->shade, shade.data(), shade.size() * 4);
+  if (!r) r = up((void**)&s->plane, plane.data(), plane.size() * 8);
   if (!r) r = up((void**)&s->emission, em.data(), em.size() * 4);
   if (r) {
     delete s;

@@ -77,15 +77,7 @@ struct Builder {
     int64_t first = (int64_t)tris.size() / 12;
     for (int64_t i = b; i < e; i++) {
       const float* t = tri + 9 * (int64_t)prims[i].id;
-      float v0[3] = {t[0], t[1], t[2]};
-      float e1[3] = {t[3] - t[0], t[4] - t[1], t[5] - t[2]};
-      float e2[3] = {t[6] - t[0], t[7] - t[1], t[8] - t[2]};
-      // n = e1 x e2 and |n|^2, rounded exactly as the hit test expects
-      float n0 = e1[1] * e2[2] - e1[2] * e2[1];
-      float n1 = e1[2] * e2[0] - e1[0] * e2[2];
-      float n2 = e1[0] * e2[1] - e1[1] * e2[0];
-      float nn = (n0 * n0 + n1 * n1) + n2 * n2;
-      float rec[12] = {v0[0], v0[1], v0[2], as_f(prims[i].id), e1[0], e1[1], e1[2], nn, e2[0], e2[1], e2[2], 0.f};
+      float rec[12] = {t[0], t[1], t[2], as_f(prims[i].id), t[3], t[4], t[5], 0.f, t[6], t[7], t[8], 0.f};
       tris.insert(tris.end(), rec, rec + 12);
     }
     int64_t cnt = e - b;
@@ -249,27 +241,15 @@ float bvh_pad_for(const float* tri, int64_t T, const float* lo, const float* hi)
   return (float)(m > 0 ? m : 1.0);
 }
 
-// Padding of one triangle's box.  The FP32 hit test can accept a point up to
-// ~4e-5 * scale / sin(beta_min) away from the exact triangle (beta_min: the
-// triangle's smallest angle; rays within ~0.6 degrees of the plane are
-// rejected); the pad is 5x that bound, capped at the scene scale.
-float triangle_pad(const float* t, float scale) {
-  double e1[3], e2[3], e3[3];
-  for (int k = 0; k < 3; k++) {
-    e1[k] = (double)t[3 + k] - t[k];
-    e2[k] = (double)t[6 + k] - t[k];
-    e3[k] = (double)t[6 + k] - t[3 + k];
-  }
-  double c[3] = {e1[1] * e2[2] - e1[2] * e2[1], e1[2] * e2[0] - e1[0] * e2[2], e1[0] * e2[1] - e1[1] * e2[0]};
-  double area2 = std::sqrt(c[0] * c[0] + c[1] * c[1] + c[2] * c[2]);
-  double L[3] = {std::sqrt(e1[0] * e1[0] + e1[1] * e1[1] + e1[2] * e1[2]),
-                 std::sqrt(e2[0] * e2[0] + e2[1] * e2[1] + e2[2] * e2[2]),
-                 std::sqrt(e3[0] * e3[0] + e3[1] * e3[1] + e3[2] * e3[2])};
-  std::sort(L, L + 3);
-  double sinb = (L[1] * L[2] > 0) ? area2 / (L[1] * L[2]) : 0.0;
-  double p = sinb > 0 ? 2e-4 * scale / sinb : scale;
-  return (float)std::min(p, (double)scale);
-}
+// Padding of one triangle's box.  A hit accepted by the watertight test is
+// the point o + t d with t rounded once to FP32 from a value that is exact for
+// vertices moved by a few units of FP32 rounding (the projection along the ray
+// is the only other inexact step; the edge functions keep exact signs), so it
+// lies within ~16 * 2^-24 * scale of the triangle's box; the slab tests of the
+// traversal (hardware reciprocal, fused multiply-add) err by a few units of
+// rounding of the coordinates, also below that.  The pad is 2^-16 * scale,
+// 16 times the bound, and independent of the triangle's shape.
+float triangle_pad(const float* /*t*/, float scale) { return std::ldexp(scale, -16); }
 
 int build_bvh(const float* tri, int64_t T, float pad, HostBvh& out, std::string& err) {
   out.nodes.clear();

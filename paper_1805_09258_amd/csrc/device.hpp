@@ -67,27 +67,68 @@ RC_DEV float dot3(float3 a, float3 b) { return (a.x * b.x + a.y * b.y) + a.z * b
 RC_DEV float3 axpy3(float t, float3 w, float3 x) { return make_float3(x.x + t * w.x, x.y + t * w.y, x.z + t * w.z); }
 RC_DEV float det3(float3 a, float3 b, float3 c) { return dot3(a, cross3(b, c)); }
 
-// Moller-Trumbore in FP32 on (v0, e1, e2); rejects rays within ~0.6 degrees
-// of the triangle plane; hit iff tmin < t < tmax.  front: the ray travels
-// against e1 x e2.
-RC_DEV bool hit_triangle(float3 o, float3 d, float dd, float4 A, float4 B, float4 C, float tmin, float tmax,
-                         float& tout, bool& front) {
-  float3 e1 = make_float3(B.x, B.y, B.z), e2 = make_float3(C.x, C.y, C.z);
-  float3 p = cross3(d, e2);
-  float det = dot3(e1, p);
-  if (!(det * det > 1e-4f * (dd * B.w))) return false;
-  float3 s = sub3(o, make_float3(A.x, A.y, A.z));
-  float u = dot3(s, p);
-  float3 q = cross3(s, e1);
-  float v = dot3(d, q);
-  float tn = dot3(e2, q);
-  bool fr = true;
-  if (det < 0.0f) { det = -det; u = -u; v = -v; tn = -tn; fr = false; }
-  if (u < 0.0f || v < 0.0f || u + v > det) return false;
-  float t = tn / det;
+// Watertight ray/triangle test (Woop, Benthin and Wald, "Watertight
+// Ray/Triangle Intersection", JCGT 2(1), 2013), written without divisions.
+// kz is the axis of the largest |d| component (ties to the lower axis) and
+// (kx, ky) = (kz + 1, kz + 2) mod 3.  Each vertex v is projected along the ray
+// to the 2-D point
+//   p(v) = (d_kz a_kx - d_kx a_kz,  d_kz a_ky - d_ky a_kz),   a = v - o,
+// in FP32 (d_kz times the sheared coordinates of the published test).  The
+// edge functions U = p(v1) x p(v2), V = p(v2) x p(v0), W = p(v0) x p(v1) are
+// FP64 from the FP32 points: the products are exact and one rounding keeps
+// each sign exact, so which side of every projected edge the ray passes is
+// decided exactly and a ray through an edge shared by two triangles of a
+// closed mesh is never lost, at any angle.  Hit iff U, V, W are all >= 0 or
+// all <= 0 and D = U + V + W != 0; then
+//   t = (U a_kz(v0) + V a_kz(v1) + W a_kz(v2)) / (D d_kz)
+// in FP64, rounded once to FP32, and tmin < t < tmax.  D d_kz has the sign of
+// d . ((v1 - v0) x (v2 - v0)), so front (the ray travels against that normal)
+// is D d_kz < 0.
+//
+// The ray is kept in the permuted frame (x, y, z) = (kx, ky, kz).
+struct WtRay {
+  float3 o, d;  // origin and direction, permuted
+  int kz;
+};
+RC_DEV float3 permute3(float3 v, int kz) {
+  return kz == 0 ? make_float3(v.y, v.z, v.x) : (kz == 1 ? make_float3(v.z, v.x, v.y) : v);
+}
+RC_DEV WtRay wt_ray(float3 o, float3 d) {
+  const float ax = fabsf(d.x), ay = fabsf(d.y), az = fabsf(d.z);
+  int k = 0;
+  float m = ax;
+  if (ay > m) {
+    k = 1;
+    m = ay;
+  }
+  if (az > m) k = 2;
+  WtRay r;
+  r.o = permute3(o, k);
+  r.d = permute3(d, k);
+  r.kz = k;
+  return r;
+}
+// Triangle record: A = (v0, id bits), B = (v1, 0), C = (v2, 0).
+RC_DEV bool hit_triangle(const WtRay& r, float4 A, float4 B, float4 C, float tmin, float tmax, float& tout,
+                         bool& front) {
+  const float3 a0 = sub3(permute3(make_float3(A.x, A.y, A.z), r.kz), r.o);
+  const float3 a1 = sub3(permute3(make_float3(B.x, B.y, B.z), r.kz), r.o);
+  const float3 a2 = sub3(permute3(make_float3(C.x, C.y, C.z), r.kz), r.o);
+  const double px0 = r.d.z * a0.x - r.d.x * a0.z, py0 = r.d.z * a0.y - r.d.y * a0.z;
+  const double px1 = r.d.z * a1.x - r.d.x * a1.z, py1 = r.d.z * a1.y - r.d.y * a1.z;
+  const double px2 = r.d.z * a2.x - r.d.x * a2.z, py2 = r.d.z * a2.y - r.d.y * a2.z;
+  const double U = px1 * py2 - py1 * px2;
+  const double V = px2 * py0 - py2 * px0;
+  const double W = px0 * py1 - py0 * px1;
+  if ((U < 0.0 || V < 0.0 || W < 0.0) && (U > 0.0 || V > 0.0 || W > 0.0)) return false;
+  const double D = (U + V) + W;
+  if (D == 0.0) return false;
+  const double num = (U * (double)a0.z + V * (double)a1.z) + W * (double)a2.z;
+  const double den = D * (double)r.d.z;
+  const float t = (float)(num / den);
   if (!(t > tmin && t < tmax)) return false;
   tout = t;
-  front = fr;
+  front = den < 0.0;
   return true;
 }
 
@@ -98,6 +139,15 @@ RC_DEV float box_exit(float3 o, float3 d, float3 lo, float3 hi) {
   if (d.y > 0.0f) t = fminf(t, (hi.y - o.y) / d.y); else if (d.y < 0.0f) t = fminf(t, (lo.y - o.y) / d.y);
   if (d.z > 0.0f) t = fminf(t, (hi.z - o.z) / d.z); else if (d.z < 0.0f) t = fminf(t, (lo.z - o.z) / d.z);
   return t > 0.0f ? t : 0.0f;
+}
+
+// The same exit distance in FP64 (the continuous value of an escaping ray).
+RC_DEV double box_exit64(float3 o, float3 d, float3 lo, float3 hi) {
+  double t = 1e300;
+  if (d.x > 0.0f) t = fmin(t, ((double)hi.x - o.x) / d.x); else if (d.x < 0.0f) t = fmin(t, ((double)lo.x - o.x) / d.x);
+  if (d.y > 0.0f) t = fmin(t, ((double)hi.y - o.y) / d.y); else if (d.y < 0.0f) t = fmin(t, ((double)lo.y - o.y) / d.y);
+  if (d.z > 0.0f) t = fmin(t, ((double)hi.z - o.z) / d.z); else if (d.z < 0.0f) t = fmin(t, ((double)lo.z - o.z) / d.z);
+  return t > 0.0 ? t : 0.0;
 }
 
 // ---------------------------------------------------------------------------
@@ -144,7 +194,7 @@ template <bool COUNT>
 RC_DEV void trace_closest(const float4* __restrict__ nodes, const float4* __restrict__ tris, float3 o, float3 d,
                                 int* stk, int& best_id, float& best_t, bool& best_front, TraceCount& cnt) {
   constexpr int kEnd = 0x7fffffff, kStay = 0x7ffffffe;
-  const float dd = dot3(d, d);
+  const WtRay wr = wt_ray(o, d);
   float3 inv, oi;
   ray_inv(d, o, inv, oi);
   best_id = -1;
@@ -160,7 +210,7 @@ RC_DEV void trace_closest(const float4* __restrict__ nodes, const float4* __rest
       if (COUNT) cnt.tris++;
       float t;
       bool fr;
-      if (hit_triangle(o, d, dd, q0, q1, q2, 0.0f, __builtin_huge_valf(), t, fr)) {
+      if (hit_triangle(wr, q0, q1, q2, 0.0f, __builtin_huge_valf(), t, fr)) {
         const int id = __float_as_int(q0.w);
         if (t < best_t || (t == best_t && id < best_id)) {
           best_t = t;
@@ -204,7 +254,7 @@ RC_DEV void trace_closest(const float4* __restrict__ nodes, const float4* __rest
 template <bool COUNT>
 RC_DEV bool occluded(const float4* __restrict__ nodes, const float4* __restrict__ tris, float3 o, float3 d,
                      int skip, int* stk, TraceCount& cnt) {
-  float dd = dot3(d, d);
+  const WtRay wr = wt_ray(o, d);
   float3 inv, oi;
   ray_inv(d, o, inv, oi);
   int sp = 0;
@@ -240,7 +290,7 @@ RC_DEV bool occluded(const float4* __restrict__ nodes, const float4* __restrict_
       if (COUNT) cnt.tris++;
       float t;
       bool fr;
-      if (__float_as_int(A.w) != skip && hit_triangle(o, d, dd, A, B, C, 1e-4f, 1.0f, t, fr)) return true;
+      if (__float_as_int(A.w) != skip && hit_triangle(wr, A, B, C, 1e-4f, 1.0f, t, fr)) return true;
     }
     if (sp == 0) return false;
     sp--;

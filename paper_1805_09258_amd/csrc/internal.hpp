@@ -16,8 +16,8 @@ namespace rc {
 //   w2 = (c0.lo.z, c0.hi.z, c1.lo.z, c1.hi.z)
 //   w3 = (child0, child1, 0, 0) as int bits: >= 0 internal node index,
 //        < 0 leaf ~((first << 3) | (count - 1)).
-// Triangle layout (48 bytes): (v0.xyz, id bits), (e1.xyz, |e1 x e2|^2),
-// (e2.xyz, 0) with e1 = v1 - v0, e2 = v2 - v0 rounded in FP32.
+// Triangle layout (48 bytes): (v0.xyz, id bits), (v1.xyz, 0), (v2.xyz, 0),
+// the vertices as given (the watertight hit test projects them along the ray).
 constexpr int kLeafMax = 4;
 constexpr int kMaxDepth = 60;
 
@@ -38,7 +38,7 @@ int build_bvh(const float* tri, int64_t T, float pad, HostBvh& out, std::string&
 // Scene coordinate scale (largest |coordinate| or box side) that sets the
 // FP32 error of an accepted ray/triangle hit.
 float bvh_pad_for(const float* tri, int64_t T, const float* lo, const float* hi);
-// Box padding of one triangle (FP32 hit error bound x 5, see bvh.cpp).
+// Box padding of one triangle (16 x the FP32 error bound of an accepted hit, see bvh.cpp).
 float triangle_pad(const float* t, float scale);
 
 }  // namespace rc

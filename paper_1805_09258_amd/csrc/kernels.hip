@@ -26,14 +26,17 @@ namespace rc {
 namespace {
 
 // One strata row in LDS, structure of arrays over the row's columns:
-// direction, hit distance, hit code ((triangle << 1) | front, or -1), rings
-// in front of the hit, surface radiance, surface light-visibility bits, and
-// ring radiance [ring][column] (holding light-visibility bits until shaded).
-constexpr int kRowFields = 8;
+// direction, hit distance (the FP32 decision value), hit code
+// ((triangle << 1) | front, or -1), rings in front of the hit, surface
+// radiance, surface light-visibility bits, the continuous hit distance as a
+// correction to the decision value (FP64 exact ray-plane distance of the
+// decided triangle, or FP64 box exit, minus t; rounded to FP32), and ring
+// radiance [ring][column] (holding light-visibility bits until shaded).
+constexpr int kRowFields = 9;
 // idle lanes that trigger a refill of the shadow-ray loop
 constexpr int kRefillMin = 12;
 struct Row {
-  float *wx, *wy, *wz, *t, *Ls, *Lm;
+  float *wx, *wy, *wz, *t, *Ls, *tlo, *Lm;
   int *code, *M, *visS;
 };
 
@@ -47,6 +50,7 @@ RC_DEV Row row_view(float* base, int cap) {
   r.M = (int*)(base + 5 * cap);
   r.Ls = base + 6 * cap;
   r.visS = (int*)(base + 7 * cap);
+  r.tlo = base + 8 * cap;
   r.Lm = base + kRowFields * cap;  // [max_rings][cap]
   return r;
 }
@@ -267,7 +271,15 @@ record_kernel(RecordArgs g) {
           const float3 w = row_direction(key, a, sectored ? (b0 + j) % nph : j, nth, nph);
           float t = grouped ? gt : R.t[j];
           const int code = grouped ? gcode : R.code[j];
-          if (code < 0) t = box_exit(x, w, g.box_lo, g.box_hi);
+          double t64;
+          if (code < 0) {
+            t = box_exit(x, w, g.box_lo, g.box_hi);
+            t64 = box_exit64(x, w, g.box_lo, g.box_hi);
+          } else {
+            const double4 pl = g.plane[code >> 1];
+            t64 = (pl.w - ((pl.x * x.x + pl.y * x.y) + pl.z * x.z)) / ((pl.x * w.x + pl.y * w.y) + pl.z * w.z);
+          }
+          R.tlo[j] = (float)(t64 - (double)t);
           int M = 0;
           while (M < MR && ring_distance(M, xr, g.ring_step) < t) M++;
           R.wx[j] = w.x;
@@ -307,7 +319,7 @@ record_kernel(RecordArgs g) {
         bool active = false;
         int task = 0, node = 0, sp = 0, lf = 0, ln = 0, skip = -1, slot = 0;
         float3 o = make_float3(0.f, 0.f, 0.f), d = o, inv = o, oi = o;
-        float dd = 0.f;
+        WtRay wr = wt_ray(o, d);
         while (true) {
           // refill idle lanes in lane order, once enough of them are idle
           const uint64_t idle = __ballot(!active);
@@ -341,7 +353,7 @@ record_kernel(RecordArgs g) {
                 slot = i * cap + j;
                 d = make_float3(L.x - o.x, L.y - o.y, L.z - o.z);
               }
-              dd = dot3(d, d);
+              wr = wt_ray(o, d);
               ray_inv(d, o, inv, oi);
               node = 0;
               sp = 0;
@@ -370,7 +382,7 @@ record_kernel(RecordArgs g) {
               if (COUNT) tc.tris++;
               float t;
               bool fr;
-              if (__float_as_int(q0.w) != skip && hit_triangle(o, d, dd, q0, q1, q2, 1e-4f, 1.0f, t, fr)) {
+              if (__float_as_int(q0.w) != skip && hit_triangle(wr, q0, q1, q2, 1e-4f, 1.0f, t, fr)) {
                 done = true;
                 blocked = true;
               } else {
@@ -465,7 +477,7 @@ record_kernel(RecordArgs g) {
           if (j < nown) {
             float3 w = make_float3(R.wx[j], R.wy[j], R.wz[j]);
             float wn = sqrtf(dot3(w, w));
-            kadd(vs, vsc, expf(-mu * R.t[j] * wn) * R.Ls[j]);
+            kadd(vs, vsc, expf(-mu * (R.t[j] + R.tlo[j]) * wn) * R.Ls[j]);
             for (int i = 0; i < R.M[j]; i++)
               kadd(vm, vmc, g.ring_step * expf(-mu * ring_distance(i, xr, g.ring_step) * wn) * R.Lm[i * cap + j]);
           }
@@ -558,7 +570,11 @@ record_kernel(RecordArgs g) {
               else { vb[0] = baseP; col[0] = b1; gid[0] = gQ; vb[1] = baseR; col[1] = b; gid[1] = gR; vb[2] = baseR; col[2] = b1; gid[2] = gS; }
             }
           }
-          float tau[3], Lv[3];
+          // per vertex: the decision distance (FP32: ring distance or hit
+          // distance, picks the far vertex), the continuous distance (the
+          // geometry of the term) and its low part (FP64 terms)
+          float dec[3], tau[3], tlo[3], Lv[3];
+          bool on_ring[3];
           float3 wv[3];
           const float rr = ring >= 0 ? ring_distance(ring, xr, g.ring_step) : 0.f;
 #pragma unroll
@@ -567,24 +583,28 @@ record_kernel(RecordArgs g) {
             int c = col[k];
             // field offsets as laid out by row_view
             wv[k] = make_float3(b[c], b[cap + c], b[2 * cap + c]);
-            float tk = b[3 * cap + c];
+            const float tk = b[3 * cap + c], lk = b[8 * cap + c];
+            bool front = false;
             if (ring < 0) {
-              tau[k] = tk;
               Lv[k] = b[6 * cap + c];
             } else {
-              bool front = ring < reinterpret_cast<const int*>(b)[5 * cap + c];
-              tau[k] = front ? rr : tk;
+              front = ring < reinterpret_cast<const int*>(b)[5 * cap + c];
               Lv[k] = front ? b[(kRowFields + ring) * cap + c] : 0.f;
             }
+            on_ring[k] = front;
+            dec[k] = front ? rr : tk;
+            tau[k] = front ? rr : tk + lk;
+            tlo[k] = front ? 0.f : lk;
           }
-          // far vertex: largest distance, ties to the smaller vertex id (the
-          // running maximum is kept in plain variables, so no array is indexed at run time)
+          // far vertex: largest decision distance, ties to the smaller vertex
+          // id (the running maximum is kept in plain variables, so no array is
+          // indexed at run time)
           int far = 0;
-          float tf = tau[0];
+          float tf = dec[0];
           int gf = gid[0];
 #pragma unroll
           for (int k = 1; k < 3; k++)
-            if (tau[k] > tf || (tau[k] == tf && gid[k] < gf)) { far = k; tf = tau[k]; gf = gid[k]; }
+            if (dec[k] > tf || (dec[k] == tf && gid[k] < gf)) { far = k; tf = dec[k]; gf = gid[k]; }
           float Lf = far == 0 ? Lv[0] : (far == 1 ? Lv[1] : Lv[2]);
           if (Lf == 0.f) continue;
           // direction determinant in FP64 (thin triangles); A = tau1 tau2 tau3 detw
@@ -604,13 +624,10 @@ record_kernel(RecordArgs g) {
           } else {
             // study mode: the whole term in FP64, folded into the compensated
             // pair as a (hi, lo) split
-            double dtau[3] = {tau[0], tau[1], tau[2]};
-            if (ring >= 0) {
-              double r64 = ((double)ring + (double)xr) * (double)g.ring_step;
+            const double r64 = ((double)ring + (double)xr) * (double)g.ring_step;
+            double dtau[3];
 #pragma unroll
-              for (int k = 0; k < 3; k++)
-                if (tau[k] == rr) dtau[k] = r64;
-            }
+            for (int k = 0; k < 3; k++) dtau[k] = on_ring[k] ? r64 : (double)dec[k] + (double)tlo[k];
             V3<double> r1 = mk(dtau[0] * wv[0].x, dtau[0] * wv[0].y, dtau[0] * wv[0].z);
             V3<double> r2 = mk(dtau[1] * wv[1].x, dtau[1] * wv[1].y, dtau[1] * wv[1].z);
             V3<double> r3 = mk(dtau[2] * wv[2].x, dtau[2] * wv[2].y, dtau[2] * wv[2].z);

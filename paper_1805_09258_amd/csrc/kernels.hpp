@@ -18,6 +18,7 @@ struct RecordArgs {
   const float4* nodes;
   const float4* tris;
   const float4* shade;     // per triangle: unit normal (xyz), albedo (w)
+  const double4* plane;    // per triangle: FP64 unit normal (xyz), normal . v0 (w)
   const float* emission;   // per triangle
   float3 box_lo, box_hi;
   int n_lights;

@@ -104,7 +104,7 @@ __global__ __launch_bounds__(64) void probe_kernel(ProbeArgs g) {
       bool active = false;
       int node = 0, sp = 0, lf = 0, ln = 0, skip = -1, dst = 0, bit = 0;
       float3 o = make_float3(0.f, 0.f, 0.f), d = o, inv = o, oi = o;
-      float dd = 0.f;
+      WtRay wr = wt_ray(o, d);
       while (true) {
         const uint64_t idle = __ballot(!active);
         if (next < total && (__popcll(idle) >= 8 || idle == ~0ull)) {
@@ -139,7 +139,7 @@ __global__ __launch_bounds__(64) void probe_kernel(ProbeArgs g) {
                 dst = kWave;
                 bit = 1 << l;
               }
-              dd = dot3(d, d);
+              wr = wt_ray(o, d);
               ray_inv(d, o, inv, oi);
               node = 0;
               sp = 0;
@@ -159,7 +159,7 @@ __global__ __launch_bounds__(64) void probe_kernel(ProbeArgs g) {
           if (ln > 0) {
             float th;
             bool fh;
-            if (__float_as_int(q0.w) != skip && hit_triangle(o, d, dd, q0, q1, q2, 1e-4f, 1.0f, th, fh)) {
+            if (__float_as_int(q0.w) != skip && hit_triangle(wr, q0, q1, q2, 1e-4f, 1.0f, th, fh)) {
               done = true;
               blocked = true;
             } else {

@@ -29,7 +29,7 @@ def trained(dev):
     cfg = PL.CacheConfig(batch=2048)
     X, y = PL.training_set(range(1000, 1004), 5000, cfg, dev)
     mlp = PL.Mlp.new(dev, seed=1)
-    hist = PL.train(mlp, X, y, epochs=8, batch=512, log=_say)
+    hist = PL.train(mlp, X, y, epochs=20, batch=512, log=_say)
     return cfg, mlp, float(y.mean().item()), hist
 
 
