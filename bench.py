@@ -168,12 +168,15 @@ def main():
 
     # untimed: algorithmic work of one launch (rays, node and triangle fetches), counted with one
     # wavefront per record so that rows recomputed by split records are not counted
-    cnt = torch.zeros(8, dtype=torch.int64, device=dev)
+    cnt = torch.zeros(12, dtype=torch.int64, device=dev)
     with torch.cuda.stream(stream):
         rc.compute_records(scene, dw, batched=True, counters=cnt, out=(value, grad, hess), workspace=ws,
                            stream=stream, splits=1 if w.n_rec <= 16384 else 0)
     stream.synchronize()
-    rays, nodes, tris, terms, c0, c1, c2, c3 = (int(x) for x in cnt.cpu().tolist())
+    rays, nodes, tris, terms, c0, c1, c2, c3, sh_iter, sh_busy, sh_refill, sh_lanes = (int(x) for x in cnt.cpu().tolist())
+    shadow_loop = {"iterations": sh_iter, "lane_utilisation": sh_busy / max(64 * sh_iter, 1),
+                   "refills": sh_refill, "lanes_per_refill": sh_lanes / max(sh_refill, 1)}
+    log(f"shadow loop: {shadow_loop}")
     ctot = max(c0 + c1 + c2 + c3, 1)
     phase_frac = {"primary_rays": c0 / ctot, "shadow_rays": c1 / ctot, "mc_value": c2 / ctot,
                   "triangle_terms": c3 / ctot}
@@ -243,6 +246,7 @@ def main():
                      "alg_bytes_per_launch": alg_bytes,
                      "alg_bytes_per_ray": (nodes * NODE_BYTES + tris * TRI_BYTES) / max(rays, 1),
                      "phase_clock_fraction": phase_frac,
+                     "shadow_loop": shadow_loop,
                      "note": "achieved counts the algorithmic node and triangle fetches of the traversal; "
                              "the BVH is served from L2/MALL, so frac can exceed 1 and the HBM bytes are "
                              "in traffic"},

@@ -91,12 +91,21 @@ typedef struct {
  *   precision : 0 = FP32 terms, compensated FP32 sums, FP64 for
  *               near-degenerate triangle terms and the final reduction
  *               (default); 1 = every triangle term in FP64 (study mode).
- *   counters  : device uint64_t[8] or NULL.  If set, the launch also counts
- *               (atomically added): rays traced, BVH nodes visited,
- *               ray/triangle tests, triangle terms evaluated, and the shader
+ *   counters  : device uint64_t[12] or NULL.  If set, the launch also
+ *               counts (atomically added): rays traced, BVH nodes visited,
+ *               ray/triangle tests, triangle terms evaluated, the shader
  *               clocks each wavefront spent in primary rays, shadow rays, the
  *               Monte Carlo value and the triangle terms (summed over
- *               wavefronts). */
+ *               wavefronts), then for the shadow-ray loop: iterations
+ *               (per wavefront), busy lanes summed over iterations, refill
+ *               events and lanes refilled.  With light bins, "BVH nodes
+ *               visited" counts bin lists opened and "ray/triangle tests"
+ *               the entries read.
+ *   shadow_bvh : 0 (default) = shadow segments from the per-light triangle
+ *               bins (built and cached on the scene at the first call with
+ *               a new set of light positions, see rc_light_bins_build);
+ *               1 = BVH traversal.  Both give the answer of testing every
+ *               triangle, so records are identical. */
 typedef struct {
   float ring_step;
   int32_t max_rings;
@@ -107,6 +116,7 @@ typedef struct {
   uint64_t seed;
   int64_t rec_base;
   uint64_t* counters;
+  int32_t shadow_bvh;
 } rc_params;
 
 /* Scene statistics reported by rc_scene_info. */
@@ -245,6 +255,45 @@ int rc_trace_rays(const rc_scene* scene, const float* orig, const float* dir, in
  * is hit with 1e-4 < t < 1.  skip device int32[n] or NULL (none). */
 int rc_occluded_rays(const rc_scene* scene, const float* orig, const float* seg, const int32_t* skip, int64_t n,
                      int32_t* occ, void* stream);
+
+/* ------------------------------------------------------------------ */
+/* Per-light triangle bins (the shadow-segment structure of the record   */
+/* kernel; point lights with shadow rays, Sec. 6)                       */
+/* ------------------------------------------------------------------ */
+/* Seen from a point light, the directions are split into the six faces of a
+ * cube and each face into bins at up to 4 levels (B / 4^k per side); each
+ * triangle is listed, with its distance from the light, in the bins its
+ * padded direction region covers, at the finest level where that is at most
+ * 4 x 4 bins.  A segment y -> light then tests only the triangles of its
+ * bins that are closer to the light than y, in order of distance.  The
+ * padding covers the hit test's FP32 error, so the answers equal those of
+ * testing every triangle.
+ *
+ * Build (host) and upload the bins of these lights, replacing any earlier
+ * set; rc_records* do this themselves at the first call with a new set of
+ * positions.  Allocates device memory (about 50 B per entry; entries per
+ * triangle fall with its size and distance).  B = 0: chosen from the triangle
+ * count.  Errors: EINVAL (bad lights or B), ENOMEM, EDEVICE. */
+int rc_light_bins_build(rc_scene* scene, const rc_point_light* lights, int n_lights, int B);
+/* Segments p_i -> light `light` (index into the last built set) answered from
+ * the bins, one per lane: occ[i] = 1 if a triangle other than skip[i] is hit
+ * with 1e-4 < t < 1 on o = p_i, d = light - p_i.  pts device float[n][3],
+ * skip device int32[n] or NULL, occ device int32[n].  Errors: EINVAL (no
+ * bins built, light out of range). */
+int rc_light_occluded(const rc_scene* scene, int light, const float* pts, const int32_t* skip, int64_t n,
+                      int32_t* occ, void* stream);
+/* The bins of one light as the kernels read them, built on the host (no
+ * device needed).  B: finest bins per face side (a power of two >= 2, or 0 =
+ * chosen from T).  Outputs: *B_out, *levels, level_off[4] (start of each
+ * level within offs), offs int32[n_offs] (per level 6 B_k^2 bin starts and a
+ * sentinel; absolute entry indices), entries float[n_entries][12] (vertices
+ * permuted for the face's axis, id bits in word 3, distance from the light
+ * minus the hit-test error in word 7).  Returns the entry count, or a
+ * negative error; with offs or entries NULL (or their capacities too small)
+ * only the counts are written. */
+int64_t rc_light_bins_host(const float* tri, int64_t T, const float box_lo[3], const float box_hi[3],
+                           const float light[3], int B, int* B_out, int* levels, int64_t* level_off, int32_t* offs,
+                           int64_t cap_offs, int64_t* n_offs, float* entries, int64_t cap_entries);
 
 /* ------------------------------------------------------------------ */
 /* Learned placement (project-defined; predicts the validity radius of  */

@@ -11,6 +11,7 @@
 #include <mutex>
 #include <sstream>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "internal.hpp"
@@ -74,14 +75,36 @@ struct rc_scene {
   float pad = 0.f;
   float box_lo[3], box_hi[3];
   float4* nodes = nullptr;
-  float4* tris = nullptr;
+  float4* tris = nullptr;     // three copies of the triangle records (copy k permuted for kz = k)
+  int tri_stride = 0;         // float4 words per copy
   float4* shade = nullptr;
   double4* plane = nullptr;
   float* emission = nullptr;
+  std::vector<float> tri_host;  // the input triangles (light bins are built from them)
+  // per-light triangle bins of the last light set (positions), device copies
+  struct {
+    int n = 0;
+    float pos[RC_MAX_LIGHTS][3];
+    int4* desc = nullptr;
+    int* offs = nullptr;
+    float4* ent = nullptr;
+    int64_t n_entries = 0;
+    void clear() {
+      if (desc) (void)hipFree(desc);
+      if (offs) (void)hipFree(offs);
+      if (ent) (void)hipFree(ent);
+      desc = nullptr;
+      offs = nullptr;
+      ent = nullptr;
+      n = 0;
+      n_entries = 0;
+    }
+  } lb;
   std::mutex mu;
   GraphCache graph;
   ~rc_scene() {
     graph.clear();
+    lb.clear();
     if (nodes) (void)hipFree(nodes);
     if (tris) (void)hipFree(tris);
     if (shade) (void)hipFree(shade);
@@ -98,6 +121,17 @@ constexpr size_t kWsQueue = 0, kWsHist = 256, kWsCursor = 256 + 4 * rc::kOrderBu
                  kWsOrder = 256 + 8 * rc::kOrderBuckets;
 constexpr int kQClassNext = 2, kQClassRange = 16;
 // after the queue order: per-record part counters, then per-part partial sums
+// launch configurations ("tiles"): persistent grid as a multiple of the
+// resident wave capacity, idle lanes that trigger a refill of the shadow
+// loop, and lanes waiting at a leaf that trigger a triangle step
+struct Tile {
+  float grid;
+  int refill_min, leaf_batch;
+};
+constexpr int kNTiles = 8;
+constexpr Tile kTiles[kNTiles] = {{1.0f, 12, 0}, {2.0f, 12, 0}, {1.0f, 8, 0},  {1.0f, 16, 0},
+                                  {1.0f, 12, 8}, {2.0f, 12, 8}, {0.5f, 12, 0}, {1.0f, 24, 0}};
+
 size_t ws_split_offset(int64_t P) { return (kWsOrder + 4 * (size_t)std::max<int64_t>(P, 0) + 255) & ~size_t(255); }
 size_t ws_partial_offset(int64_t Pm) { return (4 * (size_t)Pm + 255) & ~size_t(255); }
 
@@ -119,6 +153,7 @@ int check_inputs(const rc_scene* s, const rc_medium* m, const rc_point_light* li
   if (p->max_n_phi < 5 || p->max_n_phi > RC_MAX_NPHI) return fail(RC_EINVAL, "max_n_phi must be in [5, %d]", RC_MAX_NPHI);
   if (p->precision != 0 && p->precision != 1) return fail(RC_EINVAL, "precision must be 0 or 1");
   if (p->common_random != 0 && p->common_random != 1) return fail(RC_EINVAL, "common_random must be 0 or 1");
+  if (p->shadow_bvh != 0 && p->shadow_bvh != 1) return fail(RC_EINVAL, "shadow_bvh must be 0 or 1");
   if (p->splits < 0 || p->splits > rc::kMaxSplits) return fail(RC_EINVAL, "splits must be in [0, %d]", rc::kMaxSplits);
   if (p->splits > 1 && P > rc::kSplitMaxRecords)
     return fail(RC_EINVAL, "splits > 1 needs P <= %d", rc::kSplitMaxRecords);
@@ -144,6 +179,66 @@ int lds_cols_for(int max_n_phi, int stack, int max_rings) {
   return std::min(max_n_phi, 33);  // deep stacks or many rings: fewer wavefronts
 }
 
+// Build and upload the light bins of these light positions unless the scene
+// already holds them.  Caller holds s->mu.
+int ensure_light_bins(rc_scene* s, const rc_point_light* lights, int n_lights, int B) {
+  if (n_lights <= 0) return RC_OK;
+  bool same = s->lb.n == n_lights && s->lb.desc != nullptr;
+  for (int l = 0; same && l < n_lights; l++)
+    same = std::memcmp(s->lb.pos[l], lights[l].pos, sizeof(float) * 3) == 0;
+  if (same && B == 0) return RC_OK;
+  if (B == 0) B = rc::light_bins_size_for(s->T);
+  std::vector<rc::LightBinsHost> h((size_t)n_lights);
+  std::vector<std::string> errs((size_t)n_lights);
+  std::vector<int> rcs((size_t)n_lights, RC_OK);
+  {
+    std::vector<std::thread> th;
+    for (int l = 0; l < n_lights; l++)
+      th.emplace_back([&, l] {
+        rcs[l] = rc::build_light_bins(s->tri_host.data(), s->T, s->pad, lights[l].pos, B, h[l], errs[l]);
+      });
+    for (auto& t : th) t.join();
+  }
+  for (int l = 0; l < n_lights; l++)
+    if (rcs[l] != RC_OK) return fail(rcs[l], "%s", errs[l].c_str());
+  // concatenate: offsets shifted to absolute entry indices
+  std::vector<int32_t> offs;
+  std::vector<float> ent;
+  std::vector<int4> desc(2 * (size_t)n_lights);
+  int64_t ebase = 0;
+  for (int l = 0; l < n_lights; l++) {
+    const int64_t obase = (int64_t)offs.size();
+    if (ebase + (int64_t)(h[l].entries.size() / 12) >= ((int64_t)1 << 31) || obase + (int64_t)h[l].offs.size() >= ((int64_t)1 << 31))
+      return fail(RC_EINVAL, "light bins: more than 2^31 entries or bins");
+    for (int32_t v : h[l].offs) offs.push_back((int32_t)(v + ebase));
+    ent.insert(ent.end(), h[l].entries.begin(), h[l].entries.end());
+    int lo[rc::kLbMaxLevels] = {0, 0, 0, 0};
+    for (int k = 0; k < h[l].nlev; k++) lo[k] = (int)(obase + h[l].lev_off[k]);
+    desc[2 * l] = make_int4(h[l].B, h[l].nlev, lo[0], lo[1]);
+    desc[2 * l + 1] = make_int4(lo[2], lo[3], 0, 0);
+    ebase += (int64_t)(h[l].entries.size() / 12);
+  }
+  ent.resize(ent.size() + 4, 0.f);
+  s->graph.clear();  // launches captured with the old buffers
+  s->lb.clear();
+  auto up = [&](void** dst, const void* src, size_t bytes) -> int {
+    if (hipMalloc(dst, std::max<size_t>(bytes, 16)) != hipSuccess) return fail(RC_ENOMEM, "hipMalloc %zu", bytes);
+    if (bytes && hipMemcpy(*dst, src, bytes, hipMemcpyHostToDevice) != hipSuccess) return fail(RC_EDEVICE, "hipMemcpy");
+    return RC_OK;
+  };
+  int r = up((void**)&s->lb.desc, desc.data(), desc.size() * sizeof(int4));
+  if (!r) r = up((void**)&s->lb.offs, offs.data(), offs.size() * 4);
+  if (!r) r = up((void**)&s->lb.ent, ent.data(), ent.size() * 4);
+  if (r) {
+    s->lb.clear();
+    return r;
+  }
+  s->lb.n = n_lights;
+  for (int l = 0; l < n_lights; l++) std::memcpy(s->lb.pos[l], lights[l].pos, sizeof(float) * 3);
+  s->lb.n_entries = ebase;
+  return RC_OK;
+}
+
 rc::RecordArgs make_args(const rc_scene* s, const rc_medium* m, const rc_point_light* lights, int n_lights,
                          const float* pos, const int32_t* nth, const int32_t* nph, int64_t P, const rc_params* p,
                          double* value, double* grad, double* hess, void* ws, const int32_t* order) {
@@ -151,6 +246,7 @@ rc::RecordArgs make_args(const rc_scene* s, const rc_medium* m, const rc_point_l
   std::memset(&a, 0, sizeof a);  // padding too: the graph cache compares whole structs
   a.nodes = s->nodes;
   a.tris = s->tris;
+  a.tri_stride = s->tri_stride;
   a.shade = s->shade;
   a.plane = s->plane;
   a.emission = s->emission;
@@ -180,6 +276,13 @@ rc::RecordArgs make_args(const rc_scene* s, const rc_medium* m, const rc_point_l
   a.queue = reinterpret_cast<unsigned int*>(static_cast<char*>(ws) + kWsQueue);
   a.counters = reinterpret_cast<unsigned long long*>(p->counters);
   a.splits = 1;
+  a.refill_min = kTiles[0].refill_min;
+  a.leaf_batch = kTiles[0].leaf_batch;
+  if (p->shadow_bvh == 0 && n_lights > 0 && s->lb.n == n_lights) {
+    a.lb_desc = s->lb.desc;
+    a.lb_offs = s->lb.offs;
+    a.lb_ent = s->lb.ent;
+  }
   return a;
 }
 
@@ -214,11 +317,6 @@ void set_splits(rc::RecordArgs& a, const rc_params* p, int64_t P, int64_t reside
   }
 }
 
-// launch configurations ("tiles"): persistent grid as a multiple of the
-// resident wave capacity
-constexpr int kNTiles = 4;
-constexpr float kTileGrid[kNTiles] = {1.0f, 2.0f, 0.5f, 4.0f};
-
 int plan(const rc_scene* s, const rc_params* p, int64_t P, int tile, int& stack, size_t& lds, int& grid,
          int64_t* resident_out = nullptr) {
   stack = rc::stack_variant(s->depth);
@@ -231,7 +329,7 @@ int plan(const rc_scene* s, const rc_params* p, int64_t P, int tile, int& stack,
   int t = (tile >= 0 && tile < kNTiles) ? tile : 0;
   int64_t resident = (int64_t)occ * s->n_cu;
   if (resident_out) *resident_out = resident;
-  int64_t gsz = (int64_t)std::llround((double)resident * kTileGrid[t]);
+  int64_t gsz = (int64_t)std::llround((double)resident * kTiles[t].grid);
   gsz = std::max<int64_t>(1, std::min<int64_t>(gsz, P * (int64_t)rc::kMaxSplits));
   grid = (int)gsz;
   return RC_OK;
@@ -310,6 +408,7 @@ int rc_scene_create(const float* tri, const float* albedo, const float* emission
   s->depth = bvh.depth;
   s->pad = pad;
   for (int k = 0; k < 3; k++) { s->box_lo[k] = box_lo[k]; s->box_hi[k] = box_hi[k]; }
+  s->tri_host.assign(tri, tri + 9 * T);
   // per-triangle shading data
   std::vector<float> shade(4 * std::max<int64_t>(T, 1), 0.f), em(std::max<int64_t>(T, 1), 0.f);
   // FP64 plane of each triangle (unit normal n from the FP32 vertices, n . v0):
@@ -334,9 +433,25 @@ int rc_scene_create(const float* tri, const float* albedo, const float* emission
       return fail(RC_EDEVICE, "hipMemcpy");
     return RC_OK;
   };
-  bvh.tris.resize(bvh.tris.size() + 4, 0.f);  // one padding word after the last triangle
+  // Three copies of the triangle records, copy k with every vertex permuted
+  // to (v[(k+1)%3], v[(k+2)%3], v[k]): a ray whose largest direction
+  // component is k reads copy k, so the watertight test selects nothing per
+  // vertex.  One padding word after the last record of the last copy keeps
+  // the traversal's fourth 16-byte load in bounds.
+  const size_t per_copy = bvh.tris.size();  // floats, 12 per triangle
+  s->tri_stride = (int)(per_copy / 4);
+  std::vector<float> tris3(3 * per_copy + 4, 0.f);
+  for (int k = 0; k < 3; k++)
+    for (size_t i = 0; i < per_copy; i += 4) {
+      const float* q = bvh.tris.data() + i;
+      float* o = tris3.data() + k * per_copy + i;
+      o[0] = q[(k + 1) % 3];
+      o[1] = q[(k + 2) % 3];
+      o[2] = q[k];
+      o[3] = q[3];  // id bits (first word) or 0
+    }
   int r = up((void**)&s->nodes, bvh.nodes.data(), bvh.nodes.size() * 4);
-  if (!r) r = up((void**)&s->tris, bvh.tris.data(), bvh.tris.size() * 4);
+  if (!r) r = up((void**)&s->tris, tris3.data(), tris3.size() * 4);
   if (!r) r = up((void**)&s->shade, shade.data(), shade.size() * 4);
   if (!r) r = up((void**)&s->plane, plane.data(), plane.size() * 8);
   if (!r) r = up((void**)&s->emission, em.data(), em.size() * 4);
@@ -413,6 +528,10 @@ int rc_records(const rc_scene* scene, const rc_medium* medium, const rc_point_li
   if (r) return r;
   if (P == 0) return RC_OK;
   rc_scene* s = const_cast<rc_scene*>(scene);
+  if (params->shadow_bvh == 0) {
+    std::lock_guard<std::mutex> lk(s->mu);
+    if ((r = ensure_light_bins(s, lights, n_lights, 0))) return r;
+  }
   int stack, grid;
   size_t lds;
   int64_t resident = 0;
@@ -433,6 +552,10 @@ int rc_records_batched(const rc_scene* scene, const rc_medium* medium, const rc_
   if (tile < -1 || tile >= kNTiles) return fail(RC_EINVAL, "tile must be in [-1, %d)", kNTiles);
   if (P == 0) return RC_OK;
   rc_scene* s = const_cast<rc_scene*>(scene);
+  if (params->shadow_bvh == 0) {
+    std::lock_guard<std::mutex> lk(s->mu);
+    if ((r = ensure_light_bins(s, lights, n_lights, 0))) return r;
+  }
   hipStream_t st = static_cast<hipStream_t>(stream);
   int stack, grid;
   size_t lds;
@@ -450,6 +573,8 @@ int rc_records_batched(const rc_scene* scene, const rc_medium* medium, const rc_
   rc::RecordArgs a = make_args(s, medium, lights, n_lights, pos, n_theta, n_phi, P, params, value, grad, hess,
                                workspace, ord);
   set_splits(a, params, P, resident, workspace);
+  a.refill_min = kTiles[tile < 0 ? 0 : tile].refill_min;
+  a.leaf_batch = kTiles[tile < 0 ? 0 : tile].leaf_batch;
   std::vector<Launch> launches;
   if (!order && a.splits == 1 && P > rc::kSplitMaxRecords) {
     // Large batches from the internal queue: one launch per n_phi class, each
@@ -593,7 +718,7 @@ int rc_trace_rays(const rc_scene* s, const float* orig, const float* dir, int64_
                   int32_t* front, void* stream) {
   if (!s || n < 0 || n > 0x7fffffff) return fail(RC_EINVAL, "invalid arguments");
   if (n > 0 && (!orig || !dir || !hit_id || !t || !front)) return fail(RC_EINVAL, "NULL pointer");
-  RC_HIP(rc::launch_trace_rays(s->nodes, s->tris, s->depth, orig, dir, (int)n, hit_id, t, front,
+  RC_HIP(rc::launch_trace_rays(s->nodes, s->tris, s->tri_stride, s->depth, orig, dir, (int)n, hit_id, t, front,
                                make_float3(s->box_lo[0], s->box_lo[1], s->box_lo[2]),
                                make_float3(s->box_hi[0], s->box_hi[1], s->box_hi[2]), static_cast<hipStream_t>(stream)));
   return RC_OK;
@@ -603,9 +728,53 @@ int rc_occluded_rays(const rc_scene* s, const float* orig, const float* seg, con
                      int32_t* occ, void* stream) {
   if (!s || n < 0 || n > 0x7fffffff) return fail(RC_EINVAL, "invalid arguments");
   if (n > 0 && (!orig || !seg || !occ)) return fail(RC_EINVAL, "NULL pointer");
-  RC_HIP(rc::launch_occluded_rays(s->nodes, s->tris, s->depth, orig, seg, skip, (int)n, occ,
+  RC_HIP(rc::launch_occluded_rays(s->nodes, s->tris, s->tri_stride, s->depth, orig, seg, skip, (int)n, occ,
                                   static_cast<hipStream_t>(stream)));
   return RC_OK;
+}
+
+int rc_light_bins_build(rc_scene* s, const rc_point_light* lights, int n_lights, int B) {
+  if (!s) return fail(RC_EINVAL, "scene is NULL");
+  if (n_lights < 1 || n_lights > RC_MAX_LIGHTS || !lights) return fail(RC_EINVAL, "n_lights must be in [1, %d]", RC_MAX_LIGHTS);
+  for (int l = 0; l < n_lights; l++)
+    if (!finite3(lights[l].pos)) return fail(RC_EINVAL, "light %d is not finite", l);
+  if (B != 0 && (B < 2 || B > 4096 || (B & (B - 1)))) return fail(RC_EINVAL, "B must be 0 or a power of two in [2, 4096]");
+  std::lock_guard<std::mutex> lk(s->mu);
+  if (B != 0) s->lb.n = 0;  // explicit size: always rebuild
+  return ensure_light_bins(s, lights, n_lights, B);
+}
+
+int rc_light_occluded(const rc_scene* s, int light, const float* pts, const int32_t* skip, int64_t n, int32_t* occ,
+                      void* stream) {
+  if (!s || n < 0 || n > 0x7fffffff) return fail(RC_EINVAL, "invalid arguments");
+  if (!s->lb.desc || light < 0 || light >= s->lb.n) return fail(RC_EINVAL, "no light bins for light %d", light);
+  if (n > 0 && (!pts || !occ)) return fail(RC_EINVAL, "NULL pointer");
+  const float4 L = make_float4(s->lb.pos[light][0], s->lb.pos[light][1], s->lb.pos[light][2], 0.f);
+  RC_HIP(rc::launch_light_occluded(s->lb.desc, s->lb.offs, s->lb.ent, light, L, pts, skip, (int)n, occ,
+                                   static_cast<hipStream_t>(stream)));
+  return RC_OK;
+}
+
+int64_t rc_light_bins_host(const float* tri, int64_t T, const float box_lo[3], const float box_hi[3],
+                           const float light[3], int B, int* B_out, int* levels, int64_t* level_off, int32_t* offs,
+                           int64_t cap_offs, int64_t* n_offs, float* entries, int64_t cap_entries) {
+  if (T < 0 || (T > 0 && !tri) || !box_lo || !box_hi || !light || !finite3(light))
+    return fail(RC_EINVAL, "invalid arguments");
+  if (B != 0 && (B < 2 || B > 4096 || (B & (B - 1)))) return fail(RC_EINVAL, "B must be 0 or a power of two in [2, 4096]");
+  rc::LightBinsHost h;
+  std::string err;
+  const float scale = rc::bvh_pad_for(tri, T, box_lo, box_hi);
+  int r = rc::build_light_bins(tri, T, scale, light, B ? B : rc::light_bins_size_for(T), h, err);
+  if (r != RC_OK) return fail(r, "%s", err.c_str());
+  const int64_t ne = (int64_t)(h.entries.size() / 12), no = (int64_t)h.offs.size();
+  if (B_out) *B_out = h.B;
+  if (levels) *levels = h.nlev;
+  if (level_off)
+    for (int k = 0; k < rc::kLbMaxLevels; k++) level_off[k] = k < h.nlev ? h.lev_off[k] : 0;
+  if (n_offs) *n_offs = no;
+  if (offs && cap_offs >= no) std::memcpy(offs, h.offs.data(), (size_t)no * 4);
+  if (entries && cap_entries >= ne) std::memcpy(entries, h.entries.data(), (size_t)ne * 48);
+  return ne;
 }
 
 /* ------------------------------------------------------------------ */
@@ -626,6 +795,7 @@ int rc_probe(const rc_scene* s, const rc_medium* m, const rc_point_light* lights
   std::memset(&a, 0, sizeof a);
   a.nodes = s->nodes;
   a.tris = s->tris;
+  a.tri_stride = s->tri_stride;
   a.shade = s->shade;
   a.emission = s->emission;
   a.box_lo = make_float3(s->box_lo[0], s->box_lo[1], s->box_lo[2]);

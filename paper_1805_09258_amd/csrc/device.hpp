@@ -85,13 +85,16 @@ RC_DEV float det3(float3 a, float3 b, float3 c) { return dot3(a, cross3(b, c)); 
 // d . ((v1 - v0) x (v2 - v0)), so front (the ray travels against that normal)
 // is D d_kz < 0.
 //
-// The ray is kept in the permuted frame (x, y, z) = (kx, ky, kz).
+// The ray is kept in the permuted frame (x, y, z) = (kx, ky, kz), and the
+// triangle array holds three copies of every triangle, copy k with its
+// vertices in the frame of kz = k, so the test itself selects nothing.
 struct WtRay {
   float3 o, d;  // origin and direction, permuted
   int kz;
 };
 RC_DEV float3 permute3(float3 v, int kz) {
-  return kz == 0 ? make_float3(v.y, v.z, v.x) : (kz == 1 ? make_float3(v.z, v.x, v.y) : v);
+  const bool b0 = kz == 0, b1 = kz == 1;
+  return make_float3(b0 ? v.y : (b1 ? v.z : v.x), b0 ? v.z : (b1 ? v.x : v.y), b0 ? v.x : (b1 ? v.y : v.z));
 }
 RC_DEV WtRay wt_ray(float3 o, float3 d) {
   const float ax = fabsf(d.x), ay = fabsf(d.y), az = fabsf(d.z);
@@ -108,12 +111,13 @@ RC_DEV WtRay wt_ray(float3 o, float3 d) {
   r.kz = k;
   return r;
 }
-// Triangle record: A = (v0, id bits), B = (v1, 0), C = (v2, 0).
+// Triangle record in the copy of the ray's kz: A = (v0, id bits), B = (v1, 0),
+// C = (v2, 0), each vertex permuted to (v_kx, v_ky, v_kz).
 RC_DEV bool hit_triangle(const WtRay& r, float4 A, float4 B, float4 C, float tmin, float tmax, float& tout,
                          bool& front) {
-  const float3 a0 = sub3(permute3(make_float3(A.x, A.y, A.z), r.kz), r.o);
-  const float3 a1 = sub3(permute3(make_float3(B.x, B.y, B.z), r.kz), r.o);
-  const float3 a2 = sub3(permute3(make_float3(C.x, C.y, C.z), r.kz), r.o);
+  const float3 a0 = sub3(make_float3(A.x, A.y, A.z), r.o);
+  const float3 a1 = sub3(make_float3(B.x, B.y, B.z), r.o);
+  const float3 a2 = sub3(make_float3(C.x, C.y, C.z), r.o);
   const double px0 = r.d.z * a0.x - r.d.x * a0.z, py0 = r.d.z * a0.y - r.d.y * a0.z;
   const double px1 = r.d.z * a1.x - r.d.x * a1.z, py1 = r.d.z * a1.y - r.d.y * a1.z;
   const double px2 = r.d.z * a2.x - r.d.x * a2.z, py2 = r.d.z * a2.y - r.d.y * a2.z;
@@ -130,6 +134,32 @@ RC_DEV bool hit_triangle(const WtRay& r, float4 A, float4 B, float4 C, float tmi
   tout = t;
   front = den < 0.0;
   return true;
+}
+
+// Per-light triangle bins: for the segment o -> o + d ending at light l
+// (wr = wt_ray(o, d)), the bin of each level that holds the direction from
+// the light to o, e = -d: face 2 kz + (e_kz > 0 ? 0 : 1), tangent coordinates
+// (e_kx, e_ky) / |e_kz|, nested levels of B >> 2k bins per side.  Writes the
+// bin indices to stk[k * 64] and returns the level count (0 if o is at the
+// light).  desc[2 l] = (B, levels, level offset 0, 1), desc[2 l + 1] = (level
+// offset 2, 3, -, -).
+RC_DEV int lb_bins(const int4* __restrict__ desc, int l, const WtRay& wr, int* stk) {
+  const int4 ds0 = desc[2 * l], ds1 = desc[2 * l + 1];
+  const int B = ds0.x, nlev = ds0.y;
+  const float ez = -wr.d.z, ex = -wr.d.x, ey = -wr.d.y;
+  if (!(fabsf(ez) > 0.0f)) return 0;
+  const float ia = 1.0f / fabsf(ez);
+  const int face = 2 * wr.kz + (ez > 0.0f ? 0 : 1);
+  const float hb = 0.5f * (float)B;
+  const int iu = min(max((int)((ex * ia + 1.0f) * hb), 0), B - 1);
+  const int iv = min(max((int)((ey * ia + 1.0f) * hb), 0), B - 1);
+  const int lo[4] = {ds0.z, ds0.w, ds1.x, ds1.y};
+#pragma unroll
+  for (int k = 0; k < 4; k++) {
+    const int Bk = B >> (2 * k);
+    if (k < nlev) stk[k * kWave] = lo[k] + (face * Bk + (iu >> (2 * k))) * Bk + (iv >> (2 * k));
+  }
+  return nlev;
 }
 
 // FP32 distance to the exit of the medium box (rays that hit nothing).
@@ -188,13 +218,19 @@ RC_DEV float slab(float lx, float hx, float ly, float hy, float lz, float hz, fl
 
 // Closest hit (smallest t, ties to the lowest triangle id): one node or one
 // triangle per loop iteration, with a single stack pop and dispatch for both
-// kinds of step (fewer divergent branches when the lanes of a wavefront trace
-// different rays in lockstep).
+// kinds of step.  leaf_batch 0: every lane takes its next step in every
+// iteration.  leaf_batch k > 0: the lanes still tracing take the same kind of
+// step in an iteration, triangle tests once at least k of them wait at a leaf
+// (or none has a node step left), node steps otherwise.  Testing a leaf later
+// only means nodes are culled against a larger best distance meanwhile; the
+// result is the same.
 template <bool COUNT>
-RC_DEV void trace_closest(const float4* __restrict__ nodes, const float4* __restrict__ tris, float3 o, float3 d,
-                                int* stk, int& best_id, float& best_t, bool& best_front, TraceCount& cnt) {
+RC_DEV void trace_closest(const float4* __restrict__ nodes, const float4* __restrict__ tris, int tri_stride, float3 o,
+                          float3 d, int* stk, int leaf_batch, int& best_id, float& best_t, bool& best_front,
+                          TraceCount& cnt) {
   constexpr int kEnd = 0x7fffffff, kStay = 0x7ffffffe;
   const WtRay wr = wt_ray(o, d);
+  const float4* const tk = tris + wr.kz * tri_stride;
   float3 inv, oi;
   ray_inv(d, o, inv, oi);
   best_id = -1;
@@ -202,7 +238,10 @@ RC_DEV void trace_closest(const float4* __restrict__ nodes, const float4* __rest
   best_front = false;
   int sp = 0, node = 0, lf = 0, ln = 0;
   while (true) {
-    const float4* src = (ln > 0) ? (tris + 3 * lf) : (nodes + 4 * node);
+    const uint64_t here = __ballot(true), at_leaf = __ballot(ln > 0);
+    const bool tri_step = at_leaf != 0ull && (__popcll(at_leaf) >= leaf_batch || at_leaf == here);
+    if (leaf_batch > 0 && (ln > 0) != tri_step) continue;
+    const float4* src = (ln > 0) ? (tk + 3 * lf) : (nodes + 4 * node);
     const float4 q0 = src[0], q1 = src[1], q2 = src[2], q3 = src[3];
     int nx = kStay;
     bool pop = false;
@@ -252,9 +291,10 @@ RC_DEV void trace_closest(const float4* __restrict__ nodes, const float4* __rest
 // Shadow segment o -> o + d: blocked iff some triangle other than `skip` is
 // hit with 1e-4 < t < 1.
 template <bool COUNT>
-RC_DEV bool occluded(const float4* __restrict__ nodes, const float4* __restrict__ tris, float3 o, float3 d,
-                     int skip, int* stk, TraceCount& cnt) {
+RC_DEV bool occluded(const float4* __restrict__ nodes, const float4* __restrict__ tris, int tri_stride, float3 o,
+                     float3 d, int skip, int* stk, TraceCount& cnt) {
   const WtRay wr = wt_ray(o, d);
+  const float4* const tk = tris + wr.kz * tri_stride;
   float3 inv, oi;
   ray_inv(d, o, inv, oi);
   int sp = 0;
@@ -285,7 +325,7 @@ RC_DEV bool occluded(const float4* __restrict__ nodes, const float4* __restrict_
     }
     int first = leaf_first(node), n = leaf_count(node);
     for (int k = 0; k < n; k++) {
-      const float4* tr = tris + 3 * (first + k);
+      const float4* tr = tk + 3 * (first + k);
       float4 A = tr[0], B = tr[1], C = tr[2];
       if (COUNT) cnt.tris++;
       float t;

@@ -5,6 +5,7 @@
 #include <string>
 #include <vector>
 
+#include "limits.hpp"
 #include "rc.h"
 
 namespace rc {
@@ -40,5 +41,22 @@ int build_bvh(const float* tri, int64_t T, float pad, HostBvh& out, std::string&
 float bvh_pad_for(const float* tri, int64_t T, const float* lo, const float* hi);
 // Box padding of one triangle (16 x the FP32 error bound of an accepted hit, see bvh.cpp).
 float triangle_pad(const float* t, float scale);
+
+// Per-light triangle bins (lightbins.cpp): levels of B / 4^k bins per cube
+// face side (k < levels <= kLbMaxLevels); offs: for each level, 6 * Bk^2
+// bin starts and a sentinel (absolute entry indices); entries: 12 floats
+// each, the triangle's vertices permuted for the face's axis, its id bits
+// (word 3) and its distance from the light minus the hit-test error,
+// rounded down (word 7); a bin's entries by increasing distance.
+struct LightBinsHost {
+  int B = 0, nlev = 0;
+  int64_t lev_off[kLbMaxLevels] = {0, 0, 0, 0};
+  std::vector<int32_t> offs;
+  std::vector<float> entries;
+};
+int light_bins_levels(int B);
+int light_bins_size_for(int64_t T);
+int build_light_bins(const float* tri, int64_t T, float scale, const float light[3], int B, LightBinsHost& out,
+                     std::string& err);
 
 }  // namespace rc

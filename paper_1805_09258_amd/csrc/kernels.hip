@@ -33,8 +33,6 @@ namespace {
 // decided triangle, or FP64 box exit, minus t; rounded to FP32), and ring
 // radiance [ring][column] (holding light-visibility bits until shaded).
 constexpr int kRowFields = 9;
-// idle lanes that trigger a refill of the shadow-ray loop
-constexpr int kRefillMin = 12;
 struct Row {
   float *wx, *wy, *wz, *t, *Ls, *tlo, *Lm;
   int *code, *M, *visS;
@@ -143,6 +141,7 @@ record_kernel(RecordArgs g) {
   TraceCount tc;
   uint32_t n_rays = 0, n_terms = 0;
   uint64_t cyc[4] = {0, 0, 0, 0};  // counting variant: shader clocks per phase
+  uint64_t sh_iter = 0, sh_busy = 0, sh_refill = 0, sh_lanes = 0;  // counting variant: shadow loop
   uint64_t t_mark = 0;
 
   const int S = g.splits;  // wavefronts per record (row ranges); 1 for large batches
@@ -242,7 +241,7 @@ record_kernel(RecordArgs g) {
             int id;
             float t;
             bool fr;
-            trace_closest<COUNT>(g.nodes, g.tris, x, w, stk, id, t, fr, tc);
+            trace_closest<COUNT>(g.nodes, g.tris, g.tri_stride, x, w, stk, g.leaf_batch, id, t, fr, tc);
             const int code = id >= 0 ? ((id << 1) | (fr ? 1 : 0)) : -1;
             if (g_hi == a) {
               R.t[c] = t;
@@ -317,21 +316,21 @@ record_kernel(RecordArgs g) {
         __syncthreads();
         int next = 0;          // next unassigned task (wave-uniform)
         bool active = false;
-        int task = 0, node = 0, sp = 0, lf = 0, ln = 0, skip = -1, slot = 0;
+        int lbit = 0, node = 0, sp = 0, lf = 0, ln = 0, skip = -1, slot = 0;
         float3 o = make_float3(0.f, 0.f, 0.f), d = o, inv = o, oi = o;
         WtRay wr = wt_ray(o, d);
         while (true) {
           // refill idle lanes in lane order, once enough of them are idle
           const uint64_t idle = __ballot(!active);
-          const bool refill = next < total && (__popcll(idle) >= kRefillMin || idle == ~0ull);
+          const bool refill = next < total && (__popcll(idle) >= g.refill_min || idle == ~0ull);
           const bool need = refill && !active;
           const uint64_t want = refill ? idle : 0ull;
           if (need) {
-            int rank = mask_rank(want);
-            task = next + rank;
+            const int task = next + mask_rank(want);
             if (task < total) {
               active = true;
               const int l = task / nvert, v = task - l * nvert;
+              lbit = 1 << l;
               const int j = find_slot(off, n, v);
               const int k = v - off[j];
               const int code = R.code[j];
@@ -354,24 +353,90 @@ record_kernel(RecordArgs g) {
                 d = make_float3(L.x - o.x, L.y - o.y, L.z - o.z);
               }
               wr = wt_ray(o, d);
-              ray_inv(d, o, inv, oi);
               node = 0;
               sp = 0;
               ln = 0;
+              if (g.lb_desc) {
+                // light bins: the bins of the direction from the light to o
+                // in this lane's (unused) stack slots; sp = their count, node
+                // = the next level, inv.x = the largest stored distance from
+                // the light that can still block
+                sp = lb_bins(g.lb_desc, l, wr, stk);
+                if (sp == 0) active = false;  // o at the light: nothing to block
+                inv.x = sqrtf(dot3(d, d)) * (1.0f + 0x1p-20f);
+              } else {
+                ray_inv(d, o, inv, oi);
+              }
               if (COUNT && own && j < n_cnt) n_rays++;
             }
           }
           next = __builtin_amdgcn_readfirstlane(next + __popcll(want));
-          if (__ballot(active) == 0ull) {
+          const uint64_t busy = __ballot(active);
+          if (COUNT) {
+            sh_iter++;
+            sh_busy += __popcll(busy);
+            if (want) {
+              sh_refill++;
+              sh_lanes += __popcll(busy & want);
+            }
+          }
+          if (busy == 0ull) {
             if (next >= total) break;
             continue;
           }
-          if (active) {
+          // leaf_batch 0: every busy lane takes its next step (node or
+          // triangle) in every iteration.  leaf_batch k > 0: one kind of step
+          // per iteration for the whole wavefront, triangle tests once at
+          // least k lanes wait at a leaf (or no lane has a node step left),
+          // node steps otherwise; lanes of the other kind wait.
+          const uint64_t at_leaf = __ballot(active && ln > 0);
+          const bool tri_step = at_leaf != 0ull && (__popcll(at_leaf) >= g.leaf_batch || at_leaf == busy);
+          if (g.lb_desc) {
+            // light bins: lf = the next entry of the current list, ln = the
+            // entries left in it; an exhausted list moves to the next level
+            if (active) {
+              bool done = false, blocked = false;
+              if (ln > 0) {
+                if (COUNT) tc.tris++;
+                const float4* e = g.lb_ent + 3 * lf;
+                const float4 q0 = e[0], q1 = e[1], q2 = e[2];
+                if (q1.w > inv.x) {
+                  ln = 0;  // sorted by distance from the light: nothing further can block
+                } else {
+                  float t;
+                  bool fr;
+                  if (__float_as_int(q0.w) != skip && hit_triangle(wr, q0, q1, q2, 1e-4f, 1.0f, t, fr)) {
+                    done = true;
+                    blocked = true;
+                  } else {
+                    lf++;
+                    ln--;
+                  }
+                }
+              } else if (node >= sp) {
+                done = true;
+              } else {
+                if (COUNT) tc.nodes++;
+                const int b = stk[node * kWave];
+                const int e0 = g.lb_offs[b], e1 = g.lb_offs[b + 1];
+                lf = e0;
+                ln = e1 - e0;
+                node++;
+              }
+              if (done) {
+                active = false;
+                if (!blocked) {
+                  if (slot < 0) atomicOr(&R.visS[-1 - slot], lbit);
+                  else atomicOr(reinterpret_cast<int*>(R.Lm) + slot, lbit);
+                }
+              }
+            }
+          } else if (active && (g.leaf_batch == 0 || (ln > 0) == tri_step)) {
             bool done = false, blocked = false;
             // one fetch per lane per iteration: the next triangle of the current
             // leaf, or the current node (the triangle array carries one word of
             // padding so the fourth load of the last triangle stays in bounds)
-            const float4* src = (ln > 0) ? (g.tris + 3 * lf) : (g.nodes + 4 * node);
+            const float4* src = (ln > 0) ? (g.tris + wr.kz * g.tri_stride + 3 * lf) : (g.nodes + 4 * node);
             const float4 q0 = src[0], q1 = src[1], q2 = src[2], q3 = src[3];
             // next: the code to visit next (a node >= 0, a leaf < 0, kEnd when
             // the stack is exhausted) or kStay to go on in the current leaf
@@ -419,9 +484,8 @@ record_kernel(RecordArgs g) {
             if (done) {
               active = false;
               if (!blocked) {
-                const int bit = 1 << (task / nvert);
-                if (slot < 0) atomicOr(&R.visS[-1 - slot], bit);
-                else atomicOr(reinterpret_cast<int*>(R.Lm) + slot, bit);
+                if (slot < 0) atomicOr(&R.visS[-1 - slot], lbit);
+                else atomicOr(reinterpret_cast<int*>(R.Lm) + slot, lbit);
               }
             }
           }
@@ -697,6 +761,10 @@ record_kernel(RecordArgs g) {
       atomicAdd(&g.counters[2], (unsigned long long)tr);
       atomicAdd(&g.counters[3], (unsigned long long)te);
       for (int k = 0; k < 4; k++) atomicAdd(&g.counters[4 + k], (unsigned long long)cyc[k]);
+      atomicAdd(&g.counters[8], (unsigned long long)sh_iter);
+      atomicAdd(&g.counters[9], (unsigned long long)sh_busy);
+      atomicAdd(&g.counters[10], (unsigned long long)sh_refill);
+      atomicAdd(&g.counters[11], (unsigned long long)sh_lanes);
     }
   }
 }
@@ -884,7 +952,8 @@ hipError_t launch_radius(const double* value, const double* hess, int P, float e
 // ---------------------------------------------------------------------------
 template <int STACK>
 __global__ __launch_bounds__(64) void trace_rays_kernel(const float4* __restrict__ nodes,
-                                                        const float4* __restrict__ tris, const float* __restrict__ o,
+                                                        const float4* __restrict__ tris, int tri_stride,
+                                                        const float* __restrict__ o,
                                                         const float* __restrict__ d, int n, int* __restrict__ hit,
                                                         float* __restrict__ t, int* __restrict__ front,
                                                         float3 lo, float3 hi) {
@@ -897,7 +966,7 @@ __global__ __launch_bounds__(64) void trace_rays_kernel(const float4* __restrict
   float tt;
   bool fr;
   TraceCount tc;
-  trace_closest<false>(nodes, tris, oo, dd, stack + threadIdx.x, id, tt, fr, tc);
+  trace_closest<false>(nodes, tris, tri_stride, oo, dd, stack + threadIdx.x, 0, id, tt, fr, tc);
   if (id < 0) tt = box_exit(oo, dd, lo, hi);
   hit[i] = id;
   t[i] = tt;
@@ -906,7 +975,7 @@ __global__ __launch_bounds__(64) void trace_rays_kernel(const float4* __restrict
 
 template <int STACK>
 __global__ __launch_bounds__(64) void occluded_rays_kernel(const float4* __restrict__ nodes,
-                                                           const float4* __restrict__ tris,
+                                                           const float4* __restrict__ tris, int tri_stride,
                                                            const float* __restrict__ o, const float* __restrict__ d,
                                                            const int* __restrict__ skip, int n, int* __restrict__ occ) {
   __shared__ int stack[STACK * kWave];
@@ -915,30 +984,76 @@ __global__ __launch_bounds__(64) void occluded_rays_kernel(const float4* __restr
   float3 oo = make_float3(o[3 * i], o[3 * i + 1], o[3 * i + 2]);
   float3 dd = make_float3(d[3 * i], d[3 * i + 1], d[3 * i + 2]);
   TraceCount tc;
-  occ[i] = occluded<false>(nodes, tris, oo, dd, skip ? skip[i] : -1, stack + threadIdx.x, tc) ? 1 : 0;
+  occ[i] = occluded<false>(nodes, tris, tri_stride, oo, dd, skip ? skip[i] : -1, stack + threadIdx.x, tc) ? 1 : 0;
 }
 
-hipError_t launch_trace_rays(const float4* nodes, const float4* tris, int depth, const float* o, const float* d, int n,
+// segments p -> light through the light bins, one per lane (the same bin
+// lookup and entry loop as the record kernel's shadow segments)
+__global__ __launch_bounds__(64) void light_occluded_kernel(const int4* __restrict__ desc,
+                                                            const int* __restrict__ offs,
+                                                            const float4* __restrict__ ent, int l, float4 L,
+                                                            const float* __restrict__ pts,
+                                                            const int* __restrict__ skip, int n,
+                                                            int* __restrict__ occ) {
+  __shared__ int lvl[kLbMaxLevels * kWave];
+  const int i = blockIdx.x * kWave + threadIdx.x;
+  if (i >= n) return;
+  const float3 o = make_float3(pts[3 * i], pts[3 * i + 1], pts[3 * i + 2]);
+  const float3 d = make_float3(L.x - o.x, L.y - o.y, L.z - o.z);
+  const int sk = skip ? skip[i] : -1;
+  const WtRay wr = wt_ray(o, d);
+  int* stk = lvl + threadIdx.x;
+  const int nlev = lb_bins(desc, l, wr, stk);
+  const float reach = sqrtf(dot3(d, d)) * (1.0f + 0x1p-20f);
+  int res = 0;
+  for (int k = 0; k < nlev && !res; k++) {
+    const int b = stk[k * kWave];
+    for (int e = offs[b]; e < offs[b + 1]; e++) {
+      const float4 q0 = ent[3 * e], q1 = ent[3 * e + 1], q2 = ent[3 * e + 2];
+      if (q1.w > reach) break;
+      float t;
+      bool fr;
+      if (__float_as_int(q0.w) != sk && hit_triangle(wr, q0, q1, q2, 1e-4f, 1.0f, t, fr)) {
+        res = 1;
+        break;
+      }
+    }
+  }
+  occ[i] = res;
+}
+
+hipError_t launch_light_occluded(const int4* desc, const int* offs, const float4* ent, int l, float4 L,
+                                 const float* pts, const int* skip, int n, int* occ, hipStream_t s) {
+  const int blocks = (n + kWave - 1) / kWave;
+  if (blocks > 0)
+    hipLaunchKernelGGL(light_occluded_kernel, dim3(blocks), dim3(kWave), 0, s, desc, offs, ent, l, L, pts, skip, n,
+                       occ);
+  return hipGetLastError();
+}
+
+hipError_t launch_trace_rays(const float4* nodes, const float4* tris, int tri_stride, int depth, const float* o,
+                             const float* d, int n,
                              int* hit, float* t, int* front, float3 lo, float3 hi, hipStream_t s) {
   int blocks = (n + kWave - 1) / kWave;
   if (blocks == 0) return hipSuccess;
   int st = stack_variant(depth);
-  if (st <= 16) hipLaunchKernelGGL(trace_rays_kernel<16>, dim3(blocks), dim3(kWave), 0, s, nodes, tris, o, d, n, hit, t, front, lo, hi);
-  else if (st <= 32) hipLaunchKernelGGL(trace_rays_kernel<32>, dim3(blocks), dim3(kWave), 0, s, nodes, tris, o, d, n, hit, t, front, lo, hi);
-  else if (st <= 48) hipLaunchKernelGGL(trace_rays_kernel<48>, dim3(blocks), dim3(kWave), 0, s, nodes, tris, o, d, n, hit, t, front, lo, hi);
-  else hipLaunchKernelGGL(trace_rays_kernel<64>, dim3(blocks), dim3(kWave), 0, s, nodes, tris, o, d, n, hit, t, front, lo, hi);
+  if (st <= 16) hipLaunchKernelGGL(trace_rays_kernel<16>, dim3(blocks), dim3(kWave), 0, s, nodes, tris, tri_stride, o, d, n, hit, t, front, lo, hi);
+  else if (st <= 32) hipLaunchKernelGGL(trace_rays_kernel<32>, dim3(blocks), dim3(kWave), 0, s, nodes, tris, tri_stride, o, d, n, hit, t, front, lo, hi);
+  else if (st <= 48) hipLaunchKernelGGL(trace_rays_kernel<48>, dim3(blocks), dim3(kWave), 0, s, nodes, tris, tri_stride, o, d, n, hit, t, front, lo, hi);
+  else hipLaunchKernelGGL(trace_rays_kernel<64>, dim3(blocks), dim3(kWave), 0, s, nodes, tris, tri_stride, o, d, n, hit, t, front, lo, hi);
   return hipGetLastError();
 }
 
-hipError_t launch_occluded_rays(const float4* nodes, const float4* tris, int depth, const float* o, const float* d,
+hipError_t launch_occluded_rays(const float4* nodes, const float4* tris, int tri_stride, int depth, const float* o,
+                                const float* d,
                                 const int* skip, int n, int* occ, hipStream_t s) {
   int blocks = (n + kWave - 1) / kWave;
   if (blocks == 0) return hipSuccess;
   int st = stack_variant(depth);
-  if (st <= 16) hipLaunchKernelGGL(occluded_rays_kernel<16>, dim3(blocks), dim3(kWave), 0, s, nodes, tris, o, d, skip, n, occ);
-  else if (st <= 32) hipLaunchKernelGGL(occluded_rays_kernel<32>, dim3(blocks), dim3(kWave), 0, s, nodes, tris, o, d, skip, n, occ);
-  else if (st <= 48) hipLaunchKernelGGL(occluded_rays_kernel<48>, dim3(blocks), dim3(kWave), 0, s, nodes, tris, o, d, skip, n, occ);
-  else hipLaunchKernelGGL(occluded_rays_kernel<64>, dim3(blocks), dim3(kWave), 0, s, nodes, tris, o, d, skip, n, occ);
+  if (st <= 16) hipLaunchKernelGGL(occluded_rays_kernel<16>, dim3(blocks), dim3(kWave), 0, s, nodes, tris, tri_stride, o, d, skip, n, occ);
+  else if (st <= 32) hipLaunchKernelGGL(occluded_rays_kernel<32>, dim3(blocks), dim3(kWave), 0, s, nodes, tris, tri_stride, o, d, skip, n, occ);
+  else if (st <= 48) hipLaunchKernelGGL(occluded_rays_kernel<48>, dim3(blocks), dim3(kWave), 0, s, nodes, tris, tri_stride, o, d, skip, n, occ);
+  else hipLaunchKernelGGL(occluded_rays_kernel<64>, dim3(blocks), dim3(kWave), 0, s, nodes, tris, tri_stride, o, d, skip, n, occ);
   return hipGetLastError();
 }
 

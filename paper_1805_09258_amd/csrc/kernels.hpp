@@ -4,6 +4,7 @@
 #include <stddef.h>
 #include <stdint.h>
 
+#include "limits.hpp"
 #include "rc.h"
 
 namespace rc {
@@ -16,7 +17,8 @@ static_assert(kOrderClasses * kOrderPerClass <= kOrderBuckets, "order buckets");
 
 struct RecordArgs {
   const float4* nodes;
-  const float4* tris;
+  const float4* tris;      // three copies of the triangle records, copy k permuted for kz = k
+  int tri_stride;          // float4 words per copy
   const float4* shade;     // per triangle: unit normal (xyz), albedo (w)
   const double4* plane;    // per triangle: FP64 unit normal (xyz), normal . v0 (w)
   const float* emission;   // per triangle
@@ -41,7 +43,16 @@ struct RecordArgs {
   double* hess;
   const int* order;        // queue order or nullptr (identity)
   unsigned int* queue;     // [0] next queue slot, [1] invalid records
+  // shadow segments from light bins (nullptr: BVH traversal): per light two
+  // int4 (B, levels, level offsets 0..3), the bin offsets (CSR over levels,
+  // faces, bins) and the entries (3 float4: permuted vertices, id bits,
+  // stored distance from the light)
+  const int4* lb_desc;
+  const int* lb_offs;
+  const float4* lb_ent;
   int splits;              // wavefronts per record (each owns a range of rows)
+  int refill_min;          // shadow loop: idle lanes that trigger a refill
+  int leaf_batch;          // traversal: lanes waiting at a leaf that trigger a triangle step
   double* partial;         // [P][splits][20] partial sums (splits > 1)
   unsigned int* done;      // [P] parts finished (splits > 1; zero before launch)
   const unsigned int* range;  // device [lo, hi): queue slots of this launch, or nullptr (all)
@@ -68,9 +79,13 @@ hipError_t launch_order(const int* nth, const int* nph, int P, unsigned int* his
 hipError_t launch_radius(const double* value, const double* hess, int P, float eps, float r_min, float r_max, float* R,
                          float* axes, hipStream_t s);
 
-hipError_t launch_trace_rays(const float4* nodes, const float4* tris, int depth, const float* o, const float* d, int n,
+hipError_t launch_light_occluded(const int4* desc, const int* offs, const float4* ent, int l, float4 L,
+                                 const float* pts, const int* skip, int n, int* occ, hipStream_t s);
+hipError_t launch_trace_rays(const float4* nodes, const float4* tris, int tri_stride, int depth, const float* o,
+                             const float* d, int n,
                              int* hit, float* t, int* front, float3 lo, float3 hi, hipStream_t s);
-hipError_t launch_occluded_rays(const float4* nodes, const float4* tris, int depth, const float* o, const float* d,
+hipError_t launch_occluded_rays(const float4* nodes, const float4* tris, int tri_stride, int depth, const float* o,
+                                const float* d,
                                 const int* skip, int n, int* occ, hipStream_t s);
 
 }  // namespace rc

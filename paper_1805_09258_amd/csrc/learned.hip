@@ -81,7 +81,7 @@ __global__ __launch_bounds__(64) void probe_kernel(ProbeArgs g) {
     int id;
     float t;
     bool fr;
-    trace_closest<false>(g.nodes, g.tris, x, w, stk, id, t, fr, tc);
+    trace_closest<false>(g.nodes, g.tris, g.tri_stride, x, w, stk, 0, id, t, fr, tc);
     const bool hit = id >= 0;
     if (!hit) t = box_exit(x, w, g.box_lo, g.box_hi);
     sw[0][lane] = w.x;
@@ -154,7 +154,7 @@ __global__ __launch_bounds__(64) void probe_kernel(ProbeArgs g) {
         }
         if (active) {
           bool done = false, blocked = false;
-          const float4* src = (ln > 0) ? (g.tris + 3 * lf) : (g.nodes + 4 * node);
+          const float4* src = (ln > 0) ? (g.tris + wr.kz * g.tri_stride + 3 * lf) : (g.nodes + 4 * node);
           const float4 q0 = src[0], q1 = src[1], q2 = src[2], q3 = src[3];
           if (ln > 0) {
             float th;

@@ -31,7 +31,8 @@ struct PlaceGrid {
 
 struct ProbeArgs {
   const float4* nodes;
-  const float4* tris;
+  const float4* tris;      // three copies, copy k permuted for kz = k
+  int tri_stride;          // float4 words per copy
   const float4* shade;
   const float* emission;
   float3 box_lo, box_hi;

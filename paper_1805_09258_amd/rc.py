@@ -43,7 +43,8 @@ class rc_params(C.Structure):
                 ("precision", C.c_int32), ("common_random", C.c_int32), ("splits", C.c_int32),
                 ("seed", C.c_uint64),
                 ("rec_base", C.c_int64),
-                ("counters", C.c_void_p)]
+                ("counters", C.c_void_p),
+                ("shadow_bvh", C.c_int32)]
 
 
 class rc_scene_stats(C.Structure):
@@ -53,7 +54,8 @@ class rc_scene_stats(C.Structure):
 
 EXPORTS = ["rc_scene_create", "rc_scene_destroy", "rc_scene_info", "rc_bvh_build_host", "rc_workspace_size",
            "rc_workspace_errors", "rc_records", "rc_records_batched", "rc_autotune", "rc_radius",
-           "rc_trace_rays", "rc_occluded_rays", "rc_probe", "rc_mlp_param_bytes", "rc_mlp_n_params", "rc_mlp_init",
+           "rc_trace_rays", "rc_occluded_rays", "rc_light_bins_build", "rc_light_occluded", "rc_light_bins_host",
+           "rc_probe", "rc_mlp_param_bytes", "rc_mlp_n_params", "rc_mlp_init",
            "rc_mlp_load", "rc_mlp_fit_features", "rc_mlp_forward", "rc_mlp_radius", "rc_mlp_train_workspace_bytes",
            "rc_mlp_train_step", "rc_place_gather", "rc_place_accept", "rc_place_cover", "rc_place_cover_grid",
            "rc_interp",
@@ -94,6 +96,13 @@ def lib():
         L.rc_trace_rays.restype = i32
         L.rc_occluded_rays.argtypes = [vp, vp, vp, vp, i64, vp, vp]
         L.rc_occluded_rays.restype = i32
+        L.rc_light_bins_build.argtypes = [vp, C.POINTER(rc_point_light), i32, i32]
+        L.rc_light_bins_build.restype = i32
+        L.rc_light_occluded.argtypes = [vp, i32, vp, vp, i64, vp, vp]
+        L.rc_light_occluded.restype = i32
+        L.rc_light_bins_host.argtypes = [vp, i64, vp, vp, vp, i32, C.POINTER(i32), C.POINTER(i32), vp, vp, i64,
+                                         C.POINTER(i64), vp, i64]
+        L.rc_light_bins_host.restype = i64
         u64 = C.c_uint64
         L.rc_probe.argtypes = [vp, C.POINTER(rc_medium), C.POINTER(rc_point_light), i32, vp, i64, u64, i64, i32, vp,
                                vp, vp]
@@ -134,6 +143,10 @@ def _check(code):
     if code < 0:
         raise RCError(code, lib().rc_last_error().decode(errors="replace"))
     return code
+
+
+def _np(a):
+    return None if a is None else a.ctypes.data_as(C.c_void_p)
 
 
 def _ptr(t):
@@ -206,10 +219,37 @@ def rc_workspace_errors(ws, stream=None):
 
 
 def make_params(ring_step, max_rings, max_n_phi, seed, rec_base=0, precision=0, counters=None, common_random=False,
-                splits=0):
+                splits=0, shadow_bvh=False):
     return rc_params(float(ring_step), int(max_rings), int(max_n_phi), int(precision), int(bool(common_random)),
                      int(splits), int(seed) & (2**64 - 1), int(rec_base),
-                     None if counters is None else counters.data_ptr())
+                     None if counters is None else counters.data_ptr(), int(bool(shadow_bvh)))
+
+
+def rc_light_bins_build(scene, lights, B=0):
+    arr, nl = _lights(lights)
+    return _check(lib().rc_light_bins_build(scene, arr, nl, int(B)))
+
+
+def rc_light_occluded(scene, light, pts, skip, occ, stream=None):
+    n = int(pts.shape[0])
+    return _check(lib().rc_light_occluded(scene, int(light), _ptr(pts), _ptr(skip), n, _ptr(occ), _stream(stream)))
+
+
+def rc_light_bins_host(tri, box_lo, box_hi, light, B=0):
+    """Host-built bins of one light: dict(B, levels, level_off, offs, entries[n][12])."""
+    tri = np.ascontiguousarray(tri, np.float32).reshape(-1, 9)
+    lo = np.ascontiguousarray(box_lo, np.float32)
+    hi = np.ascontiguousarray(box_hi, np.float32)
+    L = np.ascontiguousarray(light, np.float32)
+    Bo, nl, no = C.c_int(0), C.c_int(0), C.c_int64(0)
+    lev = np.zeros(4, np.int64)
+    ne = _check(lib().rc_light_bins_host(_np(tri), tri.shape[0], _np(lo), _np(hi), _np(L), int(B), C.byref(Bo),
+                                         C.byref(nl), _np(lev), None, 0, C.byref(no), None, 0))
+    offs = np.zeros(no.value, np.int32)
+    ent = np.zeros((ne, 12), np.float32)
+    _check(lib().rc_light_bins_host(_np(tri), tri.shape[0], _np(lo), _np(hi), _np(L), int(B), C.byref(Bo),
+                                    C.byref(nl), _np(lev), _np(offs), no.value, C.byref(no), _np(ent), ne))
+    return {"B": Bo.value, "levels": nl.value, "level_off": lev[:nl.value].copy(), "offs": offs, "entries": ent}
 
 
 def rc_records(scene, sigma_s, sigma_a, lights, pos, n_theta, n_phi, params, value, grad, hess, workspace,
@@ -404,12 +444,13 @@ class DeviceWorkload:
 
 
 def compute_records(scene: Scene, dw: DeviceWorkload, batched=False, use_graph=False, tile=-1, order=None,
-                    precision=0, counters=None, out=None, workspace=None, stream=None, splits=0):
+                    precision=0, counters=None, out=None, workspace=None, stream=None, splits=0, shadow_bvh=False):
     """Records for every point of a DeviceWorkload; returns (value, grad, hess, workspace)."""
     w = dw.w
     value, grad, hess = out if out is not None else dw.outputs()
     ws = workspace if workspace is not None else dw.workspace()
-    prm = make_params(w.ring_step, w.max_rings, dw.max_n_phi, w.seed, 0, precision, counters, splits=splits)
+    prm = make_params(w.ring_step, w.max_rings, dw.max_n_phi, w.seed, 0, precision, counters, splits=splits,
+                      shadow_bvh=shadow_bvh)
     if batched:
         rc_records_batched(scene.handle, w.sigma_s, w.sigma_a, w.lights, dw.pos, dw.n_theta, dw.n_phi, prm, order,
                            use_graph, tile, value, grad, hess, ws, stream)

@@ -219,3 +219,99 @@ def test_binding_constants_match_header():
     assert int(defs["RC_PLACE_STATE_INTS"]) == rc.RC_PLACE_STATE_INTS
     assert (int(defs["RC_MAX_LIGHTS"]), int(defs["RC_MAX_RINGS"]), int(defs["RC_MAX_NPHI"])) == (
         rc.RC_MAX_LIGHTS, rc.RC_MAX_RINGS, rc.RC_MAX_NPHI)
+
+
+def _bin_candidates(b, L, y):
+    """Triangle ids the kernels test for the segment y -> L: every entry of
+    the segment's bin on each level up to the first stored distance beyond
+    the segment (the same FP32 bin arithmetic as the kernels)."""
+    d = (np.float32(L) - np.float32(y)).astype(np.float32)
+    ad = np.abs(d)
+    kz = 0
+    if ad[1] > ad[kz]:
+        kz = 1
+    if ad[2] > ad[kz]:
+        kz = 2
+    kx, ky = (kz + 1) % 3, (kz + 2) % 3
+    ez, ex, ey = -d[kz], -d[kx], -d[ky]
+    if not abs(ez) > 0:
+        return []
+    ia = np.float32(1.0) / np.float32(abs(ez))
+    face = 2 * kz + (0 if ez > 0 else 1)
+    B = b["B"]
+    hb = np.float32(0.5) * np.float32(B)
+    iu = min(max(int(np.float32((np.float32(ex * ia) + np.float32(1)) * hb)), 0), B - 1)
+    iv = min(max(int(np.float32((np.float32(ey * ia) + np.float32(1)) * hb)), 0), B - 1)
+    reach = np.float32(np.sqrt(np.float32(d @ d))) * np.float32(1 + 2.0 ** -20)
+    ids = []
+    for k in range(b["levels"]):
+        Bk = B >> (2 * k)
+        bi = b["level_off"][k] + (face * Bk + (iu >> (2 * k))) * Bk + (iv >> (2 * k))
+        for e in range(b["offs"][bi], b["offs"][bi + 1]):
+            if b["entries"][e, 7] > reach:
+                break
+            ids.append(int(b["entries"][e, 3:4].view(np.int32)[0]))
+    return ids
+
+
+def _adversarial_points(tri, L, rng, n):
+    """Points whose segment to the light skims triangle edges and vertices,
+    lies on cube-face boundaries seen from the light, or starts next to it."""
+    t3 = tri.reshape(-1, 3, 3).astype(np.float64)
+    j = rng.integers(0, len(t3), n)
+    e = rng.integers(0, 3, n)
+    s = rng.uniform(0, 1, n)
+    a, b_ = t3[j, e], t3[j, (e + 1) % 3]
+    p = a + s[:, None] * (b_ - a)
+    far = L + rng.uniform(1.02, 3.0, (n, 1)) * (p - L)
+    diag = np.stack([np.full(n, 1.0), rng.choice([-1.0, 1.0], n), rng.uniform(-1, 1, n)], 1)
+    diag = L + rng.uniform(0.05, 0.8, (n, 1)) * rng.permuted(diag, axis=1)
+    near = L + rng.normal(size=(n, 3)) * 10 ** rng.uniform(-4, -1, (n, 1))
+    return np.concatenate([far, diag, near])
+
+
+@pytest.mark.parametrize("scene", ["c2", "c3", "degenerate"])
+def test_light_bins_answer_every_segment_like_all_triangles(scene):
+    """The bins of a light list, for every segment y -> light, a superset of
+    the triangles the watertight test can accept on it: testing only a
+    segment's bin candidates (oracle decision rule) gives the answer of
+    testing every triangle, on random segments and on segments that skim
+    edges, run along cube-face boundaries or start next to the light."""
+    from oracle import oracle as O
+    rng = np.random.default_rng({"c2": 3, "c3": 4, "degenerate": 5}[scene])
+    if scene == "c2":
+        w = W.make_c2(P=1, n_soup=1500, seed=41)
+    elif scene == "c3":
+        w = W.make_c3(P=1, n_tri=3000, seed=42)
+    else:
+        w = W.make_c2(P=1, n_soup=200, seed=43)
+        # triangles through the light, next to it and edge-on to it
+        L = w.lights[0, :3].astype(np.float64)
+        extra = np.array([np.r_[L + [-0.1, 0, -0.1], L + [0.1, 0, -0.1], L + [0, 0, 0.1]],
+                          np.r_[L + [1e-5, -0.05, -0.05], L + [1e-5, 0.05, -0.05], L + [1e-5, 0, 0.05]],
+                          np.r_[L + [-0.2, -0.3, 0.0], L + [0.2, -0.3, 0.0], L + [0.0, -0.3, 1e-7]]], np.float32)
+        w.tri = np.concatenate([w.tri, extra])
+        w.albedo = np.concatenate([w.albedo, np.full(3, 0.7, np.float32)])
+    sc = O.Scene(w.tri, w.albedo, None, w.box_lo, w.box_hi)
+    for li in range(min(2, len(w.lights))):
+        L = w.lights[li, :3].astype(np.float32)
+        b = rc.rc_light_bins_host(w.tri, w.box_lo, w.box_hi, L)
+        assert b["levels"] >= 1 and b["entries"].shape[0] > 0
+        pts = np.concatenate([rng.uniform(w.box_lo, w.box_hi, (600, 3)),
+                              _adversarial_points(w.tri, L.astype(np.float64), rng, 300)]).astype(np.float32)
+        pts = pts[np.all((pts > w.box_lo) & (pts < w.box_hi), axis=1)]
+        skip = np.where(rng.uniform(size=len(pts)) < 0.2, rng.integers(0, w.n_tri, len(pts)), -1)
+        seg = (L[None, :] - pts).astype(np.float32)
+        full = sc.occluded(pts, seg, skip=skip, brute=True)
+        mism = 0
+        for i in range(len(pts)):
+            ids = sorted(set(_bin_candidates(b, L, pts[i])))
+            if not ids:
+                sub = False
+            else:
+                ssc = O.Scene(w.tri[ids], w.albedo[ids], None, w.box_lo, w.box_hi)
+                sk = ids.index(skip[i]) if skip[i] in ids else -1
+                sub = bool(ssc.occluded(pts[i:i + 1], seg[i:i + 1], skip=np.array([sk]), brute=True)[0])
+            mism += int(sub != bool(full[i]))
+        assert mism == 0, (scene, li, mism, len(pts))
+        assert full.sum() >= 10

@@ -78,10 +78,55 @@ def test_ray_queries_equal_oracle_brute_force(dev):
     sc.close()
 
 
+def test_light_bin_segments_equal_oracle_brute_force(dev):
+    """Shadow segments y -> light answered from the per-light bins on the GPU
+    equal the oracle's brute-force answers, for random points and for points
+    whose segments skim triangle edges, run along cube-face boundaries seen
+    from the light or start next to it."""
+    from tests.test_abi_host import _adversarial_points
+    w = W.make_c2(P=4, n_soup=3000, seed=17)
+    sc = rc.Scene.from_workload(w)
+    osc = O.Scene.from_workload(w)
+    rc.rc_light_bins_build(sc.handle, w.lights)
+    rng = np.random.default_rng(9)
+    for li in range(len(w.lights)):
+        L = w.lights[li, :3].astype(np.float32)
+        pts = np.concatenate([rng.uniform(w.box_lo, w.box_hi, (12000, 3)),
+                              _adversarial_points(w.tri, L.astype(np.float64), rng, 3000)]).astype(np.float32)
+        pts = pts[np.all((pts > w.box_lo) & (pts < w.box_hi), axis=1)]
+        skip = np.where(rng.uniform(size=len(pts)) < 0.3, rng.integers(0, w.n_tri, len(pts)), -1).astype(np.int32)
+        occ = torch.empty(len(pts), dtype=torch.int32, device=dev)
+        _say(f"light {li}: {len(pts)} segments")
+        rc.rc_light_occluded(sc.handle, li, torch.as_tensor(pts, device=dev), torch.as_tensor(skip, device=dev), occ)
+        torch.cuda.synchronize()
+        ref = osc.occluded(pts, (L[None, :] - pts).astype(np.float32), skip=skip.astype(np.int64), brute=True)
+        got = occ.cpu().numpy().astype(bool)
+        assert np.array_equal(got, ref), (li, int((got != ref).sum()))
+        assert 0.05 < ref.mean() < 0.95
+    sc.close()
+
+
+def test_light_bin_and_bvh_shadows_give_identical_records(dev):
+    """Records whose shadow segments come from the light bins equal, bit for
+    bit, records whose shadow segments traverse the BVH."""
+    w = W.make_c2(P=300, n_soup=4000, seed=18)
+    sc = rc.Scene.from_workload(w)
+    dw = rc.DeviceWorkload(w)
+    out = []
+    for bvh in (False, True):
+        v, g, h, ws = rc.compute_records(sc, dw, batched=True, shadow_bvh=bvh)
+        torch.cuda.synchronize()
+        assert rc.rc_workspace_errors(ws) == 0
+        out.append((v.clone(), g.clone(), h.clone()))
+    for a, b in zip(out[0], out[1]):
+        assert torch.equal(a, b)
+    sc.close()
+
+
 def test_c1_all_records_match_oracle(dev):
     w = W.make_c1()
     _say("C1: 64 records x 256 directions, 16 triangles")
-    cnt = torch.zeros(8, dtype=torch.int64, device=dev)
+    cnt = torch.zeros(12, dtype=torch.int64, device=dev)
     (v, g, h), errs = gpu_records(w, counters=cnt)
     assert errs == 0
     ref = O.records_for(w)
@@ -99,7 +144,7 @@ def test_records_split_over_wavefronts_match_oracle(dev, splits):
     w = W.make_c1(P=40)
     sc = rc.Scene.from_workload(w)
     dw = rc.DeviceWorkload(w)
-    cnt = torch.zeros(8, dtype=torch.int64, device=dev)
+    cnt = torch.zeros(12, dtype=torch.int64, device=dev)
     v, g, h, ws = rc.compute_records(sc, dw, batched=True, counters=cnt, splits=splits)
     v1, g1, h1, _ = rc.compute_records(sc, dw, batched=True, splits=1)
     torch.cuda.synchronize()
@@ -124,7 +169,7 @@ def test_wide_rows_done_in_column_sectors_match_oracle(dev, nth, nph, splits):
     w.n_phi = np.full(w.n_rec, nph, np.int32)
     sc = rc.Scene.from_workload(w)
     dw = rc.DeviceWorkload(w)
-    cnt = torch.zeros(8, dtype=torch.int64, device=dev)
+    cnt = torch.zeros(12, dtype=torch.int64, device=dev)
     v, g, h, ws = rc.compute_records(sc, dw, batched=True, counters=cnt, splits=splits)
     torch.cuda.synchronize()
     assert rc.rc_workspace_errors(ws) == 0
