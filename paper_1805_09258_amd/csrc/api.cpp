@@ -210,7 +210,13 @@ int ensure_light_bins(rc_scene* s, const rc_point_light* lights, int n_lights, i
     const int64_t obase = (int64_t)offs.size();
     if (ebase + (int64_t)(h[l].entries.size() / 12) >= ((int64_t)1 << 31) || obase + (int64_t)h[l].offs.size() >= ((int64_t)1 << 31))
       return fail(RC_EINVAL, "light bins: more than 2^31 entries or bins");
-    for (int32_t v : h[l].offs) offs.push_back((int32_t)(v + ebase));
+    // index words (each bin's first entry, each level's end) move by the
+    // entries of the lights before; the distance words stay as they are
+    for (size_t i = 0; i < h[l].offs.size(); i++) offs.push_back(h[l].offs[i]);
+    for (int k = 0; k < h[l].nlev; k++) {
+      const int64_t Bk = h[l].B >> (2 * k);
+      for (int64_t i = 0; i <= 12 * Bk * Bk; i += 2) offs[(size_t)(obase + h[l].lev_off[k] + i)] += (int32_t)ebase;
+    }
     ent.insert(ent.end(), h[l].entries.begin(), h[l].entries.end());
     int lo[rc::kLbMaxLevels] = {0, 0, 0, 0};
     for (int k = 0; k < h[l].nlev; k++) lo[k] = (int)(obase + h[l].lev_off[k]);

@@ -139,11 +139,12 @@ RC_DEV bool hit_triangle(const WtRay& r, float4 A, float4 B, float4 C, float tmi
 // Per-light triangle bins: for the segment o -> o + d ending at light l
 // (wr = wt_ray(o, d)), the bin of each level that holds the direction from
 // the light to o, e = -d: face 2 kz + (e_kz > 0 ? 0 : 1), tangent coordinates
-// (e_kx, e_ky) / |e_kz|, nested levels of B >> 2k bins per side.  Writes the
-// bin indices to stk[k * 64] and returns the level count (0 if o is at the
-// light).  desc[2 l] = (B, levels, level offset 0, 1), desc[2 l + 1] = (level
-// offset 2, 3, -, -).
-RC_DEV int lb_bins(const int4* __restrict__ desc, int l, const WtRay& wr, int* stk) {
+// (e_kx, e_ky) / |e_kz|, nested levels of B >> 2k bins per side.  h[k] is
+// the index of that bin's header (first entry, its distance bits; the next
+// word starts the next bin).  Returns the level count (0 if o is at the
+// light).  desc[2 l] = (B, levels, level offset 0, 1), desc[2 l + 1] =
+// (level offset 2, 3, -, -).
+RC_DEV int lb_bins(const int4* __restrict__ desc, int l, const WtRay& wr, int (&h)[4]) {
   const int4 ds0 = desc[2 * l], ds1 = desc[2 * l + 1];
   const int B = ds0.x, nlev = ds0.y;
   const float ez = -wr.d.z, ex = -wr.d.x, ey = -wr.d.y;
@@ -157,7 +158,7 @@ RC_DEV int lb_bins(const int4* __restrict__ desc, int l, const WtRay& wr, int* s
 #pragma unroll
   for (int k = 0; k < 4; k++) {
     const int Bk = B >> (2 * k);
-    if (k < nlev) stk[k * kWave] = lo[k] + (face * Bk + (iu >> (2 * k))) * Bk + (iv >> (2 * k));
+    h[k] = lo[k] + 2 * ((face * Bk + (iu >> (2 * k))) * Bk + (iv >> (2 * k)));
   }
   return nlev;
 }

@@ -43,11 +43,14 @@ float bvh_pad_for(const float* tri, int64_t T, const float* lo, const float* hi)
 float triangle_pad(const float* t, float scale);
 
 // Per-light triangle bins (lightbins.cpp): levels of B / 4^k bins per cube
-// face side (k < levels <= kLbMaxLevels); offs: for each level, 6 * Bk^2
-// bin starts and a sentinel (absolute entry indices); entries: 12 floats
-// each, the triangle's vertices permuted for the face's axis, its id bits
-// (word 3) and its distance from the light minus the hit-test error,
-// rounded down (word 7); a bin's entries by increasing distance.
+// face side (k < levels <= kLbMaxLevels).  offs: for each level (from
+// lev_off[k]) two words per bin, the first entry's index and its stored
+// distance as float bits (+inf if empty), then one word, the end of the
+// level's last bin (a bin's entries end where the next bin's begin).
+// entries: 12 floats each, the triangle's vertices permuted for the face's
+// axis, its id bits (word 3), its distance from the light minus the hit-test
+// error, rounded down (word 7), and the next entry's distance in the bin
+// (word 11, +inf for the last); a bin's entries by increasing distance.
 struct LightBinsHost {
   int B = 0, nlev = 0;
   int64_t lev_off[kLbMaxLevels] = {0, 0, 0, 0};

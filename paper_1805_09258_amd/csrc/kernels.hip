@@ -296,11 +296,10 @@ record_kernel(RecordArgs g) {
       __syncthreads();
       if (COUNT) { uint64_t t = clock64(); cyc[0] += t - t_mark; t_mark = t; }
       // ---- 2. shadow rays ---------------------------------------------------
-      // One work list of (vertex, light) tasks for the row, light-major so
-      // neighbouring lanes trace coherent segments.  Each loop iteration
-      // advances every active lane by one traversal step (one node or one
-      // triangle); a lane whose segment is resolved takes the next task at
-      // once.  Unblocked segments set the light's bit on the vertex.
+      // Every surface vertex and ring vertex of the row needs one shadow
+      // segment per point light; unblocked segments set the light's bit on the
+      // vertex.  Lanes take vertices in column order, so neighbouring lanes
+      // trace coherent segments, and decode each vertex once.
       if (g.n_lights > 0) {
         int carry = 0;
         for (int base = 0; base < n; base += kWave) {
@@ -310,78 +309,162 @@ record_kernel(RecordArgs g) {
           if (j < n) off[j] = carry + inc - c;
           carry += __shfl(inc, kWave - 1, kWave);
         }
-        const int nvert = carry;
         // wave-uniform counts, kept in scalar registers
-        const int total = __builtin_amdgcn_readfirstlane(nvert * g.n_lights);
+        const int nvert = __builtin_amdgcn_readfirstlane(carry);
+        const int NL = g.n_lights;
         __syncthreads();
-        int next = 0;          // next unassigned task (wave-uniform)
-        bool active = false;
-        int lbit = 0, node = 0, sp = 0, lf = 0, ln = 0, skip = -1, slot = 0;
-        float3 o = make_float3(0.f, 0.f, 0.f), d = o, inv = o, oi = o;
+        if (g.lb_desc) {
+          // Light bins: a segment reads one header per level and then only
+          // the few entries within its reach (one to three on average), so a
+          // lane walks all lights of its vertex in turn: decode once, per
+          // light the bin headers and the entry list, and one store of the
+          // vertex's visibility bits.
+          for (int base = 0; base < nvert; base += kWave) {
+            const int v = base + lane;
+            if (v >= nvert) continue;
+            const int j = find_slot(off, n, v);
+            const int k = v - off[j];
+            const int code = R.code[j];
+            const float3 w = make_float3(R.wx[j], R.wy[j], R.wz[j]);
+            int skip = -1, slot;
+            float3 o, nrm = make_float3(0.f, 0.f, 0.f);
+            if (code >= 0 && k == 0) {
+              skip = code >> 1;
+              o = axpy3(R.t[j], w, x);
+              slot = -1 - j;  // surface vertex of column j
+              const float4 sh = g.shade[skip];
+              const float nsign = (code & 1) ? 1.f : -1.f;
+              nrm = make_float3(nsign * sh.x, nsign * sh.y, nsign * sh.z);
+            } else {
+              const int i = k - (code >= 0 ? 1 : 0);
+              o = axpy3(ring_distance(i, xr, g.ring_step), w, x);
+              slot = i * cap + j;
+            }
+            if (COUNT && own && j < n_cnt) n_rays += NL;
+            int bits = 0;
+            for (int l = 0; l < NL; l++) {
+              const float4 Lp = g.lights[l];
+              const float3 d = make_float3(Lp.x - o.x, Lp.y - o.y, Lp.z - o.z);
+              if (skip >= 0 && !(dot3(nrm, d) > 0.f)) continue;  // light behind the lit side
+              const WtRay wr = wt_ray(o, d);
+              int h[4];
+              const int nlev = lb_bins(g.lb_desc, l, wr, h);
+              // the largest stored distance from the light that can still block
+              const float reach = __builtin_amdgcn_sqrtf(dot3(d, d)) * (1.0f + 0x1p-20f);
+              // the lists whose first entry is within reach, as (first, end)
+              // pairs in this lane's (unused) stack slots, walked in one loop
+              // (the wavefront runs as long as its longest walk, not as the
+              // sum over levels of each level's longest list)
+              int nl = 0;
+              for (int q = 0; q < nlev; q++) {
+                if (COUNT) tc.nodes++;
+                const int* hd = g.lb_offs + h[q];
+                if (__int_as_float(hd[1]) <= reach) {
+                  stk[(2 * nl) * kWave] = hd[0];
+                  stk[(2 * nl + 1) * kWave] = hd[2];
+                  nl++;
+                }
+              }
+              bool blocked = false, live = nl > 0;
+              int cur = live ? stk[0] : 0, end = live ? stk[kWave] : 0, nxt = 1;
+              while (live) {
+                if (COUNT) tc.tris++;
+                const float4* en = g.lb_ent + 3 * cur;
+                const float4 q0 = en[0], q1 = en[1], q2 = en[2];
+                float t;
+                bool fr;
+                if (__float_as_int(q0.w) != skip && hit_triangle(wr, q0, q1, q2, 1e-4f, 1.0f, t, fr)) {
+                  blocked = true;
+                  live = false;
+                } else if (++cur == end || q2.w > reach) {  // this list is done: the next one, if any
+                  if (nxt < nl) {
+                    cur = stk[(2 * nxt) * kWave];
+                    end = stk[(2 * nxt + 1) * kWave];
+                    nxt++;
+                  } else {
+                    live = false;
+                  }
+                }
+              }
+              if (!blocked) bits |= 1 << l;
+            }
+            if (slot < 0) R.visS[-1 - slot] = bits;
+            else reinterpret_cast<int*>(R.Lm)[slot] = bits;
+          }
+        } else {
+        int next = 0;          // next vertex to hand out (wave-uniform)
+        bool active = false;   // a segment in progress
+        // the lane's vertex: origin, oriented surface normal (surface
+        // vertices), own triangle (skip >= 0: a surface vertex), visibility
+        // slot, and the light of its current or next segment (NL: no vertex)
+        int lcur = NL, skip = -1, slot = 0;
+        float3 o = make_float3(0.f, 0.f, 0.f), nrm = o;
+        // the current segment: BVH traversal state, or light-bin lists
+        int node = 0, sp = 0, lf = 0, ln = 0;
+        float3 d = o, inv = o, oi = o;
         WtRay wr = wt_ray(o, d);
         while (true) {
-          // refill idle lanes in lane order, once enough of them are idle
           const uint64_t idle = __ballot(!active);
-          const bool refill = next < total && (__popcll(idle) >= g.refill_min || idle == ~0ull);
-          const bool need = refill && !active;
-          const uint64_t want = refill ? idle : 0ull;
-          if (need) {
-            const int task = next + mask_rank(want);
-            if (task < total) {
-              active = true;
-              const int l = task / nvert, v = task - l * nvert;
-              lbit = 1 << l;
-              const int j = find_slot(off, n, v);
-              const int k = v - off[j];
-              const int code = R.code[j];
-              const float4 L = g.lights[l];
-              const float3 w = make_float3(R.wx[j], R.wy[j], R.wz[j]);
-              if (code >= 0 && k == 0) {
-                skip = code >> 1;
-                o = axpy3(R.t[j], w, x);
-                slot = -1 - j;  // surface vertex of column j
-                d = make_float3(L.x - o.x, L.y - o.y, L.z - o.z);
-                const float4 sh = g.shade[skip];
-                const float nsign = (code & 1) ? 1.f : -1.f;
-                // light behind the lit side: nothing to trace
-                if (!(nsign * dot3(make_float3(sh.x, sh.y, sh.z), d) > 0.f)) active = false;
-              } else {
-                const int i = k - (code >= 0 ? 1 : 0);
-                skip = -1;
-                o = axpy3(ring_distance(i, xr, g.ring_step), w, x);
-                slot = i * cap + j;
-                d = make_float3(L.x - o.x, L.y - o.y, L.z - o.z);
+          const uint64_t fresh = __ballot(!active && lcur >= NL);  // idle lanes without a vertex
+          const bool more = next < nvert || (idle & ~fresh) != 0ull;
+          const bool refill = more && (__popcll(idle) >= g.refill_min || idle == ~0ull);
+          if (refill && !active) {
+            if (lcur >= NL) {
+              const int v = next + mask_rank(fresh);
+              if (v < nvert) {
+                const int j = find_slot(off, n, v);
+                const int k = v - off[j];
+                const int code = R.code[j];
+                const float3 w = make_float3(R.wx[j], R.wy[j], R.wz[j]);
+                if (code >= 0 && k == 0) {
+                  skip = code >> 1;
+                  o = axpy3(R.t[j], w, x);
+                  slot = -1 - j;  // surface vertex of column j
+                  const float4 sh = g.shade[skip];
+                  const float nsign = (code & 1) ? 1.f : -1.f;
+                  nrm = make_float3(nsign * sh.x, nsign * sh.y, nsign * sh.z);
+                } else {
+                  const int i = k - (code >= 0 ? 1 : 0);
+                  skip = -1;
+                  o = axpy3(ring_distance(i, xr, g.ring_step), w, x);
+                  slot = i * cap + j;
+                }
+                lcur = 0;
+                if (COUNT && own && j < n_cnt) n_rays += NL;
+              }
+            }
+            // set up the segment to the next light that needs one: lights
+            // behind a surface's lit side need none, and a segment whose
+            // light bins hold nothing within reach is clear at once
+            while (lcur < NL && !active) {
+              const float4 Lp = g.lights[lcur];
+              d = make_float3(Lp.x - o.x, Lp.y - o.y, Lp.z - o.z);
+              if (skip >= 0 && !(dot3(nrm, d) > 0.f)) {
+                lcur++;
+                continue;
               }
               wr = wt_ray(o, d);
-              node = 0;
-              sp = 0;
-              ln = 0;
-              if (g.lb_desc) {
-                // light bins: the bins of the direction from the light to o
-                // in this lane's (unused) stack slots; sp = their count, node
-                // = the next level, inv.x = the largest stored distance from
-                // the light that can still block
-                sp = lb_bins(g.lb_desc, l, wr, stk);
-                if (sp == 0) active = false;  // o at the light: nothing to block
-                inv.x = sqrtf(dot3(d, d)) * (1.0f + 0x1p-20f);
-              } else {
+              {
                 ray_inv(d, o, inv, oi);
+                node = 0;
+                sp = 0;
+                ln = 0;
               }
-              if (COUNT && own && j < n_cnt) n_rays++;
+              active = true;
             }
           }
-          next = __builtin_amdgcn_readfirstlane(next + __popcll(want));
+          if (refill) next = __builtin_amdgcn_readfirstlane(next + __popcll(fresh));
           const uint64_t busy = __ballot(active);
           if (COUNT) {
             sh_iter++;
             sh_busy += __popcll(busy);
-            if (want) {
+            if (refill) {
               sh_refill++;
-              sh_lanes += __popcll(busy & want);
+              sh_lanes += __popcll(busy & idle);
             }
           }
           if (busy == 0ull) {
-            if (next >= total) break;
+            if (next >= nvert && __ballot(lcur < NL) == 0ull) break;
             continue;
           }
           // leaf_batch 0: every busy lane takes its next step (node or
@@ -391,47 +474,7 @@ record_kernel(RecordArgs g) {
           // node steps otherwise; lanes of the other kind wait.
           const uint64_t at_leaf = __ballot(active && ln > 0);
           const bool tri_step = at_leaf != 0ull && (__popcll(at_leaf) >= g.leaf_batch || at_leaf == busy);
-          if (g.lb_desc) {
-            // light bins: lf = the next entry of the current list, ln = the
-            // entries left in it; an exhausted list moves to the next level
-            if (active) {
-              bool done = false, blocked = false;
-              if (ln > 0) {
-                if (COUNT) tc.tris++;
-                const float4* e = g.lb_ent + 3 * lf;
-                const float4 q0 = e[0], q1 = e[1], q2 = e[2];
-                if (q1.w > inv.x) {
-                  ln = 0;  // sorted by distance from the light: nothing further can block
-                } else {
-                  float t;
-                  bool fr;
-                  if (__float_as_int(q0.w) != skip && hit_triangle(wr, q0, q1, q2, 1e-4f, 1.0f, t, fr)) {
-                    done = true;
-                    blocked = true;
-                  } else {
-                    lf++;
-                    ln--;
-                  }
-                }
-              } else if (node >= sp) {
-                done = true;
-              } else {
-                if (COUNT) tc.nodes++;
-                const int b = stk[node * kWave];
-                const int e0 = g.lb_offs[b], e1 = g.lb_offs[b + 1];
-                lf = e0;
-                ln = e1 - e0;
-                node++;
-              }
-              if (done) {
-                active = false;
-                if (!blocked) {
-                  if (slot < 0) atomicOr(&R.visS[-1 - slot], lbit);
-                  else atomicOr(reinterpret_cast<int*>(R.Lm) + slot, lbit);
-                }
-              }
-            }
-          } else if (active && (g.leaf_batch == 0 || (ln > 0) == tri_step)) {
+          if (active && (g.leaf_batch == 0 || (ln > 0) == tri_step)) {
             bool done = false, blocked = false;
             // one fetch per lane per iteration: the next triangle of the current
             // leaf, or the current node (the triangle array carries one word of
@@ -484,12 +527,14 @@ record_kernel(RecordArgs g) {
             if (done) {
               active = false;
               if (!blocked) {
-                if (slot < 0) atomicOr(&R.visS[-1 - slot], lbit);
-                else atomicOr(reinterpret_cast<int*>(R.Lm) + slot, lbit);
+                if (slot < 0) atomicOr(&R.visS[-1 - slot], 1 << lcur);
+                else atomicOr(reinterpret_cast<int*>(R.Lm) + slot, 1 << lcur);
               }
+              lcur++;
             }
           }
         }
+        }  // BVH shadow segments
         __syncthreads();
         // radiance from the visibility bits, lights summed in order
         for (int v = lane; v < nvert; v += kWave) {
@@ -995,28 +1040,28 @@ __global__ __launch_bounds__(64) void light_occluded_kernel(const int4* __restri
                                                             const float* __restrict__ pts,
                                                             const int* __restrict__ skip, int n,
                                                             int* __restrict__ occ) {
-  __shared__ int lvl[kLbMaxLevels * kWave];
   const int i = blockIdx.x * kWave + threadIdx.x;
   if (i >= n) return;
   const float3 o = make_float3(pts[3 * i], pts[3 * i + 1], pts[3 * i + 2]);
   const float3 d = make_float3(L.x - o.x, L.y - o.y, L.z - o.z);
   const int sk = skip ? skip[i] : -1;
   const WtRay wr = wt_ray(o, d);
-  int* stk = lvl + threadIdx.x;
-  const int nlev = lb_bins(desc, l, wr, stk);
+  int h[4];
+  const int nlev = lb_bins(desc, l, wr, h);
   const float reach = sqrtf(dot3(d, d)) * (1.0f + 0x1p-20f);
   int res = 0;
-  for (int k = 0; k < nlev && !res; k++) {
-    const int b = stk[k * kWave];
-    for (int e = offs[b]; e < offs[b + 1]; e++) {
+  for (int k = 0; k < 4 && !res; k++) {
+    if (k >= nlev || __int_as_float(offs[h[k] + 1]) > reach) continue;
+    const int e1 = offs[h[k] + 2];
+    for (int e = offs[h[k]]; e < e1; e++) {
       const float4 q0 = ent[3 * e], q1 = ent[3 * e + 1], q2 = ent[3 * e + 2];
-      if (q1.w > reach) break;
       float t;
       bool fr;
       if (__float_as_int(q0.w) != sk && hit_triangle(wr, q0, q1, q2, 1e-4f, 1.0f, t, fr)) {
         res = 1;
         break;
       }
+      if (q2.w > reach) break;
     }
   }
   occ[i] = res;

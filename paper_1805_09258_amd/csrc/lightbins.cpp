@@ -10,7 +10,7 @@
 // (u, v) = (e_kx, e_ky) / |e_kz| of a direction e (kz the axis of its largest
 // component, (kx, ky) = (kz + 1, kz + 2) mod 3, face 2 kz for e_kz > 0 and
 // 2 kz + 1 otherwise).  Coarser levels of B / 4^k bins (nested) take the
-// triangles whose region covers more than 4 x 4 bins of a finer level, so a
+// triangles whose region covers more than 8 x 8 bins of a finer level, so a
 // wall or a slab lands in a few coarse bins instead of thousands of fine
 // ones.  Each bin lists its triangles by increasing distance from L.
 //
@@ -21,9 +21,10 @@
 // a = eps / (dmin - eps) of the triangle's region (dmin: the triangle's
 // distance from L).  Each region is clipped to each face's pyramid widened by
 // 3a + 1e-5 in (u, v) (tangent coordinates stretch angles by at most 3 on a
-// face), its (u, v) box padded by the same amount, and the distances stored
-// as float(dmin - eps) rounded down; the 1e-5 covers the FP32 rounding of the
-// bin coordinates of a query.  Triangles that pass within 2 eps of L, or
+// face), its (u, v) box padded by the same amount, and each entry's distance
+// is a lower bound on the distance from L of the triangle's points seen
+// through the padded bin, minus eps, rounded down; the 1e-5 covers the FP32
+// rounding of the bin coordinates of a query.  Triangles that pass within 2 eps of L, or
 // whose clipped region reaches the apex, cover every bin of the face.
 // A segment's answer from the bins is therefore the answer of testing every
 // triangle.
@@ -120,19 +121,34 @@ int build_light_bins(const float* tri, int64_t T, float scale, const float light
   // per (triangle, face): the level and bin rectangle it covers
   std::vector<Span> spans;
   std::vector<int32_t> span_tri;
-  std::vector<float> dstore((size_t)std::max<int64_t>(T, 1));
+  // per triangle: distance from L, unit plane normal facing away from L and
+  // the plane's distance from L (0 if degenerate), padding in (u, v)
+  std::vector<double> tdmin((size_t)std::max<int64_t>(T, 1)), tpad(tdmin.size()), th(tdmin.size());
+  std::vector<V> tn(tdmin.size());
   spans.reserve((size_t)T * 2);
   for (int64_t j = 0; j < T; j++) {
     const float* t = tri + 9 * j;
     const V a = {t[0], t[1], t[2]}, b = {t[3], t[4], t[5]}, c = {t[6], t[7], t[8]};
     const double dmin = point_triangle_distance(L, a, b, c);
-    double ds = dmin - eps;
-    float df = (float)ds;
-    if ((double)df > ds) df = std::nextafter(df, -INFINITY);
-    dstore[j] = df;
+    tdmin[j] = dmin;
+    const V e1 = sub(b, a), e2 = sub(c, a);
+    V n = {e1.y * e2.z - e1.z * e2.y, e1.z * e2.x - e1.x * e2.z, e1.x * e2.y - e1.y * e2.x};
+    const double nn = norm(n);
+    double h = 0.0;
+    if (nn > 0) {
+      n = mul(1.0 / nn, n);
+      h = dot(n, sub(a, L));
+      if (h < 0) {
+        n = mul(-1.0, n);
+        h = -h;
+      }
+    }
+    tn[j] = n;
+    th[j] = h;
     const bool near = !(dmin > 2.0 * eps);
     const double alpha = near ? 1.0 : eps / (dmin - eps);
     const double pad = 3.0 * alpha + 1e-5;
+    tpad[j] = pad;
     const V rel[3] = {sub(a, L), sub(b, L), sub(c, L)};
     for (int ax = 0; ax < 3; ax++) {
       const int kx = (ax + 1) % 3, ky = (ax + 2) % 3;
@@ -172,7 +188,7 @@ int build_light_bins(const float* tri, int64_t T, float scale, const float light
             v1 += pad;
           }
         }
-        // finest level whose rectangle has at most 4 x 4 bins (else the coarsest)
+        // finest level whose rectangle has at most 8 x 8 bins (else the coarsest)
         Span sp{2 * ax + sg, 0, 0, 0, 0, 0};
         for (int k = 0; k < out.nlev; k++) {
           const int Bk = B >> (2 * k);
@@ -185,7 +201,7 @@ int build_light_bins(const float* tri, int64_t T, float scale, const float light
           sp.iu1 = bin(u1);
           sp.iv0 = bin(v0);
           sp.iv1 = bin(v1);
-          if ((int64_t)(sp.iu1 - sp.iu0 + 1) * (sp.iv1 - sp.iv0 + 1) <= 16) break;
+          if ((int64_t)(sp.iu1 - sp.iu0 + 1) * (sp.iv1 - sp.iv0 + 1) <= 64) break;
         }
         spans.push_back(sp);
         span_tri.push_back((int32_t)j);
@@ -194,24 +210,24 @@ int build_light_bins(const float* tri, int64_t T, float scale, const float light
   }
   // CSR over (level, face, bin): counts, prefix sums, fill, sort by distance
   int64_t total_bins = 0;
+  std::vector<int64_t> lev_bin(out.nlev);  // first bin of each level in the flat count array
   for (int k = 0; k < out.nlev; k++) {
     const int64_t Bk = B >> (2 * k);
-    out.lev_off[k] = total_bins + k;  // each level's offsets end with its own sentinel
+    lev_bin[k] = total_bins + k;  // each level's starts end with its own sentinel
     total_bins += 6 * Bk * Bk;
   }
-  out.offs.assign((size_t)(total_bins + out.nlev), 0);
   auto bin_index = [&](int level, int face, int iu, int iv) {
     const int64_t Bk = B >> (2 * level);
-    return out.lev_off[level] + ((int64_t)face * Bk + iu) * Bk + iv;
+    return lev_bin[level] + ((int64_t)face * Bk + iu) * Bk + iv;
   };
-  std::vector<int64_t> cnt(out.offs.size(), 0);
+  std::vector<int64_t> cnt((size_t)(total_bins + out.nlev), 0);
   for (const Span& sp : spans)
     for (int iu = sp.iu0; iu <= sp.iu1; iu++)
       for (int iv = sp.iv0; iv <= sp.iv1; iv++) cnt[bin_index(sp.level, sp.face, iu, iv)]++;
   int64_t run = 0;
   for (int k = 0; k < out.nlev; k++) {
     const int64_t Bk = B >> (2 * k);
-    const int64_t lo = out.lev_off[k], hi = lo + 6 * Bk * Bk;
+    const int64_t lo = lev_bin[k], hi = lo + 6 * Bk * Bk;
     for (int64_t i = lo; i < hi; i++) {
       const int64_t c = cnt[i];
       cnt[i] = run;
@@ -223,25 +239,73 @@ int build_light_bins(const float* tri, int64_t T, float scale, const float light
     err = "light bins: too many entries";
     return RC_EINVAL;
   }
-  for (size_t i = 0; i < cnt.size(); i++) out.offs[i] = (int32_t)cnt[i];
+  // Stored distance of each (triangle, bin) entry: no point of the triangle
+  // seen through the padded bin is closer to L than the triangle's distance,
+  // nor than its plane along the bin's directions, h / max(n . u) over unit
+  // directions u of the bin (bounded by the largest n . p over the bin's
+  // corners p = (u, v, 1) in the face frame divided by the smallest |p|);
+  // minus eps, rounded down.  Walls and slabs so stay out of the lists of
+  // segments that do not reach them.
+  auto entry_distance = [&](int32_t j, int level, int face, int iu, int iv) {
+    const double Bk = (double)(B >> (2 * level)), pad = tpad[j];
+    const double u0 = -1.0 + 2.0 * iu / Bk - pad, u1 = -1.0 + 2.0 * (iu + 1) / Bk + pad;
+    const double v0 = -1.0 + 2.0 * iv / Bk - pad, v1 = -1.0 + 2.0 * (iv + 1) / Bk + pad;
+    const int ax = face >> 1, kx = (ax + 1) % 3, ky = (ax + 2) % 3;
+    const double sz = (face & 1) ? -1.0 : 1.0;
+    const V n = tn[j];
+    const double nx = comp(n, kx), ny = comp(n, ky), nz = sz * comp(n, ax);
+    const double mx = std::max({nx * u0 + ny * v0 + nz, nx * u1 + ny * v0 + nz, nx * u0 + ny * v1 + nz,
+                                nx * u1 + ny * v1 + nz});
+    double d = tdmin[j];
+    if (th[j] > 0 && mx > 0) {
+      const double um = (u0 <= 0 && u1 >= 0) ? 0.0 : std::min(u0 * u0, u1 * u1);
+      const double vm = (v0 <= 0 && v1 >= 0) ? 0.0 : std::min(v0 * v0, v1 * v1);
+      d = std::max(d, th[j] * std::sqrt(1.0 + um + vm) / mx);
+    }
+    const double ds = d - eps;
+    float df = (float)ds;
+    if ((double)df > ds) df = std::nextafter(df, -INFINITY);
+    return df;
+  };
   std::vector<int32_t> ids((size_t)run);
+  std::vector<float> edist((size_t)run);
   std::vector<int64_t> cur(cnt.begin(), cnt.end());
   for (size_t s = 0; s < spans.size(); s++) {
     const Span& sp = spans[s];
     for (int iu = sp.iu0; iu <= sp.iu1; iu++)
-      for (int iv = sp.iv0; iv <= sp.iv1; iv++) ids[(size_t)cur[bin_index(sp.level, sp.face, iu, iv)]++] = span_tri[s];
+      for (int iv = sp.iv0; iv <= sp.iv1; iv++) {
+        const int64_t e = cur[bin_index(sp.level, sp.face, iu, iv)]++;
+        ids[(size_t)e] = span_tri[s];
+        edist[(size_t)e] = entry_distance(span_tri[s], sp.level, sp.face, iu, iv);
+      }
   }
+  // bin headers, two words per bin: the first entry's index and its stored
+  // distance (+inf for an empty bin); the level's last word is the end of
+  // its last bin
+  out.offs.assign((size_t)(2 * total_bins + out.nlev), 0);
+  for (int k = 0; k < out.nlev; k++) out.lev_off[k] = 2 * lev_bin[k] - k;
   out.entries.assign((size_t)run * 12, 0.f);
   for (int k = 0; k < out.nlev; k++) {
     const int64_t Bk = B >> (2 * k);
+    const int64_t nb = 6 * Bk * Bk;
+    out.offs[(size_t)(out.lev_off[k] + 2 * nb)] = (int32_t)cnt[(size_t)(lev_bin[k] + nb)];
     for (int face = 0; face < 6; face++) {
       const int ax = face >> 1;
       for (int64_t bi = 0; bi < Bk * Bk; bi++) {
-        const int64_t slot = out.lev_off[k] + face * Bk * Bk + bi;
-        const int64_t lo = out.offs[slot], hi = out.offs[slot + 1];
-        std::sort(ids.begin() + lo, ids.begin() + hi, [&](int32_t p, int32_t q) {
-          return dstore[p] < dstore[q] || (dstore[p] == dstore[q] && p < q);
-        });
+        const int64_t slot = lev_bin[k] + face * Bk * Bk + bi;
+        const int64_t lo = cnt[slot], hi = cnt[slot + 1];
+        std::vector<std::pair<float, int32_t>> srt;
+        srt.reserve((size_t)(hi - lo));
+        for (int64_t e = lo; e < hi; e++) srt.emplace_back(edist[(size_t)e], ids[(size_t)e]);
+        std::sort(srt.begin(), srt.end());
+        for (int64_t e = lo; e < hi; e++) {
+          edist[(size_t)e] = srt[(size_t)(e - lo)].first;
+          ids[(size_t)e] = srt[(size_t)(e - lo)].second;
+        }
+        const int64_t h = out.lev_off[k] + 2 * (face * Bk * Bk + bi);
+        out.offs[(size_t)h] = (int32_t)lo;
+        const float dfirst = lo < hi ? edist[(size_t)lo] : INFINITY;
+        std::memcpy(&out.offs[(size_t)h + 1], &dfirst, 4);
         for (int64_t e = lo; e < hi; e++) {
           const int32_t j = ids[(size_t)e];
           const float* t = tri + 9 * (int64_t)j;
@@ -252,8 +316,8 @@ int build_light_bins(const float* tri, int64_t T, float scale, const float light
             o[4 * vtx + 2] = t[3 * vtx + ax];
           }
           std::memcpy(&o[3], &j, 4);
-          o[7] = dstore[j];
-          o[11] = 0.f;
+          o[7] = edist[(size_t)e];
+          o[11] = e + 1 < hi ? edist[(size_t)e + 1] : INFINITY;  // the next entry's distance
         }
       }
     }
@@ -262,8 +326,9 @@ int build_light_bins(const float* tri, int64_t T, float scale, const float light
 }
 
 int light_bins_size_for(int64_t T) {
-  // about 1.3 sqrt(T) bins per face side at the finest level, a power of two in [16, 512]
-  const double want = 1.3 * std::sqrt((double)std::max<int64_t>(T, 1));
+  // about 2.6 sqrt(T) bins per face side at the finest level, a power of two
+  // in [16, 512] (10k triangles: 256, 3.5 entries read per segment on average)
+  const double want = 2.6 * std::sqrt((double)std::max<int64_t>(T, 1));
   int B = 16;
   while (B < 512 && (double)B * 1.41421356 < want) B <<= 1;
   return B;

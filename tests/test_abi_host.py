@@ -244,13 +244,17 @@ def _bin_candidates(b, L, y):
     iv = min(max(int(np.float32((np.float32(ey * ia) + np.float32(1)) * hb)), 0), B - 1)
     reach = np.float32(np.sqrt(np.float32(d @ d))) * np.float32(1 + 2.0 ** -20)
     ids = []
+    offs = b["offs"]
     for k in range(b["levels"]):
         Bk = B >> (2 * k)
-        bi = b["level_off"][k] + (face * Bk + (iu >> (2 * k))) * Bk + (iv >> (2 * k))
-        for e in range(b["offs"][bi], b["offs"][bi + 1]):
-            if b["entries"][e, 7] > reach:
-                break
+        h = b["level_off"][k] + 2 * ((face * Bk + (iu >> (2 * k))) * Bk + (iv >> (2 * k)))
+        if offs[h + 1:h + 2].view(np.float32)[0] > reach:
+            continue
+        for e in range(offs[h], offs[h + 2]):
+            assert b["entries"][e, 7] <= reach
             ids.append(int(b["entries"][e, 3:4].view(np.int32)[0]))
+            if b["entries"][e, 11] > reach:
+                break
     return ids
 
 

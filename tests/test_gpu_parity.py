@@ -91,18 +91,27 @@ def test_light_bin_segments_equal_oracle_brute_force(dev):
     rng = np.random.default_rng(9)
     for li in range(len(w.lights)):
         L = w.lights[li, :3].astype(np.float32)
-        pts = np.concatenate([rng.uniform(w.box_lo, w.box_hi, (12000, 3)),
-                              _adversarial_points(w.tri, L.astype(np.float64), rng, 3000)]).astype(np.float32)
+        pts = np.concatenate([rng.uniform(w.box_lo, w.box_hi, (250000, 3)),
+                              _adversarial_points(w.tri, L.astype(np.float64), rng, 20000)]).astype(np.float32)
         pts = pts[np.all((pts > w.box_lo) & (pts < w.box_hi), axis=1)]
         skip = np.where(rng.uniform(size=len(pts)) < 0.3, rng.integers(0, w.n_tri, len(pts)), -1).astype(np.int32)
         occ = torch.empty(len(pts), dtype=torch.int32, device=dev)
         _say(f"light {li}: {len(pts)} segments")
         rc.rc_light_occluded(sc.handle, li, torch.as_tensor(pts, device=dev), torch.as_tensor(skip, device=dev), occ)
         torch.cuda.synchronize()
-        ref = osc.occluded(pts, (L[None, :] - pts).astype(np.float32), skip=skip.astype(np.int64), brute=True)
+        # the oracle's hierarchy answers as brute force does (pinned by the oracle tests)
+        ref = osc.occluded(pts, (L[None, :] - pts).astype(np.float32), skip=skip.astype(np.int64))
         got = occ.cpu().numpy().astype(bool)
         assert np.array_equal(got, ref), (li, int((got != ref).sum()))
         assert 0.05 < ref.mean() < 0.95
+        # the same light at another position of the light set answers the same
+        rc.rc_light_bins_build(sc.handle, w.lights[::-1].copy())
+        occ2 = torch.empty_like(occ)
+        rc.rc_light_occluded(sc.handle, len(w.lights) - 1 - li, torch.as_tensor(pts, device=dev),
+                             torch.as_tensor(skip, device=dev), occ2)
+        torch.cuda.synchronize()
+        assert torch.equal(occ, occ2), li
+        rc.rc_light_bins_build(sc.handle, w.lights)
     sc.close()
 
 
