@@ -9,9 +9,9 @@ from pathlib import Path
 HERE = Path(__file__).resolve().parent
 
 
-def build(verbose=False):
-    src = HERE / "rco.c"
-    out = HERE / "liboracle.so"
+def build(verbose=False, src=None, out=None):
+    src = HERE / "rco.c" if src is None else Path(src)
+    out = HERE / "liboracle.so" if out is None else Path(out)
     cmd = ["gcc", "-O2", "-std=c11", "-fopenmp", "-ffp-contract=off", "-fno-fast-math", "-fPIC",
            "-shared", "-Wall", "-Wextra", "-o", str(out), str(src), "-lm"]
     if verbose:

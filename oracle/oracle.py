@@ -26,10 +26,20 @@ _HERE = Path(__file__).resolve().parent
 _LIB = None
 
 
+_LIB_PATH = None  # None: oracle/liboracle.so
+
+
+def use_library(path=None):
+    """Load the oracle from another build of rco.c (tests of the pins build
+    copies with planted mistakes); None restores oracle/liboracle.so."""
+    global _LIB, _LIB_PATH
+    _LIB, _LIB_PATH = None, path
+
+
 def lib():
     global _LIB
     if _LIB is None:
-        path = _HERE / "liboracle.so"
+        path = Path(_LIB_PATH) if _LIB_PATH is not None else _HERE / "liboracle.so"
         if not path.exists():
             from . import build as _b  # noqa: F401  (oracle/build.py)
             _b.build()
@@ -42,6 +52,8 @@ def lib():
         L.rco_records.argtypes = [vp, f32, f32, vp, i32, vp, vp, vp, vp, i64, f32, i32, u64, vp,
                                   vp, vp, vp, vp, i32]
         L.rco_records.restype = i32
+        L.rco_values.argtypes = [vp, f32, f32, vp, i32, vp, vp, vp, vp, i64, f32, i32, u64, vp, i32]
+        L.rco_values.restype = i32
         L.rco_trace.argtypes = [vp, vp, vp, i64, i32, vp, vp, vp]
         L.rco_trace.restype = i32
         L.rco_occluded.argtypes = [vp, vp, vp, vp, i64, i32, vp]
@@ -148,6 +160,24 @@ def records(scene: Scene, sigma_s, sigma_a, lights, pos, n_theta, n_phi, rec_id=
     if want_stats:
         out["stats"] = st
     return out
+
+
+def values(scene: Scene, sigma_s, sigma_a, lights, pos, n_theta, n_phi, rec_id=None, ring_step=0.1,
+           max_rings=20, seed=0, nthreads=0):
+    """Monte Carlo values only (no triangulation): [P, 2]."""
+    pos = _c(pos, np.float32).reshape(-1, 3)
+    P = pos.shape[0]
+    nt = _c(np.broadcast_to(n_theta, (P,)), np.int32)
+    npf = _c(np.broadcast_to(n_phi, (P,)), np.int32)
+    rid = _c(np.arange(P) if rec_id is None else np.broadcast_to(rec_id, (P,)), np.uint64)
+    li = _c(lights, np.float32).reshape(-1, 4)
+    val = np.zeros((P, 2))
+    rc = lib().rco_values(scene._h, float(sigma_s), float(sigma_a), _p(li), li.shape[0], _p(pos), _p(nt), _p(npf),
+                          _p(rid), P, float(ring_step), int(max_rings), int(seed) & (2**64 - 1), _p(val),
+                          int(nthreads))
+    if rc != 0:
+        raise ValueError(f"rco_values failed ({rc})")
+    return val
 
 
 def records_for(w, idx=None, xeval=None, nthreads=0, scene=None):

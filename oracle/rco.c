@@ -740,6 +740,22 @@ static void add_term(acc_t* acc, const double* y1, const double* y2, const doubl
   acc->n++;
 }
 
+/* Monte Carlo value (Eq. outLF): mean over the N strata (poles excluded) of
+ * the surface radiance attenuated to x (SS) and of the ring radiances in
+ * front of the hit, attenuated to x and weighted by 1/pdf = ring_step (MS) */
+static void mc_value(const rco_verts* v, const rco_params* p, double* val) {
+  const int N = v->nth * v->nph, R = p->max_rings;
+  const double mu = (double)p->sigma_s + (double)p->sigma_a;
+  double VS = 0.0, VM = 0.0;
+  for (int k = 1; k <= N; k++) {
+    f3 w = v->w32[k];
+    double wn = sqrt((double)w.x * w.x + (double)w.y * w.y + (double)w.z * w.z);
+    VS += exp(-mu * v->t64[k] * wn) * v->Ls[k];
+    for (int i = 0; i < v->M[k]; i++) VM += (double)p->ring_step * exp(-mu * v->r64[i] * wn) * v->Lm[(size_t)k * R + i];
+  }
+  val[0] = VS / N; val[1] = VM / N;
+}
+
 /* far vertex: the largest FP32 decision distance, ties to the lowest id */
 static int far_vertex(const int* ids, const float* dist) {
   int best = 0;
@@ -763,15 +779,7 @@ static int one_record(const rco_scene* s, const rco_params* p, const float* x, i
   double mu = (double)p->sigma_s + (double)p->sigma_a;
   double x64[3] = {x[0], x[1], x[2]};
   const double* xe = xeval ? xeval : x64;
-  /* Monte Carlo value (Eq. outLF): mean over the N strata (poles excluded) */
-  double VS = 0.0, VM = 0.0;
-  for (int k = 1; k <= N; k++) {
-    f3 w = v.w32[k];
-    double wn = sqrt((double)w.x * w.x + (double)w.y * w.y + (double)w.z * w.z);
-    VS += exp(-mu * v.t64[k] * wn) * v.Ls[k];
-    for (int i = 0; i < v.M[k]; i++) VM += (double)p->ring_step * exp(-mu * v.r64[i] * wn) * v.Lm[(size_t)k * R + i];
-  }
-  val[0] = VS / N; val[1] = VM / N;
+  mc_value(&v, p, val);
   /* triangulated derivatives */
   tri3* tris = (tri3*)malloc(sizeof(tri3) * 2 * N);
   if (!tris) { verts_free(&v); return RCO_ENOMEM; }
@@ -870,6 +878,32 @@ int rco_records(const rco_scene* s, float sigma_s, float sigma_a, const float* l
     int rc = one_record(s, &p, pos + 3 * i, n_theta[i], n_phi[i], rec_id[i], xeval ? xeval + 3 * i : NULL,
                         value + 2 * i, grad + 6 * i, hess + 12 * i, stats ? stats + RCO_NSTAT * i : NULL);
     if (rc) err |= 1;
+  }
+  return err ? RCO_ENOMEM : RCO_OK;
+}
+
+/* The Monte Carlo values of records only (the value part of rco_records,
+ * without the triangulation): brute-force references at large N. */
+int rco_values(const rco_scene* s, float sigma_s, float sigma_a, const float* lights, int L,
+               const float* pos, const int32_t* n_theta, const int32_t* n_phi, const uint64_t* rec_id, int64_t P,
+               float ring_step, int max_rings, uint64_t seed, double* value, int nthreads) {
+  if (!s || P < 0 || (P > 0 && (!pos || !n_theta || !n_phi || !rec_id || !value))) return RCO_EINVAL;
+  if (L < 0 || (L > 0 && !lights) || !(ring_step > 0.0f) || max_rings < 0 || sigma_s < 0 || sigma_a < 0) return RCO_EINVAL;
+  for (int64_t i = 0; i < P; i++)
+    if (n_theta[i] < 2 || n_phi[i] < 5) return RCO_EINVAL;
+  rco_params p = {sigma_s, sigma_a, lights, L, ring_step, max_rings, seed};
+  int err = 0;
+#ifdef _OPENMP
+  if (nthreads > 0) omp_set_num_threads(nthreads);
+#else
+  (void)nthreads;
+#endif
+#pragma omp parallel for schedule(dynamic, 1) reduction(| : err)
+  for (int64_t i = 0; i < P; i++) {
+    rco_verts v;
+    if (build_verts(s, &p, pos + 3 * i, n_theta[i], n_phi[i], rec_id[i], &v)) { err |= 1; continue; }
+    mc_value(&v, &p, value + 2 * i);
+    verts_free(&v);
   }
   return err ? RCO_ENOMEM : RCO_OK;
 }

@@ -1,0 +1,73 @@
+"""The oracle's pins catch plausible mistakes: each case builds a copy of the
+oracle's C source with one planted mistake, loads it in place of the oracle,
+and requires the named pin to fail on it.  CPU only; the copies live in a
+temporary directory."""
+import inspect
+
+import pytest
+
+from oracle import build as OB
+from oracle import oracle as O
+from tests import test_oracle_pins as pins
+
+SRC = OB.HERE / "rco.c"
+
+# (name, text in rco.c, replacement, pins of which at least one must fail)
+MUTATIONS = [
+    # Sec. 4: an occluder closer than the ring puts the vertex at the occluder
+    ("ring vertex kept at its ring distance behind an occluder",
+     "double tt = in_front ? v.r64[i] : v.t64[id[q]];", "double tt = v.r64[i];",
+     ["test_medium_ring_gradient_converges_to_fd_of_brute_force_values"]),
+    ("far-vertex choice by the ring distance of the clamped vertex",
+     "dd[q] = in_front ? v.r32[i] : v.t32[id[q]];", "dd[q] = v.r32[i];",
+     ["test_medium_ring_gradient_converges_to_fd_of_brute_force_values"]),
+    # App. A: transmittance gradient
+    ("sign of grad T", "gT[i] = -mu * (u[i] / r) * t;", "gT[i] = mu * (u[i] / r) * t;",
+     [("test_transmittance_closed_form_and_fd", {"mu": 0.3})]),
+    # Eq. SSSegALHessianSimp: the F * HT term
+    ("dropped F HT term of the Hessian", "gF[i] * gT[j] + F * HT[3 * i + j]);", "gF[i] * gT[j]);",
+     ["test_record_derivatives_are_exact_calculus_of_triangulated_value",
+      "test_emitting_plane_under_medium_matches_exponential_integrals"]),
+    # far vertex (the first to be occluded): nearest instead
+    ("nearest instead of furthest vertex", "if (dist[k] > dist[best] ||", "if (dist[k] < dist[best] ||",
+     ["test_black_occluder_in_uniform_field_converges_to_closed_form",
+      "test_medium_ring_gradient_converges_to_fd_of_brute_force_values"]),
+]
+
+
+def _call(pin):
+    name, given = (pin, {}) if isinstance(pin, str) else pin
+    fn = getattr(pins, name)
+    params = inspect.signature(fn).parameters
+    # parametrized pins: their first parameter set unless given
+    marks = getattr(fn, "pytestmark", [])
+    args = {}
+    for m in marks:
+        if m.name == "parametrize":
+            names = [n.strip() for n in m.args[0].split(",")]
+            vals = m.args[1][0]
+            vals = vals if len(names) > 1 else (vals,)
+            args.update(dict(zip(names, vals)))
+    args.update(given)
+    fn(**{k: v for k, v in args.items() if k in params})
+
+
+@pytest.mark.parametrize("name,old,new,pin_names", MUTATIONS, ids=[m[0] for m in MUTATIONS])
+def test_planted_mistake_fails_a_pin(tmp_path, name, old, new, pin_names):
+    text = SRC.read_text()
+    assert text.count(old) == 1, f"mutation site not unique: {old}"
+    src = tmp_path / "rco_mut.c"
+    src.write_text(text.replace(old, new))
+    so = tmp_path / "liboracle_mut.so"
+    OB.build(src=src, out=so)
+    failed = []
+    try:
+        O.use_library(so)
+        for pn in pin_names:
+            try:
+                _call(pn)
+            except AssertionError:
+                failed.append(pn)
+    finally:
+        O.use_library(None)
+    assert failed, f"no pin caught: {name}"  # the pins pass on the oracle itself (test_oracle_pins)
