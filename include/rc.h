@@ -264,7 +264,7 @@ int rc_occluded_rays(const rc_scene* scene, const float* orig, const float* seg,
  * cube and each face into bins at up to 4 levels (B / 4^k per side); each
  * triangle is listed, with its distance from the light, in the bins its
  * padded direction region covers, at the finest level where that is at most
- * 8 x 8 bins.  A segment y -> light then tests only the triangles of its
+ * 32 x 32 bins.  A segment y -> light then tests only the triangles of its
  * bins that are closer to the light than y, in order of distance.  The
  * padding covers the hit test's FP32 error, so the answers equal those of
  * testing every triangle.

@@ -10,7 +10,7 @@
 // (u, v) = (e_kx, e_ky) / |e_kz| of a direction e (kz the axis of its largest
 // component, (kx, ky) = (kz + 1, kz + 2) mod 3, face 2 kz for e_kz > 0 and
 // 2 kz + 1 otherwise).  Coarser levels of B / 4^k bins (nested) take the
-// triangles whose region covers more than 8 x 8 bins of a finer level, so a
+// triangles whose region covers more than 32 x 32 bins of a finer level, so a
 // wall or a slab lands in a few coarse bins instead of thousands of fine
 // ones.  Each bin lists its triangles by increasing distance from L.
 //
@@ -188,7 +188,7 @@ int build_light_bins(const float* tri, int64_t T, float scale, const float light
             v1 += pad;
           }
         }
-        // finest level whose rectangle has at most 8 x 8 bins (else the coarsest)
+        // finest level whose rectangle has at most 32 x 32 bins (else the coarsest)
         Span sp{2 * ax + sg, 0, 0, 0, 0, 0};
         for (int k = 0; k < out.nlev; k++) {
           const int Bk = B >> (2 * k);
@@ -201,7 +201,7 @@ int build_light_bins(const float* tri, int64_t T, float scale, const float light
           sp.iu1 = bin(u1);
           sp.iv0 = bin(v0);
           sp.iv1 = bin(v1);
-          if ((int64_t)(sp.iu1 - sp.iu0 + 1) * (sp.iv1 - sp.iv0 + 1) <= 64) break;
+          if ((int64_t)(sp.iu1 - sp.iu0 + 1) * (sp.iv1 - sp.iv0 + 1) <= 1024) break;
         }
         spans.push_back(sp);
         span_tri.push_back((int32_t)j);
@@ -220,10 +220,84 @@ int build_light_bins(const float* tri, int64_t T, float scale, const float light
     const int64_t Bk = B >> (2 * level);
     return lev_bin[level] + ((int64_t)face * Bk + iu) * Bk + iv;
   };
+  // Stored distance of each (triangle, bin) entry: the distance from L of the
+  // part of the triangle seen through the padded bin (the triangle clipped to
+  // the bin's pyramid: the closest point of a convex planar polygon), minus
+  // eps, rounded down; +inf when nothing of the triangle is seen through it
+  // (the bin lies in a corner of the triangle's (u, v) box), and such entries
+  // are dropped.  Walls and slabs so stay out of the lists of segments that
+  // do not reach them.
+  auto entry_distance = [&](int32_t j, int level, int face, int iu, int iv) -> float {
+    const double Bk = (double)(B >> (2 * level)), pad = tpad[j];
+    const double u0 = -1.0 + 2.0 * iu / Bk - pad, u1 = -1.0 + 2.0 * (iu + 1) / Bk + pad;
+    const double v0 = -1.0 + 2.0 * iv / Bk - pad, v1 = -1.0 + 2.0 * (iv + 1) / Bk + pad;
+    const int ax = face >> 1, kx = (ax + 1) % 3, ky = (ax + 2) % 3;
+    const double sz = (face & 1) ? -1.0 : 1.0;
+    const float* t = tri + 9 * (int64_t)j;
+    V poly[16], tmp[16];
+    for (int q = 0; q < 3; q++) {
+      const V r = {t[3 * q] - L.x, t[3 * q + 1] - L.y, t[3 * q + 2] - L.z};
+      poly[q] = {comp(r, kx), comp(r, ky), sz * comp(r, ax)};
+    }
+    int n = clip(poly, 3, tmp, [u0](V p) { return p.x - u0 * p.z; });
+    n = clip(tmp, n, poly, [u1](V p) { return u1 * p.z - p.x; });
+    n = clip(poly, n, tmp, [v0](V p) { return p.y - v0 * p.z; });
+    n = clip(tmp, n, poly, [v1](V p) { return v1 * p.z - p.y; });
+    if (n == 0) return INFINITY;
+    // closest point of the polygon to the origin (L): the plane's foot if
+    // inside, else the nearest edge point
+    double d = 1e300;
+    const V nrm = tn[j];
+    const V nf = {comp(nrm, kx), comp(nrm, ky), sz * comp(nrm, ax)};
+    const double hp = dot(nf, poly[0]);
+    bool inside = n >= 3 && norm(nf) > 0;
+    const V foot = mul(hp, nf);
+    double sgn = 0;
+    for (int q = 0; q < n && inside; q++) {
+      const V a = poly[q], b = poly[(q + 1) % n];
+      const V e = sub(b, a), f = sub(foot, a);
+      const V c = {e.y * f.z - e.z * f.y, e.z * f.x - e.x * f.z, e.x * f.y - e.y * f.x};
+      const double sd = dot(c, nf);
+      if (sd != 0) {
+        if (sgn == 0) sgn = sd;
+        else if ((sd > 0) != (sgn > 0)) inside = false;
+      }
+    }
+    if (inside) d = std::fabs(hp);
+    for (int q = 0; q < n; q++) {
+      const V a = poly[q], b = poly[(q + 1) % n];
+      const V e = sub(b, a);
+      const double ee = dot(e, e);
+      double tq = ee > 0 ? -dot(a, e) / ee : 0.0;
+      tq = std::min(1.0, std::max(0.0, tq));
+      d = std::min(d, norm(add(a, mul(tq, e))));
+    }
+    d = std::max(d, tdmin[j]);
+    const double ds = d - eps;
+    float df = (float)ds;
+    if ((double)df > ds) df = std::nextafter(df, -INFINITY);
+    return df;
+  };
   std::vector<int64_t> cnt((size_t)(total_bins + out.nlev), 0);
-  for (const Span& sp : spans)
+  // entries: (bin, distance, triangle) of every span bin that sees the triangle
+  struct Ent {
+    int64_t bin;
+    float d;
+    int32_t j;
+  };
+  std::vector<Ent> ents;
+  ents.reserve(spans.size() * 4);
+  for (size_t s = 0; s < spans.size(); s++) {
+    const Span& sp = spans[s];
     for (int iu = sp.iu0; iu <= sp.iu1; iu++)
-      for (int iv = sp.iv0; iv <= sp.iv1; iv++) cnt[bin_index(sp.level, sp.face, iu, iv)]++;
+      for (int iv = sp.iv0; iv <= sp.iv1; iv++) {
+        const float d = entry_distance(span_tri[s], sp.level, sp.face, iu, iv);
+        if (!(d < INFINITY)) continue;
+        const int64_t b = bin_index(sp.level, sp.face, iu, iv);
+        ents.push_back({b, d, span_tri[s]});
+        cnt[b]++;
+      }
+  }
   int64_t run = 0;
   for (int k = 0; k < out.nlev; k++) {
     const int64_t Bk = B >> (2 * k);
@@ -239,46 +313,15 @@ int build_light_bins(const float* tri, int64_t T, float scale, const float light
     err = "light bins: too many entries";
     return RC_EINVAL;
   }
-  // Stored distance of each (triangle, bin) entry: no point of the triangle
-  // seen through the padded bin is closer to L than the triangle's distance,
-  // nor than its plane along the bin's directions, h / max(n . u) over unit
-  // directions u of the bin (bounded by the largest n . p over the bin's
-  // corners p = (u, v, 1) in the face frame divided by the smallest |p|);
-  // minus eps, rounded down.  Walls and slabs so stay out of the lists of
-  // segments that do not reach them.
-  auto entry_distance = [&](int32_t j, int level, int face, int iu, int iv) {
-    const double Bk = (double)(B >> (2 * level)), pad = tpad[j];
-    const double u0 = -1.0 + 2.0 * iu / Bk - pad, u1 = -1.0 + 2.0 * (iu + 1) / Bk + pad;
-    const double v0 = -1.0 + 2.0 * iv / Bk - pad, v1 = -1.0 + 2.0 * (iv + 1) / Bk + pad;
-    const int ax = face >> 1, kx = (ax + 1) % 3, ky = (ax + 2) % 3;
-    const double sz = (face & 1) ? -1.0 : 1.0;
-    const V n = tn[j];
-    const double nx = comp(n, kx), ny = comp(n, ky), nz = sz * comp(n, ax);
-    const double mx = std::max({nx * u0 + ny * v0 + nz, nx * u1 + ny * v0 + nz, nx * u0 + ny * v1 + nz,
-                                nx * u1 + ny * v1 + nz});
-    double d = tdmin[j];
-    if (th[j] > 0 && mx > 0) {
-      const double um = (u0 <= 0 && u1 >= 0) ? 0.0 : std::min(u0 * u0, u1 * u1);
-      const double vm = (v0 <= 0 && v1 >= 0) ? 0.0 : std::min(v0 * v0, v1 * v1);
-      d = std::max(d, th[j] * std::sqrt(1.0 + um + vm) / mx);
-    }
-    const double ds = d - eps;
-    float df = (float)ds;
-    if ((double)df > ds) df = std::nextafter(df, -INFINITY);
-    return df;
-  };
   std::vector<int32_t> ids((size_t)run);
   std::vector<float> edist((size_t)run);
   std::vector<int64_t> cur(cnt.begin(), cnt.end());
-  for (size_t s = 0; s < spans.size(); s++) {
-    const Span& sp = spans[s];
-    for (int iu = sp.iu0; iu <= sp.iu1; iu++)
-      for (int iv = sp.iv0; iv <= sp.iv1; iv++) {
-        const int64_t e = cur[bin_index(sp.level, sp.face, iu, iv)]++;
-        ids[(size_t)e] = span_tri[s];
-        edist[(size_t)e] = entry_distance(span_tri[s], sp.level, sp.face, iu, iv);
-      }
+  for (const Ent& e : ents) {
+    const int64_t k = cur[e.bin]++;
+    ids[(size_t)k] = e.j;
+    edist[(size_t)k] = e.d;
   }
+  std::vector<Ent>().swap(ents);
   // bin headers, two words per bin: the first entry's index and its stored
   // distance (+inf for an empty bin); the level's last word is the end of
   // its last bin
@@ -327,10 +370,11 @@ int build_light_bins(const float* tri, int64_t T, float scale, const float light
 
 int light_bins_size_for(int64_t T) {
   // about 2.6 sqrt(T) bins per face side at the finest level, a power of two
-  // in [16, 512] (10k triangles: 256, 3.5 entries read per segment on average)
+  // in [16, 1024] (10k triangles: 256, 1.4 entries read per segment; 1M
+  // triangles with slabs: 1024, 5.8)
   const double want = 2.6 * std::sqrt((double)std::max<int64_t>(T, 1));
   int B = 16;
-  while (B < 512 && (double)B * 1.41421356 < want) B <<= 1;
+  while (B < 1024 && (double)B * 1.41421356 < want) B <<= 1;
   return B;
 }
 
