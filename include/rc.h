@@ -39,6 +39,7 @@ extern "C" {
 #define RC_ENOMEM (-2)   /* host or device allocation failed */
 #define RC_EDEVICE (-3)  /* HIP runtime error (text in rc_last_error) */
 #define RC_ENODEV (-4)   /* no usable gfx950 device */
+#define RC_ETIMEOUT (-5) /* rc_records_wait: no record finished within the time limit */
 
 #define RC_MAX_LIGHTS 16
 #define RC_MAX_RINGS 64
@@ -215,6 +216,17 @@ int rc_records_batched(const rc_scene* scene, const rc_medium* medium, const rc_
                        int n_lights, const float* pos, const int32_t* n_theta, const int32_t* n_phi, int64_t P,
                        const rc_params* params, const int32_t* order, int use_graph, int tile,
                        double* value, double* grad, double* hess, void* workspace, void* stream);
+
+/* Watchdog for a record call on `stream` (rc_records or
+ * rc_records_batched with this workspace): waits until the stream has
+ * finished the work queued on it so far; returns RC_ETIMEOUT if it has not
+ * and no record (or record part) has finished for timeout_ms milliseconds.
+ * The record kernel counts finished records in the workspace, and this call
+ * reads that count through a copy on a stream of its own, so it sees
+ * progress while the kernel runs.  A timeout does not stop the kernel: the
+ * caller decides what to do (the stream stays busy).  Errors: EINVAL,
+ * EDEVICE. */
+int rc_records_wait(const void* workspace, int timeout_ms, void* stream);
 
 /* Time every launch configuration on the given inputs (synchronises
  * `stream`) and return the fastest configuration index in *best_tile; the

@@ -116,7 +116,7 @@ struct rc_scene {
 namespace {
 
 // queue area (256 bytes): [0] next item, [1] invalid records, [2..6] next item
-// of each n_phi class launch, [16..25] class ranges [lo, hi)
+// of each n_phi class launch, [8] records finished, [16..25] class ranges [lo, hi)
 constexpr size_t kWsQueue = 0, kWsHist = 256, kWsCursor = 256 + 4 * rc::kOrderBuckets,
                  kWsOrder = 256 + 8 * rc::kOrderBuckets;
 constexpr int kQClassNext = 2, kQClassRange = 16;
@@ -572,7 +572,7 @@ int rc_records_batched(const rc_scene* scene, const rc_medium* medium, const rc_
   unsigned int* q = reinterpret_cast<unsigned int*>(ws + kWsQueue);
   if (!ord) {
     int32_t* o = reinterpret_cast<int32_t*>(ws + kWsOrder);
-    RC_HIP(rc::launch_order(n_theta, n_phi, (int)P, reinterpret_cast<unsigned int*>(ws + kWsHist),
+    RC_HIP(rc::launch_order(n_theta, n_phi, (int)P, params->max_n_phi, reinterpret_cast<unsigned int*>(ws + kWsHist),
                             reinterpret_cast<unsigned int*>(ws + kWsCursor), o, q + kQClassRange, st));
     ord = o;
   }
@@ -645,6 +645,45 @@ int rc_records_batched(const rc_scene* scene, const rc_medium* medium, const rc_
   }
   RC_HIP(hipGraphLaunch(gc.exec, st));
   return RC_OK;
+}
+
+int rc_records_wait(const void* workspace, int timeout_ms, void* stream) {
+  if (!workspace || timeout_ms < 0) return fail(RC_EINVAL, "workspace is NULL or timeout_ms < 0");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  // nothing here may wait on `stream`: no allocation of pinned memory, no
+  // copy on the null stream; progress is read into pageable memory through a
+  // non-blocking stream
+  hipEvent_t ev = nullptr;
+  hipStream_t side = nullptr;
+  unsigned int hostv = 0;
+  unsigned int* host = &hostv;
+  auto done = [&](int code) {
+    if (ev) (void)hipEventDestroy(ev);
+    if (side) (void)hipStreamDestroy(side);
+    return code;
+  };
+  if (hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess || hipEventRecord(ev, st) != hipSuccess ||
+      hipStreamCreateWithFlags(&side, hipStreamNonBlocking) != hipSuccess)
+    return done(fail(RC_EDEVICE, "watchdog setup failed"));
+  const unsigned int* progress = static_cast<const unsigned int*>(workspace) + rc::kQueueDone;
+  unsigned int last = 0xffffffffu;
+  auto t_last = std::chrono::steady_clock::now();
+  while (true) {
+    const hipError_t q = hipEventQuery(ev);
+    if (q == hipSuccess) return done(RC_OK);
+    if (q != hipErrorNotReady) return done(fail(RC_EDEVICE, "stream failed: %s", hipGetErrorString(q)));
+    if (hipMemcpyAsync(host, progress, sizeof(unsigned int), hipMemcpyDeviceToHost, side) != hipSuccess ||
+        hipStreamSynchronize(side) != hipSuccess)
+      return done(fail(RC_EDEVICE, "progress read failed"));
+    const auto now = std::chrono::steady_clock::now();
+    if (*host != last) {
+      last = *host;
+      t_last = now;
+    } else if (std::chrono::duration_cast<std::chrono::milliseconds>(now - t_last).count() >= timeout_ms) {
+      return done(fail(RC_ETIMEOUT, "no record finished for %d ms (%u finished)", timeout_ms, last));
+    }
+    std::this_thread::sleep_for(std::chrono::microseconds(500));
+  }
 }
 
 int rc_autotune(const rc_scene* scene, const rc_medium* medium, const rc_point_light* lights, int n_lights,

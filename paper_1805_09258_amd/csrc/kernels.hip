@@ -789,6 +789,7 @@ record_kernel(RecordArgs g) {
       __syncthreads();
     }
     if (lane < 2) g.value[2 * rec + lane] = racc[lane] / (double)N;
+    if (lane == 0) atomicAdd(&g.queue[kQueueDone], 1u);  // progress, read by the host watchdog
     if (lane < 18) {
       int c = lane / 9, k = lane % 9;
       if (k < 3) g.grad[6 * rec + 3 * c + k] = racc[2 + lane];
@@ -819,6 +820,7 @@ record_kernel(RecordArgs g) {
 // ---------------------------------------------------------------------------
 __global__ void reset_queue_kernel(unsigned int* q) {
   if (threadIdx.x < 2) q[threadIdx.x] = 0u;
+  if (threadIdx.x == 0) q[kQueueDone] = 0u;
 }
 
 // Queue of records grouped by n_phi class (the LDS a record's rows need:
@@ -827,15 +829,18 @@ __global__ void reset_queue_kernel(unsigned int* q) {
 // octave); ties in any order (records do not interact).  The scan also
 // writes each class's queue range [lo, hi) to class_range[2 * class].
 RC_DEV int order_class(int nph) { return nph <= 16 ? 0 : (nph <= 32 ? 1 : (nph <= 64 ? 2 : (nph <= 128 ? 3 : 4))); }
-RC_DEV int order_bucket(int nth, int nph) {
+// A record with n_phi above the call's max_n_phi (invalid: the record kernel
+// writes NaN and counts it) is queued in max_n_phi's class, so that one of
+// the launches pops it.
+RC_DEV int order_bucket(int nth, int nph, int max_nph) {
   const float n = fmaxf((float)nth * (float)nph, 1.f);
   const int cb = min(max((int)(log2f(n) * 4.f), 0), kOrderPerClass - 1);
-  return (kOrderClasses - 1 - order_class(nph)) * kOrderPerClass + (kOrderPerClass - 1 - cb);
+  return (kOrderClasses - 1 - order_class(min(nph, max_nph))) * kOrderPerClass + (kOrderPerClass - 1 - cb);
 }
-__global__ void order_hist_kernel(const int* nth, const int* nph, int P, unsigned int* hist) {
+__global__ void order_hist_kernel(const int* nth, const int* nph, int P, int max_nph, unsigned int* hist) {
   int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= P) return;
-  atomicAdd(&hist[order_bucket(nth[i], nph[i])], 1u);
+  atomicAdd(&hist[order_bucket(nth[i], nph[i], max_nph)], 1u);
 }
 __global__ void order_scan_kernel(unsigned int* hist, unsigned int* cursor, unsigned int* class_range) {
   if (threadIdx.x == 0) {
@@ -849,10 +854,11 @@ __global__ void order_scan_kernel(unsigned int* hist, unsigned int* cursor, unsi
     }
   }
 }
-__global__ void order_scatter_kernel(const int* nth, const int* nph, int P, unsigned int* cursor, int* order) {
+__global__ void order_scatter_kernel(const int* nth, const int* nph, int P, int max_nph, unsigned int* cursor,
+                                     int* order) {
   int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= P) return;
-  unsigned int p = atomicAdd(&cursor[order_bucket(nth[i], nph[i])], 1u);
+  unsigned int p = atomicAdd(&cursor[order_bucket(nth[i], nph[i], max_nph)], 1u);
   order[p] = i;
 }
 __global__ void zero_u32_kernel(unsigned int* p, int n) {
@@ -974,13 +980,13 @@ hipError_t launch_zero_u32(unsigned int* p, int n, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t launch_order(const int* nth, const int* nph, int P, unsigned int* hist, unsigned int* cursor, int* order,
+hipError_t launch_order(const int* nth, const int* nph, int P, int max_nph, unsigned int* hist, unsigned int* cursor, int* order,
                         unsigned int* class_range, hipStream_t s) {
   hipLaunchKernelGGL(zero_u32_kernel, dim3(1), dim3(kOrderBuckets), 0, s, hist, kOrderBuckets);
   int blocks = (P + 255) / 256;
-  if (blocks > 0) hipLaunchKernelGGL(order_hist_kernel, dim3(blocks), dim3(256), 0, s, nth, nph, P, hist);
+  if (blocks > 0) hipLaunchKernelGGL(order_hist_kernel, dim3(blocks), dim3(256), 0, s, nth, nph, P, max_nph, hist);
   hipLaunchKernelGGL(order_scan_kernel, dim3(1), dim3(64), 0, s, hist, cursor, class_range);
-  if (blocks > 0) hipLaunchKernelGGL(order_scatter_kernel, dim3(blocks), dim3(256), 0, s, nth, nph, P, cursor, order);
+  if (blocks > 0) hipLaunchKernelGGL(order_scatter_kernel, dim3(blocks), dim3(256), 0, s, nth, nph, P, max_nph, cursor, order);
   return hipGetLastError();
 }
 

@@ -10,6 +10,7 @@
 namespace rc {
 
 constexpr int kOrderBuckets = 256;
+constexpr int kQueueDone = 8;  // workspace queue word: records finished (progress)
 constexpr int kOrderClasses = 5;    // n_phi classes: <= 16, 32, 64, 128, 256
 constexpr int kOrderPerClass = 48;  // cost buckets per class (1/4 octave of N)
 constexpr int kClassCap[kOrderClasses] = {16, 32, 64, 128, 256};
@@ -74,7 +75,7 @@ hipError_t launch_reset(unsigned int* q, hipStream_t s);
 hipError_t launch_zero_u32(unsigned int* p, int n, hipStream_t s);
 constexpr int kMaxSplits = 8;        // wavefronts per record at most
 constexpr int kSplitMaxRecords = 16384;  // batches up to this size may split records
-hipError_t launch_order(const int* nth, const int* nph, int P, unsigned int* hist, unsigned int* cursor, int* order,
+hipError_t launch_order(const int* nth, const int* nph, int P, int max_nph, unsigned int* hist, unsigned int* cursor, int* order,
                         unsigned int* class_range, hipStream_t s);
 hipError_t launch_radius(const double* value, const double* hess, int P, float eps, float r_min, float r_max, float* R,
                          float* axes, hipStream_t s);

@@ -21,6 +21,7 @@ LIB_PATH = Path(os.environ.get("RC_LIBRARY", str(_PKG / "librc.so")))
 
 RC_OK, RC_EINVAL, RC_ENOMEM, RC_EDEVICE, RC_ENODEV = 0, -1, -2, -3, -4
 RC_MAX_LIGHTS, RC_MAX_RINGS, RC_MAX_NPHI = 16, 64, 256
+RC_ETIMEOUT = -5
 RC_PLACE_STATE_INTS = 4101  # placement state: 5 counters + one status word per gathered candidate
 
 
@@ -53,7 +54,7 @@ class rc_scene_stats(C.Structure):
 
 
 EXPORTS = ["rc_scene_create", "rc_scene_destroy", "rc_scene_info", "rc_bvh_build_host", "rc_workspace_size",
-           "rc_workspace_errors", "rc_records", "rc_records_batched", "rc_autotune", "rc_radius",
+           "rc_workspace_errors", "rc_records", "rc_records_batched", "rc_records_wait", "rc_autotune", "rc_radius",
            "rc_trace_rays", "rc_occluded_rays", "rc_light_bins_build", "rc_light_occluded", "rc_light_bins_host",
            "rc_probe", "rc_mlp_param_bytes", "rc_mlp_n_params", "rc_mlp_init",
            "rc_mlp_load", "rc_mlp_fit_features", "rc_mlp_forward", "rc_mlp_radius", "rc_mlp_train_workspace_bytes",
@@ -88,6 +89,8 @@ def lib():
         L.rc_records.restype = i32
         L.rc_records_batched.argtypes = rec + [vp, i32, i32, vp, vp, vp, vp, vp]
         L.rc_records_batched.restype = i32
+        L.rc_records_wait.argtypes = [vp, i32, vp]
+        L.rc_records_wait.restype = i32
         L.rc_autotune.argtypes = rec + [vp, vp, vp, vp, C.c_char_p, C.POINTER(i32), vp, C.POINTER(i32), vp]
         L.rc_autotune.restype = i32
         L.rc_radius.argtypes = [vp, vp, i64, f32, f32, f32, vp, vp, vp]
@@ -223,6 +226,10 @@ def make_params(ring_step, max_rings, max_n_phi, seed, rec_base=0, precision=0, 
     return rc_params(float(ring_step), int(max_rings), int(max_n_phi), int(precision), int(bool(common_random)),
                      int(splits), int(seed) & (2**64 - 1), int(rec_base),
                      None if counters is None else counters.data_ptr(), int(bool(shadow_bvh)))
+
+
+def rc_records_wait(workspace, timeout_ms, stream=None):
+    return _check(lib().rc_records_wait(_ptr(workspace), int(timeout_ms), _stream(stream)))
 
 
 def rc_light_bins_build(scene, lights, B=0):

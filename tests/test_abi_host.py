@@ -319,3 +319,9 @@ def test_light_bins_answer_every_segment_like_all_triangles(scene):
             mism += int(sub != bool(full[i]))
         assert mism == 0, (scene, li, mism, len(pts))
         assert full.sum() >= 10
+
+
+def test_watchdog_rejects_bad_arguments_without_a_device():
+    ws = np.zeros(64, np.uint32)
+    assert rc.lib().rc_records_wait(None, 100, None) == rc.RC_EINVAL
+    assert rc.lib().rc_records_wait(ws.ctypes.data_as(rc.C.c_void_p), -1, None) == rc.RC_EINVAL

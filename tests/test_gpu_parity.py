@@ -268,6 +268,65 @@ def test_empty_and_invalid_records(dev):
     sc.close()
 
 
+def test_large_batch_with_n_phi_above_its_bound(dev):
+    """Large batches (more than 16384 records) run one launch per n_phi class
+    up to max_n_phi's class; a record whose n_phi exceeds max_n_phi, in a
+    higher class, is still popped: its outputs are NaN and it is counted, and
+    every other record is computed."""
+    P = 20000
+    w = W.make_c1(P=P)
+    w.n_theta = np.full(P, 4, np.int32)
+    w.n_phi = np.full(P, 8, np.int32)
+    w.n_phi[[7, 12345]] = [40, 200]     # classes <= 64 and <= 256, above max_n_phi = 32
+    w.n_phi[100] = 24
+    sc = rc.Scene.from_workload(w)
+    dw = rc.DeviceWorkload(w)
+    dw.max_n_phi = 32
+    v, g, h, ws = rc.compute_records(sc, dw, batched=True)
+    torch.cuda.synchronize()
+    assert rc.rc_workspace_errors(ws) == 2
+    v, g, h = v.cpu().numpy(), g.cpu().numpy(), h.cpu().numpy()
+    assert np.all(np.isnan(v[[7, 12345]])) and np.all(np.isnan(g[[7, 12345]])) and np.all(np.isnan(h[[7, 12345]]))
+    ok = np.setdiff1d(np.arange(P), [7, 12345])
+    assert np.all(np.isfinite(v[ok])) and np.all(np.isfinite(h[ok]))
+    idx = np.array([0, 100, 19999])
+    ref = O.records_for(w, idx)
+    assert_parity(v[idx], g[idx], h[idx], ref, "large batch next to out-of-bound n_phi")
+    sc.close()
+
+
+def test_watchdog_times_out_while_the_stream_is_held_and_returns_once_it_runs(dev):
+    """rc_records_wait reports ETIMEOUT when no record finishes within the
+    limit, and returns normally once the records run.  The stall is forced
+    from the host: a host function that sleeps holds the stream, so no kernel
+    ever waits on anything."""
+    import ctypes
+    import time
+    w = W.make_c1(P=64)
+    sc = rc.Scene.from_workload(w)
+    dw = rc.DeviceWorkload(w)
+    ws = dw.workspace()
+    s = torch.cuda.Stream()
+    rc.compute_records(sc, dw, batched=True, workspace=ws, stream=s)  # builds and caches the light bins
+    torch.cuda.synchronize()
+    hip = ctypes.CDLL("libamdhip64.so")
+    hold = ctypes.CFUNCTYPE(None, ctypes.c_void_p)(lambda _: time.sleep(1.5))
+    hip.hipLaunchHostFunc.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]
+    assert hip.hipLaunchHostFunc(ctypes.c_void_p(s.cuda_stream), ctypes.cast(hold, ctypes.c_void_p), None) == 0
+    with torch.cuda.stream(s):
+        v, g, h, _ = rc.compute_records(sc, dw, batched=True, workspace=ws, stream=s)
+    t0 = time.time()
+    with pytest.raises(rc.RCError) as e:
+        rc.rc_records_wait(ws, 300, stream=s)
+    assert e.value.code == rc.RC_ETIMEOUT and time.time() - t0 < 1.4
+    assert rc.rc_records_wait(ws, 10000, stream=s) == 0
+    torch.cuda.synchronize()
+    assert rc.rc_workspace_errors(ws) == 0 and bool(torch.isfinite(v).all())
+    ref = O.records_for(w, np.arange(4))
+    assert_parity(v[:4].cpu().numpy(), g[:4].cpu().numpy(), h[:4].cpu().numpy(), ref, "records after the watchdog")
+    sc.close()
+
+
 def test_deterministic_batched_and_graph_replays_bitwise_equal(dev):
     w = W.make_c2(P=300, n_soup=3000, seed=41)
     w.n_theta = np.where(np.arange(300) % 3 == 0, 16, 8).astype(np.int32)
