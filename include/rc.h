@@ -89,9 +89,11 @@ typedef struct {
  *               leave FP64 partial sums that the last one adds in part order,
  *               so results are deterministic for a given count and differ
  *               from an unsplit record only in FP64 rounding.
- *   precision : 0 = FP32 terms, compensated FP32 sums, FP64 for
- *               near-degenerate triangle terms and the final reduction
- *               (default); 1 = every triangle term in FP64 (study mode).
+ *   precision : 0 = FP32 terms with the two quantities that cancel for
+ *               near-degenerate (thin) triangles -- the direction
+ *               determinant and grad A -- in FP64, compensated FP32 sums,
+ *               FP64 final reduction (default); 1 = every triangle term in
+ *               FP64 (study mode).
  *   counters  : device uint64_t[12] or NULL.  If set, the launch also
  *               counts (atomically added): rays traced, BVH nodes visited,
  *               ray/triangle tests, triangle terms evaluated, the shader

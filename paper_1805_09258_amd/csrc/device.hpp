@@ -410,20 +410,27 @@ RC_DEV float r_exp<float>(float v) { return expf(v); }
 template <>
 RC_DEV double r_exp<double>(double v) { return exp(v); }
 
-// Returns false if the triangle is degenerate for this precision (caller
-// retries in FP64 or drops a term of zero measure).
+// Returns false (no term) for a degenerate triangle: A = 0 (the vertices
+// coplanar with x: a term of zero measure) or all vertices at x.
 // q_k = t_k w_k: vertex k at ray distance t_k along direction w_k.
 // detw = w1 . (w2 x w3), supplied by the caller in FP64 precision: for thin
-// (near-zero-area) triangles it is the one quantity FP32 cannot resolve, and
-// A = q1 . (q2 x q3) = t1 t2 t3 detw exactly.
+// (near-zero-area) triangles it is one of the two quantities FP32 cannot
+// resolve (cs below is the other), and A = q1 . (q2 x q3) = t1 t2 t3 detw
+// exactly.
 //
 // F is invariant under scaling of the vertices about x, grad F scales as 1/s
 // and HF as 1/s^2: the form factor is evaluated on vertices divided by
 // s = max_k |r_k| and rescaled, which keeps B ~ |r|^3 and 1/D^2 ~ |r|^-12 inside
 // the FP32 range for vertices arbitrarily close to x.
+//
+// cs = (q2 - q1) x (q3 - q1) = q1 x q2 + q2 x q3 + q3 x q1 is supplied in
+// FP64 as well: it is grad A up to sign, and for thin triangles (vertices
+// nearly collinear as seen from x) its three cross products nearly cancel,
+// which costs FP32 all its digits (per-term Hessian errors up to 5e-2 on
+// 1M-triangle scenes; 2e-6 with cs in FP64).
 template <typename R>
-RC_DEV bool triangle_term(V3<R> q1, V3<R> q2, V3<R> q3, R t1, R t2, R t3, R detw, int far, R wL, R mu, R* g,
-                          R* h) {
+RC_DEV bool triangle_term(V3<R> q1, V3<R> q2, V3<R> q3, R t1, R t2, R t3, R detw, V3<double> cs, int far, R wL,
+                          R mu, R* g, R* h) {
   const R inv2pi = (R)(1.0 / (2.0 * kPi));
   R m1 = r_sqrt(dotv(q1, q1)), m2 = r_sqrt(dotv(q2, q2)), m3 = r_sqrt(dotv(q3, q3));
   R sc = m1 > m2 ? (m1 > m3 ? m1 : m3) : (m2 > m3 ? m2 : m3);
@@ -431,7 +438,6 @@ RC_DEV bool triangle_term(V3<R> q1, V3<R> q2, V3<R> q3, R t1, R t2, R t3, R detw
   R isc = (R)1 / sc;
   V3<R> r1 = isc * q1, r2 = isc * q2, r3 = isc * q3;
   R l1 = m1 * isc, l2 = m2 * isc, l3 = m3 * isc;
-  V3<R> c12 = crossv(r1, r2), c23 = crossv(r2, r3), c31 = crossv(r3, r1);
   R A = ((t1 * isc) * (t2 * isc) * (t3 * isc)) * detw;
   R d12 = dotv(r1, r2), d23 = dotv(r2, r3), d13 = dotv(r1, r3);
   R B = l1 * l2 * l3 + d12 * l3 + d23 * l1 + d13 * l2;
@@ -439,7 +445,8 @@ RC_DEV bool triangle_term(V3<R> q1, V3<R> q2, V3<R> q3, R t1, R t2, R t3, R detw
   R sg = A < 0 ? (R)-1 : (R)1;
   if (A == (R)0) return false;
   V3<R> u1 = ((R)1 / l1) * r1, u2 = ((R)1 / l2) * r2, u3 = ((R)1 / l3) * r3;
-  V3<R> a = (-sg) * (c12 + c23 + c31);
+  const double isc2 = (double)isc * (double)isc;
+  V3<R> a = (-sg) * mk((R)(cs.x * isc2), (R)(cs.y * isc2), (R)(cs.z * isc2));
   // b = grad B, with grad l_k = -u_k
   V3<R> b = (-(l2 * l3 + d23)) * u1 + (-(l1 * l3 + d13)) * u2 + (-(l1 * l2 + d12)) * u3;
   b = b - l3 * (r1 + r2) - l1 * (r2 + r3) - l2 * (r1 + r3);

@@ -14,7 +14,8 @@
 //   4. form the triangles between the previous row and this one (polar fans
 //      at the ends, two triangles per quad elsewhere) and evaluate every
 //      (triangle, ring) term, again compacted across lanes, into per-lane
-//      compensated FP32 sums (FP64 for near-degenerate terms);
+//      compensated FP32 sums (FP32 terms whose two thin-triangle
+//      quantities, the direction determinant and grad A, are FP64);
 // and finally reduces the 64 lanes in FP64 with cross-lane shuffles.
 #include <hip/hip_runtime.h>
 
@@ -726,7 +727,12 @@ record_kernel(RecordArgs g) {
             V3<float> r1 = mk(tau[0] * wv[0].x, tau[0] * wv[0].y, tau[0] * wv[0].z);
             V3<float> r2 = mk(tau[1] * wv[1].x, tau[1] * wv[1].y, tau[1] * wv[1].z);
             V3<float> r3 = mk(tau[2] * wv[2].x, tau[2] * wv[2].y, tau[2] * wv[2].z);
-            if (triangle_term<float>(r1, r2, r3, tau[0], tau[1], tau[2], (float)dw, far, wL, mu, gg, hh)) {
+            // grad A up to sign, in FP64 from the same vertices (thin triangles)
+            const V3<double> p1 = mk((double)tau[0] * wv[0].x, (double)tau[0] * wv[0].y, (double)tau[0] * wv[0].z);
+            const V3<double> p2 = mk((double)tau[1] * wv[1].x, (double)tau[1] * wv[1].y, (double)tau[1] * wv[1].z);
+            const V3<double> p3 = mk((double)tau[2] * wv[2].x, (double)tau[2] * wv[2].y, (double)tau[2] * wv[2].z);
+            const V3<double> cs = crossv(p2 - p1, p3 - p1);
+            if (triangle_term<float>(r1, r2, r3, tau[0], tau[1], tau[2], (float)dw, cs, far, wL, mu, gg, hh)) {
               const float t9[9] = {gg[0], gg[1], gg[2], hh[0], hh[1], hh[2], hh[3], hh[4], hh[5]};
               add_term(acc, accc, t9);
             }
@@ -742,7 +748,9 @@ record_kernel(RecordArgs g) {
             V3<double> r3 = mk(dtau[2] * wv[2].x, dtau[2] * wv[2].y, dtau[2] * wv[2].z);
             double g64[3], h64[6];
             double wL64 = ring < 0 ? (double)Lf : (double)g.ring_step * (double)Lf;
-            if (triangle_term<double>(r1, r2, r3, dtau[0], dtau[1], dtau[2], dw, far, wL64, (double)mu, g64, h64)) {
+            const V3<double> cs = crossv(r2 - r1, r3 - r1);
+            if (triangle_term<double>(r1, r2, r3, dtau[0], dtau[1], dtau[2], dw, cs, far, wL64, (double)mu, g64,
+                                      h64)) {
               float hi[9], lo[9];
 #pragma unroll
               for (int k = 0; k < 9; k++) {

@@ -209,17 +209,17 @@ def test_small_batches_split_automatically_on_the_c2_scene(dev):
 def test_c2_full_size_sampled_records_match_oracle(dev):
     """C2 at its full size (10k records, 1024 directions, 10k-triangle soup in a
     closed room, 4 lights) in the benchmark's launch configuration (batched
-    persistent launch from a device-built queue, graph replay); a seeded
-    sample of records is recomputed by the oracle."""
+    persistent launch from a device-built queue, graph replay); a seeded 1 %
+    sample of the records (100) is recomputed by the oracle."""
     w = W.make_c2()
     _say("C2 full:", w.n_rec, "records,", w.n_tri, "triangles")
     s = torch.cuda.Stream()
     with torch.cuda.stream(s):
         (v, g, h), errs = gpu_records(w, batched=True, use_graph=True, stream=s)
     assert errs == 0
-    idx = np.sort(np.random.default_rng(123).choice(w.n_rec, size=24, replace=False))
+    idx = np.sort(np.random.default_rng(123).choice(w.n_rec, size=w.n_rec // 100, replace=False))  # 1 %
     ref = O.records_for(w, idx)
-    assert_parity(v[idx], g[idx], h[idx], ref, "C2 sample")
+    assert_parity(v[idx], g[idx], h[idx], ref, "C2 1% sample")
     assert np.all(np.isfinite(v)) and np.all(np.isfinite(g)) and np.all(np.isfinite(h))
 
 
