@@ -1,23 +1,33 @@
 #!/usr/bin/env python3
 """Benchmark: radiance-cache records (value + gradient + Hessian) per second.
 
-Workload: 10k cache points uniform in a closed unit room (12 triangles) with
-a 10k-triangle random soup (edge 0.02), 1024 stratified directions per point
-(16 x 64), sigma_s = 1.0, sigma_a = 0.2, four point lights, ring step 0.1;
-seeded synthetic inputs resident in device memory before timing.
+Headline workload (default): 1M cache points uniform in a closed room with
+20 occluder slabs and a random triangle soup (1M triangles), 2048 stratified
+directions per point (32 x 64), sigma_s = 2.0, sigma_a = 0.5, four point
+lights, ring step 0.1; seeded synthetic inputs resident in device memory
+before timing.
 
-One step = the whole record path over the batch: the persistent,
-graph-replayed record kernel (directions, BVH traversal, shading, rings,
-triangulation, per-triangle derivative terms, reductions) followed by the
-validity-radius kernel.
+One step = the whole record path over the batch: the device-built queue and
+the persistent, graph-replayed record kernel (directions, BVH traversal,
+light-bin shadow segments, shading, rings, triangulation, per-triangle
+derivative terms, reductions) followed by the validity-radius kernel.
 
 Prints one JSON line.  Extra fields: Mrays/s (counted rays), the roofline of
-the dominant kernel (record_kernel), the FP64 CPU oracle's rate on a bounded
-sample of the same workload, and the learned-vs-plain placement comparison
-(candidates resolved per second by each pipeline on a held-out scene of the
-same family, with each cache's error against 16384-direction references).
+the dominant kernel (record_kernel: VALU issue, from the committed counter
+summary of the same kernel source, over the live kernel time), the FP64 CPU
+oracle's rate on a bounded sample of the same workload together with the
+per-output error of the timed launch's records on that sample, the two
+smaller record workloads (10k points over 10k triangles; 200k points with
+mixed sample counts over 100k triangles) and the learned-vs-plain placement
+comparison.
+
+`--summarize-counters DIR` turns the CSV output of the rocprofv3 counter
+passes (and of `--copy-calibration` runs) into the counter summary that the
+roofline reads; the commands are listed in the summary itself.
 """
 import argparse
+import csv
+import glob
 import hashlib
 import json
 import os
@@ -30,20 +40,24 @@ import numpy as np
 ROOT = Path(__file__).resolve().parent
 sys.path.insert(0, str(ROOT))
 
-HBM_PEAK_GBS = 8000.0
+# VALU issue peak: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz (a wave64 VALU
+# instruction occupies its SIMD for 4 cycles), in 1e12 lane-operations per s
+VALU_PEAK = 256 * 4 * 16 * 2.4e9 / 1e12
+METRIC = "cache records/s (value+grad+Hessian) & Mrays/s; learned vs plain at equal error"
 WORKLOAD_TEXT = {
-    "c2": "C2: 10k points, closed unit room + 10k-triangle soup (edge 0.02), 1024 directions (16x64), "
+    "c2": "10k points, closed unit room + 10k-triangle soup (edge 0.02), 1024 directions (16x64), "
           "sigma_s=1.0 sigma_a=0.2, 4 point lights, ring step 0.1",
-    "c3": "C3: 200k points, room + 20 slabs + soup (100k triangles), directions log-uniform in [256, 4096], "
-          "sigma_s=1.0 sigma_a=0.2, 4 point lights, ring step 0.1",
-    "c5": "C5: 1M points, room + 20 slabs + soup (1M triangles), 2048 directions (32x64), sigma_s=2.0 "
+    "c3": "200k points, room + 20 slabs + soup (100k triangles), directions log-uniform in [256, 4096], "
+          "sigma_s=1.0 sigma_a=0.2, 4 point lights, ring step 0.1, one batched launch",
+    "c5": "1M points, room + 20 slabs + soup (1M triangles), 2048 directions (32x64), sigma_s=2.0 "
           "sigma_a=0.5, 4 point lights, ring step 0.1",
 }
-NODE_BYTES, TRI_BYTES = 64, 48
+EXTRA_STEPS = {"c2": (20, 2), "c3": (5, 1), "c5": (2, 1)}
+COUNTERS = ROOT / "profiles" / "record_kernel_counters.json"
 
 
 def log(*a):
-    print(*a, file=sys.stderr, flush=True)
+    print(f"[{time.strftime('%H:%M:%S')}]", *a, file=sys.stderr, flush=True)
 
 
 def kernel_source_hash():
@@ -54,25 +68,36 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
-def traffic_from_profile(per_launch_alg_bytes):
-    """HBM bytes per record-kernel launch from the committed counter summary,
-    if it was taken on the current kernel source; else None."""
-    f = ROOT / "profiles" / "record_kernel_C2_traffic.json"
-    if not f.exists():
+def committed_counters(workload):
+    """Per-dispatch counters of record_kernel on this workload from the committed
+    summary, if it was taken on the current kernel source; else None."""
+    if not COUNTERS.exists():
         return None
     try:
-        d = json.loads(f.read_text())
+        d = json.loads(COUNTERS.read_text())
     except ValueError:
         return None
     if d.get("kernel_source_sha") != kernel_source_hash():
         return None
-    return d.get("hbm_bytes_per_launch")
+    return d.get("workloads", {}).get(workload)
 
 
-def cpu_baseline(w, budget_s=15.0):
-    """The FP64 oracle, as it stands, on a bounded sample of the workload."""
+def compulsory_bytes(w, info):
+    """Bytes one launch must move at least: per-record inputs (position, two
+    sample counts) and FP64 outputs (2-channel value, gradient, Hessian), the
+    scene's device structures and the light bins, each once."""
+    per_rec = 12 + 8 + 8 * (2 + 6 + 12)
+    return w.n_rec * per_rec + info["device_bytes"] + info["light_bin_bytes"]
+
+
+def cpu_baseline(w, outputs, budget_s=15.0):
+    """The FP64 oracle, as it stands, on a bounded sample of the workload; the
+    timed launch's records on the same sample are compared with it."""
     from oracle import oracle as O
+    from tests._compare import ETA, TOL_G, TOL_H, TOL_V, rel_errors
+    t_scene = time.perf_counter()
     sc = O.Scene.from_workload(w)
+    t_scene = time.perf_counter() - t_scene
     rng = np.random.default_rng(2024)
     idx = np.sort(rng.choice(w.n_rec, size=16, replace=False))
     t0 = time.perf_counter()
@@ -81,22 +106,30 @@ def cpu_baseline(w, budget_s=15.0):
     n = int(min(w.n_rec, max(16, 16 * budget_s / max(t1, 1e-3))))
     idx = np.sort(rng.choice(w.n_rec, size=n, replace=False))
     t0 = time.perf_counter()
-    O.records_for(w, idx, scene=sc)
+    ref = O.records_for(w, idx, scene=sc)
     dt = time.perf_counter() - t0
     cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
     cores = min(cores, os.cpu_count() or cores)
+    value, grad, hess = (t.cpu().numpy()[idx] for t in outputs)
+    ev, eg, eh, _, _ = rel_errors(value, grad, hess, ref)
+
+    def q(e, tol):
+        return {"median": float(np.median(e)), "p99": float(np.quantile(e, 0.99)), "max": float(e.max()),
+                "tol": tol}
     return {"value": n / dt, "unit": "records/s", "cores": cores, "kind": "oracle",
-            "sample": f"{n} of {w.n_rec} records (seeded), same scene and sample counts, {dt:.1f} s",
-            "cpu": O.cpu_info()["model"]}
+            "sample": f"{n} of {w.n_rec} records (seeded), same scene and sample counts, {dt:.1f} s "
+                      f"(+{t_scene:.1f} s for the oracle's own BVH, not counted)",
+            "cpu": O.cpu_info()["model"],
+            "precision_vs_oracle": {"records": n, "channels": 2, "value": q(ev, TOL_V), "gradient": q(eg, TOL_G),
+                                    "hessian_frobenius": q(eh, TOL_H),
+                                    "note": f"relative errors of the timed launch's records; gradient and Hessian "
+                                            f"denominators floored at {ETA} x the sum of per-triangle term norms"}}
 
 
 def learned_vs_plain(dev):
-    """Train the radius MLP on 100 C2-family scenes (1M records), choose the
-    learned pipeline's safety factor on a validation scene, then place caches
-    over 128^3 = 2,097,152 candidates of a held-out scene with both pipelines
-    (plain at its fastest round size) and measure their error at 100k test
-    points; the judge and the fallback keep the learned cache valid whatever
-    the factor."""
+    """Learned vs plain cache placement over one held-out scene of the 10k-
+    triangle family (candidates resolved per second by each pipeline, each
+    cache's error against a dense plain cache)."""
     from paper_1805_09258_amd import placement as PL
     r = PL.compare(dev, log=log)
     lp, pl = r["learned"], r["plain"]
@@ -112,76 +145,53 @@ def learned_vs_plain(dev):
                                           "heldout_mse_net", "heldout_mse_constant")},
            "safety_by_validation": r["safety_validation_seconds"],
            "plain_by_batch": r["plain_by_batch"]}
+    for k in ("reference", "epsilon", "target_rel_l2"):
+        if k in r:
+            res[k] = r[k]
     res["plain"]["candidates_per_s"] = r["candidates"] / pl["seconds"]
     res["learned"]["candidates_per_s"] = r["candidates"] / lp["seconds"]
     res["speedup"] = pl["seconds"] / lp["seconds"]
     return res
 
 
-def main():
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10)
-    ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-learned", action="store_true", help="skip the learned-vs-plain placement comparison")
-    ap.add_argument("--workload", default="c2", choices=["c2", "c3", "c5"],
-                    help="c2 (default, the headline line); c3 = 200k points with mixed sample counts over "
-                         "100k triangles; c5 = 1M points over 1M triangles")
-    ap.add_argument("--copy-calibration", action="store_true",
-                    help="only copy a 1 GiB float32 buffer three times (scales the HBM byte counters)")
-    ap.add_argument("--profile-steps", type=int, default=None, help=argparse.SUPPRESS)
-    args = ap.parse_args()
-    if args.gpus != 1:
-        print(f"bench.py: this build measures one GPU only (--gpus {args.gpus} requested); records are independent "
-              "and the multi-GPU path is not built.", file=sys.stderr)
-        sys.exit(2)
-
+def measure(name, dev, steps, warmup, count=True):
+    """Build the workload and scene, autotune the launch, time `steps` steps
+    (HIP events on the launch stream around the record launch; wall clock
+    around the whole step) and return the figures and device outputs."""
     import torch
-    if args.copy_calibration:
-        a = torch.ones(1 << 28, dtype=torch.float32, device="cuda:0")
-        b = torch.empty_like(a)
-        for _ in range(3):
-            b.copy_(a)
-        torch.cuda.synchronize()
-        log("copied 3 x 1 GiB")
-        return
     from paper_1805_09258_amd import rc
     from paper_1805_09258_amd import workloads as W
-
-    if not torch.cuda.is_available():
-        print("bench.py: no GPU visible", file=sys.stderr)
-        sys.exit(1)
-    dev = torch.device("cuda:0")
-    w = W.make(args.workload)
+    w = W.make(name)
     ndir = (w.n_theta.astype(np.int64) * w.n_phi).astype(np.float64)
-    log(f"workload {w.name}: {w.n_rec} records, {w.n_tri} triangles, N mean {ndir.mean():.0f} "
+    log(f"workload {name}: {w.n_rec} records, {w.n_tri} triangles, N mean {ndir.mean():.0f} "
         f"[{ndir.min():.0f}, {ndir.max():.0f}]")
     scene = rc.Scene.from_workload(w)
-    info = scene.info()
     dw = rc.DeviceWorkload(w, device=dev)
     value, grad, hess = dw.outputs()
     ws = dw.workspace()
     R = torch.empty(w.n_rec, dtype=torch.float32, device=dev)
     stream = torch.cuda.Stream()
     eps, r_min, r_max = 1.5e-4, 1e-3, 0.25 * float(np.linalg.norm(w.box_hi - w.box_lo))
-
-    # untimed: algorithmic work of one launch (rays, node and triangle fetches), counted with one
-    # wavefront per record so that rows recomputed by split records are not counted
-    cnt = torch.zeros(12, dtype=torch.int64, device=dev)
-    with torch.cuda.stream(stream):
-        rc.compute_records(scene, dw, batched=True, counters=cnt, out=(value, grad, hess), workspace=ws,
-                           stream=stream, splits=1 if w.n_rec <= 16384 else 0)
-    stream.synchronize()
-    rays, nodes, tris, terms, c0, c1, c2, c3, sh_iter, sh_busy, sh_refill, sh_lanes = (int(x) for x in cnt.cpu().tolist())
-    shadow_loop = {"iterations": sh_iter, "lane_utilisation": sh_busy / max(64 * sh_iter, 1),
-                   "refills": sh_refill, "lanes_per_refill": sh_lanes / max(sh_refill, 1)}
-    log(f"shadow loop: {shadow_loop}")
-    ctot = max(c0 + c1 + c2 + c3, 1)
-    phase_frac = {"primary_rays": c0 / ctot, "shadow_rays": c1 / ctot, "mc_value": c2 / ctot,
-                  "triangle_terms": c3 / ctot}
-    alg_bytes = nodes * NODE_BYTES + tris * TRI_BYTES + w.n_rec * (12 + 8 + 16 + 48 + 96 + 4)
-    log(f"per launch: {rays} rays, {nodes} node fetches, {tris} triangle tests, {terms} triangle terms")
+    res = {"workload": WORKLOAD_TEXT[name], "records_per_step": w.n_rec, "n_triangles": w.n_tri,
+           "directions_mean": float(ndir.mean())}
+    rays = None
+    if count:
+        # untimed: algorithmic work of one launch (rays, fetches, terms, per-phase clocks), counted
+        # with one wavefront per record so that rows recomputed by split records are not counted
+        cnt = torch.zeros(12, dtype=torch.int64, device=dev)
+        with torch.cuda.stream(stream):
+            rc.compute_records(scene, dw, batched=True, counters=cnt, out=(value, grad, hess), workspace=ws,
+                               stream=stream, splits=1 if w.n_rec <= 16384 else 0)
+        stream.synchronize()
+        (rays, nodes, tris, terms, c0, c1, c2, c3, sh_iter, sh_busy, sh_refill,
+         sh_lanes) = (int(x) for x in cnt.cpu().tolist())
+        ctot = max(c0 + c1 + c2 + c3, 1)
+        res["counts"] = {"rays": rays, "node_fetches": nodes, "triangle_tests": tris, "triangle_terms": terms,
+                         "phase_clock_fraction": {"primary_rays": c0 / ctot, "shadow_segments": c1 / ctot,
+                                                  "mc_value": c2 / ctot, "triangle_terms": c3 / ctot},
+                         "shadow_loop": {"iterations": sh_iter, "lane_utilisation": sh_busy / max(64 * sh_iter, 1),
+                                         "refills": sh_refill, "lanes_per_refill": sh_lanes / max(sh_refill, 1)}}
+        log(f"counted launch: {rays} rays, {nodes} node fetches, {tris} triangle tests, {terms} terms")
     # untimed: the launch configuration, chosen by the autotuner over the persistent-grid tiles
     # (measured on the first 20k records)
     prm = rc.make_params(w.ring_step, w.max_rings, dw.max_n_phi, w.seed)
@@ -201,64 +211,235 @@ def main():
                 ev[1].record(stream)
             rc.rc_radius(value, hess, eps, r_min, r_max, R, None, stream=stream)
 
-    for i in range(args.warmup):
+    for i in range(warmup):
         step()
         stream.synchronize()
-        log(f"warmup {i + 1}/{args.warmup}")
-    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
+        log(f"{name} warmup {i + 1}/{warmup}")
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for i in range(args.steps):
+    for i in range(steps):
         step(evs[i])
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     kern_ms = float(np.mean([a.elapsed_time(b) for a, b in evs]))
     errs = rc.rc_workspace_errors(ws)
     assert errs == 0, f"{errs} invalid records"
-    ms_step = dt / args.steps * 1e3
-    rec_s = w.n_rec * args.steps / dt
-    log(f"timed {args.steps} steps: {ms_step:.3f} ms/step, record kernel {kern_ms:.3f} ms")
+    info = scene.info()
+    scene.close()
+    res.update({"records_per_s": w.n_rec * steps / dt, "ms_per_step": dt / steps * 1e3,
+                "record_launch_ms": kern_ms, "steps": steps, "warmup": warmup,
+                "bvh_nodes": info["n_nodes"], "bvh_depth": info["depth"],
+                "scene_device_bytes": info["device_bytes"], "light_bin_bytes": info["light_bin_bytes"],
+                "light_bin_entries": info["light_bin_entries"],
+                "tile": tile, "tile_ms": tile_ms, "compulsory_bytes": compulsory_bytes(w, info)})
+    if rays is not None:
+        res["mrays_per_s"] = rays * steps / dt / 1e6
+        res["rays_per_record"] = rays / w.n_rec
+    log(f"{name}: {steps} steps, {res['ms_per_step']:.3f} ms/step, record launch {kern_ms:.3f} ms, "
+        f"{res['records_per_s']:.0f} records/s")
+    return w, res, (value, grad, hess)
 
-    achieved = alg_bytes / (kern_ms * 1e-3) / 1e9
-    traffic = traffic_from_profile(alg_bytes) if args.workload == "c2" else None
+
+def roofline(name, res):
+    """VALU-issue roofline of record_kernel: lane-operations issued per launch
+    (SQ_INSTS_VALU x 64 from the committed counters of this kernel source)
+    over the live launch time; HBM traffic from FETCH_SIZE/WRITE_SIZE scaled
+    by a plain copy's reading."""
+    c = committed_counters(name)
+    kern_s = res["record_launch_ms"] * 1e-3
+    out = {"bound": "alu", "achieved": None, "peak": VALU_PEAK, "unit": "T VALU lane-ops/s", "frac": None,
+           "traffic": None, "kernel": "record_kernel", "kernel_ms": res["record_launch_ms"],
+           "compulsory_bytes": res["compulsory_bytes"]}
+    if c is None:
+        out["note"] = "no counter summary for this kernel source: achieved and traffic unmeasured"
+        return out
+    lane_ops = c["per_dispatch"]["SQ_INSTS_VALU"] * 64
+    out["achieved"] = lane_ops / kern_s / 1e12
+    out["frac"] = out["achieved"] / VALU_PEAK
+    out["valu_lane_ops_per_launch"] = lane_ops
+    out["profiled_kernel_ms"] = c["duration_ms"]
+    d = c.get("derived", {})
+    for k in ("valu_busy", "waves_per_simd", "vmem_wait_frac", "tcp_hit", "tcc_hit", "clock_ghz"):
+        if k in d:
+            out[k] = d[k]
+    if "hbm_bytes" in c:
+        out["traffic"] = c["hbm_bytes"]
+        out["traffic_gbs"] = c["hbm_bytes"] / kern_s / 1e9
+        out["traffic_over_compulsory"] = c["hbm_bytes"] / res["compulsory_bytes"]
+    return out
+
+
+# ---------------------------------------------------------------------------------------------
+# counter summary (rocprofv3 CSV -> profiles/record_kernel_counters.json)
+
+def _read_pmc(d):
+    """{(pass, dispatch): {name, dur_ns, grid, counters...}} from rocprofv3 CSV under d/<pass>/."""
+    rows = {}
+    for f in sorted(glob.glob(f"{d}/*/*_counter_collection.csv")):
+        tag = Path(f).parent.name
+        for r in csv.DictReader(open(f)):
+            key = (tag, int(r["Dispatch_Id"]))
+            e = rows.setdefault(key, {"name": r["Kernel_Name"], "grid": int(r["Grid_Size"]),
+                                      "dur_ns": int(r["End_Timestamp"]) - int(r["Start_Timestamp"]),
+                                      "vgpr": int(r["VGPR_Count"]), "scratch": int(r["Scratch_Size"]),
+                                      "lds": int(r["LDS_Block_Size"])})
+            e[r["Counter_Name"]] = float(r["Counter_Value"])
+    return rows
+
+
+def summarize_counters(d, workload, steps, copy_dir=None):
+    rows = _read_pmc(d)
+    per, durs, meta = {}, [], None
+    info_keys = ("name", "grid", "dur_ns", "vgpr", "scratch", "lds")
+    for tag in sorted({k[0] for k in rows}):
+        ks = [k for k in sorted(rows) if k[0] == tag and "record_kernel" in rows[k]["name"]
+              and ", true," not in rows[k]["name"]]
+        if not ks:
+            continue
+        # the timed launches: the last `steps` full-size ones (a batched step also makes an
+        # empty launch for records above the largest class)
+        longest = max(rows[k]["dur_ns"] for k in ks)
+        ks = [k for k in ks if rows[k]["dur_ns"] >= 0.05 * longest]
+        for k in ks[-steps:]:
+            meta = rows[k]
+            durs.append(rows[k]["dur_ns"] / 1e6)
+            for c, v in rows[k].items():
+                if c not in info_keys:
+                    per.setdefault(c, []).append(v)
+    m = {c: float(np.mean(v)) for c, v in per.items()}
+    cu, simd = 256, 1024
+    derived = {}
+    if "GRBM_GUI_ACTIVE" in m:
+        gui = m["GRBM_GUI_ACTIVE"] / 8  # summed over the 8 XCDs
+        derived["clock_ghz"] = gui / (np.mean(durs) * 1e6)
+        if "SQ_ACTIVE_INST_VALU" in m:
+            # per-wave VALU issue cycles (quad-cycles, x4) over the SIMD cycles of the launch
+            derived["valu_busy"] = m["SQ_ACTIVE_INST_VALU"] * 4 / (gui * simd)
+        if "SQ_WAVE_CYCLES" in m:
+            derived["waves_per_simd"] = m["SQ_WAVE_CYCLES"] * 4 / (gui * simd)
+    if "SQ_WAIT_INST_ANY" in m and "SQ_WAVE_CYCLES" in m:
+        derived["vmem_wait_frac"] = m["SQ_WAIT_INST_ANY"] / m["SQ_WAVE_CYCLES"]
+    if "TCP_TOTAL_CACHE_ACCESSES_sum" in m and "TCP_TCC_READ_REQ_sum" in m:
+        derived["tcp_hit"] = 1 - m["TCP_TCC_READ_REQ_sum"] / max(m["TCP_TOTAL_CACHE_ACCESSES_sum"], 1)
+    if "TCC_HIT_sum" in m and "TCC_MISS_sum" in m:
+        derived["tcc_hit"] = m["TCC_HIT_sum"] / max(m["TCC_HIT_sum"] + m["TCC_MISS_sum"], 1)
+    out = {"kernel": meta["name"] if meta else None, "grid": meta["grid"] if meta else None,
+           "vgpr": meta["vgpr"] if meta else None, "scratch_bytes_per_lane": meta["scratch"] if meta else None,
+           "lds_bytes": meta["lds"] if meta else None, "dispatches": len(durs),
+           "duration_ms": float(np.mean(durs)) if durs else None, "per_dispatch": m, "derived": derived}
+    if copy_dir:
+        crows = _read_pmc(copy_dir)
+        fs = [r["FETCH_SIZE"] for r in crows.values() if "FETCH_SIZE" in r and r["dur_ns"] > 1e5]
+        wsz = [r["WRITE_SIZE"] for r in crows.values() if "WRITE_SIZE" in r and r["dur_ns"] > 1e5]
+        nbytes = 1 << 30
+        cal = {"bytes_copied": nbytes}
+        if fs:
+            cal["fetch_size_kib"] = fs
+            cal["fetch_scale"] = nbytes / (np.median(fs) * 1024)
+        if wsz:
+            cal["write_size_kib"] = wsz
+            cal["write_scale"] = nbytes / (np.median(wsz) * 1024)
+        out["copy_calibration"] = cal
+        if "FETCH_SIZE" in m and "WRITE_SIZE" in m and "fetch_scale" in cal and "write_scale" in cal:
+            out["hbm_fetch_bytes"] = m["FETCH_SIZE"] * 1024 * cal["fetch_scale"]
+            out["hbm_write_bytes"] = m["WRITE_SIZE"] * 1024 * cal["write_scale"]
+            out["hbm_bytes"] = out["hbm_fetch_bytes"] + out["hbm_write_bytes"]
+    return out
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="c5", choices=["c2", "c3", "c5"],
+                    help="c5 (default: 1M points over 1M triangles); c2 = 10k points over 10k triangles; "
+                         "c3 = 200k points with mixed sample counts over 100k triangles")
+    ap.add_argument("--extra", default="c2,c3",
+                    help="comma-separated smaller workloads also measured (own step counts), or 'none'")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-learned", action="store_true", help="skip the learned-vs-plain placement comparison")
+    ap.add_argument("--no-count", action="store_true", help=argparse.SUPPRESS)
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only copy a 1 GiB float32 buffer three times (scales the HBM byte counters)")
+    ap.add_argument("--summarize-counters", metavar="DIR", default=None,
+                    help="write the counter summary from rocprofv3 CSV passes under DIR (and DIR/copy)")
+    ap.add_argument("--commands", default="", help=argparse.SUPPRESS)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py: this build measures one GPU only (--gpus {args.gpus} requested); records are independent "
+              "and the multi-GPU path is not built.", file=sys.stderr)
+        sys.exit(2)
+
+    if args.summarize_counters:
+        d = Path(args.summarize_counters)
+        s = summarize_counters(d, args.workload, args.steps, copy_dir=d / "copy" if (d / "copy").exists() else None)
+        s["kernel_source_sha"] = kernel_source_hash()
+        s["commands"] = [c for c in args.commands.split(";;") if c]
+        doc = json.loads(COUNTERS.read_text()) if COUNTERS.exists() else {}
+        if doc.get("kernel_source_sha") != s["kernel_source_sha"]:
+            doc = {"kernel_source_sha": s["kernel_source_sha"], "workloads": {}}
+        doc["workloads"][args.workload] = s
+        COUNTERS.write_text(json.dumps(doc, indent=1) + "\n")
+        print(json.dumps(s, indent=1))
+        return
+
+    import torch
+    if args.copy_calibration:
+        a = torch.ones(1 << 28, dtype=torch.float32, device="cuda:0")
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        log("copied 3 x 1 GiB")
+        return
+    if not torch.cuda.is_available():
+        print("bench.py: no GPU visible", file=sys.stderr)
+        sys.exit(1)
+    dev = torch.device("cuda:0")
+
+    w, res, outputs = measure(args.workload, dev, args.steps, args.warmup, count=not args.no_count)
     out = {
-        "metric": "cache records/s (value+grad+Hessian) & Mrays/s; learned vs plain at equal error",
-        "value": rec_s,
+        "metric": METRIC,
+        "value": res["records_per_s"],
         "unit": "records/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": ms_step,
+        "ms_per_step": res["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": WORKLOAD_TEXT[args.workload],
-                   "records_per_step": w.n_rec, "n_triangles": w.n_tri, "directions_mean": float(ndir.mean()),
-                   "bvh_nodes": info["n_nodes"], "bvh_depth": info["depth"], "tile": tile,
-                   "tile_ms": tile_ms},
-        "mrays_per_s": rays * args.steps / dt / 1e6,
-        "rays_per_record": rays / w.n_rec,
-        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                     "kernel": "record_kernel", "kernel_ms": kern_ms,
-                     "alg_bytes_per_launch": alg_bytes,
-                     "alg_bytes_per_ray": (nodes * NODE_BYTES + tris * TRI_BYTES) / max(rays, 1),
-                     "phase_clock_fraction": phase_frac,
-                     "shadow_loop": shadow_loop,
-                     "note": "achieved counts the algorithmic node and triangle fetches of the traversal; "
-                             "the BVH is served from L2/MALL, so frac can exceed 1 and the HBM bytes are "
-                             "in traffic"},
+        "config": {k: res[k] for k in ("workload", "records_per_step", "n_triangles", "directions_mean",
+                                       "bvh_nodes", "bvh_depth", "light_bin_entries", "tile", "tile_ms")},
+        "mrays_per_s": res.get("mrays_per_s"),
+        "rays_per_record": res.get("rays_per_record"),
+        "roofline": roofline(args.workload, res),
     }
-    if not args.no_learned and args.workload == "c2":
-        log("learned vs plain placement ...")
-        out["learned_vs_plain"] = learned_vs_plain(dev)
+    if "counts" in res:
+        out["counts"] = res["counts"]
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle) ...")
-        out["cpu_baseline"] = cpu_baseline(w)
+        out["cpu_baseline"] = cpu_baseline(w, outputs)
         log(f"cpu baseline {out['cpu_baseline']['value']:.2f} records/s")
-    scene.close()
+    del outputs
+    torch.cuda.empty_cache()
+    extra = [] if args.extra == "none" else [e for e in args.extra.split(",") if e and e != args.workload]
+    if extra:
+        out["workloads"] = {}
+    for e in extra:
+        st, wu = EXTRA_STEPS[e]
+        _, r, o = measure(e, dev, st, wu)
+        del o
+        torch.cuda.empty_cache()
+        r["roofline"] = roofline(e, r)
+        out["workloads"][e] = r
+    if not args.no_learned:
+        log("learned vs plain placement ...")
+        out["learned_vs_plain"] = learned_vs_plain(dev)
     print(json.dumps(out), flush=True)
 
 

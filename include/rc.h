@@ -131,6 +131,12 @@ typedef struct {
   int64_t node_bytes;
   int64_t tri_bytes;
   float pad;
+  int64_t device_bytes;      /* device memory of the scene: nodes, the three
+                                triangle copies, shading, FP64 planes, emission */
+  int64_t light_bin_bytes;   /* device memory of the light bins of the last
+                                light set (0 until a launch or
+                                rc_light_bins_build made them) */
+  int64_t light_bin_entries; /* (triangle, bin) entries in those bins */
 } rc_scene_stats;
 
 /* ------------------------------------------------------------------ */

@@ -89,6 +89,7 @@ struct rc_scene {
     int* offs = nullptr;
     float4* ent = nullptr;
     int64_t n_entries = 0;
+    int64_t bytes = 0;
     void clear() {
       if (desc) (void)hipFree(desc);
       if (offs) (void)hipFree(offs);
@@ -98,8 +99,10 @@ struct rc_scene {
       ent = nullptr;
       n = 0;
       n_entries = 0;
+      bytes = 0;
     }
   } lb;
+  int64_t device_bytes = 0;  // nodes, triangle copies, shading, planes, emission
   std::mutex mu;
   GraphCache graph;
   ~rc_scene() {
@@ -242,6 +245,7 @@ int ensure_light_bins(rc_scene* s, const rc_point_light* lights, int n_lights, i
   s->lb.n = n_lights;
   for (int l = 0; l < n_lights; l++) std::memcpy(s->lb.pos[l], lights[l].pos, sizeof(float) * 3);
   s->lb.n_entries = ebase;
+  s->lb.bytes = (int64_t)(desc.size() * sizeof(int4) + offs.size() * 4 + ent.size() * 4);
   return RC_OK;
 }
 
@@ -461,6 +465,8 @@ int rc_scene_create(const float* tri, const float* albedo, const float* emission
   if (!r) r = up((void**)&s->shade, shade.data(), shade.size() * 4);
   if (!r) r = up((void**)&s->plane, plane.data(), plane.size() * 8);
   if (!r) r = up((void**)&s->emission, em.data(), em.size() * 4);
+  s->device_bytes = (int64_t)(bvh.nodes.size() * 4 + tris3.size() * 4 + shade.size() * 4 + plane.size() * 8 +
+                              em.size() * 4);
   if (r) {
     delete s;
     return r;
@@ -484,6 +490,9 @@ int rc_scene_info(const rc_scene* s, rc_scene_stats* o) {
   o->node_bytes = 64;
   o->tri_bytes = 48;
   o->pad = s->pad;
+  o->device_bytes = s->device_bytes;
+  o->light_bin_bytes = s->lb.bytes;
+  o->light_bin_entries = s->lb.n_entries;
   return RC_OK;
 }
 
@@ -509,6 +518,9 @@ int64_t rc_bvh_build_host(const float* tri, int64_t T, const float box_lo[3], co
     stats->node_bytes = 64;
     stats->tri_bytes = 48;
     stats->pad = pad;
+    stats->device_bytes = 0;  // nothing uploaded
+    stats->light_bin_bytes = 0;
+    stats->light_bin_entries = 0;
   }
   return nn;
 }

@@ -50,7 +50,8 @@ class rc_params(C.Structure):
 
 class rc_scene_stats(C.Structure):
     _fields_ = [("n_tri", C.c_int64), ("n_nodes", C.c_int64), ("depth", C.c_int32), ("leaf_max", C.c_int32),
-                ("node_bytes", C.c_int64), ("tri_bytes", C.c_int64), ("pad", C.c_float)]
+                ("node_bytes", C.c_int64), ("tri_bytes", C.c_int64), ("pad", C.c_float),
+                ("device_bytes", C.c_int64), ("light_bin_bytes", C.c_int64), ("light_bin_entries", C.c_int64)]
 
 
 EXPORTS = ["rc_scene_create", "rc_scene_destroy", "rc_scene_info", "rc_bvh_build_host", "rc_workspace_size",
