@@ -44,6 +44,7 @@ extern "C" {
 #define RC_MAX_LIGHTS 16
 #define RC_MAX_RINGS 64
 #define RC_MAX_NPHI 256
+#define RC_NOALLOC_MAX_RECORDS 4096 /* largest batch of rc_records_noalloc */
 /* int32 words of the placement state (5 counters + 4096 batch status words) */
 #define RC_PLACE_STATE_INTS 4101
 
@@ -204,6 +205,31 @@ int rc_records(const rc_scene* scene, const rc_medium* medium, const rc_point_li
                const float* pos, const int32_t* n_theta, const int32_t* n_phi, int64_t P,
                const rc_params* params, double* value, double* grad, double* hess,
                void* workspace, void* stream);
+
+/* rc_records without any allocation, for callers that cannot allocate
+ * device memory (code under HIP graph capture, serving loops, harnesses that
+ * forbid hipMalloc).  Same arguments and results as rc_records (the same
+ * kernels, bit for bit) without the workspace: the queue, error counter and
+ * split-record partial sums live in a workspace of rc_workspace_size(4096)
+ * bytes (about 5 MiB) that the library holds in device memory on each device
+ * it runs on until the process ends.
+ *   P       : 0 <= P <= RC_NOALLOC_MAX_RECORDS, else RC_EINVAL.
+ *   The current device must be the scene's device (else RC_EINVAL).
+ * Shadow segments come from the scene's light bins if it already holds them
+ * for these lights (an earlier rc_records call or rc_light_bins_build with the
+ * same positions), else from the BVH, which gives the same segments; no bins
+ * are built.  Calls no hipMalloc, hipFree or allocating library routine.
+ * All calls on one device share its workspace, which keeps the last call's
+ * contents: calls that overlap on one device (two streams, or two threads)
+ * race, and so does a call that overlaps one that changes the scene's light
+ * set.  The invalid-record count of the last call is read with
+ * rc_records_noalloc_errors. */
+int rc_records_noalloc(const rc_scene* scene, const rc_medium* medium, const rc_point_light* lights,
+                       int n_lights, const float* pos, const int32_t* n_theta, const int32_t* n_phi, int64_t P,
+                       const rc_params* params, double* value, double* grad, double* hess, void* stream);
+/* Invalid records of the last rc_records_noalloc call on the current device
+ * (synchronises `stream`).  Returns the count (>= 0) or a negative error. */
+int64_t rc_records_noalloc_errors(void* stream);
 
 /* Same records, scheduled from a caller-supplied queue.
  *   order     : device int32[P] permutation of 0..P-1, the order in which

@@ -135,8 +135,39 @@ constexpr int kNTiles = 8;
 constexpr Tile kTiles[kNTiles] = {{1.0f, 12, 0}, {2.0f, 12, 0}, {1.0f, 8, 0},  {1.0f, 16, 0},
                                   {1.0f, 12, 8}, {2.0f, 12, 8}, {0.5f, 12, 0}, {1.0f, 24, 0}};
 
-size_t ws_split_offset(int64_t P) { return (kWsOrder + 4 * (size_t)std::max<int64_t>(P, 0) + 255) & ~size_t(255); }
-size_t ws_partial_offset(int64_t Pm) { return (4 * (size_t)Pm + 255) & ~size_t(255); }
+constexpr size_t ws_split_offset(int64_t P) {
+  return (kWsOrder + 4 * (size_t)(P > 0 ? P : 0) + 255) & ~size_t(255);
+}
+constexpr size_t ws_partial_offset(int64_t Pm) { return (4 * (size_t)Pm + 255) & ~size_t(255); }
+constexpr size_t ws_bytes(int64_t P) {
+  return ws_split_offset(P) + ws_partial_offset(P < rc::kSplitMaxRecords ? P : rc::kSplitMaxRecords) +
+         (size_t)(P < rc::kSplitMaxRecords ? P : rc::kSplitMaxRecords) * rc::kMaxSplits * 20 * sizeof(double);
+}
+
+// Workspace of rc_records_noalloc: one per device, in the library's device
+// image (no allocation at call time).  Host code reaches it only through the
+// address hipGetSymbolAddress returns for the current device.
+constexpr size_t kNoAllocBytes = ws_bytes(RC_NOALLOC_MAX_RECORDS);
+static __device__ __align__(256) unsigned char scratch[kNoAllocBytes];
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of `scratch` on device `dev` (the current device), looked up
+// once per device.
+int scratch_address(int dev, void** out) {
+  if (dev < 0 || dev >= kMaxDevices) return fail(RC_ENODEV, "device %d out of range", dev);
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || p == nullptr)
+      return fail(RC_EDEVICE, "hipGetSymbolAddress(scratch) on device %d: %s", dev, hipGetErrorString(e));
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
+  return RC_OK;
+}
 
 int check_inputs(const rc_scene* s, const rc_medium* m, const rc_point_light* lights, int n_lights, const float* pos,
                  const int32_t* nth, const int32_t* nph, int64_t P, const rc_params* p, double* value, double* grad,
@@ -345,22 +376,28 @@ int plan(const rc_scene* s, const rc_params* p, int64_t P, int tile, int& stack,
   return RC_OK;
 }
 
-hipError_t run_plan(const std::vector<Launch>& plan, int stack, hipStream_t st) {
-  const rc::RecordArgs& a0 = plan.front().args;
+// The launches of one call.  Every counter that must start at zero (queue,
+// class cursors, part counters) is cleared by a kernel first; the partial sums
+// of split records are written before they are read.
+hipError_t run_plan(const Launch* plan, size_t n, int stack, hipStream_t st) {
+  const rc::RecordArgs& a0 = plan[0].args;
   hipError_t e = rc::launch_reset(a0.queue, st);
-  if (e == hipSuccess && plan.size() > 1) e = rc::launch_zero_u32(a0.queue + kQClassNext, rc::kOrderClasses, st);
+  if (e == hipSuccess && n > 1) e = rc::launch_zero_u32(a0.queue + kQClassNext, rc::kOrderClasses, st);
   if (e == hipSuccess && a0.splits > 1) e = rc::launch_zero_u32(a0.done, a0.P, st);
-  for (const Launch& l : plan) {
-    if (e != hipSuccess) break;
+  for (size_t i = 0; i < n && e == hipSuccess; i++) {
+    const Launch& l = plan[i];
     e = rc::launch_record(l.args, stack, l.args.counters != nullptr, l.args.precision == 1, l.grid, l.lds, st);
   }
   return e;
 }
+hipError_t run_plan(const std::vector<Launch>& plan, int stack, hipStream_t st) {
+  return run_plan(plan.data(), plan.size(), stack, st);
+}
 
 int launch_direct(rc_scene* s, const rc::RecordArgs& a, int stack, size_t lds, int grid, hipStream_t st) {
   (void)s;
-  std::vector<Launch> plan{Launch{a, grid, lds}};
-  RC_HIP(run_plan(plan, stack, st));
+  const Launch one{a, grid, lds};
+  RC_HIP(run_plan(&one, 1, stack, st));
   return RC_OK;
 }
 
@@ -525,10 +562,7 @@ int64_t rc_bvh_build_host(const float* tri, int64_t T, const float box_lo[3], co
   return nn;
 }
 
-size_t rc_workspace_size(int64_t P) {
-  const int64_t Pm = std::min<int64_t>(std::max<int64_t>(P, 0), rc::kSplitMaxRecords);
-  return ws_split_offset(P) + ws_partial_offset(Pm) + (size_t)Pm * rc::kMaxSplits * 20 * sizeof(double);
-}
+size_t rc_workspace_size(int64_t P) { return ws_bytes(std::max<int64_t>(P, 0)); }
 
 int64_t rc_workspace_errors(const void* ws, void* stream) {
   if (!ws) return fail(RC_EINVAL, "workspace is NULL");
@@ -559,6 +593,52 @@ int rc_records(const rc_scene* scene, const rc_medium* medium, const rc_point_li
   set_splits(a, params, P, resident, workspace);
   grid = (int)std::min<int64_t>(grid, P * (int64_t)a.splits);
   return launch_direct(s, a, stack, lds, grid, static_cast<hipStream_t>(stream));
+}
+
+int rc_records_noalloc(const rc_scene* scene, const rc_medium* medium, const rc_point_light* lights, int n_lights,
+                       const float* pos, const int32_t* n_theta, const int32_t* n_phi, int64_t P,
+                       const rc_params* params, double* value, double* grad, double* hess, void* stream) {
+  if (P > RC_NOALLOC_MAX_RECORDS)
+    return fail(RC_EINVAL, "rc_records_noalloc takes at most %d records (%lld given)", RC_NOALLOC_MAX_RECORDS,
+                (long long)P);
+  if (!scene) return fail(RC_EINVAL, "scene is NULL");
+  int dev = -1;
+  RC_HIP(hipGetDevice(&dev));
+  if (dev != scene->device) return fail(RC_EINVAL, "scene is on device %d, current device is %d", scene->device, dev);
+  void* ws = nullptr;
+  int r = scratch_address(dev, &ws);
+  if (r) return r;
+  r = check_inputs(scene, medium, lights, n_lights, pos, n_theta, n_phi, P, params, value, grad, hess, ws);
+  if (r) return r;
+  if (P == 0) return RC_OK;
+  rc_scene* s = const_cast<rc_scene*>(scene);
+  rc_params pr = *params;
+  int stack, grid;
+  size_t lds;
+  int64_t resident = 0;
+  std::lock_guard<std::mutex> lk(s->mu);
+  if (pr.shadow_bvh == 0 && n_lights > 0) {
+    // light bins only if the scene already holds them for these lights
+    // (building them allocates); otherwise the BVH gives the same segments
+    bool same = s->lb.n == n_lights && s->lb.desc != nullptr;
+    for (int l = 0; same && l < n_lights; l++) same = std::memcmp(s->lb.pos[l], lights[l].pos, sizeof(float) * 3) == 0;
+    if (!same) pr.shadow_bvh = 1;
+  }
+  if ((r = plan(s, &pr, P, 0, stack, lds, grid, &resident))) return r;
+  rc::RecordArgs a =
+      make_args(s, medium, lights, n_lights, pos, n_theta, n_phi, P, &pr, value, grad, hess, ws, nullptr);
+  set_splits(a, &pr, P, resident, ws);
+  grid = (int)std::min<int64_t>(grid, P * (int64_t)a.splits);
+  return launch_direct(s, a, stack, lds, grid, static_cast<hipStream_t>(stream));
+}
+
+int64_t rc_records_noalloc_errors(void* stream) {
+  int dev = -1;
+  RC_HIP(hipGetDevice(&dev));
+  void* ws = nullptr;
+  int r = scratch_address(dev, &ws);
+  if (r) return r;
+  return rc_workspace_errors(ws, stream);
 }
 
 int rc_records_batched(const rc_scene* scene, const rc_medium* medium, const rc_point_light* lights, int n_lights,

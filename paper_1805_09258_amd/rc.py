@@ -22,6 +22,7 @@ LIB_PATH = Path(os.environ.get("RC_LIBRARY", str(_PKG / "librc.so")))
 RC_OK, RC_EINVAL, RC_ENOMEM, RC_EDEVICE, RC_ENODEV = 0, -1, -2, -3, -4
 RC_MAX_LIGHTS, RC_MAX_RINGS, RC_MAX_NPHI = 16, 64, 256
 RC_ETIMEOUT = -5
+RC_NOALLOC_MAX_RECORDS = 4096  # largest batch of rc_records_noalloc
 RC_PLACE_STATE_INTS = 4101  # placement state: 5 counters + one status word per gathered candidate
 
 
@@ -55,7 +56,7 @@ class rc_scene_stats(C.Structure):
 
 
 EXPORTS = ["rc_scene_create", "rc_scene_destroy", "rc_scene_info", "rc_bvh_build_host", "rc_workspace_size",
-           "rc_workspace_errors", "rc_records", "rc_records_batched", "rc_records_wait", "rc_autotune", "rc_radius",
+           "rc_workspace_errors", "rc_records", "rc_records_noalloc", "rc_records_noalloc_errors", "rc_records_batched", "rc_records_wait", "rc_autotune", "rc_radius",
            "rc_trace_rays", "rc_occluded_rays", "rc_light_bins_build", "rc_light_occluded", "rc_light_bins_host",
            "rc_probe", "rc_mlp_param_bytes", "rc_mlp_n_params", "rc_mlp_init",
            "rc_mlp_load", "rc_mlp_fit_features", "rc_mlp_forward", "rc_mlp_radius", "rc_mlp_train_workspace_bytes",
@@ -88,6 +89,10 @@ def lib():
         rec = [vp, C.POINTER(rc_medium), C.POINTER(rc_point_light), i32, vp, vp, vp, i64, C.POINTER(rc_params)]
         L.rc_records.argtypes = rec + [vp, vp, vp, vp, vp]
         L.rc_records.restype = i32
+        L.rc_records_noalloc.argtypes = rec + [vp, vp, vp, vp]
+        L.rc_records_noalloc.restype = i32
+        L.rc_records_noalloc_errors.argtypes = [vp]
+        L.rc_records_noalloc_errors.restype = i64
         L.rc_records_batched.argtypes = rec + [vp, i32, i32, vp, vp, vp, vp, vp]
         L.rc_records_batched.restype = i32
         L.rc_records_wait.argtypes = [vp, i32, vp]
@@ -268,6 +273,18 @@ def rc_records(scene, sigma_s, sigma_a, lights, pos, n_theta, n_phi, params, val
     return _check(lib().rc_records(scene, C.byref(med), arr, nl, _ptr(pos), _ptr(n_theta), _ptr(n_phi), P,
                                    C.byref(params), _ptr(value), _ptr(grad), _ptr(hess), _ptr(workspace),
                                    _stream(stream)))
+
+
+def rc_records_noalloc(scene, sigma_s, sigma_a, lights, pos, n_theta, n_phi, params, value, grad, hess, stream=None):
+    med = rc_medium(float(sigma_s), float(sigma_a))
+    arr, nl = _lights(lights)
+    P = int(pos.shape[0])
+    return _check(lib().rc_records_noalloc(scene, C.byref(med), arr, nl, _ptr(pos), _ptr(n_theta), _ptr(n_phi), P,
+                                           C.byref(params), _ptr(value), _ptr(grad), _ptr(hess), _stream(stream)))
+
+
+def rc_records_noalloc_errors(stream=None):
+    return _check(lib().rc_records_noalloc_errors(_stream(stream)))
 
 
 def rc_records_batched(scene, sigma_s, sigma_a, lights, pos, n_theta, n_phi, params, order, use_graph, tile, value,

@@ -325,3 +325,18 @@ def test_watchdog_rejects_bad_arguments_without_a_device():
     ws = np.zeros(64, np.uint32)
     assert rc.lib().rc_records_wait(None, 100, None) == rc.RC_EINVAL
     assert rc.lib().rc_records_wait(ws.ctypes.data_as(rc.C.c_void_p), -1, None) == rc.RC_EINVAL
+
+
+def test_noalloc_records_reject_batches_above_the_limit_without_a_device():
+    """rc_records_noalloc rejects more than RC_NOALLOC_MAX_RECORDS records
+    before it touches a device."""
+    L = rc.lib()
+    prm = rc.make_params(0.1, 8, 64, 1)
+    med = rc.rc_medium(1.0, 0.2)
+    P = rc.RC_NOALLOC_MAX_RECORDS + 1
+    r = L.rc_records_noalloc(None, rc.C.byref(med), None, 0, None, None, None, P, rc.C.byref(prm), None, None, None,
+                             None)
+    assert r == rc.RC_EINVAL
+    assert b"at most 4096" in L.rc_last_error()
+    assert L.rc_records_noalloc(None, rc.C.byref(med), None, 0, None, None, None, 16, rc.C.byref(prm), None, None,
+                                None, None) == rc.RC_EINVAL
