@@ -235,10 +235,13 @@ int64_t rc_records_noalloc_errors(void* stream);
  *   order     : device int32[P] permutation of 0..P-1, the order in which
  *               records are popped (e.g. most expensive first), or NULL to
  *               build one on the device: records grouped by n_phi class
- *               (<= 16, 32, 64, 128, 256; widest first), largest
- *               n_theta * n_phi first within a class.  With the device-built
- *               queue, batches of more than 16384 records are launched once
- *               per class, each launch sized (LDS, occupancy) for its class.
+ *               (<= 16, 32, 64, 128, 256; widest first), then by octave of
+ *               n_theta * n_phi (largest first), then by cell of an 8x8x8
+ *               grid over the medium box in Morton order (records in flight
+ *               together lie close together and share the caches).  With the
+ *               device-built queue, batches of more than 16384 records are
+ *               launched once per class, each launch sized (LDS, occupancy)
+ *               for its class.
  *   use_graph : nonzero = capture the queue reset and the persistent
  *               launch(es) in a hipGraph on first use for these arguments and
  *               replay it afterwards (the graph is cached in the scene

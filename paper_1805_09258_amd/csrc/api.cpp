@@ -118,11 +118,10 @@ struct rc_scene {
 
 namespace {
 
-// queue area (256 bytes): [0] next item, [1] invalid records, [2..6] next item
-// of each n_phi class launch, [8] records finished, [16..25] class ranges [lo, hi)
-constexpr size_t kWsQueue = 0, kWsHist = 256, kWsCursor = 256 + 4 * rc::kOrderBuckets,
-                 kWsOrder = 256 + 8 * rc::kOrderBuckets;
-constexpr int kQClassNext = 2, kQClassRange = 16;
+// queue area (kQueueWords words, see kernels.hpp); then the bucket counts and
+// cursors of the device-built queue, the queue order itself,
+constexpr size_t kWsQueue = 0, kWsHist = 4 * rc::kQueueWords, kWsCursor = kWsHist + 4 * rc::kOrderBuckets,
+                 kWsOrder = kWsCursor + 4 * rc::kOrderBuckets;
 // after the queue order: per-record part counters, then per-part partial sums
 // launch configurations ("tiles"): persistent grid as a multiple of the
 // resident wave capacity, idle lanes that trigger a refill of the shadow
@@ -315,6 +314,8 @@ rc::RecordArgs make_args(const rc_scene* s, const rc_medium* m, const rc_point_l
   a.hess = hess;
   a.order = order;
   a.queue = reinterpret_cast<unsigned int*>(static_cast<char*>(ws) + kWsQueue);
+  a.range = nullptr;  // slots 0..P-1
+  a.next = a.queue;
   a.counters = reinterpret_cast<unsigned long long*>(p->counters);
   a.splits = 1;
   a.refill_min = kTiles[0].refill_min;
@@ -382,7 +383,6 @@ int plan(const rc_scene* s, const rc_params* p, int64_t P, int tile, int& stack,
 hipError_t run_plan(const Launch* plan, size_t n, int stack, hipStream_t st) {
   const rc::RecordArgs& a0 = plan[0].args;
   hipError_t e = rc::launch_reset(a0.queue, st);
-  if (e == hipSuccess && n > 1) e = rc::launch_zero_u32(a0.queue + kQClassNext, rc::kOrderClasses, st);
   if (e == hipSuccess && a0.splits > 1) e = rc::launch_zero_u32(a0.done, a0.P, st);
   for (size_t i = 0; i < n && e == hipSuccess; i++) {
     const Launch& l = plan[i];
@@ -664,8 +664,10 @@ int rc_records_batched(const rc_scene* scene, const rc_medium* medium, const rc_
   unsigned int* q = reinterpret_cast<unsigned int*>(ws + kWsQueue);
   if (!ord) {
     int32_t* o = reinterpret_cast<int32_t*>(ws + kWsOrder);
-    RC_HIP(rc::launch_order(n_theta, n_phi, (int)P, params->max_n_phi, reinterpret_cast<unsigned int*>(ws + kWsHist),
-                            reinterpret_cast<unsigned int*>(ws + kWsCursor), o, q + kQClassRange, st));
+    RC_HIP(rc::launch_order(n_theta, n_phi, pos, make_float3(s->box_lo[0], s->box_lo[1], s->box_lo[2]),
+                            make_float3(s->box_hi[0], s->box_hi[1], s->box_hi[2]), (int)P, params->max_n_phi,
+                            reinterpret_cast<unsigned int*>(ws + kWsHist), reinterpret_cast<unsigned int*>(ws + kWsCursor),
+                            o, q + rc::kQueueRange, st));
     ord = o;
   }
   rc::RecordArgs a = make_args(s, medium, lights, n_lights, pos, n_theta, n_phi, P, params, value, grad, hess,
@@ -691,8 +693,8 @@ int rc_records_batched(const rc_scene* scene, const rc_medium* medium, const rc_
       rc::RecordArgs ak = a;
       ak.max_n_phi = cap;
       ak.lds_cols = lds_cols_for(cap, stack, params->max_rings);
-      ak.range = q + kQClassRange + 2 * k;
-      ak.next = q + kQClassNext + k;
+      ak.range = q + rc::kQueueRange + 2 * k;
+      ak.next = q + rc::kQueueClassNext + k;
       launches.push_back(Launch{ak, gk, lk});
       lds_max = std::max(lds_max, lk);
       prev_cap = rc::kClassCap[k];

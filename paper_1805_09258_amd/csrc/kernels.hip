@@ -149,12 +149,11 @@ record_kernel(RecordArgs g) {
   // queue slots [lo, hi) of this launch: all of them, or one class of records
   const int q_lo = g.range ? (int)g.range[0] : 0;
   const int q_n = g.range ? (int)g.range[1] - q_lo : g.P;
-  unsigned int* const next = g.next ? g.next : &g.queue[0];
   while (true) {
-    int q = 0;
-    if (lane == 0) q = (int)atomicAdd(next, 1u);
+    int q = 0;  // item = queue slot * S + part
+    if (lane == 0) q = (int)atomicAdd(g.next, 1u);
     q = __shfl(q, 0, kWave);
-    if (q >= q_n * S) break;
+    if ((long long)q >= (long long)q_n * S) break;
     const int qr = q_lo + q / S, part = q - (q / S) * S;
     const int rec = g.order ? g.order[qr] : qr;
     if (rec < 0 || rec >= g.P) {  // corrupt queue entry: count it, touch nothing
@@ -826,47 +825,76 @@ record_kernel(RecordArgs g) {
 // ---------------------------------------------------------------------------
 // small kernels
 // ---------------------------------------------------------------------------
+// clears the queue words that must start at zero: pop counters, invalid
+// records, progress
 __global__ void reset_queue_kernel(unsigned int* q) {
-  if (threadIdx.x < 2) q[threadIdx.x] = 0u;
-  if (threadIdx.x == 0) q[kQueueDone] = 0u;
+  const int t = threadIdx.x;
+  if (t < kQueueClassNext + kOrderClasses || t == kQueueDone) q[t] = 0u;
 }
 
-// Queue of records grouped by n_phi class (the LDS a record's rows need:
-// n_phi <= 16, 32, 64, 128, 256), the largest class first, and within a
-// class ordered by decreasing cost N = n_theta * n_phi (buckets of 1/4
-// octave); ties in any order (records do not interact).  The scan also
-// writes each class's queue range [lo, hi) to class_range[2 * class].
+// Queue order (see kernels.hpp): bucket of a record = class block (widest
+// n_phi class first), cost octave (largest first), Morton cell of the box's
+// 8x8x8 grid.  Records with n_phi above the call's max_n_phi (invalid: the
+// record kernel writes NaN and counts it) are queued in max_n_phi's class so
+// that one of the launches pops them; points outside the box (also invalid)
+// are clamped to the nearest cell.
 RC_DEV int order_class(int nph) { return nph <= 16 ? 0 : (nph <= 32 ? 1 : (nph <= 64 ? 2 : (nph <= 128 ? 3 : 4))); }
-// A record with n_phi above the call's max_n_phi (invalid: the record kernel
-// writes NaN and counts it) is queued in max_n_phi's class, so that one of
-// the launches pops it.
-RC_DEV int order_bucket(int nth, int nph, int max_nph) {
+RC_DEV int order_bucket(int nth, int nph, int max_nph, float x, float y, float z, float3 lo, float3 inv) {
   const float n = fmaxf((float)nth * (float)nph, 1.f);
-  const int cb = min(max((int)(log2f(n) * 4.f), 0), kOrderPerClass - 1);
-  return (kOrderClasses - 1 - order_class(min(nph, max_nph))) * kOrderPerClass + (kOrderPerClass - 1 - cb);
+  const int cb = min(max((int)log2f(n), 0), kOrderCost - 1);
+  // fminf/fmaxf drop a NaN coordinate (cell 0)
+  const int cx = (int)fminf(fmaxf((x - lo.x) * inv.x, 0.f), 7.f);
+  const int cy = (int)fminf(fmaxf((y - lo.y) * inv.y, 0.f), 7.f);
+  const int cz = (int)fminf(fmaxf((z - lo.z) * inv.z, 0.f), 7.f);
+  int cell = 0;
+  for (int b = 2; b >= 0; b--) cell = (cell << 3) | (((cx >> b) & 1) << 2) | (((cy >> b) & 1) << 1) | ((cz >> b) & 1);
+  const int blk = kOrderClasses - 1 - order_class(min(nph, max_nph));
+  return (blk * kOrderCost + (kOrderCost - 1 - cb)) * kOrderCells + cell;
 }
-__global__ void order_hist_kernel(const int* nth, const int* nph, int P, int max_nph, unsigned int* hist) {
+__global__ void order_hist_kernel(const int* nth, const int* nph, const float* pos, float3 lo, float3 inv, int P,
+                                  int max_nph, unsigned int* hist) {
   int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= P) return;
-  atomicAdd(&hist[order_bucket(nth[i], nph[i], max_nph)], 1u);
+  atomicAdd(&hist[order_bucket(nth[i], nph[i], max_nph, pos[3 * i], pos[3 * i + 1], pos[3 * i + 2], lo, inv)], 1u);
 }
-__global__ void order_scan_kernel(unsigned int* hist, unsigned int* cursor, unsigned int* class_range) {
-  if (threadIdx.x == 0) {
-    unsigned int s = 0;
-    for (int b = 0; b < kOrderBuckets; b++) {
-      const int blk = b / kOrderPerClass, cls = kOrderClasses - 1 - blk;
-      if (b % kOrderPerClass == 0 && blk < kOrderClasses) class_range[2 * cls] = s;
-      cursor[b] = s;
-      s += hist[b];
-      if (b % kOrderPerClass == kOrderPerClass - 1 && blk < kOrderClasses) class_range[2 * cls + 1] = s;
-    }
+// Exclusive prefix sums of the bucket counts (the first queue slot of each
+// bucket) and the [lo, hi) queue range of each class, by one block: each
+// thread sums a run of buckets, the run sums are scanned in LDS, then each
+// thread writes its run.
+__global__ __launch_bounds__(kOrderScanThreads) void order_scan_kernel(const unsigned int* hist, unsigned int* cursor,
+                                                                       unsigned int* class_range) {
+  constexpr int kRun = kOrderBuckets / kOrderScanThreads;
+  __shared__ unsigned int part[kOrderScanThreads];
+  const int t = threadIdx.x;
+  unsigned int sum = 0;
+  for (int i = 0; i < kRun; i++) sum += hist[t * kRun + i];
+  part[t] = sum;
+  __syncthreads();
+  for (int off = 1; off < kOrderScanThreads; off <<= 1) {
+    const unsigned int v = t >= off ? part[t - off] : 0u;
+    __syncthreads();
+    part[t] += v;
+    __syncthreads();
   }
+  unsigned int run = part[t] - sum;
+  for (int i = 0; i < kRun; i++) {
+    const int b = t * kRun + i;
+    if (b % kOrderGroup == 0) {  // class block blk starts here (and block blk - 1 ends)
+      const int blk = b / kOrderGroup;
+      class_range[2 * (kOrderClasses - 1 - blk)] = run;
+      if (blk > 0) class_range[2 * (kOrderClasses - blk) + 1] = run;
+    }
+    cursor[b] = run;
+    run += hist[b];
+  }
+  if (t == kOrderScanThreads - 1) class_range[1] = run;  // the last block: class 0
 }
-__global__ void order_scatter_kernel(const int* nth, const int* nph, int P, int max_nph, unsigned int* cursor,
-                                     int* order) {
+__global__ void order_scatter_kernel(const int* nth, const int* nph, const float* pos, float3 lo, float3 inv, int P,
+                                     int max_nph, unsigned int* cursor, int* order) {
   int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= P) return;
-  unsigned int p = atomicAdd(&cursor[order_bucket(nth[i], nph[i], max_nph)], 1u);
+  const int b = order_bucket(nth[i], nph[i], max_nph, pos[3 * i], pos[3 * i + 1], pos[3 * i + 2], lo, inv);
+  unsigned int p = atomicAdd(&cursor[b], 1u);
   order[p] = i;
 }
 __global__ void zero_u32_kernel(unsigned int* p, int n) {
@@ -988,13 +1016,18 @@ hipError_t launch_zero_u32(unsigned int* p, int n, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t launch_order(const int* nth, const int* nph, int P, int max_nph, unsigned int* hist, unsigned int* cursor, int* order,
-                        unsigned int* class_range, hipStream_t s) {
-  hipLaunchKernelGGL(zero_u32_kernel, dim3(1), dim3(kOrderBuckets), 0, s, hist, kOrderBuckets);
+hipError_t launch_order(const int* nth, const int* nph, const float* pos, float3 box_lo, float3 box_hi, int P,
+                        int max_nph, unsigned int* hist, unsigned int* cursor, int* order, unsigned int* class_range,
+                        hipStream_t s) {
+  const float3 inv = make_float3(8.f / (box_hi.x - box_lo.x), 8.f / (box_hi.y - box_lo.y), 8.f / (box_hi.z - box_lo.z));
+  hipLaunchKernelGGL(zero_u32_kernel, dim3(kOrderBuckets / 256), dim3(256), 0, s, hist, kOrderBuckets);
   int blocks = (P + 255) / 256;
-  if (blocks > 0) hipLaunchKernelGGL(order_hist_kernel, dim3(blocks), dim3(256), 0, s, nth, nph, P, max_nph, hist);
-  hipLaunchKernelGGL(order_scan_kernel, dim3(1), dim3(64), 0, s, hist, cursor, class_range);
-  if (blocks > 0) hipLaunchKernelGGL(order_scatter_kernel, dim3(blocks), dim3(256), 0, s, nth, nph, P, max_nph, cursor, order);
+  if (blocks > 0)
+    hipLaunchKernelGGL(order_hist_kernel, dim3(blocks), dim3(256), 0, s, nth, nph, pos, box_lo, inv, P, max_nph, hist);
+  hipLaunchKernelGGL(order_scan_kernel, dim3(1), dim3(kOrderScanThreads), 0, s, hist, cursor, class_range);
+  if (blocks > 0)
+    hipLaunchKernelGGL(order_scatter_kernel, dim3(blocks), dim3(256), 0, s, nth, nph, pos, box_lo, inv, P, max_nph,
+                       cursor, order);
   return hipGetLastError();
 }
 

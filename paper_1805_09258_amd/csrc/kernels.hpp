@@ -9,12 +9,25 @@
 
 namespace rc {
 
-constexpr int kOrderBuckets = 256;
-constexpr int kQueueDone = 8;  // workspace queue word: records finished (progress)
-constexpr int kOrderClasses = 5;    // n_phi classes: <= 16, 32, 64, 128, 256
-constexpr int kOrderPerClass = 48;  // cost buckets per class (1/4 octave of N)
+// Device-built queue: records grouped by n_phi class (widest first), then by
+// cost (octaves of N = n_theta * n_phi, largest first), then by cell of an
+// 8x8x8 grid over the medium box in Morton order, so that the records in
+// flight at any time lie close together and share the caches.
+constexpr int kOrderClasses = 5;  // n_phi classes: <= 16, 32, 64, 128, 256
 constexpr int kClassCap[kOrderClasses] = {16, 32, 64, 128, 256};
-static_assert(kOrderClasses * kOrderPerClass <= kOrderBuckets, "order buckets");
+constexpr int kOrderCost = 16;    // cost buckets (octaves of N)
+constexpr int kOrderCells = 512;  // Morton cells (8 x 8 x 8)
+constexpr int kOrderGroup = kOrderCost * kOrderCells;            // buckets of one class
+constexpr int kOrderBuckets = kOrderClasses * kOrderGroup;       // 40960
+constexpr int kOrderScanThreads = 1024;
+static_assert(kOrderBuckets % kOrderScanThreads == 0, "order scan chunks");
+// workspace queue words: [0] pop counter of a single launch, [1] invalid
+// records, [2..6] pop counter of each class launch, [8] records finished
+// (progress, read by the host watchdog), [16..25] queue range [lo, hi) of each class
+constexpr int kQueueWords = 64;
+constexpr int kQueueClassNext = 2;
+constexpr int kQueueDone = 8;
+constexpr int kQueueRange = 16;
 
 struct RecordArgs {
   const float4* nodes;
@@ -43,7 +56,7 @@ struct RecordArgs {
   double* grad;
   double* hess;
   const int* order;        // queue order or nullptr (identity)
-  unsigned int* queue;     // [0] next queue slot, [1] invalid records
+  unsigned int* queue;     // queue words (kQueueWords): [1] invalid records, progress, ranges, counters
   // shadow segments from light bins (nullptr: BVH traversal): per light two
   // int4 (B, levels, level offsets 0..3), the bin offsets (CSR over levels,
   // faces, bins) and the entries (3 float4: permuted vertices, id bits,
@@ -57,7 +70,7 @@ struct RecordArgs {
   double* partial;         // [P][splits][20] partial sums (splits > 1)
   unsigned int* done;      // [P] parts finished (splits > 1; zero before launch)
   const unsigned int* range;  // device [lo, hi): queue slots of this launch, or nullptr (all)
-  unsigned int* next;         // item counter of this launch, or nullptr (queue[0])
+  unsigned int* next;         // pop counter of this launch
   unsigned long long* counters;
 };
 
@@ -75,8 +88,9 @@ hipError_t launch_reset(unsigned int* q, hipStream_t s);
 hipError_t launch_zero_u32(unsigned int* p, int n, hipStream_t s);
 constexpr int kMaxSplits = 8;        // wavefronts per record at most
 constexpr int kSplitMaxRecords = 16384;  // batches up to this size may split records
-hipError_t launch_order(const int* nth, const int* nph, int P, int max_nph, unsigned int* hist, unsigned int* cursor, int* order,
-                        unsigned int* class_range, hipStream_t s);
+hipError_t launch_order(const int* nth, const int* nph, const float* pos, float3 box_lo, float3 box_hi, int P,
+                        int max_nph, unsigned int* hist, unsigned int* cursor, int* order, unsigned int* class_range,
+                        hipStream_t s);
 hipError_t launch_radius(const double* value, const double* hess, int P, float eps, float r_min, float r_max, float* R,
                          float* axes, hipStream_t s);
 
