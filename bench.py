@@ -128,8 +128,9 @@ def cpu_baseline(w, outputs, budget_s=15.0):
 
 def learned_vs_plain(dev):
     """Learned vs plain cache placement over one held-out scene of the 10k-
-    triangle family (candidates resolved per second by each pipeline, each
-    cache's error against a dense plain cache)."""
+    triangle family: candidates resolved per second by each pipeline, and each
+    cache's error against the dense plain cache (records at the test points
+    with the random numbers every cached record uses)."""
     from paper_1805_09258_amd import placement as PL
     r = PL.compare(dev, log=log)
     lp, pl = r["learned"], r["plain"]
@@ -140,14 +141,13 @@ def learned_vs_plain(dev):
            "learned": {k: lp[k] for k in keep + ("probes", "records_learned", "passes", "uncovered_after_judge",
                                                  "fallback_rounds", "fallback_records", "seconds_rounds",
                                                  "seconds_records_judge", "seconds_fallback", "safety") if k in lp},
-           "reference_noise": r["reference_noise"], "no_cache_error": r["no_cache"],
+           "independent_records_error": r["independent_records"],
            "training": {k: r[k] for k in ("train_samples", "train_data_seconds", "train_seconds", "train_mse",
                                           "heldout_mse_net", "heldout_mse_constant")},
-           "safety_by_validation": r["safety_validation_seconds"],
+           "safety_by_validation": r["safety_validation"],
            "plain_by_batch": r["plain_by_batch"]}
-    for k in ("reference", "epsilon", "target_rel_l2"):
-        if k in r:
-            res[k] = r[k]
+    for k in ("reference", "epsilon", "error_band"):
+        res[k] = r[k]
     res["plain"]["candidates_per_s"] = r["candidates"] / pl["seconds"]
     res["learned"]["candidates_per_s"] = r["candidates"] / lp["seconds"]
     res["speedup"] = pl["seconds"] / lp["seconds"]
