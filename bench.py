@@ -232,7 +232,8 @@ def measure(name, dev, steps, warmup, count=True):
                 "bvh_nodes": info["n_nodes"], "bvh_depth": info["depth"],
                 "scene_device_bytes": info["device_bytes"], "light_bin_bytes": info["light_bin_bytes"],
                 "light_bin_entries": info["light_bin_entries"],
-                "tile": tile, "tile_ms": tile_ms, "compulsory_bytes": compulsory_bytes(w, info)})
+                "tile": tile, "tile_settings": rc.rc_tile_info(tile), "tile_ms": tile_ms,
+                "compulsory_bytes": compulsory_bytes(w, info)})
     if rays is not None:
         res["mrays_per_s"] = rays * steps / dt / 1e6
         res["rays_per_record"] = rays / w.n_rec
@@ -414,7 +415,8 @@ def main():
         "dtype": "f32",
         "data": "synthetic",
         "config": {k: res[k] for k in ("workload", "records_per_step", "n_triangles", "directions_mean",
-                                       "bvh_nodes", "bvh_depth", "light_bin_entries", "tile", "tile_ms")},
+                                       "bvh_nodes", "bvh_depth", "light_bin_entries", "tile", "tile_settings",
+                                       "tile_ms")},
         "mrays_per_s": res.get("mrays_per_s"),
         "rays_per_record": res.get("rays_per_record"),
         "roofline": roofline(args.workload, res),

@@ -267,13 +267,24 @@ int rc_records_wait(const void* workspace, int timeout_ms, void* stream);
 
 /* Time every launch configuration on the given inputs (synchronises
  * `stream`) and return the fastest configuration index in *best_tile; the
- * per-configuration milliseconds go to ms_out[n_tiles] if non-NULL.  The
- * result is remembered in the on-disk cache `cache_path` (a text file; NULL
- * = no cache) keyed by device name, scene size and workload shape. */
+ * per-configuration milliseconds (mean of two runs after a warm-up run) go
+ * to ms_out[n_tiles] if non-NULL (n_tiles <= 16).  A configuration sets the
+ * persistent grid (a multiple of the resident wavefronts), the idle-lane
+ * threshold that refills the BVH shadow loop, the waiting-lane threshold of
+ * a triangle step, and the resident wavefronts per SIMD the LDS row width
+ * is sized for (4, 3 or 2: wider rows need fewer column sectors but hide
+ * less latency).  The result is remembered in the on-disk cache
+ * `cache_path` (a text file; NULL = no cache) keyed by device name, scene
+ * size and workload shape. */
 int rc_autotune(const rc_scene* scene, const rc_medium* medium, const rc_point_light* lights, int n_lights,
                 const float* pos, const int32_t* n_theta, const int32_t* n_phi, int64_t P,
                 const rc_params* params, double* value, double* grad, double* hess, void* workspace,
                 const char* cache_path, int* best_tile, float* ms_out, int* n_tiles, void* stream);
+/* The settings of launch configuration `tile` (0 <= tile < n_tiles of
+ * rc_autotune): grid multiple, refill threshold, triangle-step threshold, LDS
+ * wavefronts per SIMD.  Host only.  Errors: EINVAL (tile out of range or a
+ * NULL output). */
+int rc_tile_info(int tile, float* grid, int* refill_min, int* leaf_batch, int* lds_waves);
 
 /* ------------------------------------------------------------------ */
 /* Validity radius (Sec. 5, Eq. radiusAniso3D; supplement Eq. S.13)     */

@@ -125,14 +125,17 @@ constexpr size_t kWsQueue = 0, kWsHist = 4 * rc::kQueueWords, kWsCursor = kWsHis
 // after the queue order: per-record part counters, then per-part partial sums
 // launch configurations ("tiles"): persistent grid as a multiple of the
 // resident wave capacity, idle lanes that trigger a refill of the shadow
-// loop, and lanes waiting at a leaf that trigger a triangle step
+// loop, lanes waiting at a leaf that trigger a triangle step, and the
+// resident wavefronts per SIMD the LDS row width is sized for (fewer: wider
+// rows, fewer column sectors, but less latency hiding)
 struct Tile {
   float grid;
-  int refill_min, leaf_batch;
+  int refill_min, leaf_batch, lds_waves;
 };
-constexpr int kNTiles = 8;
-constexpr Tile kTiles[kNTiles] = {{1.0f, 12, 0}, {2.0f, 12, 0}, {1.0f, 8, 0},  {1.0f, 16, 0},
-                                  {1.0f, 12, 8}, {2.0f, 12, 8}, {0.5f, 12, 0}, {1.0f, 24, 0}};
+constexpr int kNTiles = 10;
+constexpr Tile kTiles[kNTiles] = {{1.0f, 12, 0, 4}, {2.0f, 12, 0, 4}, {1.0f, 8, 0, 4},  {1.0f, 16, 0, 4},
+                                  {1.0f, 12, 8, 4}, {2.0f, 12, 8, 4}, {0.5f, 12, 0, 4}, {1.0f, 24, 0, 4},
+                                  {1.0f, 12, 0, 3}, {1.0f, 12, 0, 2}};
 
 constexpr size_t ws_split_offset(int64_t P) {
   return (kWsOrder + 4 * (size_t)(P > 0 ? P : 0) + 255) & ~size_t(255);
@@ -204,8 +207,9 @@ int check_inputs(const rc_scene* s, const rc_medium* m, const rc_point_light* li
 // 1/W of the CU's 160 KB.  Measured at 64 columns: whole rows at 8 wavefronts
 // per CU gave 0.79x the records/s of 33-column LDS rows at 12, and 26-column
 // LDS rows at 16 gave 1.09x those at 12.
-int lds_cols_for(int max_n_phi, int stack, int max_rings) {
-  const size_t budget = (size_t)160 * 1024 / (4 * rc::record_waves_per_simd(stack));
+int lds_cols_for(int max_n_phi, int stack, int max_rings, int lds_waves = 0) {
+  const int wps = lds_waves > 0 ? std::min(lds_waves, rc::record_waves_per_simd(stack)) : rc::record_waves_per_simd(stack);
+  const size_t budget = (size_t)160 * 1024 / (4 * wps);
   if (rc::record_lds_bytes(stack, max_n_phi, max_rings) <= budget) return max_n_phi;
   for (int w = std::min(32, max_n_phi - 1); w >= 8; w--)
     if (rc::record_lds_bytes(stack, w + 1, max_rings) <= budget) return w + 1;
@@ -362,13 +366,14 @@ void set_splits(rc::RecordArgs& a, const rc_params* p, int64_t P, int64_t reside
 int plan(const rc_scene* s, const rc_params* p, int64_t P, int tile, int& stack, size_t& lds, int& grid,
          int64_t* resident_out = nullptr) {
   stack = rc::stack_variant(s->depth);
-  lds = rc::record_lds_bytes(stack, lds_cols_for(p->max_n_phi, stack, p->max_rings), p->max_rings);
+  const int t = (tile >= 0 && tile < kNTiles) ? tile : 0;
+  lds = rc::record_lds_bytes(stack, lds_cols_for(p->max_n_phi, stack, p->max_rings, kTiles[t].lds_waves),
+                             p->max_rings);
   if (lds > 160 * 1024) return fail(RC_EINVAL, "max_n_phi x max_rings needs %zu bytes of LDS (> 160 KiB)", lds);
   hipError_t e = rc::prepare_record(stack, p->counters != nullptr, p->precision == 1, lds);
   if (e != hipSuccess) return fail(RC_EDEVICE, "kernel attribute: %s", hipGetErrorString(e));
   int occ = rc::record_occupancy(stack, p->counters != nullptr, p->precision == 1, lds);
   if (occ < 1) occ = 1;
-  int t = (tile >= 0 && tile < kNTiles) ? tile : 0;
   int64_t resident = (int64_t)occ * s->n_cu;
   if (resident_out) *resident_out = resident;
   int64_t gsz = (int64_t)std::llround((double)resident * kTiles[t].grid);
@@ -675,6 +680,7 @@ int rc_records_batched(const rc_scene* scene, const rc_medium* medium, const rc_
   set_splits(a, params, P, resident, workspace);
   a.refill_min = kTiles[tile < 0 ? 0 : tile].refill_min;
   a.leaf_batch = kTiles[tile < 0 ? 0 : tile].leaf_batch;
+  a.lds_cols = lds_cols_for(params->max_n_phi, stack, params->max_rings, kTiles[tile < 0 ? 0 : tile].lds_waves);
   std::vector<Launch> launches;
   if (!order && a.splits == 1 && P > rc::kSplitMaxRecords) {
     // Large batches from the internal queue: one launch per n_phi class, each
@@ -692,7 +698,7 @@ int rc_records_batched(const rc_scene* scene, const rc_medium* medium, const rc_
       if ((r = plan(s, &pk, P, tile, sk, lk, gk, &rk))) return r;
       rc::RecordArgs ak = a;
       ak.max_n_phi = cap;
-      ak.lds_cols = lds_cols_for(cap, stack, params->max_rings);
+      ak.lds_cols = lds_cols_for(cap, stack, params->max_rings, kTiles[tile < 0 ? 0 : tile].lds_waves);
       ak.range = q + rc::kQueueRange + 2 * k;
       ak.next = q + rc::kQueueClassNext + k;
       launches.push_back(Launch{ak, gk, lk});
@@ -778,6 +784,16 @@ int rc_records_wait(const void* workspace, int timeout_ms, void* stream) {
     }
     std::this_thread::sleep_for(std::chrono::microseconds(500));
   }
+}
+
+int rc_tile_info(int tile, float* grid, int* refill_min, int* leaf_batch, int* lds_waves) {
+  if (tile < 0 || tile >= kNTiles) return fail(RC_EINVAL, "tile must be in [0, %d)", kNTiles);
+  if (!grid || !refill_min || !leaf_batch || !lds_waves) return fail(RC_EINVAL, "NULL output");
+  *grid = kTiles[tile].grid;
+  *refill_min = kTiles[tile].refill_min;
+  *leaf_batch = kTiles[tile].leaf_batch;
+  *lds_waves = kTiles[tile].lds_waves;
+  return RC_OK;
 }
 
 int rc_autotune(const rc_scene* scene, const rc_medium* medium, const rc_point_light* lights, int n_lights,

@@ -56,7 +56,7 @@ class rc_scene_stats(C.Structure):
 
 
 EXPORTS = ["rc_scene_create", "rc_scene_destroy", "rc_scene_info", "rc_bvh_build_host", "rc_workspace_size",
-           "rc_workspace_errors", "rc_records", "rc_records_noalloc", "rc_records_noalloc_errors", "rc_records_batched", "rc_records_wait", "rc_autotune", "rc_radius",
+           "rc_workspace_errors", "rc_records", "rc_records_noalloc", "rc_records_noalloc_errors", "rc_records_batched", "rc_records_wait", "rc_autotune", "rc_tile_info", "rc_radius",
            "rc_trace_rays", "rc_occluded_rays", "rc_light_bins_build", "rc_light_occluded", "rc_light_bins_host",
            "rc_probe", "rc_mlp_param_bytes", "rc_mlp_n_params", "rc_mlp_init",
            "rc_mlp_load", "rc_mlp_fit_features", "rc_mlp_forward", "rc_mlp_radius", "rc_mlp_train_workspace_bytes",
@@ -99,6 +99,8 @@ def lib():
         L.rc_records_wait.restype = i32
         L.rc_autotune.argtypes = rec + [vp, vp, vp, vp, C.c_char_p, C.POINTER(i32), vp, C.POINTER(i32), vp]
         L.rc_autotune.restype = i32
+        L.rc_tile_info.argtypes = [i32, C.POINTER(f32), C.POINTER(i32), C.POINTER(i32), C.POINTER(i32)]
+        L.rc_tile_info.restype = i32
         L.rc_radius.argtypes = [vp, vp, i64, f32, f32, f32, vp, vp, vp]
         L.rc_radius.restype = i32
         L.rc_trace_rays.argtypes = [vp, vp, vp, i64, vp, vp, vp, vp]
@@ -310,6 +312,12 @@ def rc_autotune(scene, sigma_s, sigma_a, lights, pos, n_theta, n_phi, params, va
                              None if cache_path is None else str(cache_path).encode(), C.byref(best),
                              _ptr(ms) if measure else None, C.byref(nt), _stream(stream)))
     return best.value, (ms[:nt.value].tolist() if measure else None)
+
+
+def rc_tile_info(tile):
+    g, r, l, w = C.c_float(0), C.c_int(0), C.c_int(0), C.c_int(0)
+    _check(lib().rc_tile_info(int(tile), C.byref(g), C.byref(r), C.byref(l), C.byref(w)))
+    return {"grid": g.value, "refill_min": r.value, "leaf_batch": l.value, "lds_waves": w.value}
 
 
 def rc_radius(value, hess, eps, r_min, r_max, R, axes=None, stream=None):

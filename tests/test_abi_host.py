@@ -340,3 +340,11 @@ def test_noalloc_records_reject_batches_above_the_limit_without_a_device():
     assert b"at most 4096" in L.rc_last_error()
     assert L.rc_records_noalloc(None, rc.C.byref(med), None, 0, None, None, None, 16, rc.C.byref(prm), None, None,
                                 None, None) == rc.RC_EINVAL
+
+
+def test_tile_table_is_readable_without_a_device():
+    tiles = [rc.rc_tile_info(t) for t in range(10)]
+    assert tiles[0] == {"grid": 1.0, "refill_min": 12, "leaf_batch": 0, "lds_waves": 4}
+    assert {t["lds_waves"] for t in tiles} == {2, 3, 4}
+    with pytest.raises(rc.RCError):
+        rc.rc_tile_info(10)
