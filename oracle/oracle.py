@@ -6,7 +6,9 @@ import this module.  It loads ``oracle/liboracle.so`` (built from
 are plain linear algebra, written here in numpy:
 
 * the validity radius of a record (Sec. 5, Eq. radiusAniso3D, with the
-  isotropic choice of the largest |eigenvalue| as in Sec. 6);
+  isotropic choice of the largest |eigenvalue| as in Sec. 6) and the
+  ellipsoid of an anisotropic cache point;
+* the sequential greedy cover (Sec. 6 insertion rule) with balls or ellipsoids;
 * the multi-point interpolation of a cache (Sec. 5, Eq. radianceTaylor, with
   the cubic kernel);
 * an FP64 reference of the small MLP used for learned placement (not part of
@@ -212,17 +214,52 @@ def _within32(q, p, R):
     return d2 < R * R
 
 
-def greedy_cover(cand, radius):
+def ellipsoid_form(Ri, vecs):
+    """Anisotropic cache point (Sec. 5, Eq. radiusAniso3D: the valid region is
+    an ellipsoid with principal radii R_i along the Hessian's eigenvectors):
+    the quadratic form M = sum_i v_i v_i^T / R_i^2, so that x' lies inside iff
+    (x' - x)^T M (x' - x) < 1.  Ri [K,3] and vecs [K,3,3] (row i = unit
+    eigenvector i) are the FP32 values a cache stores; each entry
+    sum_i (v_i[a] v_i[b]) / (R_i R_i) is formed in FP64 (terms added in axis
+    order) and rounded once to FP32.  Returns float32 [K,6] =
+    (m00, m01, m02, m11, m12, m22)."""
+    R = np.asarray(Ri, np.float32).astype(np.float64).reshape(-1, 3)
+    V = np.asarray(vecs, np.float32).astype(np.float64).reshape(-1, 3, 3)
+    out = np.zeros((len(R), 6), np.float32)
+    for e, (a, b) in enumerate(((0, 0), (0, 1), (0, 2), (1, 1), (1, 2), (2, 2))):
+        t = [(V[:, i, a] * V[:, i, b]) / (R[:, i] * R[:, i]) for i in range(3)]
+        out[:, e] = ((t[0] + t[1]) + t[2]).astype(np.float32)
+    return out
+
+
+def _within_form32(q, p, form):
+    """(q - p)^T M (q - p) < 1 in FP32, evaluated as
+    ((m00 dx^2 + m11 dy^2) + m22 dz^2) + 2 ((m01 dx dy + m02 dx dz) + m12 dy dz)
+    with every product and sum rounded to FP32 in that order (the cover and
+    interpolation decision of anisotropic points, taken alike on both sides)."""
+    d = np.asarray(q, np.float32) - np.asarray(p, np.float32)
+    m = np.asarray(form, np.float32)
+    dx, dy, dz = d[..., 0], d[..., 1], d[..., 2]
+    diag = (m[..., 0] * (dx * dx) + m[..., 3] * (dy * dy)) + m[..., 5] * (dz * dz)
+    off = (m[..., 1] * (dx * dy) + m[..., 2] * (dx * dz)) + m[..., 4] * (dy * dz)
+    return (diag + np.float32(2) * off) < np.float32(1)
+
+
+def greedy_cover(cand, radius, form=None):
     """Sequential greedy cover (Sec. 6 insertion rule applied to a candidate
     list): visit the candidates in index order and accept one unless an already
-    accepted point p lies closer to it than p's radius.  Returns the accepted
+    accepted point p lies inside p's valid region: the ball of p's radius, or,
+    with form [C,6] (anisotropic points), p's ellipsoid.  Returns the accepted
     indices in acceptance order."""
     cand = np.asarray(cand, np.float32)
     radius = np.asarray(radius, np.float32)
     acc = []
     for i in range(len(cand)):
-        if acc and np.any(_within32(cand[i], cand[acc], radius[acc])):
-            continue
+        if acc:
+            inside = (_within32(cand[i], cand[acc], radius[acc]) if form is None
+                      else _within_form32(cand[i], cand[acc], np.asarray(form, np.float32)[acc]))
+            if np.any(inside):
+                continue
         acc.append(i)
     return np.array(acc, np.int64)
 
@@ -309,27 +346,41 @@ def radius(value, hess6, eps, r_min, r_max, anisotropic=False):
 # --------------------------------------------------------------------------
 # Sec. 5: interpolation from several cache points (Eq. radianceTaylor)
 # --------------------------------------------------------------------------
-def interpolate(cache_pos, cache_val, cache_grad, cache_R, query):
+def interpolate(cache_pos, cache_val, cache_grad, cache_R, query, cache_form=None):
     """L(x') = sum_k [L_k + grad L_k . (x' - x_k)] w_k / sum_k w_k over the
-    cache points whose radius contains x', with w = 3d^2 - 2d^3,
+    cache points whose valid region contains x', with w = 3d^2 - 2d^3,
     d = 1 - |x' - x_k| / R_k.  Returns (L [Q], covered [Q]).
     The membership test |x' - x_k| < R_k is taken in FP32 (see _within32);
-    everything else is FP64."""
+    everything else is FP64.  With cache_form [K,6] (anisotropic points) the
+    region is the ellipsoid (see _within_form32) and d = 1 - sqrt(q) with
+    q = (x' - x_k)^T M_k (x' - x_k) in FP64: the normalised distance that is 1
+    on the ellipsoid, as |x' - x_k| / R_k is on the sphere."""
     cp = np.asarray(cache_pos, np.float64)
     cv = np.asarray(cache_val, np.float64)
     cg = np.asarray(cache_grad, np.float64)
     cR = np.asarray(cache_R, np.float64)
     q = np.asarray(query, np.float64)
     q32, cp32, cR32 = (np.asarray(a, np.float32) for a in (query, cache_pos, cache_R))
+    F = None if cache_form is None else np.asarray(cache_form, np.float32)
     out = np.zeros(len(q))
     cov = np.zeros(len(q), bool)
     for i, x in enumerate(q):
         dx = x[None, :] - cp
-        dist = np.sqrt((dx * dx).sum(1))
-        m = _within32(q32[i][None, :], cp32, cR32)
+        if F is None:
+            m = _within32(q32[i][None, :], cp32, cR32)
+        else:
+            m = _within_form32(q32[i][None, :], cp32, F)
         if not m.any():
             continue
-        d = 1.0 - dist[m] / cR[m]
+        if F is None:
+            dist = np.sqrt((dx * dx).sum(1))
+            d = 1.0 - dist[m] / cR[m]
+        else:
+            f = F[m].astype(np.float64)
+            e = dx[m]
+            qf = ((f[:, 0] * e[:, 0] ** 2 + f[:, 3] * e[:, 1] ** 2 + f[:, 5] * e[:, 2] ** 2)
+                  + 2 * (f[:, 1] * e[:, 0] * e[:, 1] + f[:, 2] * e[:, 0] * e[:, 2] + f[:, 4] * e[:, 1] * e[:, 2]))
+            d = 1.0 - np.sqrt(np.maximum(qf, 0.0))
         w = 3 * d * d - 2 * d * d * d
         num = ((cv[m] + (cg[m] * dx[m]).sum(1)) * w).sum()
         den = w.sum()

@@ -4,6 +4,8 @@ and requires the named pin to fail on it.  CPU only; the copies live in a
 temporary directory."""
 import inspect
 
+import numpy as np
+
 import pytest
 
 from oracle import build as OB
@@ -71,3 +73,41 @@ def test_planted_mistake_fails_a_pin(tmp_path, name, old, new, pin_names):
     finally:
         O.use_library(None)
     assert failed, f"no pin caught: {name}"  # the pins pass on the oracle itself (test_oracle_pins)
+
+
+# Planted mistakes in the oracle's numpy parts (anisotropic cache points)
+def _form_transposed(orig):
+    def f(Ri, vecs):
+        return orig(Ri, np.transpose(np.asarray(vecs, np.float32).reshape(-1, 3, 3), (0, 2, 1)))
+    return f
+
+
+def _within_without_factor_two(orig):
+    def f(q, p, form):
+        d = np.asarray(q, np.float32) - np.asarray(p, np.float32)
+        m = np.asarray(form, np.float32)
+        dx, dy, dz = d[..., 0], d[..., 1], d[..., 2]
+        diag = (m[..., 0] * (dx * dx) + m[..., 3] * (dy * dy)) + m[..., 5] * (dz * dz)
+        off = (m[..., 1] * (dx * dy) + m[..., 2] * (dx * dz)) + m[..., 4] * (dy * dz)
+        return (diag + off) < np.float32(1)
+    return f
+
+
+PY_MUTATIONS = [
+    ("ellipsoid built from eigenvector columns", "ellipsoid_form", _form_transposed,
+     ["test_ellipsoid_form_has_the_axes_as_eigenvectors"]),
+    ("off-diagonal terms of the form counted once", "_within_form32", _within_without_factor_two,
+     ["test_ellipsoid_membership_along_and_off_the_axes"]),
+]
+
+
+@pytest.mark.parametrize("name,attr,make,pin_names", PY_MUTATIONS, ids=[m[0] for m in PY_MUTATIONS])
+def test_planted_numpy_mistake_fails_a_pin(monkeypatch, name, attr, make, pin_names):
+    monkeypatch.setattr(O, attr, make(getattr(O, attr)))
+    failed = []
+    for pn in pin_names:
+        try:
+            _call(pn)
+        except AssertionError:
+            failed.append(pn)
+    assert failed, f"no pin caught: {name}"

@@ -770,3 +770,124 @@ def test_medium_ring_gradient_converges_to_fd_of_brute_force_values():
     assert rel_se < 0.04, rel_se
     slope = np.polyfit(np.log([1024, 4096, 16384]), np.log(errs), 1)[0]
     assert slope <= -0.35 and errs[-1] <= 0.08, (errs, slope)
+
+
+# ---------------------------------------------------------------------------
+# Anisotropic cache points (Sec. 5, Eq. radiusAniso3D: ellipsoidal valid
+# regions along the Hessian's eigenvectors)
+# ---------------------------------------------------------------------------
+def _random_axes(rng, K, lo=0.02, hi=0.3):
+    R = rng.uniform(lo, hi, (K, 3)).astype(np.float32)
+    V = np.stack([np.linalg.qr(rng.normal(size=(3, 3)))[0].T for _ in range(K)]).astype(np.float32)
+    return R, V
+
+
+def _form_matrix(f):
+    f = np.asarray(f, np.float64)
+    return np.array([[f[0], f[1], f[2]], [f[1], f[3], f[4]], [f[2], f[4], f[5]]])
+
+
+def test_ellipsoid_form_has_the_axes_as_eigenvectors():
+    rng = np.random.default_rng(501)
+    R, V = _random_axes(rng, 64)
+    F = O.ellipsoid_form(R, V)
+    for k in range(64):
+        M = _form_matrix(F[k])
+        for i in range(3):
+            v = V[k, i].astype(np.float64)
+            np.testing.assert_allclose(M @ v, v / float(R[k, i]) ** 2, rtol=0, atol=2e-5 / float(R[k, i]) ** 2)
+
+
+def test_ellipsoid_membership_along_and_off_the_axes():
+    rng = np.random.default_rng(502)
+    R, V = _random_axes(rng, 40)
+    F = O.ellipsoid_form(R, V)
+    p = rng.uniform(0.3, 0.7, (40, 3)).astype(np.float32)
+    for k in range(40):
+        for i in range(3):
+            for s, inside in ((0.999, True), (1.001, False), (-0.999, True), (-1.001, False)):
+                q = (p[k].astype(np.float64) + s * float(R[k, i]) * V[k, i]).astype(np.float32)
+                assert bool(O._within_form32(q, p[k], F[k])) == inside, (k, i, s)
+    # random offsets: the FP32 decision equals the exact one away from the surface
+    for k in range(40):
+        d = rng.uniform(-0.35, 0.35, (500, 3))
+        q = (p[k].astype(np.float64) + d).astype(np.float32)
+        dd = q.astype(np.float64) - p[k].astype(np.float64)
+        exact = ((dd @ V[k].astype(np.float64).T) ** 2 / R[k].astype(np.float64) ** 2).sum(1)
+        got = O._within_form32(q, p[k][None, :], F[k][None, :])
+        far = np.abs(exact - 1) > 1e-4
+        assert far.sum() > 400
+        assert np.array_equal(got[far], exact[far] < 1)
+
+
+def test_equal_radii_ellipsoid_is_the_ball():
+    rng = np.random.default_rng(503)
+    C = 400
+    cand = rng.uniform(0, 1, (C, 3)).astype(np.float32)
+    Rb = np.float32(0.11)
+    R = np.full((C, 3), Rb, np.float32)
+    _, V = _random_axes(rng, C)
+    F = O.ellipsoid_form(R, V)
+    np.testing.assert_allclose(F[:, [0, 3, 5]], 1 / float(Rb) ** 2, rtol=2e-6)
+    np.testing.assert_allclose(F[:, [1, 2, 4]], 0, atol=2e-6 / float(Rb) ** 2)
+    # keep candidates whose pairwise distances stay clear of R, where rounding could differ
+    d = np.linalg.norm(cand[:, None, :].astype(np.float64) - cand[None, :, :], axis=-1)
+    near = (np.abs(d - float(Rb)) < 1e-4 * float(Rb)).any(1)
+    cand = cand[~near]
+    keep_f = F[~near]
+    a = O.greedy_cover(cand, np.full(len(cand), Rb, np.float32))
+    b = O.greedy_cover(cand, np.full(len(cand), Rb, np.float32), form=keep_f)
+    assert len(a) > 20 and np.array_equal(a, b)
+
+
+def test_anisotropic_greedy_cover_satisfies_the_sequential_rule():
+    """Brute force: each candidate is accepted iff no earlier accepted point's
+    ellipsoid contains it (the rule characterises the sequential output)."""
+    rng = np.random.default_rng(504)
+    C = 300
+    cand = rng.uniform(0, 1, (C, 3)).astype(np.float32)
+    R, V = _random_axes(rng, C, 0.03, 0.25)
+    F = O.ellipsoid_form(R, V)
+    acc = O.greedy_cover(cand, R.min(1), form=F)
+    is_acc = np.zeros(C, bool)
+    is_acc[acc] = True
+    assert np.all(np.diff(acc) > 0) and 10 < len(acc) < C
+    for i in range(C):
+        earlier = [j for j in acc if j < i]
+        inside = any(bool(O._within_form32(cand[i], cand[j], F[j])) for j in earlier)
+        assert is_acc[i] == (not inside), i
+    # anisotropy matters: the ball of the smallest radius gives another cover
+    assert not np.array_equal(acc, O.greedy_cover(cand, R.min(1)))
+
+
+def test_anisotropic_interpolation_single_point_and_ball_limit():
+    rng = np.random.default_rng(505)
+    R, V = _random_axes(rng, 1, 0.1, 0.3)
+    F = O.ellipsoid_form(R, V)
+    p = np.array([[0.5, 0.5, 0.5]], np.float32)
+    val = np.array([2.0])
+    grad = np.array([[0.3, -0.2, 0.5]])
+    for i in range(3):
+        for s in (0.25, 0.5, 0.9):
+            q = (p[0].astype(np.float64) + s * float(R[0, i]) * V[0, i]).astype(np.float32)
+            L, cov = O.interpolate(p, val, grad, R.min(1), q[None, :], cache_form=F)
+            assert cov[0]
+            np.testing.assert_allclose(L[0], 2.0 + grad[0] @ (q.astype(np.float64) - p[0]), rtol=1e-12)
+        q = (p[0].astype(np.float64) + 1.01 * float(R[0, i]) * V[0, i]).astype(np.float32)
+        L, cov = O.interpolate(p, val, grad, R.min(1), q[None, :], cache_form=F)
+        assert not cov[0] and L[0] == 0
+    # several points with equal radii: the ellipsoid weights are the ball's
+    K = 30
+    cp = rng.uniform(0.3, 0.7, (K, 3)).astype(np.float32)
+    Rb = np.full(K, 0.15, np.float32)
+    _, VV = _random_axes(rng, K)
+    FF = O.ellipsoid_form(np.repeat(Rb[:, None], 3, 1), VV)
+    cv = rng.uniform(1, 2, K)
+    cg = rng.normal(size=(K, 3))
+    qs = rng.uniform(0.3, 0.7, (200, 3)).astype(np.float32)
+    d = np.linalg.norm(qs[:, None, :].astype(np.float64) - cp[None].astype(np.float64), axis=-1)
+    qs = qs[~(np.abs(d - 0.15) < 1e-4).any(1)]
+    a, ca = O.interpolate(cp, cv, cg, Rb, qs)
+    b, cb = O.interpolate(cp, cv, cg, Rb, qs, cache_form=FF)
+    assert np.array_equal(ca, cb) and ca.sum() > 100
+    np.testing.assert_allclose(b, a, rtol=1e-5)
