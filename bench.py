@@ -148,6 +148,9 @@ def learned_vs_plain(dev):
            "plain_by_batch": r["plain_by_batch"]}
     for k in ("reference", "epsilon", "error_band"):
         res[k] = r[k]
+    an = r["anisotropic_plain"]
+    res["anisotropic_plain"] = {k: an[k] for k in keep if k in an}
+    res["anisotropic_plain"]["candidates_per_s"] = r["candidates"] / an["seconds"]
     res["plain"]["candidates_per_s"] = r["candidates"] / pl["seconds"]
     res["learned"]["candidates_per_s"] = r["candidates"] / lp["seconds"]
     res["speedup"] = pl["seconds"] / lp["seconds"]

@@ -441,6 +441,15 @@ int rc_mlp_train_step(void* params, float* state, const float* X, const float* t
  *           must lie in cell lo + [i, i+1) * cell (host float[3] each) up to
  *           rounding; dims host int32[3], product < 2^31; cand and covered
  *           hold exactly dims[0] * dims[1] * dims[2] candidates.
+ * Anisotropic points (Sec. 5, Eq. radiusAniso3D: the valid region is an
+ * ellipsoid along the Hessian's eigenvectors): with batch_form (device
+ * float[batch][6], from rc_ellipsoid_form) accept tests the ellipsoids of
+ * the batch and appends them to accepted_form (device float[.][6]); cover
+ * and cover_grid test accepted_form if it is not NULL.  The test is
+ * d^T M d < 1 with d = candidate - point, evaluated in FP32 as
+ * ((m00 dx^2 + m11 dy^2) + m22 dz^2) + 2 ((m01 dx dy + m02 dx dz) + m12 dy dz);
+ * batch_R / accepted_R then hold the ellipsoid's largest radius (the grid
+ * search bound).  NULL forms: balls, as above.
  * Errors: EINVAL for NULL pointers, sizes out of range, a bad batch size or a
  * bad grid; the kernels themselves only read indices the state holds. */
 int rc_place_gather(const float* cand, const float* radius, const int32_t* order, int64_t C, const uint8_t* covered,
@@ -448,12 +457,19 @@ int rc_place_gather(const float* cand, const float* radius, const int32_t* order
 int rc_place_accept(const float* cand, const int32_t* batch_idx, const float* batch_R, uint8_t* covered,
                     int32_t* state, int32_t* accepted, float* accepted_R, float* accepted_pos,
                     const double* batch_value, const double* batch_grad, double* cache_value, double* cache_grad,
-                    void* stream);
+                    const float* batch_form, float* accepted_form, void* stream);
 int rc_place_cover(const float* cand, int64_t C, uint8_t* covered, const int32_t* state, const int32_t* accepted,
-                   const float* accepted_R, int64_t first, int64_t count, void* stream);
+                   const float* accepted_R, int64_t first, int64_t count, const float* accepted_form, void* stream);
 int rc_place_cover_grid(const float* cand, const int32_t dims[3], const float lo[3], const float cell[3],
                         uint8_t* covered, const int32_t* state, const int32_t* accepted, const float* accepted_R,
-                        int64_t first, int64_t count, void* stream);
+                        int64_t first, int64_t count, const float* accepted_form, void* stream);
+
+/* The ellipsoid of anisotropic points (Sec. 5, Eq. radiusAniso3D) from the
+ * axes rc_radius writes (device float[K][12]): form[k] = (m00, m01, m02, m11,
+ * m12, m22) of M = sum_i v_i v_i^T / R_i^2 (each entry formed in FP64, terms
+ * in axis order, rounded once to FP32), device float[K][6]; r_max (device
+ * float[K] or NULL) = the largest R_i. */
+int rc_ellipsoid_form(const float* axes, int64_t K, float* form, float* r_max, void* stream);
 
 /* Radiance from a cache (Sec. 5, Eq. radianceTaylor): weighted first-order
  * Taylor expansions of every cache point whose radius contains the query,
@@ -461,10 +477,13 @@ int rc_place_cover_grid(const float* cand, const int32_t dims[3], const float lo
  * [K][2] and cache_grad [K][2][3] are records (channels summed).  out device
  * double[Q] (0 where uncovered), hits device int32[Q] or NULL.  With
  * ref_value (device double[Q][2]) each block of 256 queries writes the sums
- * of (out - ref)^2 and ref^2 over its covered queries to err_partial[2b..]. */
+ * of (out - ref)^2 and ref^2 over its covered queries to err_partial[2b..].
+ * cache_form (device float[K][6] or NULL): anisotropic points, membership by
+ * the FP32 ellipsoid test of rc_place_accept and d = 1 - sqrt(e) with e the
+ * FP64 value of d^T M d (cache_R is then not read). */
 int rc_interp(const float* cache_pos, const double* cache_value, const double* cache_grad, const float* cache_R,
               int64_t K, const float* query, int64_t Q, double* out, int32_t* hits, const double* ref_value,
-              double* err_partial, void* stream);
+              double* err_partial, const float* cache_form, void* stream);
 
 /* ------------------------------------------------------------------ */
 /* Diagnostics                                                          */

@@ -1046,30 +1046,32 @@ int rc_place_gather(const float* cand, const float* radius, const int32_t* order
 int rc_place_accept(const float* cand, const int32_t* batch_idx, const float* batch_R, uint8_t* covered,
                     int32_t* state, int32_t* accepted, float* accepted_R, float* accepted_pos,
                     const double* batch_value, const double* batch_grad, double* cache_value, double* cache_grad,
-                    void* stream) {
+                    const float* batch_form, float* accepted_form, void* stream) {
   if (!cand || !batch_idx || !batch_R || !covered || !state || !accepted || !accepted_R)
     return fail(RC_EINVAL, "NULL pointer");
+  if (!batch_form != !accepted_form) return fail(RC_EINVAL, "batch_form and accepted_form: both or neither");
   const bool any = batch_value || batch_grad || cache_value || cache_grad;
   const bool all = batch_value && batch_grad && cache_value && cache_grad;
   if (any && !all) return fail(RC_EINVAL, "batch_value, batch_grad, cache_value, cache_grad: all or none");
-  RC_HIP(rc::launch_place_accept(cand, batch_idx, batch_R, covered, state, accepted, accepted_R, accepted_pos,
-                                 batch_value, batch_grad, cache_value, cache_grad, static_cast<hipStream_t>(stream)));
+  RC_HIP(rc::launch_place_accept(cand, batch_idx, batch_R, batch_form, covered, state, accepted, accepted_R,
+                                 accepted_form, accepted_pos, batch_value, batch_grad, cache_value, cache_grad,
+                                 static_cast<hipStream_t>(stream)));
   return RC_OK;
 }
 
 int rc_place_cover(const float* cand, int64_t C, uint8_t* covered, const int32_t* state, const int32_t* accepted,
-                   const float* accepted_R, int64_t first, int64_t count, void* stream) {
+                   const float* accepted_R, int64_t first, int64_t count, const float* accepted_form, void* stream) {
   if (C < 0 || C > 0x7fffffff || !cand || !covered || !accepted || !accepted_R || (first < 0 && !state))
     return fail(RC_EINVAL, "invalid arguments");
   if (first > 0x7fffffff || count < 0 || count > 0x7fffffff) return fail(RC_EINVAL, "first/count out of range");
-  RC_HIP(rc::launch_place_cover(cand, (int)C, covered, state, accepted, accepted_R, (int)first, (int)count,
-                                static_cast<hipStream_t>(stream)));
+  RC_HIP(rc::launch_place_cover(cand, (int)C, covered, state, accepted, accepted_R, accepted_form, (int)first,
+                                (int)count, static_cast<hipStream_t>(stream)));
   return RC_OK;
 }
 
 int rc_place_cover_grid(const float* cand, const int32_t dims[3], const float lo[3], const float cell[3],
                         uint8_t* covered, const int32_t* state, const int32_t* accepted, const float* accepted_R,
-                        int64_t first, int64_t count, void* stream) {
+                        int64_t first, int64_t count, const float* accepted_form, void* stream) {
   if (!cand || !dims || !lo || !cell || !covered || !accepted || !accepted_R || (first < 0 && !state))
     return fail(RC_EINVAL, "NULL pointer");
   if (first > 0x7fffffff || count < 0 || count > 0x7fffffff) return fail(RC_EINVAL, "first/count out of range");
@@ -1087,20 +1089,27 @@ int rc_place_cover_grid(const float* cand, const int32_t dims[3], const float lo
   g.nz = dims[2];
   g.lo = make_float3(lo[0], lo[1], lo[2]);
   g.inv_h = make_float3(1.f / cell[0], 1.f / cell[1], 1.f / cell[2]);
-  RC_HIP(rc::launch_place_cover_grid(cand, g, covered, state, accepted, accepted_R, (int)first, (int)count,
-                                     rc::kPlaceMaxBatch, static_cast<hipStream_t>(stream)));
+  RC_HIP(rc::launch_place_cover_grid(cand, g, covered, state, accepted, accepted_R, accepted_form, (int)first,
+                                     (int)count, rc::kPlaceMaxBatch, static_cast<hipStream_t>(stream)));
   return RC_OK;
 }
 
 int rc_interp(const float* cache_pos, const double* cache_value, const double* cache_grad, const float* cache_R,
               int64_t K, const float* query, int64_t Q, double* out, int32_t* hits, const double* ref_value,
-              double* err_partial, void* stream) {
+              double* err_partial, const float* cache_form, void* stream) {
   if (K < 0 || K > 0x7fffffff || Q < 0 || Q > 0x7fffffff) return fail(RC_EINVAL, "K or Q out of range");
   if ((K > 0 && (!cache_pos || !cache_value || !cache_grad || !cache_R)) || (Q > 0 && (!query || !out)) ||
       (ref_value && !err_partial))
     return fail(RC_EINVAL, "NULL pointer");
-  RC_HIP(rc::launch_interp(cache_pos, cache_value, cache_grad, cache_R, (int)K, query, (int)Q, out, hits, ref_value,
-                           err_partial, static_cast<hipStream_t>(stream)));
+  RC_HIP(rc::launch_interp(cache_pos, cache_value, cache_grad, cache_R, cache_form, (int)K, query, (int)Q, out, hits,
+                           ref_value, err_partial, static_cast<hipStream_t>(stream)));
+  return RC_OK;
+}
+
+int rc_ellipsoid_form(const float* axes, int64_t K, float* form, float* r_max, void* stream) {
+  if (K < 0 || K > 0x7fffffff) return fail(RC_EINVAL, "K out of range");
+  if (K > 0 && (!axes || !form)) return fail(RC_EINVAL, "NULL pointer");
+  RC_HIP(rc::launch_ellipsoid_form(axes, (int)K, form, r_max, static_cast<hipStream_t>(stream)));
   return RC_OK;
 }
 

@@ -717,13 +717,30 @@ RC_DEV bool within(float cx, float cy, float cz, float px, float py, float pz, f
   const float dx = cx - px, dy = cy - py, dz = cz - pz;
   return dx * dx + dy * dy + dz * dz < R * R;
 }
+// Anisotropic points (Eq. radiusAniso3D): inside the ellipsoid of the form
+// m = (m00, m01, m02, m11, m12, m22) iff d^T M d < 1, d = candidate - point,
+// every product and sum in FP32 in this order.
+RC_DEV float form_q(float dx, float dy, float dz, const float* __restrict__ m) {
+  const float diag = (m[0] * (dx * dx) + m[3] * (dy * dy)) + m[5] * (dz * dz);
+  const float off = (m[1] * (dx * dy) + m[2] * (dx * dz)) + m[4] * (dy * dz);
+  return diag + 2.f * off;
+}
+RC_DEV bool within_form(float cx, float cy, float cz, float px, float py, float pz, const float* __restrict__ m) {
+  return form_q(cx - px, cy - py, cz - pz, m) < 1.f;
+}
+// Is candidate c inside the valid region of point p with radius R (ball) or
+// form m (ellipsoid, if m is not null)?
+RC_DEV bool inside(float cx, float cy, float cz, float px, float py, float pz, float R, const float* __restrict__ m) {
+  return m ? within_form(cx, cy, cz, px, py, pz, m) : within(cx, cy, cz, px, py, pz, R);
+}
 
 // Verdict of batch entry j from the entries i < j, one lane per i: 2 if an
 // accepted entry covers j, 0 if an undecided one does (and no accepted one),
-// else 1.  ps: x, y, z, R of the batch; status(i) reads entry i's state
-// (0 undecided, 1 accepted, 2 rejected).  Called by all 64 lanes of a wave.
+// else 1.  ps: x, y, z, R of the batch; form: the batch's ellipsoids
+// ([batch][6]) or null (balls); status(i) reads entry i's state (0
+// undecided, 1 accepted, 2 rejected).  Called by all 64 lanes of a wave.
 template <typename Status>
-RC_DEV int wave_verdict(const float4* ps, int j, Status status, int lane) {
+RC_DEV int wave_verdict(const float4* ps, const float* __restrict__ form, int j, Status status, int lane) {
   const float4 pj = ps[j];
   bool und = false;
   for (int i0 = 0; i0 < j; i0 += kWave) {
@@ -731,7 +748,7 @@ RC_DEV int wave_verdict(const float4* ps, int j, Status status, int lane) {
     bool acc = false;
     if (i < j) {
       const float4 pi = ps[i];
-      if (within(pj.x, pj.y, pj.z, pi.x, pi.y, pi.z, pi.w)) {
+      if (inside(pj.x, pj.y, pj.z, pi.x, pi.y, pi.z, pi.w, form ? form + 6 * i : nullptr)) {
         const int si = status(i);
         acc = si == 1;
         und = und || si == 0;
@@ -810,6 +827,7 @@ __global__ __launch_bounds__(kPlaceThreads) void place_gather_kernel(const float
 __global__ __launch_bounds__(kPlaceResolveThreads) void place_resolve_kernel(const float* __restrict__ cand,
                                                                            const int* __restrict__ batch_idx,
                                                                            const float* __restrict__ batch_R,
+                                                                           const float* __restrict__ batch_form,
                                                                            int* __restrict__ state) {
   __shared__ float4 ps[kPlaceMaxBatch];
   constexpr int kWaves = kPlaceResolveThreads / kWave;
@@ -826,7 +844,7 @@ __global__ __launch_bounds__(kPlaceResolveThreads) void place_resolve_kernel(con
   const int j = j0 + threadIdx.x / kWave;
   volatile int* stv = state + kPlaceStatus;
   if (j >= m || stv[j] != 0) return;
-  const int verdict = wave_verdict(ps, j, [stv](int i) { return stv[i]; }, lane);
+  const int verdict = wave_verdict(ps, batch_form, j, [stv](int i) { return stv[i]; }, lane);
   if (verdict != 0 && lane == 0) stv[j] = verdict;
 }
 
@@ -838,9 +856,10 @@ __global__ __launch_bounds__(kPlaceResolveThreads) void place_resolve_kernel(con
 // decision; the smallest undecided entry is always decided in the next pass.
 __global__ __launch_bounds__(kPlaceThreads) void place_accept_kernel(
     const float* __restrict__ cand, const int* __restrict__ batch_idx, const float* __restrict__ batch_R,
-    unsigned char* __restrict__ covered, int* __restrict__ state, int* __restrict__ accepted,
-    float* __restrict__ accepted_R, float* __restrict__ accepted_pos, const double* __restrict__ bval,
-    const double* __restrict__ bgrad, double* __restrict__ cval, double* __restrict__ cgrad) {
+    const float* __restrict__ batch_form, unsigned char* __restrict__ covered, int* __restrict__ state,
+    int* __restrict__ accepted, float* __restrict__ accepted_R, float* __restrict__ accepted_form,
+    float* __restrict__ accepted_pos, const double* __restrict__ bval, const double* __restrict__ bgrad,
+    double* __restrict__ cval, double* __restrict__ cgrad) {
   __shared__ float4 ps[kPlaceMaxBatch];  // x, y, z, R of the batch
   __shared__ unsigned char st[kPlaceMaxBatch];  // 0 undecided, 1 accepted, 2 rejected
   __shared__ int wtot[kPlaceThreads / kWave];
@@ -861,7 +880,7 @@ __global__ __launch_bounds__(kPlaceThreads) void place_accept_kernel(
     for (int j = wv; j < m; j += kPlaceThreads / kWave) {  // one wave per entry
       if (*(volatile unsigned char*)&st[j] != 0) continue;
       volatile unsigned char* stv = st;
-      const int verdict = wave_verdict(ps, j, [stv](int i) { return (int)stv[i]; }, lane);
+      const int verdict = wave_verdict(ps, batch_form, j, [stv](int i) { return (int)stv[i]; }, lane);
       if (verdict != 0) {
         if (lane == 0) *(volatile unsigned char*)&st[j] = (unsigned char)verdict;
       } else {
@@ -892,6 +911,10 @@ __global__ __launch_bounds__(kPlaceThreads) void place_accept_kernel(
       const float4 p = ps[j];
       accepted[dst] = batch_idx[j];
       accepted_R[dst] = p.w;
+      if (accepted_form) {
+#pragma unroll
+        for (int e = 0; e < 6; e++) accepted_form[6 * dst + e] = batch_form[6 * j + e];
+      }
       if (accepted_pos) {
         accepted_pos[3 * dst] = p.x;
         accepted_pos[3 * dst + 1] = p.y;
@@ -918,7 +941,8 @@ __global__ __launch_bounds__(kPlaceThreads) void place_accept_kernel(
 
 __global__ void place_cover_kernel(const float* __restrict__ cand, int C, unsigned char* __restrict__ covered,
                                    const int* __restrict__ state, const int* __restrict__ accepted,
-                                   const float* __restrict__ accepted_R, int first, int count) {
+                                   const float* __restrict__ accepted_R, const float* __restrict__ accepted_form,
+                                   int first, int count) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= C || covered[i]) return;
   const int b = first >= 0 ? first : state[2];
@@ -926,7 +950,8 @@ __global__ void place_cover_kernel(const float* __restrict__ cand, int C, unsign
   const float cx = cand[3 * i], cy = cand[3 * i + 1], cz = cand[3 * i + 2];
   for (int a = 0; a < nn; a++) {
     const int p = accepted[b + a];
-    if (within(cx, cy, cz, cand[3 * p], cand[3 * p + 1], cand[3 * p + 2], accepted_R[b + a])) {
+    if (inside(cx, cy, cz, cand[3 * p], cand[3 * p + 1], cand[3 * p + 2], accepted_R[b + a],
+               accepted_form ? accepted_form + 6 * (b + a) : nullptr)) {
       covered[i] = 1;
       return;
     }
@@ -937,12 +962,13 @@ __global__ void place_cover_kernel(const float* __restrict__ cand, int C, unsign
 // and lies in cell lo + [i, i + 1) * h.  One wavefront per accepted point
 // visits the cells of the point's bounding box grown by one cell (so that
 // rounding at cell faces cannot hide a candidate) and marks the candidates
-// within its radius.
+// within its radius (or ellipsoid, whose largest radius bounds the box).
 __global__ __launch_bounds__(256) void place_cover_grid_kernel(const float* __restrict__ cand, PlaceGrid g,
                                                                unsigned char* __restrict__ covered,
                                                                const int* __restrict__ state,
                                                                const int* __restrict__ accepted,
-                                                               const float* __restrict__ accepted_R, int first,
+                                                               const float* __restrict__ accepted_R,
+                                                               const float* __restrict__ accepted_form, int first,
                                                                int count) {
   const int lane = threadIdx.x & (kWave - 1);
   const int b = first >= 0 ? first : state[2];
@@ -950,8 +976,9 @@ __global__ __launch_bounds__(256) void place_cover_grid_kernel(const float* __re
   for (int a = blockIdx.x * 4 + (threadIdx.x >> 6); a < nn; a += gridDim.x * 4) {
     const int p = accepted[b + a];
     const float px = cand[3 * p], py = cand[3 * p + 1], pz = cand[3 * p + 2];
-    const float R = accepted_R[b + a];
+    const float R = accepted_R[b + a];  // ball radius, or the ellipsoid's largest radius
     if (!(R > 0.f) || !(R < 3.0e38f)) continue;
+    const float* m = accepted_form ? accepted_form + 6 * (b + a) : nullptr;
     int lo3[3], n3[3];
     const float pc[3] = {px, py, pz};
     const float glo[3] = {g.lo.x, g.lo.y, g.lo.z}, gih[3] = {g.inv_h.x, g.inv_h.y, g.inv_h.z};
@@ -973,7 +1000,7 @@ __global__ __launch_bounds__(256) void place_cover_grid_kernel(const float* __re
       const int iy = lo3[1] + r / n3[2], iz = lo3[2] + r % n3[2];
       const int c = (ix * g.ny + iy) * g.nz + iz;
       if (covered[c]) continue;
-      if (within(cand[3 * c], cand[3 * c + 1], cand[3 * c + 2], px, py, pz, R)) covered[c] = 1;
+      if (inside(cand[3 * c], cand[3 * c + 1], cand[3 * c + 2], px, py, pz, R, m)) covered[c] = 1;
     }
   }
 }
@@ -982,17 +1009,21 @@ __global__ __launch_bounds__(256) void place_cover_grid_kernel(const float* __re
 // Cache interpolation (Eq. radianceTaylor): first-order Taylor from every
 // cache point whose radius contains x', cubic kernel w = 3d^2 - 2d^3,
 // d = 1 - |x' - x_k| / R_k; FP64 accumulation.  Brute force over the cache.
+// Anisotropic points: membership d^T M d < 1 (FP32) and d = 1 - sqrt(d^T M d)
+// (FP64).
 // ---------------------------------------------------------------------------
 // cval [K][2] and cgrad [K][2][3] are records (the two channels are summed);
 // if ref [Q][2] is given, block b writes (sum (L - L_ref)^2, sum L_ref^2) over
 // its covered queries to err[2b], err[2b+1].
 __global__ __launch_bounds__(256) void interp_kernel(const float* __restrict__ cpos, const double* __restrict__ cval,
                                                      const double* __restrict__ cgrad, const float* __restrict__ cR,
-                                                     int K, const float* __restrict__ q, int Q, double* __restrict__ out,
+                                                     const float* __restrict__ cform, int K,
+                                                     const float* __restrict__ q, int Q, double* __restrict__ out,
                                                      int* __restrict__ hits, const double* __restrict__ ref,
                                                      double* __restrict__ err) {
   __shared__ double rs[2][256];
   __shared__ float sp[256 * 4];
+  __shared__ float sf[256 * 6];
   __shared__ double sv[256 * 4];
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   const float qx = i < Q ? q[3 * i] : 0.f, qy = i < Q ? q[3 * i + 1] : 0.f, qz = i < Q ? q[3 * i + 2] : 0.f;
@@ -1006,6 +1037,8 @@ __global__ __launch_bounds__(256) void interp_kernel(const float* __restrict__ c
       sp[4 * threadIdx.x + 1] = cpos[3 * k + 1];
       sp[4 * threadIdx.x + 2] = cpos[3 * k + 2];
       sp[4 * threadIdx.x + 3] = cR[k];
+      if (cform)
+        for (int e = 0; e < 6; e++) sf[6 * threadIdx.x + e] = cform[6 * k + e];
       sv[4 * threadIdx.x] = cval[2 * k] + cval[2 * k + 1];
       sv[4 * threadIdx.x + 1] = cgrad[6 * k] + cgrad[6 * k + 3];
       sv[4 * threadIdx.x + 2] = cgrad[6 * k + 1] + cgrad[6 * k + 4];
@@ -1015,10 +1048,23 @@ __global__ __launch_bounds__(256) void interp_kernel(const float* __restrict__ c
     const int m = (K - base) < 256 ? (K - base) : 256;
     for (int j = 0; j < m; j++) {
       const float dx = qx - sp[4 * j], dy = qy - sp[4 * j + 1], dz = qz - sp[4 * j + 2], R = sp[4 * j + 3];
-      const float d2 = dx * dx + dy * dy + dz * dz;
-      if (d2 < R * R) {
-        const double dist = sqrt((double)d2);
-        const double d = 1.0 - dist / (double)R;
+      bool in;
+      double d;  // 1 - normalised distance: 1 at the point, 0 on the region's boundary
+      if (cform) {
+        const float* m = sf + 6 * j;
+        in = form_q(dx, dy, dz, m) < 1.f;
+        // the weight from the form in FP64 (the FP32 value cancels near the point)
+        const double ex = (double)qx - (double)sp[4 * j], ey = (double)qy - (double)sp[4 * j + 1],
+                     ez = (double)qz - (double)sp[4 * j + 2];
+        const double diag = ((double)m[0] * (ex * ex) + (double)m[3] * (ey * ey)) + (double)m[5] * (ez * ez);
+        const double off = ((double)m[1] * (ex * ey) + (double)m[2] * (ex * ez)) + (double)m[4] * (ey * ez);
+        d = 1.0 - sqrt(fmax(diag + 2.0 * off, 0.0));
+      } else {
+        const float d2 = dx * dx + dy * dy + dz * dz;
+        in = d2 < R * R;
+        d = 1.0 - sqrt((double)d2) / (double)R;
+      }
+      if (in) {
         const double w = 3.0 * d * d - 2.0 * d * d * d;
         const double L = sv[4 * j] + sv[4 * j + 1] * dx + sv[4 * j + 2] * dy + sv[4 * j + 3] * dz;
         num += w * L;
@@ -1050,6 +1096,30 @@ __global__ __launch_bounds__(256) void interp_kernel(const float* __restrict__ c
       err[2 * blockIdx.x + 1] = rs[1][0];
     }
   }
+}
+
+// Ellipsoid of an anisotropic point from the axes the radius kernel writes
+// ([12]: R_1..R_3, then the unit eigenvectors as rows): form entries
+// sum_i (v_i[a] v_i[b]) / (R_i R_i) in FP64 (axis order), rounded to FP32,
+// and the largest radius (bounds the ellipsoid).
+__global__ void ellipsoid_form_kernel(const float* __restrict__ axes, int K, float* __restrict__ form,
+                                      float* __restrict__ Rmax) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= K) return;
+  const float* a = axes + 12 * k;
+  double R2[3], v[3][3];
+  for (int i = 0; i < 3; i++) {
+    R2[i] = (double)a[i] * (double)a[i];
+    for (int c = 0; c < 3; c++) v[i][c] = (double)a[3 + 3 * i + c];
+  }
+  const int ea[6] = {0, 0, 0, 1, 1, 2}, eb[6] = {0, 1, 2, 1, 2, 2};
+  for (int e = 0; e < 6; e++) {
+    const double t0 = (v[0][ea[e]] * v[0][eb[e]]) / R2[0];
+    const double t1 = (v[1][ea[e]] * v[1][eb[e]]) / R2[1];
+    const double t2 = (v[2][ea[e]] * v[2][eb[e]]) / R2[2];
+    form[6 * k + e] = (float)((t0 + t1) + t2);
+  }
+  if (Rmax) Rmax[k] = fmaxf(fmaxf(a[0], a[1]), a[2]);
 }
 
 // ---------------------------------------------------------------------------
@@ -1113,46 +1183,55 @@ hipError_t launch_place_gather(const float* cand, const float* radius, const int
   return hipGetLastError();
 }
 
-hipError_t launch_place_accept(const float* cand, const int* batch_idx, const float* batch_R, unsigned char* covered,
-                               int* state, int* accepted, float* accepted_R, float* accepted_pos, const double* bval,
-                               const double* bgrad, double* cval, double* cgrad, hipStream_t s) {
+hipError_t launch_place_accept(const float* cand, const int* batch_idx, const float* batch_R, const float* batch_form,
+                               unsigned char* covered, int* state, int* accepted, float* accepted_R,
+                               float* accepted_form, float* accepted_pos, const double* bval, const double* bgrad,
+                               double* cval, double* cgrad, hipStream_t s) {
   // a few wide passes decide almost every entry; the one-workgroup kernel
   // finishes whatever chains of coverers remain and appends the result
   for (int pass = 0; pass < kPlacePasses; pass++)
     hipLaunchKernelGGL(place_resolve_kernel, dim3(kPlaceMaxBatch / (kPlaceResolveThreads / kWave)),
-                       dim3(kPlaceResolveThreads), 0, s, cand, batch_idx, batch_R, state);
-  hipLaunchKernelGGL(place_accept_kernel, dim3(1), dim3(kPlaceThreads), 0, s, cand, batch_idx, batch_R, covered, state,
-                     accepted, accepted_R, accepted_pos, bval, bgrad, cval, cgrad);
+                       dim3(kPlaceResolveThreads), 0, s, cand, batch_idx, batch_R, batch_form, state);
+  hipLaunchKernelGGL(place_accept_kernel, dim3(1), dim3(kPlaceThreads), 0, s, cand, batch_idx, batch_R, batch_form,
+                     covered, state, accepted, accepted_R, accepted_form, accepted_pos, bval, bgrad, cval, cgrad);
   return hipGetLastError();
 }
 
 hipError_t launch_place_cover(const float* cand, int C, unsigned char* covered, const int* state, const int* accepted,
-                              const float* accepted_R, int first, int count, hipStream_t s) {
+                              const float* accepted_R, const float* accepted_form, int first, int count,
+                              hipStream_t s) {
   const int blocks = (C + 255) / 256;
   if (blocks > 0)
     hipLaunchKernelGGL(place_cover_kernel, dim3(blocks), dim3(256), 0, s, cand, C, covered, state, accepted, accepted_R,
-                       first, count);
+                       accepted_form, first, count);
   return hipGetLastError();
 }
 
 hipError_t launch_place_cover_grid(const float* cand, const PlaceGrid& g, unsigned char* covered, const int* state,
-                                   const int* accepted, const float* accepted_R, int first, int count, int max_points,
-                                   hipStream_t s) {
+                                   const int* accepted, const float* accepted_R, const float* accepted_form, int first,
+                                   int count, int max_points, hipStream_t s) {
   int pts = first >= 0 ? count : max_points;
   if (pts <= 0) return hipSuccess;
   int blocks = (pts + 3) / 4;
   if (blocks > 65536) blocks = 65536;
   hipLaunchKernelGGL(place_cover_grid_kernel, dim3(blocks), dim3(256), 0, s, cand, g, covered, state, accepted,
-                     accepted_R, first, count);
+                     accepted_R, accepted_form, first, count);
   return hipGetLastError();
 }
 
-hipError_t launch_interp(const float* cpos, const double* cval, const double* cgrad, const float* cR, int K,
-                         const float* q, int Q, double* out, int* hits, const double* ref, double* err, hipStream_t s) {
+hipError_t launch_interp(const float* cpos, const double* cval, const double* cgrad, const float* cR,
+                         const float* cform, int K, const float* q, int Q, double* out, int* hits, const double* ref,
+                         double* err, hipStream_t s) {
   const int blocks = (Q + 255) / 256;
   if (blocks > 0)
-    hipLaunchKernelGGL(interp_kernel, dim3(blocks), dim3(256), 0, s, cpos, cval, cgrad, cR, K, q, Q, out, hits, ref,
-                       err);
+    hipLaunchKernelGGL(interp_kernel, dim3(blocks), dim3(256), 0, s, cpos, cval, cgrad, cR, cform, K, q, Q, out, hits,
+                       ref, err);
+  return hipGetLastError();
+}
+
+hipError_t launch_ellipsoid_form(const float* axes, int K, float* form, float* Rmax, hipStream_t s) {
+  const int blocks = (K + 255) / 256;
+  if (blocks > 0) hipLaunchKernelGGL(ellipsoid_form_kernel, dim3(blocks), dim3(256), 0, s, axes, K, form, Rmax);
   return hipGetLastError();
 }
 

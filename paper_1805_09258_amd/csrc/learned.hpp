@@ -61,16 +61,20 @@ hipError_t launch_feature_stats(const float* X, int n, float* partial, int block
 hipError_t launch_place_gather(const float* cand, const float* radius, const int* order, int C,
                                const unsigned char* covered, int* state, int* batch_idx, float* batch_pos,
                                float* batch_R, int batch, hipStream_t s);
-hipError_t launch_place_accept(const float* cand, const int* batch_idx, const float* batch_R, unsigned char* covered,
-                               int* state, int* accepted, float* accepted_R, float* accepted_pos, const double* bval,
-                               const double* bgrad, double* cval, double* cgrad, hipStream_t s);
+hipError_t launch_place_accept(const float* cand, const int* batch_idx, const float* batch_R, const float* batch_form,
+                               unsigned char* covered, int* state, int* accepted, float* accepted_R,
+                               float* accepted_form, float* accepted_pos, const double* bval, const double* bgrad,
+                               double* cval, double* cgrad, hipStream_t s);
 hipError_t launch_place_cover(const float* cand, int C, unsigned char* covered, const int* state, const int* accepted,
-                              const float* accepted_R, int first, int count, hipStream_t s);
+                              const float* accepted_R, const float* accepted_form, int first, int count,
+                              hipStream_t s);
 hipError_t launch_place_cover_grid(const float* cand, const PlaceGrid& g, unsigned char* covered, const int* state,
-                                   const int* accepted, const float* accepted_R, int first, int count, int max_points,
-                                   hipStream_t s);
-hipError_t launch_interp(const float* cpos, const double* cval, const double* cgrad, const float* cR, int K,
-                         const float* q, int Q, double* out, int* hits, const double* ref, double* err, hipStream_t s);
+                                   const int* accepted, const float* accepted_R, const float* accepted_form, int first,
+                                   int count, int max_points, hipStream_t s);
+hipError_t launch_interp(const float* cpos, const double* cval, const double* cgrad, const float* cR,
+                         const float* cform, int K, const float* q, int Q, double* out, int* hits, const double* ref,
+                         double* err, hipStream_t s);
+hipError_t launch_ellipsoid_form(const float* axes, int K, float* form, float* Rmax, hipStream_t s);
 hipError_t launch_mlp_init(void* params, float* state, unsigned long long seed, hipStream_t s);
 hipError_t launch_mlp_sync(void* params, const float* master, hipStream_t s);
 

@@ -47,6 +47,7 @@ class CacheConfig:
     batch: int = 4096            # candidates per round (plain and learned)
     common_random: bool = True   # every record draws the same random numbers (id record_id)
     record_id: int = 7_000_003   # that id
+    anisotropic: bool = False    # plain pipeline: ellipsoidal points (Eq. radiusAniso3D) instead of balls
 
 
 class SceneContext:
@@ -101,9 +102,10 @@ class PlacementResult:
     pos: object                  # device float[K][3]
     value: object                # device double[K][2]
     grad: object                 # device double[K][2][3]
-    R: object                    # device float[K] (true radii)
+    R: object                    # device float[K] (true radii; the largest axis for ellipsoids)
     K: int
     stats: dict = field(default_factory=dict)
+    form: object = None          # device float[K][6] (ellipsoids of anisotropic points) or None
 
 
 class Placer:
@@ -129,6 +131,12 @@ class Placer:
         self.acc = torch.zeros(C, dtype=torch.int32, device=device)
         self.accR = torch.zeros(C, dtype=torch.float32, device=device)
         self.accpos = torch.zeros((C, 3), dtype=torch.float32, device=device)
+        if cfg.anisotropic:
+            self.baxes = torch.zeros((B, 12), dtype=torch.float32, device=device)
+            self.bform = torch.zeros((B, 6), dtype=torch.float32, device=device)
+            self.accform = torch.zeros((C, 6), dtype=torch.float32, device=device)
+        else:
+            self.baxes = self.bform = self.accform = None
         self.cval = torch.zeros((C, 2), dtype=torch.float64, device=device)
         self.cgrad = torch.zeros((C, 2, 3), dtype=torch.float64, device=device)
         n = max(B, 1)
@@ -157,9 +165,10 @@ class Placer:
                            order=self.order)
         return int(self.state[4].item())
 
-    def _cover_last_round(self):
+    def _cover_last_round(self, form=None):
         c = self.cands
-        rc.rc_place_cover_grid(self.cand, c.dims, c.lo, c.cell, self.covered, self.state, self.acc, self.accR)
+        rc.rc_place_cover_grid(self.cand, c.dims, c.lo, c.cell, self.covered, self.state, self.acc, self.accR,
+                               accepted_form=form)
 
     def _plain_rounds(self, batch=None):
         """Rounds with full records until every candidate is decided."""
@@ -170,17 +179,23 @@ class Placer:
             if m == 0:
                 break
             self._records(self.bpos[:m], self.bval, self.bgrad, self.bhess, self.bws, self.nth, self.nph)
-            rc.rc_radius(self.bval[:m], self.bhess[:m], cfg.eps, cfg.r_min, cfg.r_max, self.bR[:m])
+            aniso = cfg.anisotropic
+            rc.rc_radius(self.bval[:m], self.bhess[:m], cfg.eps, cfg.r_min, cfg.r_max, self.bR[:m],
+                         self.baxes[:m] if aniso else None)
+            if aniso:  # ellipsoids; bR becomes the largest radius (the cover's search bound)
+                rc.rc_ellipsoid_form(self.baxes[:m], self.bform[:m], self.bR[:m])
             rc.rc_place_accept(self.cand, self.bidx, self.bR, self.covered, self.state, self.acc, self.accR,
-                               self.accpos, self.bval, self.bgrad, self.cval, self.cgrad)
-            self._cover_last_round()
+                               self.accpos, self.bval, self.bgrad, self.cval, self.cgrad,
+                               batch_form=self.bform if aniso else None, accepted_form=self.accform if aniso else None)
+            self._cover_last_round(self.accform if aniso else None)
             rounds += 1
             records += m
         return rounds, records
 
-    def _result(self, stats):
+    def _result(self, stats, form=None):
         K = int(self.state[1].item())
-        return PlacementResult(self.accpos[:K], self.cval[:K], self.cgrad[:K], self.accR[:K], K, stats)
+        return PlacementResult(self.accpos[:K], self.cval[:K], self.cgrad[:K], self.accR[:K], K, stats,
+                               None if form is None else form[:K])
 
     # -- pipelines ------------------------------------------------------------
     def plain(self, batch=None):
@@ -192,7 +207,8 @@ class Placer:
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
         res = self._result({"seconds": dt, "rounds": rounds, "records": records,
-                            "batch": self.cfg.batch if batch is None else min(int(batch), self.cfg.batch)})
+                            "batch": self.cfg.batch if batch is None else min(int(batch), self.cfg.batch)},
+                           self.accform)
         res.stats["accepted"] = res.K
         return res
 
@@ -241,6 +257,8 @@ class Placer:
         rounds for whatever is left (fewer than plain_below candidates, or
         after the last pass)."""
         import torch
+        if self.cfg.anisotropic:
+            raise ValueError("the learned pipeline places isotropic points (the network predicts one radius)")
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         self._reset()
@@ -315,7 +333,7 @@ def cache_error(res: PlacementResult, query, ref_value, device, lights=None, lig
     hits = torch.zeros(Q, dtype=torch.int32, device=device)
     nb = (Q + 255) // 256
     err = torch.zeros(2 * max(nb, 1), dtype=torch.float64, device=device)
-    rc.rc_interp(res.pos, res.value, res.grad, res.R, query, out, hits, ref_value, err)
+    rc.rc_interp(res.pos, res.value, res.grad, res.R, query, out, hits, ref_value, err, cache_form=res.form)
     e = err.view(-1, 2).sum(0).cpu().numpy()
     cov = hits > 0
     ref = ref_value.sum(1)
@@ -515,6 +533,14 @@ def compare(device, train_seeds=range(1000, 1100), P_train=10_000, val_seed=1099
         if best is None or st["seconds"] < best["seconds"]:
             best = st
     out["plain"] = best
+    # the same plain pipeline with ellipsoidal points (Eq. radiusAniso3D) at the same eps and round size
+    from dataclasses import replace
+    placer_a = Placer(ctx, cands, replace(cfg, anisotropic=True), device)
+    ra = median_run(lambda: placer_a.plain(best["batch"]))
+    out["anisotropic_plain"] = dict(ra.stats, **cache_error(ra, q, ref, device, we.lights))
+    if log:
+        log("anisotropic plain", out["anisotropic_plain"])
+    del placer_a
     r = median_run(lambda: placer.learned(mlp, safety))
     out["learned"] = dict(r.stats, safety=safety, **cache_error(r, q, ref, device, we.lights))
     if log:

@@ -61,7 +61,7 @@ EXPORTS = ["rc_scene_create", "rc_scene_destroy", "rc_scene_info", "rc_bvh_build
            "rc_probe", "rc_mlp_param_bytes", "rc_mlp_n_params", "rc_mlp_init",
            "rc_mlp_load", "rc_mlp_fit_features", "rc_mlp_forward", "rc_mlp_radius", "rc_mlp_train_workspace_bytes",
            "rc_mlp_train_step", "rc_place_gather", "rc_place_accept", "rc_place_cover", "rc_place_cover_grid",
-           "rc_interp",
+           "rc_ellipsoid_form", "rc_interp",
            "rc_last_error", "rc_version"]
 
 _LIB = None
@@ -136,13 +136,15 @@ def lib():
         L.rc_mlp_train_step.restype = i32
         L.rc_place_gather.argtypes = [vp, vp, vp, i64, vp, vp, vp, vp, vp, i32, vp]
         L.rc_place_gather.restype = i32
-        L.rc_place_accept.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp]
+        L.rc_place_accept.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp]
         L.rc_place_accept.restype = i32
-        L.rc_place_cover.argtypes = [vp, i64, vp, vp, vp, vp, i64, i64, vp]
+        L.rc_place_cover.argtypes = [vp, i64, vp, vp, vp, vp, i64, i64, vp, vp]
         L.rc_place_cover.restype = i32
-        L.rc_place_cover_grid.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, i64, i64, vp]
+        L.rc_place_cover_grid.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, i64, i64, vp, vp]
         L.rc_place_cover_grid.restype = i32
-        L.rc_interp.argtypes = [vp, vp, vp, vp, i64, vp, i64, vp, vp, vp, vp, vp]
+        L.rc_ellipsoid_form.argtypes = [vp, i64, vp, vp, vp]
+        L.rc_ellipsoid_form.restype = i32
+        L.rc_interp.argtypes = [vp, vp, vp, vp, i64, vp, i64, vp, vp, vp, vp, vp, vp]
         L.rc_interp.restype = i32
         L.rc_last_error.restype = C.c_char_p
         L.rc_version.restype = C.c_char_p
@@ -391,31 +393,40 @@ def rc_place_gather(cand, radius, covered, state, batch_idx, batch_pos, batch_R,
 
 
 def rc_place_accept(cand, batch_idx, batch_R, covered, state, accepted, accepted_R, accepted_pos=None,
-                    batch_value=None, batch_grad=None, cache_value=None, cache_grad=None, stream=None):
+                    batch_value=None, batch_grad=None, cache_value=None, cache_grad=None, batch_form=None,
+                    accepted_form=None, stream=None):
     return _check(lib().rc_place_accept(_ptr(cand), _ptr(batch_idx), _ptr(batch_R), _ptr(covered), _ptr(state),
                                         _ptr(accepted), _ptr(accepted_R), _ptr(accepted_pos), _ptr(batch_value),
-                                        _ptr(batch_grad), _ptr(cache_value), _ptr(cache_grad), _stream(stream)))
+                                        _ptr(batch_grad), _ptr(cache_value), _ptr(cache_grad), _ptr(batch_form),
+                                        _ptr(accepted_form), _stream(stream)))
 
 
-def rc_place_cover(cand, covered, state, accepted, accepted_R, first=-1, count=0, stream=None):
+def rc_place_cover(cand, covered, state, accepted, accepted_R, first=-1, count=0, accepted_form=None, stream=None):
     return _check(lib().rc_place_cover(_ptr(cand), int(cand.shape[0]), _ptr(covered), _ptr(state), _ptr(accepted),
-                                       _ptr(accepted_R), int(first), int(count), _stream(stream)))
+                                       _ptr(accepted_R), int(first), int(count), _ptr(accepted_form),
+                                       _stream(stream)))
 
 
-def rc_place_cover_grid(cand, dims, lo, cell, covered, state, accepted, accepted_R, first=-1, count=0, stream=None):
+def rc_place_cover_grid(cand, dims, lo, cell, covered, state, accepted, accepted_R, first=-1, count=0,
+                        accepted_form=None, stream=None):
     d = np.ascontiguousarray(dims, np.int32)
     l0 = np.ascontiguousarray(lo, np.float32)
     ce = np.ascontiguousarray(cell, np.float32)
     return _check(lib().rc_place_cover_grid(_ptr(cand), _ptr(d), _ptr(l0), _ptr(ce), _ptr(covered), _ptr(state),
                                             _ptr(accepted), _ptr(accepted_R), int(first), int(count),
-                                            _stream(stream)))
+                                            _ptr(accepted_form), _stream(stream)))
+
+
+def rc_ellipsoid_form(axes, form, r_max=None, stream=None):
+    return _check(lib().rc_ellipsoid_form(_ptr(axes), int(axes.shape[0]), _ptr(form), _ptr(r_max),
+                                          _stream(stream)))
 
 
 def rc_interp(cache_pos, cache_value, cache_grad, cache_R, query, out, hits=None, ref_value=None, err_partial=None,
-              stream=None):
+              cache_form=None, stream=None):
     return _check(lib().rc_interp(_ptr(cache_pos), _ptr(cache_value), _ptr(cache_grad), _ptr(cache_R),
                                   int(cache_pos.shape[0]), _ptr(query), int(query.shape[0]), _ptr(out), _ptr(hits),
-                                  _ptr(ref_value), _ptr(err_partial), _stream(stream)))
+                                  _ptr(ref_value), _ptr(err_partial), _ptr(cache_form), _stream(stream)))
 
 
 def rc_version():
