@@ -369,12 +369,13 @@ int build_light_bins(const float* tri, int64_t T, float scale, const float light
 }
 
 int light_bins_size_for(int64_t T) {
-  // about 2.6 sqrt(T) bins per face side at the finest level, a power of two
-  // in [16, 1024] (10k triangles: 256, 1.4 entries read per segment; 1M
-  // triangles with slabs: 1024, 5.8)
-  const double want = 2.6 * std::sqrt((double)std::max<int64_t>(T, 1));
+  // about 2 sqrt(T) bins per face side at the finest level, a power of two in
+  // [16, 2048] (measured launch times: 100k triangles with slabs 463 ms at 512,
+  // 467 at 1024; 1M triangles 5237 ms at 512, 4819 at 1024, 4688 at 2048 with
+  // 3.9 GB of bins for four lights)
+  const double want = 2.0 * std::sqrt((double)std::max<int64_t>(T, 1));
   int B = 16;
-  while (B < 1024 && (double)B * 1.41421356 < want) B <<= 1;
+  while (B < 2048 && (double)B * 1.41421356 < want) B <<= 1;
   return B;
 }
 
