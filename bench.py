@@ -61,9 +61,11 @@ def log(*a):
 
 
 def kernel_source_hash():
+    """sha256 prefix of the sources that make the record kernel and its launches
+    (every file of paper_1805_09258_amd/csrc but the learned-placement ones)."""
     h = hashlib.sha256()
     for p in sorted((ROOT / "paper_1805_09258_amd" / "csrc").glob("*")):
-        if p.suffix in (".hip", ".hpp", ".cpp"):
+        if p.suffix in (".hip", ".hpp", ".cpp") and not p.stem.startswith("learned"):
             h.update(p.read_bytes())
     return h.hexdigest()[:16]
 
@@ -192,8 +194,11 @@ def measure(name, dev, steps, warmup, count=True):
         res["counts"] = {"rays": rays, "node_fetches": nodes, "triangle_tests": tris, "triangle_terms": terms,
                          "phase_clock_fraction": {"primary_rays": c0 / ctot, "shadow_segments": c1 / ctot,
                                                   "mc_value": c2 / ctot, "triangle_terms": c3 / ctot},
-                         "shadow_loop": {"iterations": sh_iter, "lane_utilisation": sh_busy / max(64 * sh_iter, 1),
-                                         "refills": sh_refill, "lanes_per_refill": sh_lanes / max(sh_refill, 1)}}
+                         "note": "node fetches come from the primary rays' BVH traversal; triangle tests include "
+                                 "the light-bin entries the shadow segments test"}
+        if sh_iter:  # the BVH shadow loop (light bins off)
+            res["counts"]["shadow_loop"] = {"iterations": sh_iter, "lane_utilisation": sh_busy / max(64 * sh_iter, 1),
+                                            "refills": sh_refill, "lanes_per_refill": sh_lanes / max(sh_refill, 1)}
         log(f"counted launch: {rays} rays, {nodes} node fetches, {tris} triangle tests, {terms} terms")
     # untimed: the launch configuration, chosen by the autotuner over the persistent-grid tiles
     # (measured on the first 20k records)
