@@ -962,7 +962,7 @@ __global__ void place_cover_kernel(const float* __restrict__ cand, int C, unsign
 // and lies in cell lo + [i, i + 1) * h.  One wavefront per accepted point
 // visits the cells of the point's bounding box grown by one cell (so that
 // rounding at cell faces cannot hide a candidate) and marks the candidates
-// within its radius (or ellipsoid, whose largest radius bounds the box).
+// within its radius (or ellipsoid, whose bounding box sets the cells).
 __global__ __launch_bounds__(256) void place_cover_grid_kernel(const float* __restrict__ cand, PlaceGrid g,
                                                                unsigned char* __restrict__ covered,
                                                                const int* __restrict__ state,
@@ -979,14 +979,27 @@ __global__ __launch_bounds__(256) void place_cover_grid_kernel(const float* __re
     const float R = accepted_R[b + a];  // ball radius, or the ellipsoid's largest radius
     if (!(R > 0.f) || !(R < 3.0e38f)) continue;
     const float* m = accepted_form ? accepted_form + 6 * (b + a) : nullptr;
+    // search half-extent per axis: R, or for an ellipsoid sqrt((M^-1)_dd) (its
+    // bounding box, from the adjugate in FP64, never above R)
+    float ext[3] = {R, R, R};
+    if (m) {
+      const double f0 = m[0], f1 = m[1], f2 = m[2], f3 = m[3], f4 = m[4], f5 = m[5];
+      const double a00 = f3 * f5 - f4 * f4, a11 = f0 * f5 - f2 * f2, a22 = f0 * f3 - f1 * f1;
+      const double det = f0 * a00 - f1 * (f1 * f5 - f2 * f4) + f2 * (f1 * f4 - f2 * f3);
+      if (det > 0.0) {
+        ext[0] = fminf(R, (float)(sqrt(fmax(a00 / det, 0.0)) * 1.0001));
+        ext[1] = fminf(R, (float)(sqrt(fmax(a11 / det, 0.0)) * 1.0001));
+        ext[2] = fminf(R, (float)(sqrt(fmax(a22 / det, 0.0)) * 1.0001));
+      }
+    }
     int lo3[3], n3[3];
     const float pc[3] = {px, py, pz};
     const float glo[3] = {g.lo.x, g.lo.y, g.lo.z}, gih[3] = {g.inv_h.x, g.inv_h.y, g.inv_h.z};
     const int gn[3] = {g.nx, g.ny, g.nz};
 #pragma unroll
     for (int d = 0; d < 3; d++) {
-      float f0 = floorf((pc[d] - R - glo[d]) * gih[d]) - 1.f;
-      float f1 = floorf((pc[d] + R - glo[d]) * gih[d]) + 1.f;
+      float f0 = floorf((pc[d] - ext[d] - glo[d]) * gih[d]) - 1.f;
+      float f1 = floorf((pc[d] + ext[d] - glo[d]) * gih[d]) + 1.f;
       f0 = fmaxf(f0, 0.f);
       f1 = fminf(f1, (float)(gn[d] - 1));
       lo3[d] = (int)f0;
