@@ -211,7 +211,7 @@ int rc_records(const rc_scene* scene, const rc_medium* medium, const rc_point_li
  * forbid hipMalloc).  Same arguments and results as rc_records (the same
  * kernels, bit for bit) without the workspace: the queue, error counter and
  * split-record partial sums live in a workspace of rc_workspace_size(4096)
- * bytes (about 5 MiB) that the library holds in device memory on each device
+ * bytes (5.3 MiB) that the library holds in device memory on each device
  * it runs on until the process ends.
  *   P       : 0 <= P <= RC_NOALLOC_MAX_RECORDS, else RC_EINVAL.
  *   The current device must be the scene's device (else RC_EINVAL).
