@@ -297,25 +297,31 @@ def _read_pmc(d):
     return rows
 
 
-def summarize_counters(d, workload, steps, copy_dir=None):
+def summarize_counters(d, workload, steps, copy_dir=None, launches=1):
+    """Counters of the timed record launches: per pass, the last `steps` steps
+    of `launches` record_kernel dispatches each (one per n_phi class of a
+    batched launch, empty classes included), summed per step, averaged over
+    steps and passes."""
     rows = _read_pmc(d)
     per, durs, meta = {}, [], None
     info_keys = ("name", "grid", "dur_ns", "vgpr", "scratch", "lds")
     for tag in sorted({k[0] for k in rows}):
         ks = [k for k in sorted(rows) if k[0] == tag and "record_kernel" in rows[k]["name"]
               and ", true," not in rows[k]["name"]]
-        if not ks:
+        if len(ks) < steps * launches:
             continue
-        # the timed launches: the last `steps` full-size ones (a batched step also makes an
-        # empty launch for records above the largest class)
-        longest = max(rows[k]["dur_ns"] for k in ks)
-        ks = [k for k in ks if rows[k]["dur_ns"] >= 0.05 * longest]
-        for k in ks[-steps:]:
-            meta = rows[k]
-            durs.append(rows[k]["dur_ns"] / 1e6)
-            for c, v in rows[k].items():
-                if c not in info_keys:
-                    per.setdefault(c, []).append(v)
+        ks = ks[-steps * launches:]
+        for st in range(steps):
+            grp = ks[st * launches:(st + 1) * launches]
+            meta = max((rows[k] for k in grp), key=lambda r: r["dur_ns"])
+            durs.append(sum(rows[k]["dur_ns"] for k in grp) / 1e6)
+            tot = {}
+            for k in grp:
+                for c, v in rows[k].items():
+                    if c not in info_keys:
+                        tot[c] = tot.get(c, 0.0) + v
+            for c, v in tot.items():
+                per.setdefault(c, []).append(v)
     m = {c: float(np.mean(v)) for c, v in per.items()}
     cu, simd = 256, 1024
     derived = {}
@@ -335,7 +341,7 @@ def summarize_counters(d, workload, steps, copy_dir=None):
         derived["tcc_hit"] = m["TCC_HIT_sum"] / max(m["TCC_HIT_sum"] + m["TCC_MISS_sum"], 1)
     out = {"kernel": meta["name"] if meta else None, "grid": meta["grid"] if meta else None,
            "vgpr": meta["vgpr"] if meta else None, "scratch_bytes_per_lane": meta["scratch"] if meta else None,
-           "lds_bytes": meta["lds"] if meta else None, "dispatches": len(durs),
+           "lds_bytes": meta["lds"] if meta else None, "steps": len(durs), "launches_per_step": launches,
            "duration_ms": float(np.mean(durs)) if durs else None, "per_dispatch": m, "derived": derived}
     if copy_dir:
         crows = _read_pmc(copy_dir)
@@ -375,6 +381,7 @@ def main():
     ap.add_argument("--summarize-counters", metavar="DIR", default=None,
                     help="write the counter summary from rocprofv3 CSV passes under DIR (and DIR/copy)")
     ap.add_argument("--commands", default="", help=argparse.SUPPRESS)
+    ap.add_argument("--launches-per-step", type=int, default=1, help=argparse.SUPPRESS)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build measures one GPU only (--gpus {args.gpus} requested); records are independent "
@@ -383,7 +390,8 @@ def main():
 
     if args.summarize_counters:
         d = Path(args.summarize_counters)
-        s = summarize_counters(d, args.workload, args.steps, copy_dir=d / "copy" if (d / "copy").exists() else None)
+        s = summarize_counters(d, args.workload, args.steps, copy_dir=d / "copy" if (d / "copy").exists() else None,
+                               launches=args.launches_per_step)
         s["kernel_source_sha"] = kernel_source_hash()
         s["commands"] = [c for c in args.commands.split(";;") if c]
         doc = json.loads(COUNTERS.read_text()) if COUNTERS.exists() else {}
