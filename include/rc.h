@@ -109,7 +109,17 @@ typedef struct {
  *               bins (built and cached on the scene at the first call with
  *               a new set of light positions, see rc_light_bins_build);
  *               1 = BVH traversal.  Both give the answer of testing every
- *               triangle, so records are identical. */
+ *               triangle, so records are identical.
+ *   max_n_theta : largest n_theta of the call, or 0 (unknown).  With a
+ *               bound, rc_records_batched traces every primary ray of the
+ *               batch first, in a separate launch where each wavefront
+ *               takes one stratum of 64 consecutive queued records (nearby
+ *               points, nearly parallel rays), into a buffer the scene holds
+ *               (8 B per ray: ceil(P / 64) * 64 * (max_n_theta * max_n_phi
+ *               + 2) rays); the record kernel then reads the hits.  The hits
+ *               are those of the record kernel's own traversal, so records
+ *               are identical.  Records with n_theta above the bound are
+ *               invalid (NaN, counted).  Not with counters. */
 typedef struct {
   float ring_step;
   int32_t max_rings;
@@ -121,6 +131,7 @@ typedef struct {
   int64_t rec_base;
   uint64_t* counters;
   int32_t shadow_bvh;
+  int32_t max_n_theta;
 } rc_params;
 
 /* Scene statistics reported by rc_scene_info. */

@@ -103,11 +103,14 @@ struct rc_scene {
     }
   } lb;
   int64_t device_bytes = 0;  // nodes, triangle copies, shading, planes, emission
+  float2* hits = nullptr;    // primary hits of the last batched call with a hits pass
+  size_t hits_bytes = 0;
   std::mutex mu;
   GraphCache graph;
   ~rc_scene() {
     graph.clear();
     lb.clear();
+    if (hits) (void)hipFree(hits);
     if (nodes) (void)hipFree(nodes);
     if (tris) (void)hipFree(tris);
     if (shade) (void)hipFree(shade);
@@ -187,6 +190,8 @@ int check_inputs(const rc_scene* s, const rc_medium* m, const rc_point_light* li
   if (!(p->ring_step > 0.f) || !std::isfinite(p->ring_step)) return fail(RC_EINVAL, "ring_step must be > 0");
   if (p->max_rings < 1 || p->max_rings > RC_MAX_RINGS) return fail(RC_EINVAL, "max_rings must be in [1, %d]", RC_MAX_RINGS);
   if (p->max_n_phi < 5 || p->max_n_phi > RC_MAX_NPHI) return fail(RC_EINVAL, "max_n_phi must be in [5, %d]", RC_MAX_NPHI);
+  if (p->max_n_theta < 0 || (p->max_n_theta > 0 && (int64_t)p->max_n_theta * p->max_n_phi + 2 > (1 << 24)))
+    return fail(RC_EINVAL, "max_n_theta must be 0 or at most 2^24 / max_n_phi");
   if (p->precision != 0 && p->precision != 1) return fail(RC_EINVAL, "precision must be 0 or 1");
   if (p->common_random != 0 && p->common_random != 1) return fail(RC_EINVAL, "common_random must be 0 or 1");
   if (p->shadow_bvh != 0 && p->shadow_bvh != 1) return fail(RC_EINVAL, "shadow_bvh must be 0 or 1");
@@ -320,6 +325,9 @@ rc::RecordArgs make_args(const rc_scene* s, const rc_medium* m, const rc_point_l
   a.queue = reinterpret_cast<unsigned int*>(static_cast<char*>(ws) + kWsQueue);
   a.range = nullptr;  // slots 0..P-1
   a.next = a.queue;
+  a.hits = nullptr;  // the record kernel traces its primary rays
+  a.hit_stride = 0;
+  a.max_n_theta = p->max_n_theta;
   a.counters = reinterpret_cast<unsigned long long*>(p->counters);
   a.splits = 1;
   a.refill_min = kTiles[0].refill_min;
@@ -388,6 +396,12 @@ int plan(const rc_scene* s, const rc_params* p, int64_t P, int tile, int& stack,
 hipError_t run_plan(const Launch* plan, size_t n, int stack, hipStream_t st) {
   const rc::RecordArgs& a0 = plan[0].args;
   hipError_t e = rc::launch_reset(a0.queue, st);
+  if (e == hipSuccess && a0.hits) {
+    // the pass covers every class: the call's n_phi bound is the widest launch's
+    rc::RecordArgs pa = a0;
+    for (size_t i = 1; i < n; i++) pa.max_n_phi = std::max(pa.max_n_phi, plan[i].args.max_n_phi);
+    e = rc::launch_primary(pa, stack, a0.P, st);
+  }
   if (e == hipSuccess && a0.splits > 1) e = rc::launch_zero_u32(a0.done, a0.P, st);
   for (size_t i = 0; i < n && e == hipSuccess; i++) {
     const Launch& l = plan[i];
@@ -681,6 +695,21 @@ int rc_records_batched(const rc_scene* scene, const rc_medium* medium, const rc_
   a.refill_min = kTiles[tile < 0 ? 0 : tile].refill_min;
   a.leaf_batch = kTiles[tile < 0 ? 0 : tile].leaf_batch;
   a.lds_cols = lds_cols_for(params->max_n_phi, stack, params->max_rings, kTiles[tile < 0 ? 0 : tile].lds_waves);
+  if (params->max_n_theta > 0 && !params->counters) {
+    // hits pass: every primary ray of the batch traced first, coherently
+    const int64_t stride = (int64_t)params->max_n_theta * params->max_n_phi + 2;
+    const size_t need = (size_t)((P + 63) / 64) * 64 * (size_t)stride * sizeof(float2);
+    std::lock_guard<std::mutex> lk(s->mu);
+    if (s->hits_bytes < need) {
+      if (s->hits) (void)hipFree(s->hits);
+      s->hits = nullptr;
+      s->hits_bytes = 0;
+      if (hipMalloc((void**)&s->hits, need) != hipSuccess) return fail(RC_ENOMEM, "hipMalloc %zu (primary hits)", need);
+      s->hits_bytes = need;
+    }
+    a.hits = s->hits;
+    a.hit_stride = (int)stride;
+  }
   std::vector<Launch> launches;
   if (!order && a.splits == 1 && P > rc::kSplitMaxRecords) {
     // Large batches from the internal queue: one launch per n_phi class, each

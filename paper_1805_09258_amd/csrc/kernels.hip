@@ -93,6 +93,15 @@ RC_DEV float3 row_direction(uint64_t key, int a, int col, int nth, int nph) {
   return stratum_direction(key, a, col, nth, nph);
 }
 
+// Position of direction (row a, column col) in a record's list of primary
+// rays: north pole 0, stratum (a, col) 1 + a * nph + col, south pole N + 1.
+RC_DEV int dir_index(int a, int col, int nth, int nph) {
+  return a < 0 ? 0 : (a == nth ? nth * nph + 1 : 1 + a * nph + col);
+}
+RC_DEV size_t hit_slot(int qr, int d, int stride) {
+  return ((size_t)(qr >> 6) * (size_t)stride + (size_t)d) * kWave + (size_t)(qr & (kWave - 1));
+}
+
 RC_DEV double wave_sum(double v) {
 #pragma unroll
   for (int s = 32; s >= 1; s >>= 1) v += __shfl_xor(v, s, kWave);
@@ -162,7 +171,8 @@ record_kernel(RecordArgs g) {
     }
     const float3 x = make_float3(g.pos[3 * rec], g.pos[3 * rec + 1], g.pos[3 * rec + 2]);
     const int nth = g.n_theta[rec], nph = g.n_phi[rec];
-    const bool bad = !(nth >= 2 && nph >= 5 && nph <= g.max_n_phi) || !(x.x >= g.box_lo.x && x.x <= g.box_hi.x) ||
+    const bool bad = !(nth >= 2 && nph >= 5 && nph <= g.max_n_phi) || (g.hits && nth > g.max_n_theta) ||
+                     !(x.x >= g.box_lo.x && x.x <= g.box_hi.x) ||
                      !(x.y >= g.box_lo.y && x.y <= g.box_hi.y) || !(x.z >= g.box_lo.z && x.z <= g.box_hi.z);
     if (bad) {
       if (part != 0) continue;  // the first part reports it
@@ -219,7 +229,7 @@ record_kernel(RecordArgs g) {
       // (a pole row has one column).  A row traced alone keeps its hits in
       // its LDS row; a pass over several rows keeps them in registers.
       if (COUNT) t_mark = clock64();
-      if (a > g_hi) {
+      if (!g.hits && a > g_hi) {
         g_lo = a;
         g_hi = a;
         int tot = n;
@@ -267,9 +277,18 @@ record_kernel(RecordArgs g) {
       for (int base = 0; base < n; base += kWave) {
         int j = base + lane;
         if (j < n) {
-          const float3 w = row_direction(key, a, sectored ? (b0 + j) % nph : j, nth, nph);
-          float t = grouped ? gt : R.t[j];
-          const int code = grouped ? gcode : R.code[j];
+          const int col = sectored ? (b0 + j) % nph : j;
+          const float3 w = row_direction(key, a, col, nth, nph);
+          float t;
+          int code;
+          if (g.hits) {  // traced by primary_kernel
+            const float2 h = g.hits[hit_slot(qr, dir_index(a, col, nth, nph), g.hit_stride)];
+            t = h.x;
+            code = __float_as_int(h.y);
+          } else {
+            t = grouped ? gt : R.t[j];
+            code = grouped ? gcode : R.code[j];
+          }
           double t64;
           if (code < 0) {
             t = box_exit(x, w, g.box_lo, g.box_hi);
@@ -823,6 +842,51 @@ record_kernel(RecordArgs g) {
 }
 
 // ---------------------------------------------------------------------------
+// primary rays of a whole batch, coherent: workgroup (b, d) traces direction
+// d of the 64 records at queue slots 64 b .. 64 b + 63 (nearby points with the
+// device-built queue, one stratum: nearly parallel rays), one lane per record,
+// with the record kernel's closest-hit traversal (so the same hits).
+// ---------------------------------------------------------------------------
+template <int STACK>
+__global__ __launch_bounds__(64) void primary_kernel(RecordArgs g, int nq, long long wg0) {
+  __shared__ int stack_lds[STACK * kWave];
+  const int lane = threadIdx.x;
+  const long long wg = wg0 + (long long)blockIdx.x;
+  const int blk = (int)(wg / g.hit_stride), d = (int)(wg - (long long)blk * g.hit_stride);
+  const int qr = blk * kWave + lane;
+  if (qr >= nq) return;
+  const int rec = g.order ? g.order[qr] : qr;
+  if (rec < 0 || rec >= g.P) return;
+  const int nth = g.n_theta[rec], nph = g.n_phi[rec];
+  const float3 x = make_float3(g.pos[3 * rec], g.pos[3 * rec + 1], g.pos[3 * rec + 2]);
+  // the record kernel's validity test: invalid records are not traced
+  if (!(nth >= 2 && nph >= 5 && nph <= g.max_n_phi && nth <= g.max_n_theta) ||
+      !(x.x >= g.box_lo.x && x.x <= g.box_hi.x) || !(x.y >= g.box_lo.y && x.y <= g.box_hi.y) ||
+      !(x.z >= g.box_lo.z && x.z <= g.box_hi.z))
+    return;
+  const int N = nth * nph;
+  if (d > N + 1) return;
+  int a, col = 0;
+  if (d == 0) {
+    a = -1;
+  } else if (d == N + 1) {
+    a = nth;
+  } else {
+    a = (d - 1) / nph;
+    col = (d - 1) - a * nph;
+  }
+  const uint64_t key = record_key(g.seed, (uint64_t)(g.rec_base + (g.common_random ? 0 : rec)));
+  const float3 w = row_direction(key, a, col, nth, nph);
+  int id;
+  float t;
+  bool fr;
+  TraceCount tc;
+  trace_closest<false>(g.nodes, g.tris, g.tri_stride, x, w, stack_lds + lane, g.leaf_batch, id, t, fr, tc);
+  const int code = id >= 0 ? ((id << 1) | (fr ? 1 : 0)) : -1;
+  g.hits[hit_slot(qr, d, g.hit_stride)] = make_float2(t, __int_as_float(code));
+}
+
+// ---------------------------------------------------------------------------
 // small kernels
 // ---------------------------------------------------------------------------
 // clears the queue words that must start at zero: pop counters, invalid
@@ -1004,6 +1068,24 @@ hipError_t prepare_record(int stack, bool count, bool f64, size_t lds) {
 hipError_t launch_record(const RecordArgs& a, int stack, bool count, bool f64, int grid, size_t lds, hipStream_t s) {
   void* args[] = {const_cast<RecordArgs*>(&a)};
   return hipLaunchKernel(select_kernel(stack, count, f64), dim3(grid), dim3(kWave), args, lds, s);
+}
+
+hipError_t launch_primary(const RecordArgs& a, int stack, int nq, hipStream_t s) {
+  const long long total = (long long)((nq + kWave - 1) / kWave) * a.hit_stride;
+  constexpr long long kChunk = 1ll << 24;  // workgroups per launch
+  for (long long w0 = 0; w0 < total; w0 += kChunk) {
+    const int n = (int)(total - w0 < kChunk ? total - w0 : kChunk);
+    switch (stack_index(stack)) {
+      case 0: hipLaunchKernelGGL(primary_kernel<16>, dim3(n), dim3(kWave), 0, s, a, nq, w0); break;
+      case 1: hipLaunchKernelGGL(primary_kernel<24>, dim3(n), dim3(kWave), 0, s, a, nq, w0); break;
+      case 2: hipLaunchKernelGGL(primary_kernel<32>, dim3(n), dim3(kWave), 0, s, a, nq, w0); break;
+      case 3: hipLaunchKernelGGL(primary_kernel<48>, dim3(n), dim3(kWave), 0, s, a, nq, w0); break;
+      default: hipLaunchKernelGGL(primary_kernel<64>, dim3(n), dim3(kWave), 0, s, a, nq, w0); break;
+    }
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
 }
 
 hipError_t launch_reset(unsigned int* q, hipStream_t s) {

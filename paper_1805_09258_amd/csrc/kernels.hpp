@@ -72,6 +72,13 @@ struct RecordArgs {
   const unsigned int* range;  // device [lo, hi): queue slots of this launch, or nullptr (all)
   unsigned int* next;         // pop counter of this launch
   unsigned long long* counters;
+  // primary hits traced by primary_kernel (or nullptr: the record kernel
+  // traces them): (t, code bits) of direction d of the record at queue slot
+  // q at hits[((q / 64) * hit_stride + d) * 64 + q % 64]; d = 0 north pole,
+  // 1 + a * n_phi + col stratum (a, col), N + 1 south pole
+  float2* hits;
+  int hit_stride;             // max_n_theta * max_n_phi + 2
+  int max_n_theta;            // records above it are invalid (with hits)
 };
 
 int stack_variant(int depth);
@@ -85,6 +92,8 @@ int record_occupancy(int stack, bool count, bool f64, size_t lds);
 hipError_t prepare_record(int stack, bool count, bool f64, size_t lds);
 hipError_t launch_record(const RecordArgs& a, int stack, bool count, bool f64, int grid, size_t lds, hipStream_t s);
 hipError_t launch_reset(unsigned int* q, hipStream_t s);
+// primary hits of queue slots [0, nq) into a.hits (every direction of every record)
+hipError_t launch_primary(const RecordArgs& a, int stack, int nq, hipStream_t s);
 hipError_t launch_zero_u32(unsigned int* p, int n, hipStream_t s);
 constexpr int kMaxSplits = 8;        // wavefronts per record at most
 constexpr int kSplitMaxRecords = 16384;  // batches up to this size may split records

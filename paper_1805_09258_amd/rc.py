@@ -46,7 +46,8 @@ class rc_params(C.Structure):
                 ("seed", C.c_uint64),
                 ("rec_base", C.c_int64),
                 ("counters", C.c_void_p),
-                ("shadow_bvh", C.c_int32)]
+                ("shadow_bvh", C.c_int32),
+                ("max_n_theta", C.c_int32)]
 
 
 class rc_scene_stats(C.Structure):
@@ -232,10 +233,10 @@ def rc_workspace_errors(ws, stream=None):
 
 
 def make_params(ring_step, max_rings, max_n_phi, seed, rec_base=0, precision=0, counters=None, common_random=False,
-                splits=0, shadow_bvh=False):
+                splits=0, shadow_bvh=False, max_n_theta=0):
     return rc_params(float(ring_step), int(max_rings), int(max_n_phi), int(precision), int(bool(common_random)),
                      int(splits), int(seed) & (2**64 - 1), int(rec_base),
-                     None if counters is None else counters.data_ptr(), int(bool(shadow_bvh)))
+                     None if counters is None else counters.data_ptr(), int(bool(shadow_bvh)), int(max_n_theta))
 
 
 def rc_records_wait(workspace, timeout_ms, stream=None):
@@ -473,6 +474,12 @@ class DeviceWorkload:
         self.n_theta = torch.as_tensor(np.ascontiguousarray(w.n_theta, np.int32), device=device)
         self.n_phi = torch.as_tensor(np.ascontiguousarray(w.n_phi, np.int32), device=device)
         self.max_n_phi = int(np.max(w.n_phi)) if len(w.n_phi) else 5
+        self.max_n_theta = int(np.max(w.n_theta)) if len(w.n_theta) else 2
+        # share of the primary-hit buffer the batch's rays fill (each record
+        # reserves max_n_theta * max_n_phi + 2 slots)
+        P = len(w.n_theta)
+        slots = ((P + 63) // 64) * 64 * (self.max_n_theta * self.max_n_phi + 2)
+        self.hits_fill = float((w.n_theta.astype(np.int64) * w.n_phi + 2).sum()) / slots if P else 0.0
 
     def outputs(self):
         import torch
@@ -488,13 +495,21 @@ class DeviceWorkload:
 
 
 def compute_records(scene: Scene, dw: DeviceWorkload, batched=False, use_graph=False, tile=-1, order=None,
-                    precision=0, counters=None, out=None, workspace=None, stream=None, splits=0, shadow_bvh=False):
-    """Records for every point of a DeviceWorkload; returns (value, grad, hess, workspace)."""
+                    precision=0, counters=None, out=None, workspace=None, stream=None, splits=0, shadow_bvh=False,
+                    hits_pass=True):
+    """Records for every point of a DeviceWorkload; returns (value, grad, hess, workspace).
+    hits_pass: give rc_records_batched the batch's largest n_theta (primary rays
+    traced in a separate coherent pass; ignored with counters) when the batch's
+    rays fill at least 3/4 of the hit buffer (uniform sample counts: measured
+    faster there, 7-11 %; with sample counts spread over an order of magnitude
+    the pass traces mostly empty slots and measured 5 % slower)."""
     w = dw.w
     value, grad, hess = out if out is not None else dw.outputs()
     ws = workspace if workspace is not None else dw.workspace()
     prm = make_params(w.ring_step, w.max_rings, dw.max_n_phi, w.seed, 0, precision, counters, splits=splits,
-                      shadow_bvh=shadow_bvh)
+                      shadow_bvh=shadow_bvh,
+                      max_n_theta=dw.max_n_theta if (hits_pass and batched and counters is None
+                                                     and dw.hits_fill >= 0.75) else 0)
     if batched:
         rc_records_batched(scene.handle, w.sigma_s, w.sigma_a, w.lights, dw.pos, dw.n_theta, dw.n_phi, prm, order,
                            use_graph, tile, value, grad, hess, ws, stream)

@@ -443,3 +443,46 @@ def test_points_very_close_to_surfaces(dev):
     assert np.all(np.isfinite(v)) and np.all(np.isfinite(g)) and np.all(np.isfinite(h))
     ref = O.records_for(w)
     assert_parity(v, g, h, ref, "near-surface points")
+
+
+@pytest.mark.parametrize("case", ["mixed classes", "split records"])
+def test_primary_hits_pass_gives_identical_records(dev, case):
+    """With the batch's largest n_theta given, the primary rays are traced in a
+    separate coherent pass and read back by the record kernel: the records
+    equal, bit for bit, those of the record kernel's own traversal."""
+    if case == "mixed classes":
+        w = W.make_c3().subset(np.arange(20000))  # several n_phi classes, launched per class
+    else:
+        w = W.make_c2(P=3000, n_soup=4000, seed=19)  # small batch: records split over wavefronts
+    sc = rc.Scene.from_workload(w)
+    dw = rc.DeviceWorkload(w)
+    out = []
+    for mnt in (0, dw.max_n_theta):
+        v, g, h = dw.outputs()
+        ws = dw.workspace()
+        prm = rc.make_params(w.ring_step, w.max_rings, dw.max_n_phi, w.seed, max_n_theta=mnt)
+        rc.rc_records_batched(sc.handle, w.sigma_s, w.sigma_a, w.lights, dw.pos, dw.n_theta, dw.n_phi, prm, None,
+                              True, -1, v, g, h, ws)
+        torch.cuda.synchronize()
+        assert rc.rc_workspace_errors(ws) == 0
+        out.append((v, g, h))
+    for a, b in zip(out[0], out[1]):
+        assert torch.equal(a, b)
+    sc.close()
+
+
+def test_primary_hits_pass_rejects_records_above_the_n_theta_bound(dev):
+    w = W.make_c2(P=20000, n_soup=2000, seed=20)
+    w.n_theta[[5, 17000]] = 32  # above the bound given below
+    sc = rc.Scene.from_workload(w)
+    dw = rc.DeviceWorkload(w)
+    v, g, h = dw.outputs()
+    ws = dw.workspace()
+    prm = rc.make_params(w.ring_step, w.max_rings, dw.max_n_phi, w.seed, max_n_theta=16)
+    rc.rc_records_batched(sc.handle, w.sigma_s, w.sigma_a, w.lights, dw.pos, dw.n_theta, dw.n_phi, prm, None,
+                          False, -1, v, g, h, ws)
+    torch.cuda.synchronize()
+    assert rc.rc_workspace_errors(ws) == 2
+    vv = v.cpu().numpy()
+    assert np.isnan(vv[[5, 17000]]).all() and np.isfinite(np.delete(vv, [5, 17000], axis=0)).all()
+    sc.close()
