@@ -328,6 +328,7 @@ rc::RecordArgs make_args(const rc_scene* s, const rc_medium* m, const rc_point_l
   a.hits = nullptr;  // the record kernel traces its primary rays
   a.hit_stride = 0;
   a.max_n_theta = p->max_n_theta;
+  a.trace_stack = rc::stack_variant(s->depth);
   a.counters = reinterpret_cast<unsigned long long*>(p->counters);
   a.splits = 1;
   a.refill_min = kTiles[0].refill_min;
@@ -371,9 +372,13 @@ void set_splits(rc::RecordArgs& a, const rc_params* p, int64_t P, int64_t reside
   }
 }
 
+// Hits pass of rc_records_batched: with an n_theta bound and no counters.
+bool hits_mode(const rc_params* p) { return p->max_n_theta > 0 && !p->counters; }
+
 int plan(const rc_scene* s, const rc_params* p, int64_t P, int tile, int& stack, size_t& lds, int& grid,
-         int64_t* resident_out = nullptr) {
-  stack = rc::stack_variant(s->depth);
+         int64_t* resident_out = nullptr, bool hits = false) {
+  // with the hits pass and light bins the record kernel traverses nothing
+  stack = (hits && p->shadow_bvh == 0) ? rc::kHitsStack : rc::stack_variant(s->depth);
   const int t = (tile >= 0 && tile < kNTiles) ? tile : 0;
   lds = rc::record_lds_bytes(stack, lds_cols_for(p->max_n_phi, stack, p->max_rings, kTiles[t].lds_waves),
                              p->max_rings);
@@ -400,7 +405,7 @@ hipError_t run_plan(const Launch* plan, size_t n, int stack, hipStream_t st) {
     // the pass covers every class: the call's n_phi bound is the widest launch's
     rc::RecordArgs pa = a0;
     for (size_t i = 1; i < n; i++) pa.max_n_phi = std::max(pa.max_n_phi, plan[i].args.max_n_phi);
-    e = rc::launch_primary(pa, stack, a0.P, st);
+    e = rc::launch_primary(pa, pa.trace_stack, a0.P, st);
   }
   if (e == hipSuccess && a0.splits > 1) e = rc::launch_zero_u32(a0.done, a0.P, st);
   for (size_t i = 0; i < n && e == hipSuccess; i++) {
@@ -677,7 +682,8 @@ int rc_records_batched(const rc_scene* scene, const rc_medium* medium, const rc_
   int stack, grid;
   size_t lds;
   int64_t resident = 0;
-  if ((r = plan(s, params, P, tile, stack, lds, grid, &resident))) return r;
+  const bool hits = hits_mode(params);
+  if ((r = plan(s, params, P, tile, stack, lds, grid, &resident, hits))) return r;
   char* ws = static_cast<char*>(workspace);
   const int32_t* ord = order;
   unsigned int* q = reinterpret_cast<unsigned int*>(ws + kWsQueue);
@@ -695,7 +701,7 @@ int rc_records_batched(const rc_scene* scene, const rc_medium* medium, const rc_
   a.refill_min = kTiles[tile < 0 ? 0 : tile].refill_min;
   a.leaf_batch = kTiles[tile < 0 ? 0 : tile].leaf_batch;
   a.lds_cols = lds_cols_for(params->max_n_phi, stack, params->max_rings, kTiles[tile < 0 ? 0 : tile].lds_waves);
-  if (params->max_n_theta > 0 && !params->counters) {
+  if (hits) {
     // hits pass: every primary ray of the batch traced first, coherently
     const int64_t stride = (int64_t)params->max_n_theta * params->max_n_phi + 2;
     const size_t need = (size_t)((P + 63) / 64) * 64 * (size_t)stride * sizeof(float2);
@@ -724,7 +730,7 @@ int rc_records_batched(const rc_scene* scene, const rc_medium* medium, const rc_
       int sk, gk;
       size_t lk;
       int64_t rk = 0;
-      if ((r = plan(s, &pk, P, tile, sk, lk, gk, &rk))) return r;
+      if ((r = plan(s, &pk, P, tile, sk, lk, gk, &rk, hits))) return r;
       rc::RecordArgs ak = a;
       ak.max_n_phi = cap;
       ak.lds_cols = lds_cols_for(cap, stack, params->max_rings, kTiles[tile < 0 ? 0 : tile].lds_waves);

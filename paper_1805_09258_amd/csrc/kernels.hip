@@ -136,6 +136,9 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(record_waves
                                                                      record_waves_per_simd(STACK)))) void
 record_kernel(RecordArgs g) {
   extern __shared__ float lds[];
+  // the smallest stack variant holds no traversal: its primary hits come
+  // from the hits pass and its shadow segments from the light bins
+  constexpr bool kOwnRays = STACK > kHitsStack;
   const int lane = threadIdx.x;
   const int cap = g.lds_cols;  // columns of an LDS row
   const int MR = g.max_rings;
@@ -229,7 +232,7 @@ record_kernel(RecordArgs g) {
       // (a pole row has one column).  A row traced alone keeps its hits in
       // its LDS row; a pass over several rows keeps them in registers.
       if (COUNT) t_mark = clock64();
-      if (!g.hits && a > g_hi) {
+      if (kOwnRays && !g.hits && a > g_hi) {
         g_lo = a;
         g_hi = a;
         int tot = n;
@@ -281,7 +284,7 @@ record_kernel(RecordArgs g) {
           const float3 w = row_direction(key, a, col, nth, nph);
           float t;
           int code;
-          if (g.hits) {  // traced by primary_kernel
+          if (!kOwnRays || g.hits) {  // traced by primary_kernel
             const float2 h = g.hits[hit_slot(qr, dir_index(a, col, nth, nph), g.hit_stride)];
             t = h.x;
             code = __float_as_int(h.y);
@@ -332,7 +335,7 @@ record_kernel(RecordArgs g) {
         const int nvert = __builtin_amdgcn_readfirstlane(carry);
         const int NL = g.n_lights;
         __syncthreads();
-        if (g.lb_desc) {
+        if (!kOwnRays || g.lb_desc) {
           // Light bins: a segment reads one header per level and then only
           // the few entries within its reach (one to three on average), so a
           // lane walks all lights of its vertex in turn: decode once, per
@@ -1039,15 +1042,15 @@ static const void* kernel_ptr() {
   return reinterpret_cast<const void*>(&record_kernel<S, C, D>);
 }
 
-// kernel variants: stack depth {16, 24, 32, 48, 64} x counting x FP64 study mode
+// kernel variants: stack depth {8 (hits pass and light bins), 16, 24, 32, 48, 64} x counting x FP64 study mode
 static int stack_index(int stack) {
-  return stack <= 16 ? 0 : (stack <= 24 ? 1 : (stack <= 32 ? 2 : (stack <= 48 ? 3 : 4)));
+  return stack <= kHitsStack ? 0 : stack <= 16 ? 1 : (stack <= 24 ? 2 : (stack <= 32 ? 3 : (stack <= 48 ? 4 : 5)));
 }
 #define RC_KVARIANTS(S) \
   {{kernel_ptr<S, false, false>(), kernel_ptr<S, false, true>()}, {kernel_ptr<S, true, false>(), kernel_ptr<S, true, true>()}}
 static const void* select_kernel(int stack, bool count, bool f64) {
-  static const void* const table[5][2][2] = {RC_KVARIANTS(16), RC_KVARIANTS(24), RC_KVARIANTS(32), RC_KVARIANTS(48),
-                                             RC_KVARIANTS(64)};
+  static const void* const table[6][2][2] = {RC_KVARIANTS(kHitsStack), RC_KVARIANTS(16), RC_KVARIANTS(24),
+                                             RC_KVARIANTS(32),         RC_KVARIANTS(48), RC_KVARIANTS(64)};
   return table[stack_index(stack)][count ? 1 : 0][f64 ? 1 : 0];
 }
 
@@ -1066,6 +1069,8 @@ hipError_t prepare_record(int stack, bool count, bool f64, size_t lds) {
 }
 
 hipError_t launch_record(const RecordArgs& a, int stack, bool count, bool f64, int grid, size_t lds, hipStream_t s) {
+  // the stackless variant needs the hits pass and, with lights, the light bins
+  if (stack <= kHitsStack && (!a.hits || (a.n_lights > 0 && !a.lb_desc))) return hipErrorInvalidValue;
   void* args[] = {const_cast<RecordArgs*>(&a)};
   return hipLaunchKernel(select_kernel(stack, count, f64), dim3(grid), dim3(kWave), args, lds, s);
 }
@@ -1075,7 +1080,7 @@ hipError_t launch_primary(const RecordArgs& a, int stack, int nq, hipStream_t s)
   constexpr long long kChunk = 1ll << 24;  // workgroups per launch
   for (long long w0 = 0; w0 < total; w0 += kChunk) {
     const int n = (int)(total - w0 < kChunk ? total - w0 : kChunk);
-    switch (stack_index(stack)) {
+    switch (stack <= 16 ? 0 : (stack <= 24 ? 1 : (stack <= 32 ? 2 : (stack <= 48 ? 3 : 4)))) {
       case 0: hipLaunchKernelGGL(primary_kernel<16>, dim3(n), dim3(kWave), 0, s, a, nq, w0); break;
       case 1: hipLaunchKernelGGL(primary_kernel<24>, dim3(n), dim3(kWave), 0, s, a, nq, w0); break;
       case 2: hipLaunchKernelGGL(primary_kernel<32>, dim3(n), dim3(kWave), 0, s, a, nq, w0); break;

@@ -28,6 +28,10 @@ constexpr int kQueueWords = 64;
 constexpr int kQueueClassNext = 2;
 constexpr int kQueueDone = 8;
 constexpr int kQueueRange = 16;
+// LDS stack of the record kernel when its primary rays come from the hits
+// pass and its shadow segments from the light bins: only the bin lists of a
+// segment (two words per level) use it
+constexpr int kHitsStack = 2 * kLbMaxLevels;
 
 struct RecordArgs {
   const float4* nodes;
@@ -79,6 +83,7 @@ struct RecordArgs {
   float2* hits;
   int hit_stride;             // max_n_theta * max_n_phi + 2
   int max_n_theta;            // records above it are invalid (with hits)
+  int trace_stack;            // traversal stack of the BVH (primary_kernel)
 };
 
 int stack_variant(int depth);

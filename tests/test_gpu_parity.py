@@ -123,7 +123,9 @@ def test_light_bin_and_bvh_shadows_give_identical_records(dev):
     dw = rc.DeviceWorkload(w)
     out = []
     for bvh in (False, True):
-        v, g, h, ws = rc.compute_records(sc, dw, batched=True, shadow_bvh=bvh)
+        # records traced in the kernel, so both runs share one LDS layout (the
+        # summation order of a record depends on its row width)
+        v, g, h, ws = rc.compute_records(sc, dw, batched=True, shadow_bvh=bvh, hits_pass=False)
         torch.cuda.synchronize()
         assert rc.rc_workspace_errors(ws) == 0
         out.append((v.clone(), g.clone(), h.clone()))
@@ -346,19 +348,34 @@ def test_deterministic_batched_and_graph_replays_bitwise_equal(dev):
     out = dw.outputs()
     ws = dw.workspace()
     reps = []
+    hreps = []
     with torch.cuda.stream(s):
         for r in range(3):
             for t in out:
                 t.fill_(float("nan"))          # eager work between graph replays
-            rc.compute_records(sc, dw, batched=True, use_graph=True, out=out, workspace=ws, stream=s)
+            # the record kernel's own traversal: the direct launches' layout
+            rc.compute_records(sc, dw, batched=True, use_graph=True, out=out, workspace=ws, stream=s,
+                               hits_pass=False)
             s.synchronize()
             reps.append([t.clone() for t in out])
+        for r in range(3):  # with the primary-hit pass (its own graph)
+            for t in out:
+                t.fill_(float("nan"))
+            prm = rc.make_params(w.ring_step, w.max_rings, dw.max_n_phi, w.seed, max_n_theta=dw.max_n_theta)
+            rc.rc_records_batched(sc.handle, w.sigma_s, w.sigma_a, w.lights, dw.pos, dw.n_theta, dw.n_phi, prm,
+                                  None, True, -1, out[0], out[1], out[2], ws, s)
+            s.synchronize()
+            hreps.append([t.clone() for t in out])
     torch.cuda.synchronize()
     for x, y in zip(a, b):
         assert torch.equal(x, y)
     for rep in reps:
         for x, y in zip(a, rep):
             assert torch.equal(x, y)
+    for rep in hreps[1:]:
+        for x, y in zip(hreps[0], rep):
+            assert torch.equal(x, y)
+    assert all(bool(torch.isfinite(t).all()) for t in hreps[0])
     sc.close()
 
 
@@ -449,7 +466,11 @@ def test_points_very_close_to_surfaces(dev):
 def test_primary_hits_pass_gives_identical_records(dev, case):
     """With the batch's largest n_theta given, the primary rays are traced in a
     separate coherent pass and read back by the record kernel: the records
-    equal, bit for bit, those of the record kernel's own traversal."""
+    equal, bit for bit, those of the record kernel's own traversal.  Both runs
+    take their shadow segments from the BVH, which keeps the record kernel's
+    LDS layout (with light bins the pass also selects a kernel without a
+    traversal stack and wider rows: other summation order, covered by the
+    oracle parity tests)."""
     if case == "mixed classes":
         w = W.make_c3().subset(np.arange(20000))  # several n_phi classes, launched per class
     else:
@@ -460,7 +481,7 @@ def test_primary_hits_pass_gives_identical_records(dev, case):
     for mnt in (0, dw.max_n_theta):
         v, g, h = dw.outputs()
         ws = dw.workspace()
-        prm = rc.make_params(w.ring_step, w.max_rings, dw.max_n_phi, w.seed, max_n_theta=mnt)
+        prm = rc.make_params(w.ring_step, w.max_rings, dw.max_n_phi, w.seed, max_n_theta=mnt, shadow_bvh=True)
         rc.rc_records_batched(sc.handle, w.sigma_s, w.sigma_a, w.lights, dw.pos, dw.n_theta, dw.n_phi, prm, None,
                               True, -1, v, g, h, ws)
         torch.cuda.synchronize()
