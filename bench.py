@@ -202,7 +202,7 @@ def measure(name, dev, steps, warmup, count=True):
         log(f"counted launch: {rays} rays, {nodes} node fetches, {tris} triangle tests, {terms} terms")
     # untimed: the launch configuration, chosen by the autotuner over the persistent-grid tiles
     # (measured on the first 20k records)
-    prm = rc.make_params(w.ring_step, w.max_rings, dw.max_n_phi, w.seed)
+    prm = rc.make_params(w.ring_step, w.max_rings, dw.max_n_phi, w.seed, max_n_theta=dw.hits_bound())
     nt = min(w.n_rec, 20_000)
     tile, tile_ms = rc.rc_autotune(scene.handle, w.sigma_s, w.sigma_a, w.lights, dw.pos[:nt], dw.n_theta[:nt],
                                    dw.n_phi[:nt], prm, value[:nt], grad[:nt], hess[:nt], ws, stream=stream)

@@ -682,7 +682,27 @@ int rc_records_batched(const rc_scene* scene, const rc_medium* medium, const rc_
   int stack, grid;
   size_t lds;
   int64_t resident = 0;
-  const bool hits = hits_mode(params);
+  bool hits = hits_mode(params);
+  if (hits) {
+    // the scene's hit buffer, grown to this batch; without the memory the
+    // record kernel traces its own primary rays
+    const int64_t stride = (int64_t)params->max_n_theta * params->max_n_phi + 2;
+    const size_t need = (size_t)((P + 63) / 64) * 64 * (size_t)stride * sizeof(float2);
+    std::lock_guard<std::mutex> lk(s->mu);
+    if (s->hits_bytes < need) {
+      s->graph.clear();  // launches captured with the old buffer
+      if (s->hits) (void)hipFree(s->hits);
+      s->hits = nullptr;
+      s->hits_bytes = 0;
+      if (hipMalloc((void**)&s->hits, need) == hipSuccess) {
+        s->hits_bytes = need;
+      } else {
+        s->hits = nullptr;
+        (void)hipGetLastError();
+        hits = false;
+      }
+    }
+  }
   if ((r = plan(s, params, P, tile, stack, lds, grid, &resident, hits))) return r;
   char* ws = static_cast<char*>(workspace);
   const int32_t* ord = order;
@@ -701,20 +721,9 @@ int rc_records_batched(const rc_scene* scene, const rc_medium* medium, const rc_
   a.refill_min = kTiles[tile < 0 ? 0 : tile].refill_min;
   a.leaf_batch = kTiles[tile < 0 ? 0 : tile].leaf_batch;
   a.lds_cols = lds_cols_for(params->max_n_phi, stack, params->max_rings, kTiles[tile < 0 ? 0 : tile].lds_waves);
-  if (hits) {
-    // hits pass: every primary ray of the batch traced first, coherently
-    const int64_t stride = (int64_t)params->max_n_theta * params->max_n_phi + 2;
-    const size_t need = (size_t)((P + 63) / 64) * 64 * (size_t)stride * sizeof(float2);
-    std::lock_guard<std::mutex> lk(s->mu);
-    if (s->hits_bytes < need) {
-      if (s->hits) (void)hipFree(s->hits);
-      s->hits = nullptr;
-      s->hits_bytes = 0;
-      if (hipMalloc((void**)&s->hits, need) != hipSuccess) return fail(RC_ENOMEM, "hipMalloc %zu (primary hits)", need);
-      s->hits_bytes = need;
-    }
+  if (hits) {  // hits pass: every primary ray of the batch traced first, coherently
     a.hits = s->hits;
-    a.hit_stride = (int)stride;
+    a.hit_stride = params->max_n_theta * params->max_n_phi + 2;
   }
   std::vector<Launch> launches;
   if (!order && a.splits == 1 && P > rc::kSplitMaxRecords) {

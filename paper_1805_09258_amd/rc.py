@@ -475,11 +475,18 @@ class DeviceWorkload:
         self.n_phi = torch.as_tensor(np.ascontiguousarray(w.n_phi, np.int32), device=device)
         self.max_n_phi = int(np.max(w.n_phi)) if len(w.n_phi) else 5
         self.max_n_theta = int(np.max(w.n_theta)) if len(w.n_theta) else 2
-        # share of the primary-hit buffer the batch's rays fill (each record
-        # reserves max_n_theta * max_n_phi + 2 slots)
+        # the primary-hit buffer of a hits pass: 8 B per slot, each record
+        # reserving max_n_theta * max_n_phi + 2 slots; the share the rays fill
         P = len(w.n_theta)
         slots = ((P + 63) // 64) * 64 * (self.max_n_theta * self.max_n_phi + 2)
+        self.hits_bytes = 8 * slots
         self.hits_fill = float((w.n_theta.astype(np.int64) * w.n_phi + 2).sum()) / slots if P else 0.0
+
+    def hits_bound(self):
+        """max_n_theta for rc_params when the hits pass pays: its buffer at most
+        32 GiB and at least a quarter filled (measured faster at fills of 0.34
+        and 1.0, with the wider-row record kernel it enables), else 0."""
+        return self.max_n_theta if (self.hits_bytes <= 32 << 30 and self.hits_fill >= 0.25) else 0
 
     def outputs(self):
         import torch
@@ -499,17 +506,14 @@ def compute_records(scene: Scene, dw: DeviceWorkload, batched=False, use_graph=F
                     hits_pass=True):
     """Records for every point of a DeviceWorkload; returns (value, grad, hess, workspace).
     hits_pass: give rc_records_batched the batch's largest n_theta (primary rays
-    traced in a separate coherent pass; ignored with counters) when the batch's
-    rays fill at least 3/4 of the hit buffer (uniform sample counts: measured
-    faster there, 7-11 %; with sample counts spread over an order of magnitude
-    the pass traces mostly empty slots and measured 5 % slower)."""
+    traced in a separate coherent pass, ignored with counters) when
+    DeviceWorkload.hits_bound says the pass pays."""
     w = dw.w
     value, grad, hess = out if out is not None else dw.outputs()
     ws = workspace if workspace is not None else dw.workspace()
     prm = make_params(w.ring_step, w.max_rings, dw.max_n_phi, w.seed, 0, precision, counters, splits=splits,
                       shadow_bvh=shadow_bvh,
-                      max_n_theta=dw.max_n_theta if (hits_pass and batched and counters is None
-                                                     and dw.hits_fill >= 0.75) else 0)
+                      max_n_theta=dw.hits_bound() if (hits_pass and batched and counters is None) else 0)
     if batched:
         rc_records_batched(scene.handle, w.sigma_s, w.sigma_a, w.lights, dw.pos, dw.n_theta, dw.n_phi, prm, order,
                            use_graph, tile, value, grad, hess, ws, stream)
