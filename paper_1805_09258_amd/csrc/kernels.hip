@@ -851,11 +851,12 @@ record_kernel(RecordArgs g) {
 // with the record kernel's closest-hit traversal (so the same hits).
 // ---------------------------------------------------------------------------
 template <int STACK>
-__global__ __launch_bounds__(64) void primary_kernel(RecordArgs g, int nq, long long wg0) {
+__global__ __launch_bounds__(64) void primary_kernel(RecordArgs g, int nq, int blk0) {
   __shared__ int stack_lds[STACK * kWave];
   const int lane = threadIdx.x;
-  const long long wg = wg0 + (long long)blockIdx.x;
-  const int blk = (int)(wg / g.hit_stride), d = (int)(wg - (long long)blk * g.hit_stride);
+  // grid (direction, block): consecutive workgroups take the directions of
+  // one block of records
+  const int d = blockIdx.x, blk = blk0 + (int)blockIdx.y;
   const int qr = blk * kWave + lane;
   if (qr >= nq) return;
   const int rec = g.order ? g.order[qr] : qr;
@@ -1076,16 +1077,16 @@ hipError_t launch_record(const RecordArgs& a, int stack, bool count, bool f64, i
 }
 
 hipError_t launch_primary(const RecordArgs& a, int stack, int nq, hipStream_t s) {
-  const long long total = (long long)((nq + kWave - 1) / kWave) * a.hit_stride;
-  constexpr long long kChunk = 1ll << 24;  // workgroups per launch
-  for (long long w0 = 0; w0 < total; w0 += kChunk) {
-    const int n = (int)(total - w0 < kChunk ? total - w0 : kChunk);
+  const int nblk = (nq + kWave - 1) / kWave;
+  constexpr int kBlocks = 65535;  // grid y per launch
+  for (int b0 = 0; b0 < nblk; b0 += kBlocks) {
+    const dim3 grid(a.hit_stride, nblk - b0 < kBlocks ? nblk - b0 : kBlocks);
     switch (stack <= 16 ? 0 : (stack <= 24 ? 1 : (stack <= 32 ? 2 : (stack <= 48 ? 3 : 4)))) {
-      case 0: hipLaunchKernelGGL(primary_kernel<16>, dim3(n), dim3(kWave), 0, s, a, nq, w0); break;
-      case 1: hipLaunchKernelGGL(primary_kernel<24>, dim3(n), dim3(kWave), 0, s, a, nq, w0); break;
-      case 2: hipLaunchKernelGGL(primary_kernel<32>, dim3(n), dim3(kWave), 0, s, a, nq, w0); break;
-      case 3: hipLaunchKernelGGL(primary_kernel<48>, dim3(n), dim3(kWave), 0, s, a, nq, w0); break;
-      default: hipLaunchKernelGGL(primary_kernel<64>, dim3(n), dim3(kWave), 0, s, a, nq, w0); break;
+      case 0: hipLaunchKernelGGL(primary_kernel<16>, grid, dim3(kWave), 0, s, a, nq, b0); break;
+      case 1: hipLaunchKernelGGL(primary_kernel<24>, grid, dim3(kWave), 0, s, a, nq, b0); break;
+      case 2: hipLaunchKernelGGL(primary_kernel<32>, grid, dim3(kWave), 0, s, a, nq, b0); break;
+      case 3: hipLaunchKernelGGL(primary_kernel<48>, grid, dim3(kWave), 0, s, a, nq, b0); break;
+      default: hipLaunchKernelGGL(primary_kernel<64>, grid, dim3(kWave), 0, s, a, nq, b0); break;
     }
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
