@@ -251,15 +251,16 @@ def measure(name, dev, steps, warmup, count=True):
 
 
 def roofline(name, res):
-    """VALU-issue roofline of record_kernel: lane-operations issued per launch
-    (SQ_INSTS_VALU x 64 from the committed counters of this kernel source)
-    over the live launch time; HBM traffic from FETCH_SIZE/WRITE_SIZE scaled
-    by a plain copy's reading."""
+    """VALU-issue roofline of one record step (the primary-hit pass and the
+    record kernel's launches): lane-operations issued per step (SQ_INSTS_VALU
+    x 64 from the committed counters of this kernel source) over the live step
+    time, and per kernel from the counter passes; traffic beyond L2 from
+    FETCH_SIZE/WRITE_SIZE scaled by a plain copy's reading."""
     c = committed_counters(name)
     kern_s = res["record_launch_ms"] * 1e-3
     out = {"bound": "alu", "achieved": None, "peak": VALU_PEAK, "unit": "T VALU lane-ops/s", "frac": None,
-           "traffic": None, "kernel": "record_kernel", "kernel_ms": res["record_launch_ms"],
-           "compulsory_bytes": res["compulsory_bytes"]}
+           "traffic": None, "kernel": "record step: primary_kernel (hits pass) + record_kernel",
+           "kernel_ms": res["record_launch_ms"], "compulsory_bytes": res["compulsory_bytes"]}
     if c is None:
         out["note"] = "no counter summary for this kernel source: achieved and traffic unmeasured"
         return out
@@ -272,6 +273,19 @@ def roofline(name, res):
     for k in ("valu_busy", "waves_per_simd", "vmem_wait_frac", "tcp_hit", "tcc_hit", "clock_ghz"):
         if k in d:
             out[k] = d[k]
+    per_k = {}
+    for kn, e in c.get("by_kernel", {}).items():
+        k = {"profiled_ms": e.get("ms")}
+        if "valu_lane_ops_per_s" in e:
+            k["achieved"] = e["valu_lane_ops_per_s"] / 1e12
+            k["frac"] = k["achieved"] / VALU_PEAK
+        if "valu_busy" in e:
+            k["valu_busy"] = e["valu_busy"]
+        if "TCC_HIT_sum" in e and "TCC_MISS_sum" in e:
+            k["tcc_hit"] = e["TCC_HIT_sum"] / max(e["TCC_HIT_sum"] + e["TCC_MISS_sum"], 1)
+        per_k[kn.replace("rc::", "")] = k
+    if per_k:
+        out["by_kernel"] = per_k
     if "hbm_bytes" in c:
         out["traffic"] = c["hbm_bytes"]
         out["traffic_gbs"] = c["hbm_bytes"] / kern_s / 1e9
@@ -298,31 +312,48 @@ def _read_pmc(d):
 
 
 def summarize_counters(d, workload, steps, copy_dir=None, launches=1):
-    """Counters of the timed record launches: per pass, the last `steps` steps
-    of `launches` record_kernel dispatches each (one per n_phi class of a
-    batched launch, empty classes included), summed per step, averaged over
-    steps and passes."""
+    """Counters of the timed steps: per pass, the last `steps` steps of
+    `launches` dispatches each (the primary-hit pass, in chunks, and one
+    record_kernel launch per n_phi class of a batched launch, empty classes
+    included), summed per step, averaged over steps and passes; also per
+    kernel."""
     rows = _read_pmc(d)
     per, durs, meta = {}, [], None
+    by_kernel = {}
     info_keys = ("name", "grid", "dur_ns", "vgpr", "scratch", "lds")
     for tag in sorted({k[0] for k in rows}):
-        ks = [k for k in sorted(rows) if k[0] == tag and "record_kernel" in rows[k]["name"]
+        ks = [k for k in sorted(rows) if k[0] == tag and ("record_kernel" in rows[k]["name"] or
+                                                           "primary_kernel" in rows[k]["name"])
               and ", true," not in rows[k]["name"]]
         if len(ks) < steps * launches:
             continue
         ks = ks[-steps * launches:]
         for st in range(steps):
             grp = ks[st * launches:(st + 1) * launches]
-            meta = max((rows[k] for k in grp), key=lambda r: r["dur_ns"])
+            meta = max((rows[k] for k in grp if "record_kernel" in rows[k]["name"]), key=lambda r: r["dur_ns"])
             durs.append(sum(rows[k]["dur_ns"] for k in grp) / 1e6)
-            tot = {}
+            tot, kt = {}, {}
             for k in grp:
+                kn = rows[k]["name"].split("(")[0].replace("void ", "")
+                e = kt.setdefault(kn, {"ms": 0.0})
+                e["ms"] += rows[k]["dur_ns"] / 1e6
                 for c, v in rows[k].items():
                     if c not in info_keys:
                         tot[c] = tot.get(c, 0.0) + v
+                        e[c] = e.get(c, 0.0) + v
             for c, v in tot.items():
                 per.setdefault(c, []).append(v)
+            for kn, e in kt.items():
+                for c, v in e.items():
+                    by_kernel.setdefault(kn, {}).setdefault(c, []).append(v)
     m = {c: float(np.mean(v)) for c, v in per.items()}
+    # per kernel: each counter averaged over the steps that read it (its pass)
+    kern = {kn: {c: float(np.mean(v)) for c, v in e.items()} for kn, e in by_kernel.items()}
+    for kn, e in kern.items():
+        if "SQ_INSTS_VALU" in e and e.get("ms"):
+            e["valu_lane_ops_per_s"] = e["SQ_INSTS_VALU"] * 64 / (e["ms"] * 1e-3)
+        if "SQ_ACTIVE_INST_VALU" in e and e.get("GRBM_GUI_ACTIVE"):
+            e["valu_busy"] = e["SQ_ACTIVE_INST_VALU"] * 4 / (e["GRBM_GUI_ACTIVE"] / 8 * 1024)
     cu, simd = 256, 1024
     derived = {}
     if "GRBM_GUI_ACTIVE" in m:
@@ -342,7 +373,8 @@ def summarize_counters(d, workload, steps, copy_dir=None, launches=1):
     out = {"kernel": meta["name"] if meta else None, "grid": meta["grid"] if meta else None,
            "vgpr": meta["vgpr"] if meta else None, "scratch_bytes_per_lane": meta["scratch"] if meta else None,
            "lds_bytes": meta["lds"] if meta else None, "steps": len(durs), "launches_per_step": launches,
-           "duration_ms": float(np.mean(durs)) if durs else None, "per_dispatch": m, "derived": derived}
+           "duration_ms": float(np.mean(durs)) if durs else None, "per_dispatch": m, "derived": derived,
+           "by_kernel": kern}
     if copy_dir:
         crows = _read_pmc(copy_dir)
         fs = [r["FETCH_SIZE"] for r in crows.values() if "FETCH_SIZE" in r and r["dur_ns"] > 1e5]
