@@ -105,12 +105,15 @@ struct rc_scene {
   int64_t device_bytes = 0;  // nodes, triangle copies, shading, planes, emission
   float2* hits = nullptr;    // primary hits of the last batched call with a hits pass
   size_t hits_bytes = 0;
+  unsigned int* vis = nullptr;  // their vertices' visibility bits (shadow pass)
+  size_t vis_bytes = 0;
   std::mutex mu;
   GraphCache graph;
   ~rc_scene() {
     graph.clear();
     lb.clear();
     if (hits) (void)hipFree(hits);
+    if (vis) (void)hipFree(vis);
     if (nodes) (void)hipFree(nodes);
     if (tris) (void)hipFree(tris);
     if (shade) (void)hipFree(shade);
@@ -195,6 +198,7 @@ int check_inputs(const rc_scene* s, const rc_medium* m, const rc_point_light* li
   if (p->precision != 0 && p->precision != 1) return fail(RC_EINVAL, "precision must be 0 or 1");
   if (p->common_random != 0 && p->common_random != 1) return fail(RC_EINVAL, "common_random must be 0 or 1");
   if (p->shadow_bvh != 0 && p->shadow_bvh != 1) return fail(RC_EINVAL, "shadow_bvh must be 0 or 1");
+  if (p->shadow_pass != 0 && p->shadow_pass != 1) return fail(RC_EINVAL, "shadow_pass must be 0 or 1");
   if (p->splits < 0 || p->splits > rc::kMaxSplits) return fail(RC_EINVAL, "splits must be in [0, %d]", rc::kMaxSplits);
   if (p->splits > 1 && P > rc::kSplitMaxRecords)
     return fail(RC_EINVAL, "splits > 1 needs P <= %d", rc::kSplitMaxRecords);
@@ -329,6 +333,9 @@ rc::RecordArgs make_args(const rc_scene* s, const rc_medium* m, const rc_point_l
   a.hit_stride = 0;
   a.max_n_theta = p->max_n_theta;
   a.trace_stack = rc::stack_variant(s->depth);
+  a.vis = nullptr;
+  a.vis_words = 0;
+  a.vis_shift = 0;
   a.counters = reinterpret_cast<unsigned long long*>(p->counters);
   a.splits = 1;
   a.refill_min = kTiles[0].refill_min;
@@ -724,6 +731,34 @@ int rc_records_batched(const rc_scene* scene, const rc_medium* medium, const rc_
   if (hits) {  // hits pass: every primary ray of the batch traced first, coherently
     a.hits = s->hits;
     a.hit_stride = params->max_n_theta * params->max_n_phi + 2;
+    // shadow pass: the same pass walks the vertices' shadow segments
+    int B = 1, shift = 0;
+    while (B < n_lights) {
+      B <<= 1;
+      shift++;
+    }
+    const int words = (params->max_rings + 1 + 32 / B - 1) / (32 / B);
+    if (params->shadow_pass && params->shadow_bvh == 0 && n_lights > 0 && a.lb_desc && words <= rc::kVisMaxWords) {
+      const size_t need = (size_t)((P + 63) / 64) * 64 * (size_t)a.hit_stride * (size_t)words * 4;
+      std::lock_guard<std::mutex> lk(s->mu);
+      if (s->vis_bytes < need) {
+        s->graph.clear();
+        if (s->vis) (void)hipFree(s->vis);
+        s->vis = nullptr;
+        s->vis_bytes = 0;
+        if (hipMalloc((void**)&s->vis, need) == hipSuccess) {
+          s->vis_bytes = need;
+        } else {
+          s->vis = nullptr;
+          (void)hipGetLastError();
+        }
+      }
+      if (s->vis) {
+        a.vis = s->vis;
+        a.vis_words = words;
+        a.vis_shift = shift;
+      }
+    }
   }
   std::vector<Launch> launches;
   if (!order && a.splits == 1 && P > rc::kSplitMaxRecords) {

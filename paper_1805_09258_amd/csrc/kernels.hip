@@ -85,6 +85,65 @@ RC_DEV int find_slot_minus(const int* off, int n, int x) {
   return lo;
 }
 
+// Visibility bits of one vertex o (bit l: the segment to light l is
+// unblocked) from the light bins.  A surface vertex (skip = its own triangle,
+// nrm = its lit-side normal) gets no bit for a light behind its lit side.
+// Each segment reads one header per level and then only the entries within
+// its reach, nearest to the light first, stopping at the first hit; the
+// lists whose first entry is within reach are kept as (first, end) pairs in
+// the lane's stack slots and walked in one loop.
+template <bool COUNT>
+RC_DEV int light_bits(const RecordArgs& g, float3 o, int skip, float3 nrm, int* stk, TraceCount& tc) {
+  int bits = 0;
+  for (int l = 0; l < g.n_lights; l++) {
+    const float4 Lp = g.lights[l];
+    const float3 d = make_float3(Lp.x - o.x, Lp.y - o.y, Lp.z - o.z);
+    if (skip >= 0 && !(dot3(nrm, d) > 0.f)) continue;  // light behind the lit side
+    const WtRay wr = wt_ray(o, d);
+    int h[4];
+    const int nlev = lb_bins(g.lb_desc, l, wr, h);
+    // the largest stored distance from the light that can still block
+    const float reach = __builtin_amdgcn_sqrtf(dot3(d, d)) * (1.0f + 0x1p-20f);
+    // the lists whose first entry is within reach, as (first, end)
+    // pairs in this lane's (unused) stack slots, walked in one loop
+    // (the wavefront runs as long as its longest walk, not as the
+    // sum over levels of each level's longest list)
+    int nl = 0;
+    for (int q = 0; q < nlev; q++) {
+      if (COUNT) tc.nodes++;
+      const int* hd = g.lb_offs + h[q];
+      if (__int_as_float(hd[1]) <= reach) {
+        stk[(2 * nl) * kWave] = hd[0];
+        stk[(2 * nl + 1) * kWave] = hd[2];
+        nl++;
+      }
+    }
+    bool blocked = false, live = nl > 0;
+    int cur = live ? stk[0] : 0, end = live ? stk[kWave] : 0, nxt = 1;
+    while (live) {
+      if (COUNT) tc.tris++;
+      const float4* en = g.lb_ent + 3 * cur;
+      const float4 q0 = en[0], q1 = en[1], q2 = en[2];
+      float t;
+      bool fr;
+      if (__float_as_int(q0.w) != skip && hit_triangle(wr, q0, q1, q2, 1e-4f, 1.0f, t, fr)) {
+        blocked = true;
+        live = false;
+      } else if (++cur == end || q2.w > reach) {  // this list is done: the next one, if any
+        if (nxt < nl) {
+          cur = stk[(2 * nxt) * kWave];
+          end = stk[(2 * nxt + 1) * kWave];
+          nxt++;
+        } else {
+          live = false;
+        }
+      }
+    }
+    if (!blocked) bits |= 1 << l;
+  }
+  return bits;
+}
+
 // Direction of column `col` of row a: row -1 is the north pole, row nth the
 // south pole, rows 0..nth-1 the strata rows.
 RC_DEV float3 row_direction(uint64_t key, int a, int col, int nth, int nph) {
@@ -335,7 +394,33 @@ record_kernel(RecordArgs g) {
         const int nvert = __builtin_amdgcn_readfirstlane(carry);
         const int NL = g.n_lights;
         __syncthreads();
-        if (!kOwnRays || g.lb_desc) {
+        if (g.vis) {
+          // walked by the hits pass: the vertices' bits of each column's ray
+          for (int base = 0; base < n; base += kWave) {
+            const int j = base + lane;
+            if (j >= n) continue;
+            const int col = sectored ? (b0 + j) % nph : j;
+            const size_t w0 =
+                ((size_t)(qr >> 6) * (size_t)g.hit_stride + (size_t)dir_index(a, col, nth, nph)) * (size_t)g.vis_words;
+            unsigned int words[kVisMaxWords];
+#pragma unroll
+            for (int q = 0; q < kVisMaxWords; q++)
+              words[q] = q < g.vis_words ? g.vis[(w0 + q) * kWave + (size_t)(qr & (kWave - 1))] : 0u;
+            const unsigned int mask = (1u << NL) - 1u;
+            auto vbits = [&](int kk) {
+              const int pos = kk << g.vis_shift;
+              unsigned int wd = 0u;
+#pragma unroll
+              for (int q = 0; q < kVisMaxWords; q++)
+                if (q == (pos >> 5)) wd = words[q];
+              return (int)((wd >> (pos & 31)) & mask);
+            };
+            const int code = R.code[j], M = R.M[j];
+            if (code >= 0) R.visS[j] = vbits(0);
+            for (int i = 0; i < M; i++) reinterpret_cast<int*>(R.Lm)[i * cap + j] = vbits(1 + i);
+            if (COUNT && own && j < n_cnt) n_rays += NL * ((code >= 0 ? 1 : 0) + M);
+          }
+        } else if (!kOwnRays || g.lb_desc) {
           // Light bins: a segment reads one header per level and then only
           // the few entries within its reach (one to three on average), so a
           // lane walks all lights of its vertex in turn: decode once, per
@@ -363,53 +448,7 @@ record_kernel(RecordArgs g) {
               slot = i * cap + j;
             }
             if (COUNT && own && j < n_cnt) n_rays += NL;
-            int bits = 0;
-            for (int l = 0; l < NL; l++) {
-              const float4 Lp = g.lights[l];
-              const float3 d = make_float3(Lp.x - o.x, Lp.y - o.y, Lp.z - o.z);
-              if (skip >= 0 && !(dot3(nrm, d) > 0.f)) continue;  // light behind the lit side
-              const WtRay wr = wt_ray(o, d);
-              int h[4];
-              const int nlev = lb_bins(g.lb_desc, l, wr, h);
-              // the largest stored distance from the light that can still block
-              const float reach = __builtin_amdgcn_sqrtf(dot3(d, d)) * (1.0f + 0x1p-20f);
-              // the lists whose first entry is within reach, as (first, end)
-              // pairs in this lane's (unused) stack slots, walked in one loop
-              // (the wavefront runs as long as its longest walk, not as the
-              // sum over levels of each level's longest list)
-              int nl = 0;
-              for (int q = 0; q < nlev; q++) {
-                if (COUNT) tc.nodes++;
-                const int* hd = g.lb_offs + h[q];
-                if (__int_as_float(hd[1]) <= reach) {
-                  stk[(2 * nl) * kWave] = hd[0];
-                  stk[(2 * nl + 1) * kWave] = hd[2];
-                  nl++;
-                }
-              }
-              bool blocked = false, live = nl > 0;
-              int cur = live ? stk[0] : 0, end = live ? stk[kWave] : 0, nxt = 1;
-              while (live) {
-                if (COUNT) tc.tris++;
-                const float4* en = g.lb_ent + 3 * cur;
-                const float4 q0 = en[0], q1 = en[1], q2 = en[2];
-                float t;
-                bool fr;
-                if (__float_as_int(q0.w) != skip && hit_triangle(wr, q0, q1, q2, 1e-4f, 1.0f, t, fr)) {
-                  blocked = true;
-                  live = false;
-                } else if (++cur == end || q2.w > reach) {  // this list is done: the next one, if any
-                  if (nxt < nl) {
-                    cur = stk[(2 * nxt) * kWave];
-                    end = stk[(2 * nxt + 1) * kWave];
-                    nxt++;
-                  } else {
-                    live = false;
-                  }
-                }
-              }
-              if (!blocked) bits |= 1 << l;
-            }
+            const int bits = light_bits<COUNT>(g, o, skip, nrm, stk, tc);
             if (slot < 0) R.visS[-1 - slot] = bits;
             else reinterpret_cast<int*>(R.Lm)[slot] = bits;
           }
@@ -888,6 +927,37 @@ __global__ __launch_bounds__(64) void primary_kernel(RecordArgs g, int nq, int b
   trace_closest<false>(g.nodes, g.tris, g.tri_stride, x, w, stack_lds + lane, g.leaf_batch, id, t, fr, tc);
   const int code = id >= 0 ? ((id << 1) | (fr ? 1 : 0)) : -1;
   g.hits[hit_slot(qr, d, g.hit_stride)] = make_float2(t, __int_as_float(code));
+  if (g.vis) {
+    // the ray's vertices as the record kernel takes them: the surface vertex
+    // (a hit) and the ring vertices in front of the hit or box exit
+    const float xr = uniform24(key, kRingIdx, 0);
+    const float tt = code < 0 ? box_exit(x, w, g.box_lo, g.box_hi) : t;
+    int M = 0;
+    while (M < g.max_rings && ring_distance(M, xr, g.ring_step) < tt) M++;
+    unsigned int words[kVisMaxWords] = {0u, 0u, 0u, 0u};
+    for (int kk = code >= 0 ? 0 : 1; kk <= M; kk++) {
+      int skip = -1;
+      float3 o, nrm = make_float3(0.f, 0.f, 0.f);
+      if (kk == 0) {
+        skip = code >> 1;
+        o = axpy3(t, w, x);
+        const float4 sh = g.shade[skip];
+        const float nsign = (code & 1) ? 1.f : -1.f;
+        nrm = make_float3(nsign * sh.x, nsign * sh.y, nsign * sh.z);
+      } else {
+        o = axpy3(ring_distance(kk - 1, xr, g.ring_step), w, x);
+      }
+      const unsigned int bits = (unsigned int)light_bits<false>(g, o, skip, nrm, stack_lds + lane, tc);
+      const int pos = kk << g.vis_shift;
+#pragma unroll
+      for (int q = 0; q < kVisMaxWords; q++)
+        if (q == (pos >> 5)) words[q] |= bits << (pos & 31);
+    }
+    const size_t w0 = ((size_t)blk * (size_t)g.hit_stride + (size_t)d) * (size_t)g.vis_words;
+#pragma unroll
+    for (int q = 0; q < kVisMaxWords; q++)
+      if (q < g.vis_words) g.vis[(w0 + q) * kWave + lane] = words[q];
+  }
 }
 
 // ---------------------------------------------------------------------------

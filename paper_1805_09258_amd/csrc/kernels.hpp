@@ -84,7 +84,15 @@ struct RecordArgs {
   int hit_stride;             // max_n_theta * max_n_phi + 2
   int max_n_theta;            // records above it are invalid (with hits)
   int trace_stack;            // traversal stack of the BVH (primary_kernel)
+  // visibility bits of every vertex of every primary ray, walked by
+  // primary_kernel (or nullptr): word w of ray (q, d) at
+  // vis[(((q / 64) * hit_stride + d) * vis_words + w) * 64 + q % 64]; vertex
+  // kk (0 the surface vertex, 1 + i ring i) holds its light bits at bit
+  // kk << vis_shift of the ray's words
+  unsigned int* vis;
+  int vis_words, vis_shift;
 };
+constexpr int kVisMaxWords = 4;
 
 int stack_variant(int depth);
 size_t record_lds_bytes(int stack, int max_n_phi, int max_rings);

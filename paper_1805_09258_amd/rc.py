@@ -47,7 +47,8 @@ class rc_params(C.Structure):
                 ("rec_base", C.c_int64),
                 ("counters", C.c_void_p),
                 ("shadow_bvh", C.c_int32),
-                ("max_n_theta", C.c_int32)]
+                ("max_n_theta", C.c_int32),
+                ("shadow_pass", C.c_int32)]
 
 
 class rc_scene_stats(C.Structure):
@@ -233,10 +234,11 @@ def rc_workspace_errors(ws, stream=None):
 
 
 def make_params(ring_step, max_rings, max_n_phi, seed, rec_base=0, precision=0, counters=None, common_random=False,
-                splits=0, shadow_bvh=False, max_n_theta=0):
+                splits=0, shadow_bvh=False, max_n_theta=0, shadow_pass=False):
     return rc_params(float(ring_step), int(max_rings), int(max_n_phi), int(precision), int(bool(common_random)),
                      int(splits), int(seed) & (2**64 - 1), int(rec_base),
-                     None if counters is None else counters.data_ptr(), int(bool(shadow_bvh)), int(max_n_theta))
+                     None if counters is None else counters.data_ptr(), int(bool(shadow_bvh)), int(max_n_theta),
+                     int(bool(shadow_pass)))
 
 
 def rc_records_wait(workspace, timeout_ms, stream=None):
@@ -503,7 +505,7 @@ class DeviceWorkload:
 
 def compute_records(scene: Scene, dw: DeviceWorkload, batched=False, use_graph=False, tile=-1, order=None,
                     precision=0, counters=None, out=None, workspace=None, stream=None, splits=0, shadow_bvh=False,
-                    hits_pass=True):
+                    hits_pass=True, shadow_pass=False):
     """Records for every point of a DeviceWorkload; returns (value, grad, hess, workspace).
     hits_pass: give rc_records_batched the batch's largest n_theta (primary rays
     traced in a separate coherent pass, ignored with counters) when
@@ -513,7 +515,8 @@ def compute_records(scene: Scene, dw: DeviceWorkload, batched=False, use_graph=F
     ws = workspace if workspace is not None else dw.workspace()
     prm = make_params(w.ring_step, w.max_rings, dw.max_n_phi, w.seed, 0, precision, counters, splits=splits,
                       shadow_bvh=shadow_bvh,
-                      max_n_theta=dw.hits_bound() if (hits_pass and batched and counters is None) else 0)
+                      max_n_theta=dw.hits_bound() if (hits_pass and batched and counters is None) else 0,
+                      shadow_pass=shadow_pass)
     if batched:
         rc_records_batched(scene.handle, w.sigma_s, w.sigma_a, w.lights, dw.pos, dw.n_theta, dw.n_phi, prm, order,
                            use_graph, tile, value, grad, hess, ws, stream)

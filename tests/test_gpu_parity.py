@@ -507,3 +507,31 @@ def test_primary_hits_pass_rejects_records_above_the_n_theta_bound(dev):
     vv = v.cpu().numpy()
     assert np.isnan(vv[[5, 17000]]).all() and np.isfinite(np.delete(vv, [5, 17000], axis=0)).all()
     sc.close()
+
+
+@pytest.mark.parametrize("case", ["mixed classes", "split records"])
+def test_shadow_pass_gives_identical_records(dev, case):
+    """With the shadow pass the hits pass also walks every vertex's shadow
+    segments and the record kernel reads the visibility bits: the records
+    equal, bit for bit, those whose segments the record kernel walks itself
+    (both runs use the hits pass, so both share one LDS layout)."""
+    if case == "mixed classes":
+        w = W.make_c3().subset(np.arange(20000))
+    else:
+        w = W.make_c2(P=3000, n_soup=4000, seed=21)
+    sc = rc.Scene.from_workload(w)
+    dw = rc.DeviceWorkload(w)
+    out = []
+    for sp in (False, True):
+        v, g, h = dw.outputs()
+        ws = dw.workspace()
+        prm = rc.make_params(w.ring_step, w.max_rings, dw.max_n_phi, w.seed, max_n_theta=dw.max_n_theta,
+                             shadow_pass=sp)
+        rc.rc_records_batched(sc.handle, w.sigma_s, w.sigma_a, w.lights, dw.pos, dw.n_theta, dw.n_phi, prm, None,
+                              True, -1, v, g, h, ws)
+        torch.cuda.synchronize()
+        assert rc.rc_workspace_errors(ws) == 0
+        out.append((v, g, h))
+    for a, b in zip(out[0], out[1]):
+        assert torch.equal(a, b)
+    sc.close()
