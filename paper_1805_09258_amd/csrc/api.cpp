@@ -1046,6 +1046,15 @@ int rc_probe(const rc_scene* s, const rc_medium* m, const rc_point_light* lights
   a.common_random = common_random;
   a.feat32 = feat32;
   a.feat16 = reinterpret_cast<__bf16*>(feat_bf16);
+  if (n_lights > 0) {  // shadow segments from the light bins of these lights
+    rc_scene* sm = const_cast<rc_scene*>(s);
+    std::lock_guard<std::mutex> lk(sm->mu);
+    int r = ensure_light_bins(sm, lights, n_lights, 0);
+    if (r) return r;
+    a.lb_desc = sm->lb.desc;
+    a.lb_offs = sm->lb.offs;
+    a.lb_ent = sm->lb.ent;
+  }
   RC_HIP(rc::launch_probe(a, s->depth, static_cast<hipStream_t>(stream)));
   return RC_OK;
 }

@@ -289,6 +289,108 @@ RC_DEV void trace_closest(const float4* __restrict__ nodes, const float4* __rest
   }
 }
 
+// Is the segment o -> light l unblocked?  From the light bins: the segment
+// reads one header per level and then only the entries within its reach,
+// nearest to the light first, stopping at the first hit (the entry of the
+// vertex's own triangle `skip` excepted); the lists whose first entry is
+// within reach are kept as (first, end) pairs in the lane's stack slots
+// (stride 64) and walked in one loop, so a wavefront runs as long as its
+// longest walk, not as the sum over levels of each level's longest list.
+template <bool COUNT>
+RC_DEV bool light_visible(float4 Lp, int l, const int4* lb_desc, const int* lb_offs, const float4* lb_ent, float3 o,
+                          int skip, int* stk, TraceCount& tc) {
+  const float3 d = make_float3(Lp.x - o.x, Lp.y - o.y, Lp.z - o.z);
+  const WtRay wr = wt_ray(o, d);
+  int h[4];
+  const int nlev = lb_bins(lb_desc, l, wr, h);
+  // the largest stored distance from the light that can still block
+  const float reach = __builtin_amdgcn_sqrtf(dot3(d, d)) * (1.0f + 0x1p-20f);
+  int nl = 0;
+  for (int q = 0; q < nlev; q++) {
+    if (COUNT) tc.nodes++;
+    const int* hd = lb_offs + h[q];
+    if (__int_as_float(hd[1]) <= reach) {
+      stk[(2 * nl) * kWave] = hd[0];
+      stk[(2 * nl + 1) * kWave] = hd[2];
+      nl++;
+    }
+  }
+  bool live = nl > 0;
+  int cur = live ? stk[0] : 0, end = live ? stk[kWave] : 0, nxt = 1;
+  while (live) {
+    if (COUNT) tc.tris++;
+    const float4* en = lb_ent + 3 * cur;
+    const float4 q0 = en[0], q1 = en[1], q2 = en[2];
+    float t;
+    bool fr;
+    if (__float_as_int(q0.w) != skip && hit_triangle(wr, q0, q1, q2, 1e-4f, 1.0f, t, fr)) {
+      return false;
+    } else if (++cur == end || q2.w > reach) {  // this list is done: the next one, if any
+      if (nxt < nl) {
+        cur = stk[(2 * nxt) * kWave];
+        end = stk[(2 * nxt + 1) * kWave];
+        nxt++;
+      } else {
+        live = false;
+      }
+    }
+  }
+  return true;
+}
+
+// Visibility bits of one vertex o (bit l: the segment to light l is
+// unblocked), light by light as light_visible walks them (the same
+// decisions, written as one loop so the record kernel keeps its register
+// allocation).  A surface vertex (skip = its own triangle, nrm = its lit-side
+// normal) gets no bit for a light behind its lit side.
+template <bool COUNT>
+RC_DEV int light_bits(const float4* lights, int n_lights, const int4* lb_desc, const int* lb_offs,
+                      const float4* lb_ent, float3 o, int skip, float3 nrm, int* stk, TraceCount& tc) {
+  int bits = 0;
+  for (int l = 0; l < n_lights; l++) {
+    const float4 Lp = lights[l];
+    const float3 d = make_float3(Lp.x - o.x, Lp.y - o.y, Lp.z - o.z);
+    if (skip >= 0 && !(dot3(nrm, d) > 0.f)) continue;  // light behind the lit side
+    const WtRay wr = wt_ray(o, d);
+    int h[4];
+    const int nlev = lb_bins(lb_desc, l, wr, h);
+    const float reach = __builtin_amdgcn_sqrtf(dot3(d, d)) * (1.0f + 0x1p-20f);
+    int nl = 0;
+    for (int q = 0; q < nlev; q++) {
+      if (COUNT) tc.nodes++;
+      const int* hd = lb_offs + h[q];
+      if (__int_as_float(hd[1]) <= reach) {
+        stk[(2 * nl) * kWave] = hd[0];
+        stk[(2 * nl + 1) * kWave] = hd[2];
+        nl++;
+      }
+    }
+    bool blocked = false, live = nl > 0;
+    int cur = live ? stk[0] : 0, end = live ? stk[kWave] : 0, nxt = 1;
+    while (live) {
+      if (COUNT) tc.tris++;
+      const float4* en = lb_ent + 3 * cur;
+      const float4 q0 = en[0], q1 = en[1], q2 = en[2];
+      float t;
+      bool fr;
+      if (__float_as_int(q0.w) != skip && hit_triangle(wr, q0, q1, q2, 1e-4f, 1.0f, t, fr)) {
+        blocked = true;
+        live = false;
+      } else if (++cur == end || q2.w > reach) {  // this list is done: the next one, if any
+        if (nxt < nl) {
+          cur = stk[(2 * nxt) * kWave];
+          end = stk[(2 * nxt + 1) * kWave];
+          nxt++;
+        } else {
+          live = false;
+        }
+      }
+    }
+    if (!blocked) bits |= 1 << l;
+  }
+  return bits;
+}
+
 // Shadow segment o -> o + d: blocked iff some triangle other than `skip` is
 // hit with 1e-4 < t < 1.
 template <bool COUNT>

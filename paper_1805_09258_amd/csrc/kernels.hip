@@ -85,65 +85,6 @@ RC_DEV int find_slot_minus(const int* off, int n, int x) {
   return lo;
 }
 
-// Visibility bits of one vertex o (bit l: the segment to light l is
-// unblocked) from the light bins.  A surface vertex (skip = its own triangle,
-// nrm = its lit-side normal) gets no bit for a light behind its lit side.
-// Each segment reads one header per level and then only the entries within
-// its reach, nearest to the light first, stopping at the first hit; the
-// lists whose first entry is within reach are kept as (first, end) pairs in
-// the lane's stack slots and walked in one loop.
-template <bool COUNT>
-RC_DEV int light_bits(const RecordArgs& g, float3 o, int skip, float3 nrm, int* stk, TraceCount& tc) {
-  int bits = 0;
-  for (int l = 0; l < g.n_lights; l++) {
-    const float4 Lp = g.lights[l];
-    const float3 d = make_float3(Lp.x - o.x, Lp.y - o.y, Lp.z - o.z);
-    if (skip >= 0 && !(dot3(nrm, d) > 0.f)) continue;  // light behind the lit side
-    const WtRay wr = wt_ray(o, d);
-    int h[4];
-    const int nlev = lb_bins(g.lb_desc, l, wr, h);
-    // the largest stored distance from the light that can still block
-    const float reach = __builtin_amdgcn_sqrtf(dot3(d, d)) * (1.0f + 0x1p-20f);
-    // the lists whose first entry is within reach, as (first, end)
-    // pairs in this lane's (unused) stack slots, walked in one loop
-    // (the wavefront runs as long as its longest walk, not as the
-    // sum over levels of each level's longest list)
-    int nl = 0;
-    for (int q = 0; q < nlev; q++) {
-      if (COUNT) tc.nodes++;
-      const int* hd = g.lb_offs + h[q];
-      if (__int_as_float(hd[1]) <= reach) {
-        stk[(2 * nl) * kWave] = hd[0];
-        stk[(2 * nl + 1) * kWave] = hd[2];
-        nl++;
-      }
-    }
-    bool blocked = false, live = nl > 0;
-    int cur = live ? stk[0] : 0, end = live ? stk[kWave] : 0, nxt = 1;
-    while (live) {
-      if (COUNT) tc.tris++;
-      const float4* en = g.lb_ent + 3 * cur;
-      const float4 q0 = en[0], q1 = en[1], q2 = en[2];
-      float t;
-      bool fr;
-      if (__float_as_int(q0.w) != skip && hit_triangle(wr, q0, q1, q2, 1e-4f, 1.0f, t, fr)) {
-        blocked = true;
-        live = false;
-      } else if (++cur == end || q2.w > reach) {  // this list is done: the next one, if any
-        if (nxt < nl) {
-          cur = stk[(2 * nxt) * kWave];
-          end = stk[(2 * nxt + 1) * kWave];
-          nxt++;
-        } else {
-          live = false;
-        }
-      }
-    }
-    if (!blocked) bits |= 1 << l;
-  }
-  return bits;
-}
-
 // Direction of column `col` of row a: row -1 is the north pole, row nth the
 // south pole, rows 0..nth-1 the strata rows.
 RC_DEV float3 row_direction(uint64_t key, int a, int col, int nth, int nph) {
@@ -448,7 +389,7 @@ record_kernel(RecordArgs g) {
               slot = i * cap + j;
             }
             if (COUNT && own && j < n_cnt) n_rays += NL;
-            const int bits = light_bits<COUNT>(g, o, skip, nrm, stk, tc);
+            const int bits = light_bits<COUNT>(g.lights, g.n_lights, g.lb_desc, g.lb_offs, g.lb_ent, o, skip, nrm, stk, tc);
             if (slot < 0) R.visS[-1 - slot] = bits;
             else reinterpret_cast<int*>(R.Lm)[slot] = bits;
           }
@@ -947,7 +888,7 @@ __global__ __launch_bounds__(64) void primary_kernel(RecordArgs g, int nq, int b
       } else {
         o = axpy3(ring_distance(kk - 1, xr, g.ring_step), w, x);
       }
-      const unsigned int bits = (unsigned int)light_bits<false>(g, o, skip, nrm, stack_lds + lane, tc);
+      const unsigned int bits = (unsigned int)light_bits<false>(g.lights, g.n_lights, g.lb_desc, g.lb_offs, g.lb_ent, o, skip, nrm, stack_lds + lane, tc);
       const int pos = kk << g.vis_shift;
 #pragma unroll
       for (int q = 0; q < kVisMaxWords; q++)

@@ -92,11 +92,26 @@ __global__ __launch_bounds__(64) void probe_kernel(ProbeArgs g) {
     vbits[lane] = 0;
     if (lane == 0) vbits[kWave] = 0;
     __syncthreads();
-    // Shadow segments, as a list of tasks: (direction k, light l) for
-    // k + 64 l < 64 L (hit point to light l, skipped when the hit's lit side
-    // faces away), then (x, light l) for l < min(L, 4).  Each loop iteration
-    // advances every busy lane by one node or one triangle; a lane whose
-    // segment is resolved takes the next task, so lanes stay busy while
+    // Shadow segments: hit point to light l (skipped when the hit's lit side
+    // faces away) for every lane's hit and light, and x to light l for
+    // l < min(L, 4).  From the light bins: each lane walks its hit's lights
+    // in turn, lanes 0..min(L,4)-1 also the segment from x.
+    if (g.lb_desc) {
+      int bits = 0;
+      if (hit) {
+        const float4 sh = g.shade[id];
+        const float nsign = fr ? 1.f : -1.f;
+        bits = light_bits<false>(g.lights, g.n_lights, g.lb_desc, g.lb_offs, g.lb_ent, axpy3(t, w, x), id,
+                                 make_float3(nsign * sh.x, nsign * sh.y, nsign * sh.z), stk, tc);
+      }
+      vbits[lane] = bits;
+      if (lane < nx && light_visible<false>(g.lights[lane], lane, g.lb_desc, g.lb_offs, g.lb_ent, x, -1, stk, tc))
+        atomicOr(&vbits[kWave], 1 << lane);
+    } else {
+    // From the BVH, as a list of tasks: (direction k, light l) for
+    // k + 64 l < 64 L, then (x, light l) for l < min(L, 4).  Each loop
+    // iteration advances every busy lane by one node or one triangle; a lane
+    // whose segment is resolved takes the next task, so lanes stay busy while
     // segments of different lengths finish.
     {
       const int total = kWave * g.n_lights + nx;
@@ -209,6 +224,7 @@ __global__ __launch_bounds__(64) void probe_kernel(ProbeArgs g) {
         }
       }
     }
+    }  // BVH shadow segments
     __syncthreads();
     // radiance of each hit: emission plus the unblocked lights, in order
     float Ls = hit ? g.emission[id] : 0.f;

@@ -46,6 +46,11 @@ struct ProbeArgs {
   int common_random;  // 1: every candidate draws with id id_base
   float* feat32;
   __bf16* feat16;
+  // light bins of these lights (shadow segments from the bins), or nullptr
+  // (BVH traversal); both give the answer of testing every triangle
+  const int4* lb_desc;
+  const int* lb_offs;
+  const float4* lb_ent;
 };
 
 int stack_variant(int depth);
