@@ -11,6 +11,8 @@ are plain linear algebra, written here in numpy:
 * the sequential greedy cover (Sec. 6 insertion rule) with balls or ellipsoids;
 * the multi-point interpolation of a cache (Sec. 5, Eq. radianceTaylor, with
   the cubic kernel);
+* the render pass that consumes a cache (Sec. 6 "Implementation"): uniform
+  ray marching of camera rays and the pixel estimates;
 * an FP64 reference of the small MLP used for learned placement (not part of
   the paper).
 
@@ -388,6 +390,62 @@ def interpolate(cache_pos, cache_val, cache_grad, cache_R, query, cache_form=Non
             out[i] = num / den
             cov[i] = True
     return out, cov
+
+
+# --------------------------------------------------------------------------
+# Sec. 6 "Implementation" and Results in 3D: the render pass that consumes the
+# cache (uniform ray marching of camera rays, step 0.1, 16 samples per pixel)
+# --------------------------------------------------------------------------
+def march(t_end, xi, step, sigma_s, sigma_t, orig, dirs):
+    """Uniform ray marching of camera rays through the medium.  Ray r starts
+    at orig[r] (inside the medium box) and ends at t_end[r] (its first surface
+    hit, or where it leaves the box); its march points lie at
+    t_k = (k + xi[r]) * step for k = 0, 1, 2, ... while t_k < t_end[r]
+    (k + xi is exact in FP64, the product is rounded once).  A point's
+    position is o + t_k d formed in FP64 and rounded once to FP32, and its
+    weight is step * sigma_s * exp(-sigma_t * t_k): the midpoint-rule term of
+    the in-scattering integral along the ray, attenuated by the transmittance
+    from the eye, so that a pixel's medium radiance is the sum of
+    weight * L_in over its points.  Points of a ray are enumerated one by one
+    (brute force).  Returns (offsets int64 [N+1], points float32 [M][3],
+    weights float64 [M])."""
+    t_end = np.asarray(t_end, np.float32)
+    xi = np.asarray(xi, np.float32)
+    o = np.asarray(orig, np.float32).astype(np.float64)
+    d = np.asarray(dirs, np.float32).astype(np.float64)
+    step = float(step)
+    offs = [0]
+    pts, wts = [], []
+    for r in range(len(t_end)):
+        k = 0
+        while True:
+            t = (k + float(xi[r])) * step
+            if not t < float(t_end[r]):
+                break
+            pts.append(o[r] + t * d[r])
+            wts.append(step * sigma_s * np.exp(-sigma_t * t))
+            k += 1
+        offs.append(offs[-1] + k)
+    P = np.asarray(pts, np.float64).reshape(-1, 3).astype(np.float32)
+    return np.asarray(offs, np.int64), P, np.asarray(wts, np.float64)
+
+
+def composite(offsets, spp, weights, L):
+    """Pixel estimates of the render pass: pixel p averages its spp rays
+    (rays p*spp .. p*spp + spp - 1), each ray contributing the sum of
+    weight * L over its march points.  FP64.  Returns [N / spp]."""
+    offsets = np.asarray(offsets, np.int64)
+    w = np.asarray(weights, np.float64)
+    L = np.asarray(L, np.float64)
+    n_pix = (len(offsets) - 1) // spp
+    out = np.zeros(n_pix)
+    for p in range(n_pix):
+        acc = 0.0
+        for r in range(p * spp, (p + 1) * spp):
+            a, b = offsets[r], offsets[r + 1]
+            acc += float(np.dot(w[a:b], L[a:b]))
+        out[p] = acc / spp
+    return out
 
 
 # --------------------------------------------------------------------------

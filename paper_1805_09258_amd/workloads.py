@@ -319,3 +319,52 @@ def uniform_points(n: int, box_lo, box_hi, seed: int) -> np.ndarray:
     lo = np.asarray(box_lo, np.float64)
     hi = np.asarray(box_hi, np.float64)
     return (lo + rng.uniform(0, 1, (n, 3)) * (hi - lo)).astype(np.float32)
+
+
+class CameraRays:
+    """Camera rays of a render pass: a pinhole camera at eye looking at
+    look_at (vertical field of view fov_deg, square pixels), width x height
+    pixels with spp jittered rays each, ordered pixel by pixel (ray
+    p * spp + s is sample s of pixel p, pixels row-major from the top-left),
+    and one uniform march offset xi per ray.  Directions are formed in FP64,
+    normalised and rounded once to FP32; every random number is drawn here
+    from the seed.  The eye must lie inside the medium box."""
+
+    def __init__(self, width: int, height: int, spp: int, eye, look_at, fov_deg: float, seed: int,
+                 up=(0.0, 1.0, 0.0)):
+        rng = np.random.default_rng(seed)
+        self.width, self.height, self.spp = int(width), int(height), int(spp)
+        eye = np.asarray(eye, np.float64)
+        fwd = np.asarray(look_at, np.float64) - eye
+        fwd /= np.linalg.norm(fwd)
+        right = np.cross(fwd, np.asarray(up, np.float64))
+        right /= np.linalg.norm(right)
+        upv = np.cross(right, fwd)
+        th = np.tan(np.radians(fov_deg) / 2)
+        n = self.width * self.height * self.spp
+        pix = np.arange(n) // self.spp
+        px = (pix % self.width).astype(np.float64)
+        py = (pix // self.width).astype(np.float64)
+        j = rng.uniform(0.0, 1.0, (n, 2))
+        u = (2.0 * (px + j[:, 0]) / self.width - 1.0) * th * self.width / self.height
+        v = (1.0 - 2.0 * (py + j[:, 1]) / self.height) * th
+        d = fwd[None, :] + u[:, None] * right[None, :] + v[:, None] * upv[None, :]
+        d /= np.linalg.norm(d, axis=1, keepdims=True)
+        self.dirs = d.astype(np.float32)
+        self.orig = np.tile(eye.astype(np.float32)[None, :], (n, 1))
+        self.xi = rng.uniform(0.0, 1.0, n).astype(np.float32)
+
+    @property
+    def n(self) -> int:
+        return self.dirs.shape[0]
+
+    @property
+    def n_pixels(self) -> int:
+        return self.width * self.height
+
+
+def render_camera(width=128, height=128, spp=16, seed=8):
+    """The render-pass camera in the closed-room scenes: eye near the z = 0
+    wall, looking at the far wall through the medium (60 degree field of
+    view)."""
+    return CameraRays(width, height, spp, eye=(0.5, 0.5, 0.04), look_at=(0.5, 0.5, 1.0), fov_deg=60.0, seed=seed)

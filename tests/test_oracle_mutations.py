@@ -93,7 +93,31 @@ def _within_without_factor_two(orig):
     return f
 
 
+def _march_from_k1(orig):
+    def f(t_end, xi, step, sigma_s, sigma_t, o, d):
+        return orig(t_end, np.asarray(xi, np.float32) + np.float32(1), step, sigma_s, sigma_t, o, d)
+    return f
+
+
+def _march_without_sigma_s(orig):
+    def f(t_end, xi, step, sigma_s, sigma_t, o, d):
+        return orig(t_end, xi, step, 1.0, sigma_t, o, d)
+    return f
+
+
+def _composite_summing_rays(orig):
+    def f(offsets, spp, weights, L):
+        return orig(offsets, spp, weights, L) * spp
+    return f
+
+
 PY_MUTATIONS = [
+    ("march starts one step late", "march", _march_from_k1,
+     ["test_march_points_in_an_empty_room_follow_the_closed_form"]),
+    ("march weight without the scattering coefficient", "march", _march_without_sigma_s,
+     ["test_march_weights_average_to_the_transmittance_integral"]),
+    ("pixel sums its rays instead of averaging them", "composite", _composite_summing_rays,
+     ["test_composite_of_constant_radiance_is_a_geometric_series"]),
     ("ellipsoid built from eigenvector columns", "ellipsoid_form", _form_transposed,
      ["test_ellipsoid_form_has_the_axes_as_eigenvectors"]),
     ("off-diagonal terms of the form counted once", "_within_form32", _within_without_factor_two,

@@ -891,3 +891,91 @@ def test_anisotropic_interpolation_single_point_and_ball_limit():
     b, cb = O.interpolate(cp, cv, cg, Rb, qs, cache_form=FF)
     assert np.array_equal(ca, cb) and ca.sum() > 100
     np.testing.assert_allclose(b, a, rtol=1e-5)
+
+
+# ---------------------------------------------------------------------------
+# the render pass (Sec. 6 "Implementation"; Results in 3D: march step 0.1)
+# ---------------------------------------------------------------------------
+def _room_rays(rng, n):
+    """Rays from the centre region of the empty unit room: FP32 origins and
+    unit directions, the oracle's closest hits, and the exact FP64 distances
+    to the walls (the room is the only geometry)."""
+    o = rng.uniform(0.3, 0.7, (n, 3)).astype(np.float32)
+    d = rng.normal(size=(n, 3))
+    d /= np.linalg.norm(d, axis=1, keepdims=True)
+    d = d.astype(np.float32)
+    d[:6] = np.array([[1, 0, 0], [-1, 0, 0], [0, 1, 0], [0, -1, 0], [0, 0, 1], [0, 0, -1]], np.float32)
+    sc = O.Scene(W.room_triangles(), np.full(12, 0.5, np.float32))
+    hid, t, _ = sc.trace(o, d, brute=True)
+    o64, d64 = o.astype(np.float64), d.astype(np.float64)
+    with np.errstate(divide="ignore"):
+        wall = np.where(d64 > 0, (1.0 - o64) / d64, np.where(d64 < 0, -o64 / d64, np.inf)).min(1)
+    return o, d, hid, t, wall
+
+
+def test_march_points_in_an_empty_room_follow_the_closed_form():
+    """Every ray from inside the closed room ends on a wall at the exact wall
+    distance; its march points are the ceil(t/step - xi) points (k + xi) step
+    along the ray, inside the room."""
+    rng = np.random.default_rng(71)
+    n = 400
+    o, d, hid, t, wall = _room_rays(rng, n)
+    assert (hid >= 0).all()
+    np.testing.assert_allclose(t, wall, rtol=2e-6)
+    xi = rng.uniform(0, 1, n).astype(np.float32)
+    step = 0.1
+    offs, P, wts = O.march(t, xi, step, 1.0, 1.2, o, d)
+    r = t.astype(np.float64) / step - xi.astype(np.float64)
+    assert np.abs(r - np.round(r)).min() > 1e-9  # no ray ends on a march point
+    np.testing.assert_array_equal(np.diff(offs), np.maximum(np.ceil(r), 0).astype(np.int64))
+    ray = np.repeat(np.arange(n), np.diff(offs))
+    k = np.arange(offs[-1]) - offs[:-1][ray]
+    tk = (k + xi[ray].astype(np.float64)) * step
+    np.testing.assert_allclose(np.linalg.norm(P.astype(np.float64) - o[ray].astype(np.float64), axis=1), tk,
+                               rtol=1e-6, atol=1e-7)
+    assert ((P >= 0) & (P <= 1)).all()
+    # the points of a ray lie on it: cross((p - o), d) = 0
+    c = np.cross(P.astype(np.float64) - o[ray].astype(np.float64), d[ray].astype(np.float64))
+    assert np.abs(c).max() < 1e-6
+
+
+def test_march_weights_average_to_the_transmittance_integral():
+    """With a uniform offset xi, the march points of one ray stratify [0, t):
+    the average of sum_k weight_k over xi is the integral of
+    sigma_s exp(-sigma_t s) over [0, t), i.e. sigma_s (1 - exp(-sigma_t t)) /
+    sigma_t (the medium radiance of a pixel seeing unit in-scattered radiance
+    everywhere).  Averaged over 4000 evenly spaced offsets."""
+    step, ss, st = 0.1, 0.8, 1.7
+    for t_end in (0.05, 0.37, 1.0, 1.6180339):
+        m = 4000
+        xi = ((np.arange(m) + 0.5) / m).astype(np.float32)
+        o = np.zeros((m, 3), np.float32)
+        dd = np.tile(np.array([[0, 0, 1]], np.float32), (m, 1))
+        offs, P, w = O.march(np.full(m, t_end, np.float32), xi, step, ss, st, o, dd)
+        per_ray = np.bincount(np.repeat(np.arange(m), np.diff(offs)), weights=w, minlength=m)
+        exact = ss * (1 - math.exp(-st * float(np.float32(t_end)))) / st
+        assert abs(per_ray.mean() - exact) < 1e-6 * exact + 1e-7
+
+
+def test_composite_of_constant_radiance_is_a_geometric_series():
+    """Constant in-scattered radiance c: a ray with n points contributes
+    step sigma_s c exp(-sigma_t xi step) (1 - r^n) / (1 - r), r = exp(-sigma_t
+    step); a pixel averages its spp rays."""
+    rng = np.random.default_rng(72)
+    spp, n_pix = 4, 50
+    N = spp * n_pix
+    t = rng.uniform(0, 1.5, N).astype(np.float32)
+    xi = rng.uniform(0, 1, N).astype(np.float32)
+    step, ss, st, c = 0.1, 1.0, 1.2, 2.5
+    o = np.zeros((N, 3), np.float32)
+    dd = np.tile(np.array([[1, 0, 0]], np.float32), (N, 1))
+    offs, P, w = O.march(t, xi, step, ss, st, o, dd)
+    pix = O.composite(offs, spp, w, np.full(len(w), c))
+    n = np.diff(offs)
+    r = math.exp(-st * step)
+    ray = step * ss * c * np.exp(-st * xi.astype(np.float64) * step) * (1 - r ** n) / (1 - r)
+    np.testing.assert_allclose(pix, ray.reshape(n_pix, spp).mean(1), rtol=1e-12)
+    # each pixel sees only its own rays: per-ray distinct radiance
+    Lr = rng.uniform(0, 1, N)
+    pix2 = O.composite(offs, spp, w, Lr[np.repeat(np.arange(N), n)])
+    np.testing.assert_allclose(pix2, (ray / c * Lr).reshape(n_pix, spp).mean(1), rtol=1e-12)
