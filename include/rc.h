@@ -45,6 +45,7 @@ extern "C" {
 #define RC_MAX_RINGS 64
 #define RC_MAX_NPHI 256
 #define RC_NOALLOC_MAX_RECORDS 4096 /* largest batch of rc_records_noalloc */
+#define RC_MARCH_MAX_POINTS_PER_RAY 1048576 /* bound on medium box diagonal / march step */
 /* int32 words of the placement state (5 counters + 4096 batch status words) */
 #define RC_PLACE_STATE_INTS 4101
 
@@ -507,6 +508,39 @@ int rc_ellipsoid_form(const float* axes, int64_t K, float* form, float* r_max, v
 int rc_interp(const float* cache_pos, const double* cache_value, const double* cache_grad, const float* cache_R,
               int64_t K, const float* query, int64_t Q, double* out, int32_t* hits, const double* ref_value,
               double* err_partial, const float* cache_form, void* stream);
+
+/* ------------------------------------------------------------------ */
+/* Render pass (Sec. 6 "Implementation"; Results in 3D: uniform ray      */
+/* marching with step 0.1): the consumer of the cache                   */
+/* ------------------------------------------------------------------ */
+/* Camera rays marched through the medium.  Ray r (orig/dir device
+ * float[n][3], origin inside the scene's medium box) ends at t_end[r]: its
+ * closest triangle hit, or where it leaves the box (the traversal of
+ * rc_trace_rays); its march points lie at t_k = (k + xi[r]) * step for
+ * k = 0, 1, ... while t_k < t_end[r] (xi device float[n], the ray's offset in
+ * [0, 1); k + xi exact in FP64, the product rounded once).  Writes t_end
+ * (device float[n]) and offsets (device int64[n + 1]): offsets[0] = 0 and
+ * offsets[r + 1] = number of points of rays 0..r, so offsets[n] is the total
+ * the caller sizes rc_march_emit's outputs with.  Directions must be nonzero.
+ * RC_EINVAL unless step > 0 and box diagonal / step <=
+ * RC_MARCH_MAX_POINTS_PER_RAY. */
+int rc_march_count(const rc_scene* scene, const float* orig, const float* dir, const float* xi, int64_t n,
+                   double step, float* t_end, int64_t* offsets, void* stream);
+/* The march points of rc_march_count's rays (same orig, dir, xi, step and its
+ * offsets): point offsets[r] + k is at o + t_k d, formed in FP64 and rounded
+ * once to FP32 (points device float[offsets[n]][3]), with quadrature weight
+ * step * sigma_s * exp(-sigma_t t_k) (weight device double[offsets[n]]): the
+ * in-scattering integral of the ray by the march points, attenuated by the
+ * transmittance from the eye (sigma_t = sigma_s + sigma_a). */
+int rc_march_emit(const float* orig, const float* dir, const float* xi, int64_t n, double step, double sigma_s,
+                  double sigma_t, const int64_t* offsets, float* points, double* weight, void* stream);
+/* Pixel estimates: pixel p (device double[n_rays / spp]) is the mean over
+ * rays p * spp .. p * spp + spp - 1 of the sum of weight * L over the ray's
+ * points (L device double[offsets[n_rays]]: in-scattered radiance at each
+ * point, e.g. from rc_interp), FP64, points taken in ray order.  RC_EINVAL
+ * unless spp >= 1 divides n_rays. */
+int rc_composite(const int64_t* offsets, int64_t n_rays, int32_t spp, const double* weight, const double* L,
+                 double* pixel, void* stream);
 
 /* ------------------------------------------------------------------ */
 /* Diagnostics                                                          */

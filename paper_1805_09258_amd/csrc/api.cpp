@@ -17,6 +17,7 @@
 #include "internal.hpp"
 #include "kernels.hpp"
 #include "learned.hpp"
+#include "render.hpp"
 
 namespace {
 
@@ -1198,6 +1199,45 @@ int rc_ellipsoid_form(const float* axes, int64_t K, float* form, float* r_max, v
   if (K < 0 || K > 0x7fffffff) return fail(RC_EINVAL, "K out of range");
   if (K > 0 && (!axes || !form)) return fail(RC_EINVAL, "NULL pointer");
   RC_HIP(rc::launch_ellipsoid_form(axes, (int)K, form, r_max, static_cast<hipStream_t>(stream)));
+  return RC_OK;
+}
+
+int rc_march_count(const rc_scene* s, const float* orig, const float* dir, const float* xi, int64_t n, double step,
+                   float* t_end, int64_t* offsets, void* stream) {
+  if (!s || n < 0 || n > 0x7fffffff) return fail(RC_EINVAL, "invalid arguments");
+  if (!offsets || (n > 0 && (!orig || !dir || !xi || !t_end))) return fail(RC_EINVAL, "NULL pointer");
+  double diag = 0.0;
+  for (int a = 0; a < 3; a++) diag += ((double)s->box_hi[a] - s->box_lo[a]) * ((double)s->box_hi[a] - s->box_lo[a]);
+  diag = std::sqrt(diag);
+  if (!(step > 0.0) || !std::isfinite(step) || diag / step > (double)RC_MARCH_MAX_POINTS_PER_RAY)
+    return fail(RC_EINVAL, "step must be positive with box diagonal / step <= %d", RC_MARCH_MAX_POINTS_PER_RAY);
+  RC_HIP(rc::launch_march_count(s->nodes, s->tris, s->tri_stride, s->depth, orig, dir, xi, (int)n, step,
+                                make_float3(s->box_lo[0], s->box_lo[1], s->box_lo[2]),
+                                make_float3(s->box_hi[0], s->box_hi[1], s->box_hi[2]), t_end,
+                                reinterpret_cast<long long*>(offsets), static_cast<hipStream_t>(stream)));
+  return RC_OK;
+}
+
+int rc_march_emit(const float* orig, const float* dir, const float* xi, int64_t n, double step, double sigma_s,
+                  double sigma_t, const int64_t* offsets, float* points, double* weight, void* stream) {
+  if (n < 0 || n > 0x7fffffff) return fail(RC_EINVAL, "n out of range");
+  if (!(step > 0.0) || !std::isfinite(step) || !std::isfinite(sigma_s) || !std::isfinite(sigma_t) || sigma_s < 0 ||
+      sigma_t < 0)
+    return fail(RC_EINVAL, "step must be positive and the coefficients finite and non-negative");
+  if (n > 0 && (!orig || !dir || !xi || !offsets || !points || !weight)) return fail(RC_EINVAL, "NULL pointer");
+  RC_HIP(rc::launch_march_emit(orig, dir, xi, (int)n, step, sigma_s, sigma_t,
+                               reinterpret_cast<const long long*>(offsets), points, weight,
+                               static_cast<hipStream_t>(stream)));
+  return RC_OK;
+}
+
+int rc_composite(const int64_t* offsets, int64_t n_rays, int32_t spp, const double* weight, const double* L,
+                 double* pixel, void* stream) {
+  if (n_rays < 0 || n_rays > 0x7fffffff || spp < 1 || n_rays % spp != 0)
+    return fail(RC_EINVAL, "n_rays must be a non-negative multiple of spp >= 1");
+  if (n_rays > 0 && (!offsets || !pixel)) return fail(RC_EINVAL, "NULL pointer");
+  RC_HIP(rc::launch_composite(reinterpret_cast<const long long*>(offsets), (int)(n_rays / spp), spp, weight, L, pixel,
+                              static_cast<hipStream_t>(stream)));
   return RC_OK;
 }
 

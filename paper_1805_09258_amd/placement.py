@@ -117,7 +117,7 @@ class Placer:
         C, B = cands.n, cfg.batch
         t = lambda a: torch.as_tensor(a, device=device)  # noqa: E731
         self.cand = t(cands.pos)
-        self.order = t(cands.order)
+        self.order = None if cands.order is None else t(cands.order)  # None: index order
         self.covered = torch.zeros(C, dtype=torch.uint8, device=device)
         self.state = torch.zeros(rc.RC_PLACE_STATE_INTS, dtype=torch.int32, device=device)
         self.bidx = torch.zeros(B, dtype=torch.int32, device=device)
@@ -167,6 +167,9 @@ class Placer:
 
     def _cover_last_round(self, form=None):
         c = self.cands
+        if getattr(c, "dims", None) is None:  # scattered candidates: every candidate against the round's points
+            rc.rc_place_cover(self.cand, self.covered, self.state, self.acc, self.accR, accepted_form=form)
+            return
         rc.rc_place_cover_grid(self.cand, c.dims, c.lo, c.cell, self.covered, self.state, self.acc, self.accR,
                                accepted_form=form)
 

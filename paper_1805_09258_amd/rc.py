@@ -23,6 +23,7 @@ RC_OK, RC_EINVAL, RC_ENOMEM, RC_EDEVICE, RC_ENODEV = 0, -1, -2, -3, -4
 RC_MAX_LIGHTS, RC_MAX_RINGS, RC_MAX_NPHI = 16, 64, 256
 RC_ETIMEOUT = -5
 RC_NOALLOC_MAX_RECORDS = 4096  # largest batch of rc_records_noalloc
+RC_MARCH_MAX_POINTS_PER_RAY = 1 << 20  # bound on medium box diagonal / march step
 RC_PLACE_STATE_INTS = 4101  # placement state: 5 counters + one status word per gathered candidate
 
 
@@ -63,7 +64,7 @@ EXPORTS = ["rc_scene_create", "rc_scene_destroy", "rc_scene_info", "rc_bvh_build
            "rc_probe", "rc_mlp_param_bytes", "rc_mlp_n_params", "rc_mlp_init",
            "rc_mlp_load", "rc_mlp_fit_features", "rc_mlp_forward", "rc_mlp_radius", "rc_mlp_train_workspace_bytes",
            "rc_mlp_train_step", "rc_place_gather", "rc_place_accept", "rc_place_cover", "rc_place_cover_grid",
-           "rc_ellipsoid_form", "rc_interp",
+           "rc_ellipsoid_form", "rc_interp", "rc_march_count", "rc_march_emit", "rc_composite",
            "rc_last_error", "rc_version"]
 
 _LIB = None
@@ -148,6 +149,13 @@ def lib():
         L.rc_ellipsoid_form.restype = i32
         L.rc_interp.argtypes = [vp, vp, vp, vp, i64, vp, i64, vp, vp, vp, vp, vp, vp]
         L.rc_interp.restype = i32
+        f64 = C.c_double
+        L.rc_march_count.argtypes = [vp, vp, vp, vp, i64, f64, vp, vp, vp]
+        L.rc_march_count.restype = i32
+        L.rc_march_emit.argtypes = [vp, vp, vp, i64, f64, f64, f64, vp, vp, vp, vp]
+        L.rc_march_emit.restype = i32
+        L.rc_composite.argtypes = [vp, i64, i32, vp, vp, vp, vp]
+        L.rc_composite.restype = i32
         L.rc_last_error.restype = C.c_char_p
         L.rc_version.restype = C.c_char_p
         _LIB = L
@@ -430,6 +438,22 @@ def rc_interp(cache_pos, cache_value, cache_grad, cache_R, query, out, hits=None
     return _check(lib().rc_interp(_ptr(cache_pos), _ptr(cache_value), _ptr(cache_grad), _ptr(cache_R),
                                   int(cache_pos.shape[0]), _ptr(query), int(query.shape[0]), _ptr(out), _ptr(hits),
                                   _ptr(ref_value), _ptr(err_partial), _ptr(cache_form), _stream(stream)))
+
+
+def rc_march_count(scene, orig, dirs, xi, step, t_end, offsets, stream=None):
+    return _check(lib().rc_march_count(scene, _ptr(orig), _ptr(dirs), _ptr(xi), int(orig.shape[0]), float(step),
+                                       _ptr(t_end), _ptr(offsets), _stream(stream)))
+
+
+def rc_march_emit(orig, dirs, xi, step, sigma_s, sigma_t, offsets, points, weight, stream=None):
+    return _check(lib().rc_march_emit(_ptr(orig), _ptr(dirs), _ptr(xi), int(orig.shape[0]), float(step),
+                                      float(sigma_s), float(sigma_t), _ptr(offsets), _ptr(points), _ptr(weight),
+                                      _stream(stream)))
+
+
+def rc_composite(offsets, spp, weight, L, pixel, stream=None):
+    return _check(lib().rc_composite(_ptr(offsets), int(offsets.shape[0]) - 1, int(spp), _ptr(weight), _ptr(L),
+                                     _ptr(pixel), _stream(stream)))
 
 
 def rc_version():

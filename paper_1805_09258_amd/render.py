@@ -1,0 +1,119 @@
+"""The render pass that consumes the radiance cache (Sec. 6 "Implementation";
+Results in 3D: 16 samples per pixel, uniform ray marching with step 0.1).
+
+1. Pre-population: one camera ray per pixel is marched through the medium
+   and its march points are the candidates of a plain greedy placement (the
+   error-metric insertion rule of Sec. 5 and 6).
+2. Render: every sample ray is marched; at each march point, in camera
+   order, the cache either holds a valid point (the radius test of
+   Eq. radiusAniso3D) or a record is computed there and inserted.  This is
+   the same greedy rule continued over the render points with the
+   pre-populated cache already in place, so it runs as further plain rounds.
+3. The in-scattered radiance at every march point is interpolated from the
+   final cache (Eq. radianceTaylor) and the pixels are composited.
+
+Every step runs in the library's kernels (rc.*); this module sequences the
+calls and holds device buffers.
+"""
+from __future__ import annotations
+
+import time
+from dataclasses import dataclass
+
+from . import rc
+from . import workloads as W
+from .placement import CacheConfig, Placer, SceneContext
+
+
+@dataclass
+class MarchCandidates:
+    """Candidates of a placement that are march points (device float[C][3],
+    visited in index order, no grid)."""
+    pos: object
+    order: object = None
+    dims: object = None
+
+    @property
+    def n(self) -> int:
+        return int(self.pos.shape[0])
+
+
+@dataclass
+class Marched:
+    offsets: object   # device int64 [N + 1]
+    points: object    # device float32 [M][3]
+    weight: object    # device float64 [M]
+    t_end: object     # device float32 [N]
+
+    @property
+    def n_points(self) -> int:
+        return int(self.points.shape[0])
+
+
+def march(ctx: SceneContext, cam: W.CameraRays, step: float, device) -> Marched:
+    """The march points of a camera's rays (rc_march_count, rc_march_emit)."""
+    import torch
+    w = ctx.w
+    T = lambda a: torch.as_tensor(a, device=device)  # noqa: E731
+    o, d, xi = T(cam.orig), T(cam.dirs), T(cam.xi)
+    N = cam.n
+    t_end = torch.empty(N, dtype=torch.float32, device=device)
+    offs = torch.empty(N + 1, dtype=torch.int64, device=device)
+    rc.rc_march_count(ctx.scene.handle, o, d, xi, step, t_end, offs)
+    M = int(offs[-1].item())
+    pts = torch.empty((M, 3), dtype=torch.float32, device=device)
+    wt = torch.empty(M, dtype=torch.float64, device=device)
+    rc.rc_march_emit(o, d, xi, step, w.sigma_s, w.sigma_s + w.sigma_a, offs, pts, wt)
+    return Marched(offs, pts, wt, t_end)
+
+
+def render(ctx: SceneContext, cam: W.CameraRays, prepop: W.CameraRays, cfg: CacheConfig, device, step=0.1,
+           batch=None):
+    """Pre-populate a cache from prepop's rays, render cam's rays through it
+    (inserting records where the cache has no valid point), and composite.
+    Returns (pixels [n_pixels] device float64, stats)."""
+    import torch
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    m0 = march(ctx, prepop, step, device)
+    pre = Placer(ctx, MarchCandidates(m0.points), cfg, device)
+    res0 = pre.plain(batch)
+    K0 = res0.K
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    # render: the candidates are the cache's K0 points followed by the render
+    # march points; the cache entries are in place (accepted, covered) and
+    # cover the render points before the rounds continue from candidate K0
+    m1 = march(ctx, cam, step, device)
+    cand = torch.cat([res0.pos, m1.points])
+    pl = Placer(ctx, MarchCandidates(cand), cfg, device)
+    pl.covered[:K0] = 1
+    pl.acc[:K0] = torch.arange(K0, dtype=torch.int32, device=device)
+    pl.accR[:K0] = res0.R
+    pl.accpos[:K0] = res0.pos
+    pl.cval[:K0] = res0.value
+    pl.cgrad[:K0] = res0.grad
+    pl.state[0] = K0   # gather cursor
+    pl.state[1] = K0   # cache size
+    if K0:
+        rc.rc_place_cover(pl.cand, pl.covered, None, pl.acc, pl.accR, 0, K0)
+    rounds, records = pl._plain_rounds(batch)
+    res = pl._result({})
+    # radiance at every march point from the final cache, and the pixels
+    M = m1.n_points
+    L = torch.zeros(M, dtype=torch.float64, device=device)
+    hits = torch.zeros(M, dtype=torch.int32, device=device)
+    rc.rc_interp(res.pos, res.value, res.grad, res.R, m1.points, L, hits)
+    pix = torch.empty(cam.n_pixels, dtype=torch.float64, device=device)
+    rc.rc_composite(m1.offsets, cam.spp, m1.weight, L, pix)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    uncovered = int((hits == 0).sum().item())
+    stats = {"rays": cam.n, "march_points": M, "prepop_rays": prepop.n, "prepop_points": m0.n_points,
+             "prepop_records": res0.stats["records"], "prepop_cache": K0, "prepop_rounds": res0.stats["rounds"],
+             "render_records": records, "render_rounds": rounds, "cache_points": res.K,
+             "inserted": res.K - K0, "uncovered_after": uncovered,
+             "seconds_prepop": t1 - t0, "seconds_render": t2 - t1,
+             "pixel_mean": float(pix.mean().item()) if cam.n_pixels else 0.0}
+    stats["march_points_per_s"] = M / stats["seconds_render"] if stats["seconds_render"] > 0 else 0.0
+    return pix, stats, (m1, res, L, hits, cand, pl)

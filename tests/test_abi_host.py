@@ -348,3 +348,19 @@ def test_tile_table_is_readable_without_a_device():
     assert {t["lds_waves"] for t in tiles} == {2, 3, 4}
     with pytest.raises(rc.RCError):
         rc.rc_tile_info(10)
+
+
+def test_render_pass_entries_reject_bad_arguments_without_a_device():
+    L = rc.lib()
+    vp = rc.C.c_void_p
+    for step in (0.0, -0.1, float("nan"), float("inf")):  # march step
+        assert L.rc_march_emit(vp(8), vp(8), vp(8), 4, step, 1.0, 1.2, vp(8), vp(8), vp(8), None) == rc.RC_EINVAL
+    assert L.rc_march_count(None, vp(8), vp(8), vp(8), 4, 0.1, vp(8), vp(8), None) == rc.RC_EINVAL
+    assert L.rc_march_emit(vp(8), vp(8), vp(8), -1, 0.1, 1.0, 1.2, vp(8), vp(8), vp(8), None) == rc.RC_EINVAL
+    assert L.rc_march_emit(vp(8), vp(8), vp(8), 4, 0.1, -1.0, 1.2, vp(8), vp(8), vp(8), None) == rc.RC_EINVAL
+    assert L.rc_march_emit(None, vp(8), vp(8), 4, 0.1, 1.0, 1.2, vp(8), vp(8), vp(8), None) == rc.RC_EINVAL
+    # pixels: spp must divide the ray count
+    assert L.rc_composite(vp(8), 10, 3, vp(8), vp(8), vp(8), None) == rc.RC_EINVAL
+    assert L.rc_composite(vp(8), 10, 0, vp(8), vp(8), vp(8), None) == rc.RC_EINVAL
+    assert L.rc_composite(None, 8, 2, vp(8), vp(8), vp(8), None) == rc.RC_EINVAL
+    assert rc.RC_MARCH_MAX_POINTS_PER_RAY == 1 << 20
