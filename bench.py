@@ -18,8 +18,9 @@ summary of the same kernel source, over the live kernel time), the FP64 CPU
 oracle's rate on a bounded sample of the same workload together with the
 per-output error of the timed launch's records on that sample, the two
 smaller record workloads (10k points over 10k triangles; 200k points with
-mixed sample counts over 100k triangles) and the learned-vs-plain placement
-comparison.
+mixed sample counts over 100k triangles), the render pass that consumes a
+cache (128 x 128 pixels x 16 samples marched with step 0.1, misses inserted)
+and the learned-vs-plain placement comparison.
 
 `--summarize-counters DIR` turns the CSV output of the rocprofv3 counter
 passes (and of `--copy-calibration` runs) into the counter summary that the
@@ -52,6 +53,7 @@ WORKLOAD_TEXT = {
     "c5": "1M points, room + 20 slabs + soup (1M triangles), 2048 directions (32x64), sigma_s=2.0 "
           "sigma_a=0.5, 4 point lights, ring step 0.1",
 }
+RENDER_PREPOP_BATCH = 512  # pre-population rounds (fastest of 256..4096 with shuffled rays)
 EXTRA_STEPS = {"c2": (20, 2), "c3": (5, 1), "c5": (2, 1)}
 COUNTERS = ROOT / "profiles" / "record_kernel_counters.json"
 
@@ -157,6 +159,33 @@ def learned_vs_plain(dev):
     res["learned"]["candidates_per_s"] = r["candidates"] / lp["seconds"]
     res["speedup"] = pl["seconds"] / lp["seconds"]
     return res
+
+
+def render_pass(dev, reps=3):
+    """The render pass that consumes the cache: 128 x 128 pixels x 16 samples
+    marched with step 0.1 through the closed-room scene of 10k triangles,
+    the cache pre-populated from one ray per pixel and completed at the
+    render's march points; one untimed pass, then the median of reps."""
+    from paper_1805_09258_amd import placement as PL
+    from paper_1805_09258_amd import render as RD
+    from paper_1805_09258_amd import workloads as W
+    w = W.make_c2(P=1)
+    ctx = PL.SceneContext(w)
+    cam, pre = W.render_camera(), W.render_camera(spp=1, seed=9, shuffle=True)
+    cfg = PL.CacheConfig()
+    RD.render(ctx, cam, pre, cfg, dev, prepop_batch=RENDER_PREPOP_BATCH)
+    runs = sorted((RD.render(ctx, cam, pre, cfg, dev, prepop_batch=RENDER_PREPOP_BATCH)[1] for _ in range(reps)),
+                  key=lambda r: r["seconds_prepop"] + r["seconds_render"])
+    ctx.close()
+    st = runs[reps // 2]
+    st["seconds_render_runs"] = [r["seconds_render"] for r in runs]
+    st["workload"] = (f"{cam.width} x {cam.height} pixels x {cam.spp} samples, march step 0.1, pre-population "
+                      f"from {pre.spp} ray per pixel in random order (rounds of {RENDER_PREPOP_BATCH}); closed unit "
+                      f"room + 10k triangles, 4 point lights; {cfg.n_theta * cfg.n_phi}-direction records, "
+                      f"eps {cfg.eps}; misses in rounds of {cfg.batch}")
+    st["seconds_per_frame"] = st["seconds_prepop"] + st["seconds_render"]
+    st["records_per_march_point"] = (st["prepop_records"] + st["render_records"]) / st["march_points"]
+    return st
 
 
 def measure(name, dev, steps, warmup, count=True):
@@ -407,6 +436,8 @@ def main():
                     help="comma-separated smaller workloads also measured (own step counts), or 'none'")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-vs-plain placement comparison")
+    ap.add_argument("--no-render", action="store_true", help="skip the render pass that consumes the cache")
+    ap.add_argument("--render-only", action="store_true", help="only the render pass (its own JSON line)")
     ap.add_argument("--no-count", action="store_true", help=argparse.SUPPRESS)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only copy a 1 GiB float32 buffer three times (scales the HBM byte counters)")
@@ -447,6 +478,9 @@ def main():
         print("bench.py: no GPU visible", file=sys.stderr)
         sys.exit(1)
     dev = torch.device("cuda:0")
+    if args.render_only:
+        print(json.dumps({"render_pass": render_pass(dev)}), flush=True)
+        return
 
     w, res, outputs = measure(args.workload, dev, args.steps, args.warmup, count=not args.no_count)
     out = {
@@ -487,6 +521,10 @@ def main():
         torch.cuda.empty_cache()
         r["roofline"] = roofline(e, r)
         out["workloads"][e] = r
+    if not args.no_render:
+        log("render pass ...")
+        out["render_pass"] = render_pass(dev)
+        log("render pass", out["render_pass"])
     if not args.no_learned:
         log("learned vs plain placement ...")
         out["learned_vs_plain"] = learned_vs_plain(dev)

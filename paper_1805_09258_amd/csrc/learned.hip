@@ -1037,9 +1037,12 @@ __global__ __launch_bounds__(256) void place_cover_grid_kernel(const float* __re
 // ---------------------------------------------------------------------------
 // Cache interpolation (Eq. radianceTaylor): first-order Taylor from every
 // cache point whose radius contains x', cubic kernel w = 3d^2 - 2d^3,
-// d = 1 - |x' - x_k| / R_k; FP64 accumulation.  Brute force over the cache.
-// Anisotropic points: membership d^T M d < 1 (FP32) and d = 1 - sqrt(d^T M d)
-// (FP64).
+// d = 1 - |x' - x_k| / R_k; FP64 accumulation.  Every query visits the cache
+// points in index order; a workgroup skips the balls that cannot reach the
+// bounding box of its 256 queries (conservative FP32 test, with the kept
+// points compacted in order, so each query sums the same points in the same
+// order as a visit of all of them).  Anisotropic points: membership
+// d^T M d < 1 (FP32) and d = 1 - sqrt(d^T M d) (FP64); no culling.
 // ---------------------------------------------------------------------------
 // cval [K][2] and cgrad [K][2][3] are records (the two channels are summed);
 // if ref [Q][2] is given, block b writes (sum (L - L_ref)^2, sum L_ref^2) over
@@ -1054,27 +1057,71 @@ __global__ __launch_bounds__(256) void interp_kernel(const float* __restrict__ c
   __shared__ float sp[256 * 4];
   __shared__ float sf[256 * 6];
   __shared__ double sv[256 * 4];
+  __shared__ float box[4][6];  // per wave: min x, y, z, max x, y, z of its queries
+  __shared__ int kept[4];
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int lane = threadIdx.x & (kWave - 1), wv = threadIdx.x / kWave;
   const float qx = i < Q ? q[3 * i] : 0.f, qy = i < Q ? q[3 * i + 1] : 0.f, qz = i < Q ? q[3 * i + 2] : 0.f;
+  {
+    const float inf = __builtin_huge_valf();
+    const float b0 = wmin(i < Q ? qx : inf), b1 = wmin(i < Q ? qy : inf), b2 = wmin(i < Q ? qz : inf);
+    const float b3 = wmax(i < Q ? qx : -inf), b4 = wmax(i < Q ? qy : -inf), b5 = wmax(i < Q ? qz : -inf);
+    if (lane == 0) {
+      box[wv][0] = b0, box[wv][1] = b1, box[wv][2] = b2;
+      box[wv][3] = b3, box[wv][4] = b4, box[wv][5] = b5;
+    }
+  }
+  __syncthreads();
+  float lo[3], hi[3];
+#pragma unroll
+  for (int a = 0; a < 3; a++) {
+    lo[a] = fminf(fminf(box[0][a], box[1][a]), fminf(box[2][a], box[3][a]));
+    hi[a] = fmaxf(fmaxf(box[0][3 + a], box[1][3 + a]), fmaxf(box[2][3 + a], box[3][3 + a]));
+  }
   double num = 0.0, den = 0.0;
   int nh = 0;
   for (int base = 0; base < K; base += 256) {
     const int k = base + threadIdx.x;
-    __syncthreads();
+    bool keep = false;
+    float c0 = 0.f, c1 = 0.f, c2 = 0.f, cr = 0.f;
     if (k < K) {
-      sp[4 * threadIdx.x] = cpos[3 * k];
-      sp[4 * threadIdx.x + 1] = cpos[3 * k + 1];
-      sp[4 * threadIdx.x + 2] = cpos[3 * k + 2];
-      sp[4 * threadIdx.x + 3] = cR[k];
+      c0 = cpos[3 * k], c1 = cpos[3 * k + 1], c2 = cpos[3 * k + 2], cr = cform ? 0.f : cR[k];
+      if (cform) {
+        keep = true;
+      } else {
+        // distance from the ball's centre to the queries' box; a query inside
+        // the ball by the FP32 test is no further than R (1 + 1e-6) from it,
+        // so a margin of 1e-4 R keeps every ball that can hold one
+        const float ex = fmaxf(fmaxf(lo[0] - c0, c0 - hi[0]), 0.f);
+        const float ey = fmaxf(fmaxf(lo[1] - c1, c1 - hi[1]), 0.f);
+        const float ez = fmaxf(fmaxf(lo[2] - c2, c2 - hi[2]), 0.f);
+        const float rm = cr * 1.0001f + 1e-30f;
+        keep = !((ex * ex + ey * ey) + ez * ez > rm * rm);
+      }
+    }
+    const unsigned long long mask = __ballot(keep);
+    __syncthreads();  // the previous tile's LDS rows are read
+    if (lane == 0) kept[wv] = __popcll(mask);
+    __syncthreads();
+    int at = __popcll(mask & ((1ull << lane) - 1ull)), m = 0;
+#pragma unroll
+    for (int w = 0; w < 4; w++) {
+      at += w < wv ? kept[w] : 0;
+      m += kept[w];
+    }
+    if (keep) {
+      sp[4 * at] = c0;
+      sp[4 * at + 1] = c1;
+      sp[4 * at + 2] = c2;
+      sp[4 * at + 3] = cr;
       if (cform)
-        for (int e = 0; e < 6; e++) sf[6 * threadIdx.x + e] = cform[6 * k + e];
-      sv[4 * threadIdx.x] = cval[2 * k] + cval[2 * k + 1];
-      sv[4 * threadIdx.x + 1] = cgrad[6 * k] + cgrad[6 * k + 3];
-      sv[4 * threadIdx.x + 2] = cgrad[6 * k + 1] + cgrad[6 * k + 4];
-      sv[4 * threadIdx.x + 3] = cgrad[6 * k + 2] + cgrad[6 * k + 5];
+        for (int e = 0; e < 6; e++) sf[6 * at + e] = cform[6 * k + e];
+      sv[4 * at] = cval[2 * k] + cval[2 * k + 1];
+      sv[4 * at + 1] = cgrad[6 * k] + cgrad[6 * k + 3];
+      sv[4 * at + 2] = cgrad[6 * k + 1] + cgrad[6 * k + 4];
+      sv[4 * at + 3] = cgrad[6 * k + 2] + cgrad[6 * k + 5];
     }
     __syncthreads();
-    const int m = (K - base) < 256 ? (K - base) : 256;
     for (int j = 0; j < m; j++) {
       const float dx = qx - sp[4 * j], dy = qy - sp[4 * j + 1], dz = qz - sp[4 * j + 2], R = sp[4 * j + 3];
       bool in;

@@ -1,9 +1,10 @@
 """The render pass that consumes the radiance cache (Sec. 6 "Implementation";
 Results in 3D: 16 samples per pixel, uniform ray marching with step 0.1).
 
-1. Pre-population: one camera ray per pixel is marched through the medium
-   and its march points are the candidates of a plain greedy placement (the
-   error-metric insertion rule of Sec. 5 and 6).
+1. Pre-population: camera rays (one per pixel, visited in a random order:
+   a uniform sampling of the camera's rays) are marched through the medium
+   and their march points are the candidates of a plain greedy placement
+   (the error-metric insertion rule of Sec. 5 and 6).
 2. Render: every sample ray is marched; at each march point, in camera
    order, the cache either holds a valid point (the radius test of
    Eq. radiusAniso3D) or a record is computed there and inserted.  This is
@@ -68,23 +69,37 @@ def march(ctx: SceneContext, cam: W.CameraRays, step: float, device) -> Marched:
 
 
 def render(ctx: SceneContext, cam: W.CameraRays, prepop: W.CameraRays, cfg: CacheConfig, device, step=0.1,
-           batch=None):
-    """Pre-populate a cache from prepop's rays, render cam's rays through it
-    (inserting records where the cache has no valid point), and composite.
-    Returns (pixels [n_pixels] device float64, stats)."""
+           batch=None, prepop_batch=None):
+    """Pre-populate a cache from prepop's rays (in their order; rounds of
+    prepop_batch candidates), render cam's rays through it (inserting records
+    where the cache has no valid point; rounds of batch), and composite.
+    Batch sizes default to cfg.batch.  Returns (pixels [n_pixels] device
+    float64, stats, device buffers)."""
     import torch
+    ev = []
+
+    def mark(name):
+        e = torch.cuda.Event(enable_timing=True)
+        e.record()
+        ev.append((name, e))
+
     torch.cuda.synchronize()
     t0 = time.perf_counter()
+    mark("start")
     m0 = march(ctx, prepop, step, device)
+    mark("march_prepop")
     pre = Placer(ctx, MarchCandidates(m0.points), cfg, device)
-    res0 = pre.plain(batch)
+    res0 = pre.plain(prepop_batch if prepop_batch is not None else batch)
     K0 = res0.K
+    mark("place_prepop")
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     # render: the candidates are the cache's K0 points followed by the render
     # march points; the cache entries are in place (accepted, covered) and
     # cover the render points before the rounds continue from candidate K0
+    mark("render_start")
     m1 = march(ctx, cam, step, device)
+    mark("march_render")
     cand = torch.cat([res0.pos, m1.points])
     pl = Placer(ctx, MarchCandidates(cand), cfg, device)
     pl.covered[:K0] = 1
@@ -98,14 +113,17 @@ def render(ctx: SceneContext, cam: W.CameraRays, prepop: W.CameraRays, cfg: Cach
     if K0:
         rc.rc_place_cover(pl.cand, pl.covered, None, pl.acc, pl.accR, 0, K0)
     rounds, records = pl._plain_rounds(batch)
+    mark("insert_misses")
     res = pl._result({})
     # radiance at every march point from the final cache, and the pixels
     M = m1.n_points
     L = torch.zeros(M, dtype=torch.float64, device=device)
     hits = torch.zeros(M, dtype=torch.int32, device=device)
     rc.rc_interp(res.pos, res.value, res.grad, res.R, m1.points, L, hits)
+    mark("interpolate")
     pix = torch.empty(cam.n_pixels, dtype=torch.float64, device=device)
     rc.rc_composite(m1.offsets, cam.spp, m1.weight, L, pix)
+    mark("composite")
     torch.cuda.synchronize()
     t2 = time.perf_counter()
     uncovered = int((hits == 0).sum().item())
@@ -116,4 +134,6 @@ def render(ctx: SceneContext, cam: W.CameraRays, prepop: W.CameraRays, cfg: Cach
              "seconds_prepop": t1 - t0, "seconds_render": t2 - t1,
              "pixel_mean": float(pix.mean().item()) if cam.n_pixels else 0.0}
     stats["march_points_per_s"] = M / stats["seconds_render"] if stats["seconds_render"] > 0 else 0.0
+    # milliseconds of device time between consecutive marks (host waits included)
+    stats["ms"] = {n: ev[i - 1][1].elapsed_time(e) for i, (n, e) in enumerate(ev) if i > 0 and n != "render_start"}
     return pix, stats, (m1, res, L, hits, cand, pl)

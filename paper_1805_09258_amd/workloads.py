@@ -331,7 +331,7 @@ class CameraRays:
     from the seed.  The eye must lie inside the medium box."""
 
     def __init__(self, width: int, height: int, spp: int, eye, look_at, fov_deg: float, seed: int,
-                 up=(0.0, 1.0, 0.0)):
+                 up=(0.0, 1.0, 0.0), shuffle=False):
         rng = np.random.default_rng(seed)
         self.width, self.height, self.spp = int(width), int(height), int(spp)
         eye = np.asarray(eye, np.float64)
@@ -353,6 +353,9 @@ class CameraRays:
         self.dirs = d.astype(np.float32)
         self.orig = np.tile(eye.astype(np.float32)[None, :], (n, 1))
         self.xi = rng.uniform(0.0, 1.0, n).astype(np.float32)
+        if shuffle:  # rays in a seeded random order (a uniform sampling of the camera's rays, not pixel order)
+            perm = rng.permutation(n)
+            self.dirs, self.orig, self.xi = self.dirs[perm], self.orig[perm], self.xi[perm]
 
     @property
     def n(self) -> int:
@@ -363,8 +366,9 @@ class CameraRays:
         return self.width * self.height
 
 
-def render_camera(width=128, height=128, spp=16, seed=8):
+def render_camera(width=128, height=128, spp=16, seed=8, shuffle=False):
     """The render-pass camera in the closed-room scenes: eye near the z = 0
     wall, looking at the far wall through the medium (60 degree field of
-    view)."""
-    return CameraRays(width, height, spp, eye=(0.5, 0.5, 0.04), look_at=(0.5, 0.5, 1.0), fov_deg=60.0, seed=seed)
+    view); shuffle: rays in a seeded random order."""
+    return CameraRays(width, height, spp, eye=(0.5, 0.5, 0.04), look_at=(0.5, 0.5, 1.0), fov_deg=60.0, seed=seed,
+                      shuffle=shuffle)

@@ -168,14 +168,15 @@ def test_render_pass_follows_the_sequential_insertion_rule(dev):
 
 
 def test_render_pass_at_full_size_sampled(dev):
-    """The 128 x 128 x 16 render of the closed-room scene: march points of a
-    seeded 1 % sample of the rays equal the oracle's bit for bit (the oracle
-    traces each sampled ray itself), and every march point ends covered."""
+    """The 128 x 128 x 16 render of the closed-room scene as the benchmark
+    runs it: march points of a seeded 1 % sample of the rays equal the
+    oracle's bit for bit (the oracle traces each sampled ray itself), and
+    every march point ends covered."""
     w = W.make_c2(P=1)
     ctx = SceneContext(w)
     cam = W.render_camera()
-    pre = W.render_camera(spp=1, seed=9)
-    pix, st, (m1, res, L, hits, cand, pl) = RD.render(ctx, cam, pre, CacheConfig(), dev)
+    pre = W.render_camera(spp=1, seed=9, shuffle=True)
+    pix, st, (m1, res, L, hits, cand, pl) = RD.render(ctx, cam, pre, CacheConfig(), dev, prepop_batch=512)
     _say("full-size render", st)
     assert st["uncovered_after"] == 0 and (hits > 0).all()
     rng = np.random.default_rng(77)
@@ -191,3 +192,38 @@ def test_render_pass_at_full_size_sampled(dev):
     assert np.array_equal(pts[sel].view(np.int32), op.view(np.int32))
     np.testing.assert_allclose(wt[sel], ow, rtol=1e-15, atol=0)
     ctx.close()
+
+
+def test_interpolation_of_march_points_matches_oracle(dev):
+    """Queries that are march points (consecutive queries close together, so
+    a workgroup skips most cache balls) and queries just inside and just
+    outside ball boundaries: the same members, counts and radiance as the
+    oracle's visit of every cache point."""
+    rng = np.random.default_rng(91)
+    w = W.make_c2(seed=23, P=1, n_soup=2000)
+    o, d, xi = _rays(rng, 512)
+    sc = rc.Scene.from_workload(w)
+    offs, pts, wt, t = _march_gpu(sc, o, d, xi, 0.1, w.sigma_s, w.sigma_s + w.sigma_a, dev)
+    sc.close()
+    K = 700
+    cp = rng.uniform(0, 1, (K, 3)).astype(np.float32)
+    cR = np.exp(rng.uniform(np.log(0.01), np.log(0.15), K)).astype(np.float32)
+    cv = rng.uniform(0, 2, (K, 2))
+    cg = rng.normal(size=(K, 2, 3))
+    u = rng.normal(size=(600, 3))
+    u /= np.linalg.norm(u, axis=1, keepdims=True)
+    j = rng.integers(0, K, 600)
+    s = np.where(np.arange(600) % 2 == 0, 1 - 3e-7, 1 + 3e-7)
+    edge = (cp[j].astype(np.float64) + (s * cR[j])[:, None] * u).astype(np.float32)
+    q = np.ascontiguousarray(np.concatenate([pts, edge]))
+    Q = q.shape[0]
+    T = lambda a: torch.as_tensor(a, device=dev)  # noqa: E731
+    out = torch.full((Q,), float("nan"), dtype=torch.float64, device=dev)
+    hits = torch.zeros(Q, dtype=torch.int32, device=dev)
+    rc.rc_interp(T(cp), T(cv), T(cg), T(cR), T(q), out, hits)
+    torch.cuda.synchronize()
+    L, cov = O.interpolate(cp, cv.sum(1), cg.sum(1), cR, q)
+    members = np.array([O._within32(q[i][None], cp, cR).sum() for i in range(Q)])
+    _say(f"interp: {Q} queries ({pts.shape[0]} march points), {cov.sum()} covered, mean members {members.mean():.1f}")
+    np.testing.assert_array_equal(hits.cpu().numpy(), np.where(cov, members, 0))
+    np.testing.assert_allclose(out.cpu().numpy(), L, rtol=1e-6, atol=1e-6)
