@@ -775,6 +775,12 @@ RC_DEV int wave_verdict(const float4* ps, const float* __restrict__ form, int j,
   return __ballot(und) ? 0 : 1;
 }
 
+// Gather: the next `batch` undecided candidates in visiting order from the
+// cursor state[0]; each chunk gives every thread kGatherPer consecutive
+// candidates, ranks the undecided ones by a workgroup prefix sum, and cuts
+// the chunk after the last one that fits.
+constexpr int kGatherPer = 4;
+
 __global__ __launch_bounds__(kPlaceThreads) void place_gather_kernel(const float* __restrict__ cand,
                                                                      const float* __restrict__ radius,
                                                                      const int* __restrict__ order, int C,
@@ -786,20 +792,32 @@ __global__ __launch_bounds__(kPlaceThreads) void place_gather_kernel(const float
   __shared__ int wtot[kPlaceThreads / kWave];
   __shared__ int s_stop;
   const int t = threadIdx.x, lane = t & (kWave - 1), wv = t / kWave;
+  constexpr int kChunk = kPlaceThreads * kGatherPer;
   for (int j = t; j < kPlaceMaxBatch; j += kPlaceThreads) state[kPlaceStatus + j] = 0;  // all undecided
   int cursor = state[0];
   int have = 0;
   while (cursor < C && have < batch) {
-    const int k = cursor + t;
-    int i = -1;
-    bool u = false;
-    if (k < C) {
-      i = order ? order[k] : k;
-      u = !covered[i];
+    int idx[kGatherPer];
+    bool u[kGatherPer];
+    int cnt = 0;
+#pragma unroll
+    for (int e = 0; e < kGatherPer; e++) {
+      const long long k = (long long)cursor + t * kGatherPer + e;
+      idx[e] = -1;
+      u[e] = false;
+      if (k < C) {
+        idx[e] = order ? order[k] : (int)k;
+        u[e] = !covered[idx[e]];
+      }
+      cnt += u[e] ? 1 : 0;
     }
-    const unsigned long long mask = __ballot(u);
-    const int below = __popcll(mask & ((1ull << lane) - 1ull));
-    if (lane == 0) wtot[wv] = __popcll(mask);
+    int incl = cnt;  // inclusive prefix of the counts within the wave
+#pragma unroll
+    for (int sh = 1; sh < kWave; sh <<= 1) {
+      const int v = __shfl_up(incl, sh, kWave);
+      if (lane >= sh) incl += v;
+    }
+    if (lane == kWave - 1) wtot[wv] = incl;
     __syncthreads();
     int off = 0, total = 0;
 #pragma unroll
@@ -808,24 +826,38 @@ __global__ __launch_bounds__(kPlaceThreads) void place_gather_kernel(const float
       total += v;
       off += (w < wv) ? v : 0;
     }
-    const int rank = off + below;  // rank among the undecided of this chunk
+    const int rank0 = off + incl - cnt;  // rank of this thread's first undecided candidate in the chunk
     const int room = batch - have;
-    int consumed = kPlaceThreads;
-    if (total > room) {
-      if (u && rank == room - 1) s_stop = t;  // the last candidate that fits
+    int consumed = kChunk;
+    if (total > room) {  // uniform across the workgroup
+      if (rank0 <= room - 1 && room - 1 < rank0 + cnt) {
+        int r = rank0;
+#pragma unroll
+        for (int e = 0; e < kGatherPer; e++)
+          if (u[e]) {
+            if (r == room - 1) s_stop = t * kGatherPer + e;  // the last candidate that fits
+            r++;
+          }
+      }
       __syncthreads();
       consumed = s_stop + 1;
     }
-    if (u && rank < room) {
-      const int q = have + rank;
-      batch_idx[q] = i;
-      batch_pos[3 * q] = cand[3 * i];
-      batch_pos[3 * q + 1] = cand[3 * i + 1];
-      batch_pos[3 * q + 2] = cand[3 * i + 2];
-      if (radius) batch_R[q] = radius[i];
-    }
+    int r = rank0;
+#pragma unroll
+    for (int e = 0; e < kGatherPer; e++)
+      if (u[e]) {
+        if (r < room) {
+          const int q = have + r, i = idx[e];
+          batch_idx[q] = i;
+          batch_pos[3 * q] = cand[3 * i];
+          batch_pos[3 * q + 1] = cand[3 * i + 1];
+          batch_pos[3 * q + 2] = cand[3 * i + 2];
+          if (radius) batch_R[q] = radius[i];
+        }
+        r++;
+      }
     have += total < room ? total : room;
-    cursor = (cursor + consumed < C) ? cursor + consumed : C;
+    cursor = ((long long)cursor + consumed < C) ? cursor + consumed : C;
     __syncthreads();  // wtot and s_stop are rewritten by the next chunk
   }
   if (t == 0) {
@@ -955,21 +987,85 @@ __global__ __launch_bounds__(kPlaceThreads) void place_accept_kernel(
   }
 }
 
-__global__ void place_cover_kernel(const float* __restrict__ cand, int C, unsigned char* __restrict__ covered,
-                                   const int* __restrict__ state, const int* __restrict__ accepted,
-                                   const float* __restrict__ accepted_R, const float* __restrict__ accepted_form,
-                                   int first, int count) {
+// Cover by the accepted points b .. b + nn - 1 (a round's, or an explicit
+// range): one candidate per thread; the points are staged through LDS 256 at
+// a time, keeping only those whose bounding ball (the radius, or an
+// ellipsoid's largest radius) reaches the box of the workgroup's candidates
+// that are still uncovered.  Covering is an OR over the points, so the
+// order of the tests does not change the result.
+__global__ __launch_bounds__(256) void place_cover_kernel(const float* __restrict__ cand, int C,
+                                                          unsigned char* __restrict__ covered,
+                                                          const int* __restrict__ state,
+                                                          const int* __restrict__ accepted,
+                                                          const float* __restrict__ accepted_R,
+                                                          const float* __restrict__ accepted_form, int first,
+                                                          int count) {
+  __shared__ float4 sp[256];
+  __shared__ float sf[256 * 6];
+  __shared__ float box[4][6];
+  __shared__ int kept[4];
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= C || covered[i]) return;
+  const int lane = threadIdx.x & (kWave - 1), wv = threadIdx.x / kWave;
   const int b = first >= 0 ? first : state[2];
   const int nn = first >= 0 ? count : state[3];
-  const float cx = cand[3 * i], cy = cand[3 * i + 1], cz = cand[3 * i + 2];
-  for (int a = 0; a < nn; a++) {
-    const int p = accepted[b + a];
-    if (inside(cx, cy, cz, cand[3 * p], cand[3 * p + 1], cand[3 * p + 2], accepted_R[b + a],
-               accepted_form ? accepted_form + 6 * (b + a) : nullptr)) {
-      covered[i] = 1;
-      return;
+  bool need = i < C && !covered[i];
+  const float cx = need ? cand[3 * i] : 0.f, cy = need ? cand[3 * i + 1] : 0.f, cz = need ? cand[3 * i + 2] : 0.f;
+  {
+    const float inf = __builtin_huge_valf();
+    const float b0 = wmin(need ? cx : inf), b1 = wmin(need ? cy : inf), b2 = wmin(need ? cz : inf);
+    const float b3 = wmax(need ? cx : -inf), b4 = wmax(need ? cy : -inf), b5 = wmax(need ? cz : -inf);
+    if (lane == 0) {
+      box[wv][0] = b0, box[wv][1] = b1, box[wv][2] = b2;
+      box[wv][3] = b3, box[wv][4] = b4, box[wv][5] = b5;
+    }
+  }
+  __syncthreads();
+  float lo[3], hi[3];
+#pragma unroll
+  for (int a = 0; a < 3; a++) {
+    lo[a] = fminf(fminf(box[0][a], box[1][a]), fminf(box[2][a], box[3][a]));
+    hi[a] = fmaxf(fmaxf(box[0][3 + a], box[1][3 + a]), fmaxf(box[2][3 + a], box[3][3 + a]));
+  }
+  for (int base = 0; base < nn; base += 256) {
+    if (!__syncthreads_or(need)) break;  // every candidate of the workgroup is covered
+    const int a = base + threadIdx.x;
+    bool keep = false;
+    float4 pr = make_float4(0.f, 0.f, 0.f, 0.f);
+    if (a < nn) {
+      const int p = accepted[b + a];
+      pr = make_float4(cand[3 * p], cand[3 * p + 1], cand[3 * p + 2], accepted_R[b + a]);
+      // a point inside by the FP32 test is within R (1 + 1e-6) of the centre
+      // (balls, and ellipsoids of largest radius R); cull only finite R > 0
+      const float ex = fmaxf(fmaxf(lo[0] - pr.x, pr.x - hi[0]), 0.f);
+      const float ey = fmaxf(fmaxf(lo[1] - pr.y, pr.y - hi[1]), 0.f);
+      const float ez = fmaxf(fmaxf(lo[2] - pr.z, pr.z - hi[2]), 0.f);
+      const float rm = pr.w * 1.0001f;
+      keep = !(pr.w > 0.f && pr.w < 3.0e38f) || !((ex * ex + ey * ey) + ez * ez > rm * rm);
+    }
+    const unsigned long long mask = __ballot(keep);
+    if (lane == 0) kept[wv] = __popcll(mask);
+    __syncthreads();
+    int at = __popcll(mask & ((1ull << lane) - 1ull)), m = 0;
+#pragma unroll
+    for (int w = 0; w < 4; w++) {
+      at += w < wv ? kept[w] : 0;
+      m += kept[w];
+    }
+    if (keep) {
+      sp[at] = pr;
+      if (accepted_form)
+        for (int e = 0; e < 6; e++) sf[6 * at + e] = accepted_form[6 * (b + a) + e];
+    }
+    __syncthreads();
+    if (need) {
+      for (int j = 0; j < m; j++) {
+        const float4 q = sp[j];
+        if (inside(cx, cy, cz, q.x, q.y, q.z, q.w, accepted_form ? sf + 6 * j : nullptr)) {
+          covered[i] = 1;
+          need = false;
+          break;
+        }
+      }
     }
   }
 }
