@@ -59,15 +59,14 @@ __global__ __launch_bounds__(64) void march_count_kernel(const float4* __restric
 
 // In-place inclusive scan of offsets[1..n] by one workgroup: tiles of
 // kScanThreads * kScanPerThread counts, each thread summing kScanPerThread
-// consecutive ones, a workgroup scan of the thread sums in LDS, and a carry
-// from tile to tile.
+// consecutive ones, a wave prefix sum of the thread sums by lane shuffles,
+// the wave totals combined through LDS, and a carry from tile to tile.
 __global__ __launch_bounds__(kScanThreads) void scan_counts_kernel(long long* __restrict__ offsets, int n) {
-  __shared__ long long part[kScanThreads];
-  __shared__ long long carry_s;
-  const int t = threadIdx.x;
-  if (t == 0) carry_s = 0;
-  __syncthreads();
+  constexpr int kWaves = kScanThreads / kWave;
+  __shared__ long long wtot[kWaves];
+  const int t = threadIdx.x, lane = t & (kWave - 1), wv = t / kWave;
   long long* c = offsets + 1;
+  long long carry = 0;  // the same in every thread
   constexpr int kTile = kScanThreads * kScanPerThread;
   for (long long base = 0; base < n; base += kTile) {
     long long v[kScanPerThread];
@@ -78,24 +77,30 @@ __global__ __launch_bounds__(kScanThreads) void scan_counts_kernel(long long* __
       v[e] = j < n ? c[j] : 0;
       sum += v[e];
     }
-    part[t] = sum;
-    __syncthreads();
-    for (int s = 1; s < kScanThreads; s <<= 1) {  // Hillis-Steele inclusive scan of the thread sums
-      const long long add = t >= s ? part[t - s] : 0;
-      __syncthreads();
-      part[t] += add;
-      __syncthreads();
+    long long incl = sum;
+#pragma unroll
+    for (int sh = 1; sh < kWave; sh <<= 1) {
+      const long long u = __shfl_up(incl, sh, kWave);
+      if (lane >= sh) incl += u;
     }
-    long long run = carry_s + (t > 0 ? part[t - 1] : 0);
+    if (lane == kWave - 1) wtot[wv] = incl;
+    __syncthreads();
+    long long off = 0, total = 0;
+#pragma unroll
+    for (int w = 0; w < kWaves; w++) {
+      const long long x = wtot[w];
+      total += x;
+      off += w < wv ? x : 0;
+    }
+    long long run = carry + off + incl - sum;
 #pragma unroll
     for (int e = 0; e < kScanPerThread; e++) {
       const long long j = base + (long long)t * kScanPerThread + e;
       run += v[e];
       if (j < n) c[j] = run;
     }
-    __syncthreads();
-    if (t == kScanThreads - 1) carry_s += part[t];
-    __syncthreads();
+    carry += total;
+    __syncthreads();  // wtot is rewritten by the next tile
   }
 }
 
@@ -122,18 +127,43 @@ __global__ __launch_bounds__(256) void march_emit_kernel(const float* __restrict
   }
 }
 
-// One thread per pixel: the mean over its spp rays of sum(weight * L), FP64,
-// points taken in ray order.
+// Pixels: one thread per ray sums weight * L over the ray's points (in
+// order) into LDS; then one thread per pixel adds its spp ray sums in ray
+// order and divides by spp.  A workgroup holds 256 / spp whole pixels.
 __global__ __launch_bounds__(256) void composite_kernel(const long long* __restrict__ offsets, int n_pixels, int spp,
                                                         const double* __restrict__ weight,
                                                         const double* __restrict__ L, double* __restrict__ pixel) {
+  __shared__ double ray[256];
+  const int per = 256 / spp;  // pixels per workgroup (spp <= 256)
+  const int p0 = blockIdx.x * per;
+  const int t = threadIdx.x;
+  const long long r = (long long)p0 * spp + t;
+  if (t < per * spp && r < (long long)n_pixels * spp) {
+    double acc = 0.0;
+    for (long long j = offsets[r]; j < offsets[r + 1]; j++) acc += weight[j] * L[j];
+    ray[t] = acc;
+  }
+  __syncthreads();
+  const int p = p0 + t;
+  if (t < per && p < n_pixels) {
+    double acc = 0.0;
+    for (int k = 0; k < spp; k++) acc += ray[t * spp + k];
+    pixel[p] = acc / spp;
+  }
+}
+
+// More than 256 samples per pixel: one thread per pixel, rays in order.
+__global__ __launch_bounds__(256) void composite_wide_kernel(const long long* __restrict__ offsets, int n_pixels,
+                                                             int spp, const double* __restrict__ weight,
+                                                             const double* __restrict__ L,
+                                                             double* __restrict__ pixel) {
   const int p = blockIdx.x * blockDim.x + threadIdx.x;
   if (p >= n_pixels) return;
   double acc = 0.0;
-  for (int r = p * spp; r < (p + 1) * spp; r++) {
-    double ray = 0.0;
-    for (long long j = offsets[r]; j < offsets[r + 1]; j++) ray += weight[j] * L[j];
-    acc += ray;
+  for (long long r = (long long)p * spp; r < (long long)(p + 1) * spp; r++) {
+    double rs = 0.0;
+    for (long long j = offsets[r]; j < offsets[r + 1]; j++) rs += weight[j] * L[j];
+    acc += rs;
   }
   pixel[p] = acc / spp;
 }
@@ -172,9 +202,15 @@ hipError_t launch_march_emit(const float* o, const float* d, const float* xi, in
 
 hipError_t launch_composite(const long long* offsets, int n_pixels, int spp, const double* weight, const double* L,
                             double* pixel, hipStream_t s) {
-  const int blocks = (n_pixels + 255) / 256;
-  if (blocks == 0) return hipSuccess;
-  hipLaunchKernelGGL(composite_kernel, dim3(blocks), dim3(256), 0, s, offsets, n_pixels, spp, weight, L, pixel);
+  if (n_pixels <= 0) return hipSuccess;
+  if (spp <= 256) {
+    const int per = 256 / spp;
+    const int blocks = (n_pixels + per - 1) / per;
+    hipLaunchKernelGGL(composite_kernel, dim3(blocks), dim3(256), 0, s, offsets, n_pixels, spp, weight, L, pixel);
+  } else {
+    hipLaunchKernelGGL(composite_wide_kernel, dim3((n_pixels + 255) / 256), dim3(256), 0, s, offsets, n_pixels, spp,
+                       weight, L, pixel);
+  }
   return hipGetLastError();
 }
 

@@ -9,7 +9,7 @@ namespace rc {
 int stack_variant(int depth);
 
 constexpr int kScanThreads = 1024;  // one workgroup scans the per-ray counts
-constexpr int kScanPerThread = 8;   // consecutive counts per thread and tile
+constexpr int kScanPerThread = 16;  // consecutive counts per thread and tile
 
 hipError_t launch_march_count(const float4* nodes, const float4* tris, int tri_stride, int depth, const float* o,
                               const float* d, const float* xi, int n, double step, float3 lo, float3 hi,

@@ -98,7 +98,7 @@ def test_march_of_no_rays_and_composite_of_empty_rays(dev):
     sc.close()
 
 
-@pytest.mark.parametrize("spp", [1, 4, 16])
+@pytest.mark.parametrize("spp", [1, 3, 4, 16, 300])
 def test_composite_equals_oracle(dev, spp):
     rng = np.random.default_rng(40 + spp)
     w = W.make_c2(seed=22, P=1, n_soup=2000)
