@@ -64,10 +64,11 @@ def log(*a):
 
 def kernel_source_hash():
     """sha256 prefix of the sources that make the record kernel and its launches
-    (every file of paper_1805_09258_amd/csrc but the learned-placement ones)."""
+    (every file of paper_1805_09258_amd/csrc but the learned-placement and
+    render-pass ones, which build other kernels)."""
     h = hashlib.sha256()
     for p in sorted((ROOT / "paper_1805_09258_amd" / "csrc").glob("*")):
-        if p.suffix in (".hip", ".hpp", ".cpp") and not p.stem.startswith("learned"):
+        if p.suffix in (".hip", ".hpp", ".cpp") and not p.stem.startswith(("learned", "render")):
             h.update(p.read_bytes())
     return h.hexdigest()[:16]
 
