@@ -537,8 +537,10 @@ int rc_march_emit(const float* orig, const float* dir, const float* xi, int64_t 
 /* Pixel estimates: pixel p (device double[n_rays / spp]) is the mean over
  * rays p * spp .. p * spp + spp - 1 of the sum of weight * L over the ray's
  * points (L device double[offsets[n_rays]]: in-scattered radiance at each
- * point, e.g. from rc_interp), FP64, points taken in ray order.  RC_EINVAL
- * unless spp >= 1 divides n_rays. */
+ * point, e.g. from rc_interp), FP64, points taken in ray order.  weight and L
+ * hold offsets[n_rays] entries each (they may be NULL only when that total is
+ * 0: the host does not read device offsets).  RC_EINVAL unless spp >= 1
+ * divides n_rays. */
 int rc_composite(const int64_t* offsets, int64_t n_rays, int32_t spp, const double* weight, const double* L,
                  double* pixel, void* stream);
 

@@ -89,6 +89,10 @@ def test_march_of_no_rays_and_composite_of_empty_rays(dev):
     z3 = np.zeros((0, 3), np.float32)
     offs, pts, wt, t = _march_gpu(sc, z3, z3, np.zeros(0, np.float32), 0.1, 1.0, 1.2, dev)
     assert offs.tolist() == [0] and pts.shape == (0, 3)
+    # a step too small for the box is refused before any launch
+    with pytest.raises(rc.RCError):
+        _march_gpu(sc, np.full((4, 3), 0.5, np.float32), np.tile(np.float32([[0, 0, 1]]), (4, 1)),
+                   np.zeros(4, np.float32), 1e-7, 1.0, 1.2, dev)
     # rays with no points (offsets equal) give zero pixels
     o = torch.zeros(9, dtype=torch.int64, device=dev)
     pix = torch.full((4,), float("nan"), dtype=torch.float64, device=dev)
