@@ -60,16 +60,19 @@ class SceneContext:
     def close(self):
         self.scene.close()
 
-    def records(self, pos, value, grad, hess, ws, nth, nph, max_n_phi, rec_base, seed=None, common_random=False):
+    def records(self, pos, value, grad, hess, ws, nth, nph, max_n_phi, rec_base, seed=None, common_random=False,
+                max_n_theta=0):
         """Full records at pos (device float[P][3]) into value/grad/hess; record
         i draws with id rec_base + i, or every record with id rec_base
-        (common_random).  Returns P."""
+        (common_random).  max_n_theta > 0 (a bound on nth) lets the launch trace
+        the primary rays in the coherent hits pass first (same values; about
+        20 % faster from 500 records up).  Returns P."""
         w = self.w
         P = pos.shape[0]
         if P == 0:
             return 0
         prm = rc.make_params(w.ring_step, w.max_rings, max(int(max_n_phi), 5), w.seed if seed is None else seed,
-                             rec_base=rec_base, common_random=common_random)
+                             rec_base=rec_base, common_random=common_random, max_n_theta=max_n_theta)
         rc.rc_records_batched(self.scene.handle, w.sigma_s, w.sigma_a, w.lights, pos, nth[:P], nph[:P], prm, None,
                               False, -1, value[:P], grad[:P], hess[:P], ws)
         return P
@@ -154,9 +157,10 @@ class Placer:
     def _records(self, pos, value, grad, hess, ws, nth, nph):
         cfg = self.cfg
         if cfg.common_random:
-            self.ctx.records(pos, value, grad, hess, ws, nth, nph, cfg.n_phi, cfg.record_id, common_random=True)
+            self.ctx.records(pos, value, grad, hess, ws, nth, nph, cfg.n_phi, cfg.record_id, common_random=True,
+                             max_n_theta=cfg.n_theta)
             return
-        n = self.ctx.records(pos, value, grad, hess, ws, nth, nph, cfg.n_phi, self._next_id)
+        n = self.ctx.records(pos, value, grad, hess, ws, nth, nph, cfg.n_phi, self._next_id, max_n_theta=cfg.n_theta)
         self._next_id += n
 
     def _gather(self, batch=None):
@@ -319,7 +323,7 @@ def direct_records(ctx: SceneContext, pts, n_theta, n_phi, rec_base, device, see
     for s in range(0, Q, chunk):
         e = min(Q, s + chunk)
         ctx.records(pts[s:e], value[s:e], grad[s:e], hess[s:e], ws, nth, nph, n_phi,
-                    rec_base if common_random else rec_base + s, seed, common_random)
+                    rec_base if common_random else rec_base + s, seed, common_random, max_n_theta=n_theta)
     return value, grad, hess
 
 
