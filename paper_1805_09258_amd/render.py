@@ -23,7 +23,7 @@ from dataclasses import dataclass
 
 from . import rc
 from . import workloads as W
-from .placement import CacheConfig, Placer, SceneContext
+from .placement import CacheConfig, PlacementResult, Placer, SceneContext
 
 
 @dataclass
@@ -68,6 +68,27 @@ def march(ctx: SceneContext, cam: W.CameraRays, step: float, device) -> Marched:
     return Marched(offs, pts, wt, t_end)
 
 
+def _empty_cache(device):
+    import torch
+    z = lambda *shape, dt=torch.float32: torch.zeros(shape, dtype=dt, device=device)  # noqa: E731
+    return PlacementResult(z(0, 3), z(0, 2, dt=torch.float64), z(0, 2, 3, dt=torch.float64), z(0), 0,
+                           {"records": 0, "rounds": 0})
+
+
+def _empty_render(cam, prepop, m0, m1, res0, device, t0, t1, ev):
+    """The render of rays with no march points and no cache: zero pixels."""
+    import torch
+    pix = torch.zeros(cam.n_pixels, dtype=torch.float64, device=device)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    stats = {"rays": cam.n, "march_points": 0, "prepop_rays": prepop.n, "prepop_points": m0.n_points,
+             "prepop_records": 0, "prepop_cache": 0, "prepop_rounds": 0, "render_records": 0, "render_rounds": 0,
+             "cache_points": 0, "inserted": 0, "uncovered_after": 0, "seconds_prepop": t1 - t0,
+             "seconds_render": t2 - t1, "pixel_mean": 0.0, "march_points_per_s": 0.0, "ms": {}}
+    z = torch.zeros(0, dtype=torch.float64, device=device)
+    return pix, stats, (m1, res0, z, torch.zeros(0, dtype=torch.int32, device=device), None, None)
+
+
 def render(ctx: SceneContext, cam: W.CameraRays, prepop: W.CameraRays, cfg: CacheConfig, device, step=0.1,
            batch=None, prepop_batch=None):
     """Pre-populate a cache from prepop's rays (in their order; rounds of
@@ -88,8 +109,11 @@ def render(ctx: SceneContext, cam: W.CameraRays, prepop: W.CameraRays, cfg: Cach
     mark("start")
     m0 = march(ctx, prepop, step, device)
     mark("march_prepop")
-    pre = Placer(ctx, MarchCandidates(m0.points), cfg, device)
-    res0 = pre.plain(prepop_batch if prepop_batch is not None else batch)
+    if m0.n_points:
+        pre = Placer(ctx, MarchCandidates(m0.points), cfg, device)
+        res0 = pre.plain(prepop_batch if prepop_batch is not None else batch)
+    else:  # no pre-population: the render inserts every cache point
+        res0 = _empty_cache(device)
     K0 = res0.K
     mark("place_prepop")
     torch.cuda.synchronize()
@@ -101,6 +125,8 @@ def render(ctx: SceneContext, cam: W.CameraRays, prepop: W.CameraRays, cfg: Cach
     m1 = march(ctx, cam, step, device)
     mark("march_render")
     cand = torch.cat([res0.pos, m1.points])
+    if cand.shape[0] == 0:  # nothing cached and no march points
+        return _empty_render(cam, prepop, m0, m1, res0, device, t0, t1, ev)
     pl = Placer(ctx, MarchCandidates(cand), cfg, device)
     pl.covered[:K0] = 1
     pl.acc[:K0] = torch.arange(K0, dtype=torch.int32, device=device)

@@ -231,3 +231,21 @@ def test_interpolation_of_march_points_matches_oracle(dev):
     _say(f"interp: {Q} queries ({pts.shape[0]} march points), {cov.sum()} covered, mean members {members.mean():.1f}")
     np.testing.assert_array_equal(hits.cpu().numpy(), np.where(cov, members, 0))
     np.testing.assert_allclose(out.cpu().numpy(), L, rtol=1e-6, atol=1e-6)
+
+
+def test_render_pass_without_prepopulation_and_without_rays(dev):
+    """No pre-population rays: every cache point is inserted at render time,
+    under the same rule; no render rays: no pixels and nothing placed."""
+    w = W.make_c2(seed=32, P=1, n_soup=2000)
+    ctx = SceneContext(w)
+    cfg = CacheConfig(n_theta=8, n_phi=32, batch=512)
+    cam = W.CameraRays(12, 8, 2, eye=(0.5, 0.5, 0.04), look_at=(0.5, 0.5, 1.0), fov_deg=60.0, seed=6)
+    none = W.CameraRays(0, 1, 1, eye=(0.5, 0.5, 0.04), look_at=(0.5, 0.5, 1.0), fov_deg=60.0, seed=7)
+    assert none.n == 0
+    pix, st, (m1, res, L, hits, cand, pl) = RD.render(ctx, cam, none, cfg, dev)
+    _say("render without pre-population", st)
+    assert st["prepop_cache"] == 0 and st["cache_points"] == st["inserted"] > 0 and st["uncovered_after"] == 0
+    _check_insertion_rule(cand.cpu().numpy(), pl.acc[:res.K].cpu().numpy().astype(np.int64), res.R.cpu().numpy(), 0)
+    pix0, st0, _ = RD.render(ctx, none, none, cfg, dev)
+    assert pix0.shape[0] == 0 and st0["cache_points"] == 0 and st0["march_points"] == 0
+    ctx.close()
