@@ -58,6 +58,8 @@ def lib():
         L.rco_records.restype = i32
         L.rco_values.argtypes = [vp, f32, f32, vp, i32, vp, vp, vp, vp, i64, f32, i32, u64, vp, i32]
         L.rco_values.restype = i32
+        L.rco_j08.argtypes = [vp, f32, f32, vp, i32, vp, vp, vp, vp, i64, f32, i32, u64, vp, vp, vp, i32]
+        L.rco_j08.restype = i32
         L.rco_trace.argtypes = [vp, vp, vp, i64, i32, vp, vp, vp]
         L.rco_trace.restype = i32
         L.rco_occluded.argtypes = [vp, vp, vp, vp, i64, i32, vp]
@@ -182,6 +184,40 @@ def values(scene: Scene, sigma_s, sigma_a, lights, pos, n_theta, n_phi, rec_id=N
     if rc != 0:
         raise ValueError(f"rco_values failed ({rc})")
     return val
+
+
+def j08(scene: Scene, sigma_s, sigma_a, lights, pos, n_theta, n_phi, rec_id=None, ring_step=0.1, max_rings=20,
+        seed=0, nthreads=0):
+    """The comparison method's occlusion-unaware gradients (Jarosz et al.
+    2008: surface hit points held fixed, medium paths moved rigidly;
+    supplement Eqs. S.3-S.4) from the record's own samples.  Returns (value
+    [P][2], grad [P][2][3], moments [P][2] = means over the directions of the
+    per-direction sample L_k and of its gradient norm |grad L_k|)."""
+    pos = _c(pos, np.float32).reshape(-1, 3)
+    P = pos.shape[0]
+    nt = _c(np.broadcast_to(n_theta, (P,)), np.int32)
+    npf = _c(np.broadcast_to(n_phi, (P,)), np.int32)
+    rid = _c(np.arange(P) if rec_id is None else rec_id, np.uint64)
+    li = _c(lights, np.float32).reshape(-1, 4)
+    val = np.zeros((P, 2))
+    grad = np.zeros((P, 2, 3))
+    mom = np.zeros((P, 2))
+    rc = lib().rco_j08(scene._h, float(sigma_s), float(sigma_a), _p(li), li.shape[0], _p(pos), _p(nt), _p(npf),
+                       _p(rid), P, float(ring_step), int(max_rings), int(seed) & (2**64 - 1), _p(val), _p(grad),
+                       _p(mom), int(nthreads))
+    if rc != 0:
+        raise ValueError(f"rco_j08 failed ({rc})")
+    return val, grad, mom
+
+
+def j08_radius(moments, eps, r_min, r_max):
+    """Eq. jaroszRadius: R = eps * sum_k L_k / sum_k |grad L_k| over the
+    record's per-direction samples, clamped to [r_min, r_max] (the paper's
+    comparison clamps to a minimum radius); moments [P][2] from j08()."""
+    m = np.asarray(moments, np.float64).reshape(-1, 2)
+    with np.errstate(divide="ignore", invalid="ignore"):
+        R = np.where(m[:, 1] > 0, eps * m[:, 0] / m[:, 1], np.inf)
+    return np.clip(R, r_min, r_max).astype(np.float32)
 
 
 def records_for(w, idx=None, xeval=None, nthreads=0, scene=None):

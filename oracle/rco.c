@@ -908,6 +908,100 @@ int rco_values(const rco_scene* s, float sigma_s, float sigma_a, const float* li
   return err ? RCO_ENOMEM : RCO_OK;
 }
 
+/* Occlusion-unaware per-sample gradients of the comparison method (the
+ * gradients of Jarosz et al. 2008 summarised in Sec. 3 and supplement
+ * Eqs. S.3-S.4), from the same samples as the record's Monte Carlo value.
+ * Single scattering: each direction's sample keeps its hit point y fixed as x
+ * moves; in surface-area form the sample is L_s T G / pdf_A, so its gradient
+ * is the sample times grad ln T + grad ln G, with T = exp(-mu r),
+ * G = (yx . n) / r^3, yx = x - y, r = |yx|: grad ln T = -mu yx / r and
+ * grad ln G = n / (yx . n) - 3 yx / r^2.  Multiple scattering: the path
+ * x -> ring vertex m -> light moves rigidly with x, so only the light
+ * connection I exp(-mu d) / d^2 (d = |l - m|, visibility held) changes:
+ * gradient = contribution * (-mu - 2 / d) (m - l) / d.  Per direction k the
+ * sample is L_k = SS_k + MS_k with gradient g_k; outputs: grad [2][3]
+ * (SS, MS; means over the N directions like the value), and the means of
+ * L_k and of |g_k| (the radius of Eq. jaroszRadius is
+ * eps * sum L_k / sum |g_k|). */
+static void j08_grad(const rco_scene* s, const rco_params* p, const float* xin, const rco_verts* v, double* grad,
+                     double* lmean, double* gmean) {
+  const int N = v->nth * v->nph;
+  const double mu = (double)p->sigma_s + (double)p->sigma_a;
+  const double x64[3] = {xin[0], xin[1], xin[2]};
+  const f3 x32 = {xin[0], xin[1], xin[2]};
+  double gs[3] = {0, 0, 0}, gm[3] = {0, 0, 0}, lsum = 0.0, nsum = 0.0;
+  for (int k = 1; k <= N; k++) {
+    const f3 w = v->w32[k];
+    const double wn = sqrt((double)w.x * w.x + (double)w.y * w.y + (double)w.z * w.z);
+    double gk[3] = {0, 0, 0}, Lk = 0.0;
+    if (v->hit[k] >= 0) {
+      const double r = v->t64[k] * wn;
+      const double S = exp(-mu * r) * v->Ls[k];
+      const double* n = s->n64 + 3 * v->hit[k];
+      const double yx[3] = {-v->t64[k] * w.x, -v->t64[k] * w.y, -v->t64[k] * w.z};
+      const double yn = d3_dot(yx, n);
+      for (int i = 0; i < 3; i++) gk[i] = S * (-mu * yx[i] / r + n[i] / yn - 3.0 * yx[i] / (r * r));
+      Lk += S;
+      for (int i = 0; i < 3; i++) gs[i] += gk[i];
+    }
+    for (int i = 0; i < v->M[k]; i++) {
+      const double y64[3] = {x64[0] + v->r64[i] * w.x, x64[1] + v->r64[i] * w.y, x64[2] + v->r64[i] * w.z};
+      const f3 y32 = {x32.x + v->r32[i] * w.x, x32.y + v->r32[i] * w.y, x32.z + v->r32[i] * w.z};
+      const double att = (double)p->ring_step * exp(-mu * v->r64[i] * wn) * (double)p->sigma_s / (4.0 * RCO_PI);
+      for (int l = 0; l < p->L; l++) {
+        const float* lp = p->lights + 4 * l;
+        const f3 seg = {lp[0] - y32.x, lp[1] - y32.y, lp[2] - y32.z};
+        if (occluded(s, y32, seg, -1)) continue;
+        const double ml[3] = {y64[0] - lp[0], y64[1] - lp[1], y64[2] - lp[2]};
+        const double d = d3_norm(ml);
+        const double c = att * (double)lp[3] * exp(-mu * d) / (d * d);
+        Lk += c;
+        for (int q = 0; q < 3; q++) {
+          const double g = c * (-mu - 2.0 / d) * ml[q] / d;
+          gk[q] += g;
+          gm[q] += g;
+        }
+      }
+    }
+    lsum += Lk;
+    nsum += d3_norm(gk);
+  }
+  for (int i = 0; i < 3; i++) {
+    grad[i] = gs[i] / N;
+    grad[3 + i] = gm[i] / N;
+  }
+  *lmean = lsum / N;
+  *gmean = nsum / N;
+}
+
+/* Values, occlusion-unaware gradients [P][2][3] and the means of the
+ * per-direction samples and of their gradient norms [P][2] for P points. */
+int rco_j08(const rco_scene* s, float sigma_s, float sigma_a, const float* lights, int L, const float* pos,
+            const int32_t* n_theta, const int32_t* n_phi, const uint64_t* rec_id, int64_t P, float ring_step,
+            int max_rings, uint64_t seed, double* value, double* grad, double* moments, int nthreads) {
+  if (!s || P < 0 || (P > 0 && (!pos || !n_theta || !n_phi || !rec_id || !value || !grad || !moments)))
+    return RCO_EINVAL;
+  if (L < 0 || (L > 0 && !lights) || !(ring_step > 0.0f) || max_rings < 0 || sigma_s < 0 || sigma_a < 0) return RCO_EINVAL;
+  for (int64_t i = 0; i < P; i++)
+    if (n_theta[i] < 2 || n_phi[i] < 5) return RCO_EINVAL;
+  rco_params p = {sigma_s, sigma_a, lights, L, ring_step, max_rings, seed};
+  int err = 0;
+#ifdef _OPENMP
+  if (nthreads > 0) omp_set_num_threads(nthreads);
+#else
+  (void)nthreads;
+#endif
+#pragma omp parallel for schedule(dynamic, 1) reduction(| : err)
+  for (int64_t i = 0; i < P; i++) {
+    rco_verts v;
+    if (build_verts(s, &p, pos + 3 * i, n_theta[i], n_phi[i], rec_id[i], &v)) { err |= 1; continue; }
+    mc_value(&v, &p, value + 2 * i);
+    j08_grad(s, &p, pos + 3 * i, &v, grad + 6 * i, moments + 2 * i, moments + 2 * i + 1);
+    verts_free(&v);
+  }
+  return err ? RCO_ENOMEM : RCO_OK;
+}
+
 /* The per-record sample directions (FP32), exported for tests of the
  * sampling layout (strata, equal solid angle, poles). [N+2][3] */
 int rco_directions(uint64_t seed, uint64_t rec, int nth, int nph, float* out) {

@@ -30,6 +30,13 @@ MUTATIONS = [
     ("dropped F HT term of the Hessian", "gF[i] * gT[j] + F * HT[3 * i + j]);", "gF[i] * gT[j]);",
      ["test_record_derivatives_are_exact_calculus_of_triangulated_value",
       "test_emitting_plane_under_medium_matches_exponential_integrals"]),
+    # comparison method's gradients (supplement Eq. S.4; rigid medium paths)
+    ("sign of the 3 yx / r^2 term of grad ln G", "- 3.0 * yx[i] / (r * r));", "+ 3.0 * yx[i] / (r * r));",
+     ["test_j08_gradient_of_an_emitting_plane_is_the_exact_gradient"]),
+    ("inverse-square falloff differentiated as 1/d", "(-mu - 2.0 / d) * ml[q] / d;", "(-mu - 1.0 / d) * ml[q] / d;",
+     ["test_j08_medium_gradient_is_the_rigid_path_derivative"]),
+    ("sign of grad ln T of the fixed-hit sample", "gk[i] = S * (-mu * yx[i] / r +", "gk[i] = S * (mu * yx[i] / r +",
+     ["test_j08_gradient_of_an_emitting_plane_is_the_exact_gradient"]),
     # far vertex (the first to be occluded): nearest instead
     ("nearest instead of furthest vertex", "if (dist[k] > dist[best] ||", "if (dist[k] < dist[best] ||",
      ["test_black_occluder_in_uniform_field_converges_to_closed_form",

@@ -979,3 +979,89 @@ def test_composite_of_constant_radiance_is_a_geometric_series():
     Lr = rng.uniform(0, 1, N)
     pix2 = O.composite(offs, spp, w, Lr[np.repeat(np.arange(N), n)])
     np.testing.assert_allclose(pix2, (ray / c * Lr).reshape(n_pix, spp).mean(1), rtol=1e-12)
+
+
+# ---------------------------------------------------------------------------
+# the comparison method's occlusion-unaware gradients (Jarosz et al. 2008;
+# supplement Eqs. S.3-S.4) and its radius (Eq. jaroszRadius)
+# ---------------------------------------------------------------------------
+def _emitting_plane():
+    Wd = 30.0
+    floor = np.array([[-Wd, -Wd, 0, Wd, -Wd, 0, Wd, Wd, 0], [-Wd, -Wd, 0, Wd, Wd, 0, -Wd, Wd, 0]], np.float32)
+    return O.Scene(floor, np.zeros(2, np.float32), np.ones(2, np.float32), (-Wd, -Wd, 0), (Wd, Wd, 4))
+
+
+def test_j08_gradient_of_an_emitting_plane_is_the_exact_gradient():
+    """Emitter L_e = 1 on z = 0 under an absorbing medium, nothing occluding:
+    holding the hit points fixed loses nothing, so the occlusion-unaware
+    gradient converges to dV/dz = -mu E1(mu h)/2 (lateral 0), and the mean of
+    the per-direction gradient norms to the hemisphere integral
+    (1/2) int_0^1 exp(-mu h/c) |(mu + 3c/h) u + e_z/h| dc (u the unit
+    direction to the hit, u_z = -c), evaluated by quadrature."""
+    from scipy.integrate import quad
+    sc = _emitting_plane()
+    mu, h = 1.0, 0.5
+    Gz = -mu * expn(1, mu * h) / 2
+
+    def norm(c):
+        a = mu + 3 * c / h
+        return math.exp(-mu * h / c) * math.sqrt(a * a - 2 * a * c / h + 1 / (h * h)) / 2
+    gnorm = quad(norm, 0, 1, limit=200)[0]
+    res = {}
+    for N in (1024, 16384):
+        nt, npf = W.strata_shape(N)
+        v, g, m = O.j08(sc, 0.0, mu, NO_LIGHTS, np.array([[0.1, -0.2, h]] * 8, np.float32), nt, npf,
+                        rec_id=np.arange(8), ring_step=0.1, max_rings=0, seed=7)
+        res[N] = (g[:, 0].mean(0), m.mean(0), v[:, 0].mean())
+    g, m, v = res[16384]
+    assert abs(g[2] - Gz) / abs(Gz) < 0.02 and np.abs(g[:2]).max() < 2e-3 * abs(Gz)
+    assert abs(res[16384][0][2] - Gz) < 0.5 * abs(res[1024][0][2] - Gz)
+    assert abs(m[0] - v) < 1e-12 and abs(m[0] - expn(2, mu * h) / 2) < 2e-4
+    assert abs(m[1] - gnorm) / gnorm < 0.02
+
+
+def test_j08_medium_gradient_is_the_rigid_path_derivative():
+    """A point light in an open absorbing medium, nothing occluding: moving x
+    moves every sampled path rigidly when the random numbers are held (same
+    record id), so the multiple-scattering gradient must equal the central
+    difference of the record's own Monte Carlo values (rings far from the
+    box, where the medium has absorbed everything)."""
+    Wd = 20.0
+    tri = np.array([[Wd - 1, Wd - 1, Wd - 1, Wd - 0.5, Wd - 1, Wd - 1, Wd - 1, Wd - 0.5, Wd - 1]], np.float32)
+    sc = O.Scene(tri, np.zeros(1, np.float32), None, (-Wd, -Wd, -Wd), (Wd, Wd, Wd))
+    light = np.array([[0.3, 0.45, -0.2, 5.0]], np.float32)
+    ss, sa = 1.0, 1.0
+    x = np.array([0.05, 0.1, 0.0])
+    kw = dict(ring_step=0.1, max_rings=60, seed=11)
+    v, g, m = O.j08(sc, ss, sa, light, x[None].astype(np.float32), 16, 64, rec_id=[3], **kw)
+    h = 2e-3
+    fd = np.zeros(3)
+    for i in range(3):
+        xp, xm = x.copy(), x.copy()
+        xp[i] += h
+        xm[i] -= h
+        vp = O.values(sc, ss, sa, light, xp[None].astype(np.float32), 16, 64, rec_id=[3], **kw)[0, 1]
+        vm = O.values(sc, ss, sa, light, xm[None].astype(np.float32), 16, 64, rec_id=[3], **kw)[0, 1]
+        fd[i] = (vp - vm) / (2 * h)
+    assert np.linalg.norm(fd) > 0.05 * v[0, 1]
+    np.testing.assert_allclose(g[0, 1], fd, rtol=2e-3, atol=2e-3 * np.linalg.norm(fd))
+    assert np.abs(g[0, 0]).max() == 0.0 and v[0, 0] == 0.0  # nothing emits or reflects
+
+
+def test_j08_radius_scales_with_eps_and_ignores_the_radiance_scale():
+    """Eq. jaroszRadius uses the ratio of summed radiance to summed gradient
+    norms: linear in eps, unchanged when every light (and so every sample)
+    is scaled, and clamped to [r_min, r_max]."""
+    w = W.make_c1(P=6)
+    sc = O.Scene.from_workload(w)
+    args = (sc, w.sigma_s, w.sigma_a)
+    _, _, m1 = O.j08(*args, w.lights, w.pos, w.n_theta, w.n_phi, ring_step=w.ring_step, max_rings=w.max_rings,
+                     seed=w.seed)
+    L2 = w.lights.copy()
+    L2[:, 3] *= 8.0
+    _, _, m2 = O.j08(*args, L2, w.pos, w.n_theta, w.n_phi, ring_step=w.ring_step, max_rings=w.max_rings, seed=w.seed)
+    np.testing.assert_allclose(m2, 8.0 * m1, rtol=1e-12)
+    R1 = O.j08_radius(m1, 0.1, 1e-6, 1e6)
+    np.testing.assert_allclose(O.j08_radius(m2, 0.1, 1e-6, 1e6), R1, rtol=1e-6)
+    np.testing.assert_allclose(O.j08_radius(m1, 0.2, 1e-6, 1e6), 2 * R1, rtol=1e-6)
+    assert (O.j08_radius(m1, 0.1, 0.05, 0.06) >= 0.05).all() and (O.j08_radius(m1, 0.1, 0.05, 0.06) <= 0.06).all()
