@@ -64,11 +64,11 @@ def log(*a):
 
 def kernel_source_hash():
     """sha256 prefix of the sources that make the record kernel and its launches
-    (every file of paper_1805_09258_amd/csrc but the learned-placement and
-    render-pass ones, which build other kernels)."""
+    (every file of paper_1805_09258_amd/csrc but the learned-placement,
+    render-pass and comparison-method ones, which build other kernels)."""
     h = hashlib.sha256()
     for p in sorted((ROOT / "paper_1805_09258_amd" / "csrc").glob("*")):
-        if p.suffix in (".hip", ".hpp", ".cpp") and not p.stem.startswith(("learned", "render")):
+        if p.suffix in (".hip", ".hpp", ".cpp") and not p.stem.startswith(("learned", "render", "j08")):
             h.update(p.read_bytes())
     return h.hexdigest()[:16]
 
@@ -187,6 +187,62 @@ def render_pass(dev, reps=3):
     st["seconds_per_frame"] = st["seconds_prepop"] + st["seconds_render"]
     st["records_per_march_point"] = (st["prepop_records"] + st["render_records"]) / st["march_points"]
     return st
+
+
+def j08_vs_ours(dev, reps=5, eps_j08=0.3):
+    """The comparison method's records (occlusion-unaware gradients and the
+    gradient-norm radius, eps = 0.3 as in the paper's Patio comparison)
+    against this method's records on the 10k-point workload: records/s of
+    each (same samples) and the radius distribution of each at its own
+    tolerance (the paper reports that the gradient-norm radius piles up at
+    the minimum radius near surfaces and lights)."""
+    import torch
+    from paper_1805_09258_amd import placement as PL
+    from paper_1805_09258_amd import rc
+    from paper_1805_09258_amd import workloads as W
+    w = W.make_c2()
+    sc = rc.Scene.from_workload(w)
+    dw = rc.DeviceWorkload(w, device=dev)
+    P = w.n_rec
+    cfg = PL.CacheConfig()
+    val = torch.zeros((P, 2), dtype=torch.float64, device=dev)
+    grad = torch.zeros((P, 2, 3), dtype=torch.float64, device=dev)
+    mom = torch.zeros((P, 2), dtype=torch.float64, device=dev)
+    Rj = torch.zeros(P, dtype=torch.float32, device=dev)
+    prm = rc.make_params(w.ring_step, w.max_rings, int(w.n_phi.max()), w.seed)
+
+    def j08():
+        rc.rc_j08_records(sc.handle, w.sigma_s, w.sigma_a, w.lights, dw.pos, dw.n_theta, dw.n_phi, prm, eps_j08,
+                          cfg.r_min, cfg.r_max, val, grad, mom, Rj)
+
+    def timed(fn):
+        fn()
+        ts = []
+        for _ in range(reps):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            fn()
+            torch.cuda.synchronize()
+            ts.append(time.perf_counter() - t0)
+        return sorted(ts)[reps // 2]
+    tj = timed(j08)
+    out = dw.outputs()
+    ws = dw.workspace()
+    to = timed(lambda: rc.compute_records(sc, dw, batched=True, out=out, workspace=ws, hits_pass=True))
+    v, g, h = out[:3] if isinstance(out, tuple) else out
+    Ro = torch.zeros(P, dtype=torch.float32, device=dev)
+    rc.rc_radius(v, h, cfg.eps, cfg.r_min, cfg.r_max, Ro)
+    torch.cuda.synchronize()
+    sc.close()
+
+    def dist(R):
+        R = R.double()
+        return {"median": float(R.median().item()), "at_r_min": float((R <= cfg.r_min * 1.0001).double().mean().item()),
+                "mean": float(R.mean().item())}
+    return {"workload": "10k points, closed unit room + 10k-triangle soup, 1024 directions, 4 point lights",
+            "j08": {"seconds": tj, "records_per_s": P / tj, "eps": eps_j08, "radius": dist(Rj)},
+            "ours": {"seconds": to, "records_per_s": P / to, "eps": cfg.eps, "radius": dist(Ro)},
+            "time_per_record_ratio": tj / to, "r_min": cfg.r_min, "r_max": cfg.r_max}
 
 
 def measure(name, dev, steps, warmup, count=True):
@@ -439,6 +495,7 @@ def main():
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-vs-plain placement comparison")
     ap.add_argument("--no-render", action="store_true", help="skip the render pass that consumes the cache")
     ap.add_argument("--render-only", action="store_true", help="only the render pass (its own JSON line)")
+    ap.add_argument("--no-j08", action="store_true", help="skip the comparison method's records")
     ap.add_argument("--no-count", action="store_true", help=argparse.SUPPRESS)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only copy a 1 GiB float32 buffer three times (scales the HBM byte counters)")
@@ -526,6 +583,10 @@ def main():
         log("render pass ...")
         out["render_pass"] = render_pass(dev)
         log("render pass", out["render_pass"])
+    if not args.no_j08:
+        log("comparison method's records ...")
+        out["j08_vs_ours"] = j08_vs_ours(dev)
+        log("j08 vs ours", out["j08_vs_ours"])
     if not args.no_learned:
         log("learned vs plain placement ...")
         out["learned_vs_plain"] = learned_vs_plain(dev)

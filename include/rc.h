@@ -545,6 +545,29 @@ int rc_composite(const int64_t* offsets, int64_t n_rays, int32_t spp, const doub
                  double* pixel, void* stream);
 
 /* ------------------------------------------------------------------ */
+/* The comparison method's records (Jarosz et al. 2008 as summarised in */
+/* Sec. 3; supplement Eqs. S.3-S.4; Eq. jaroszRadius)                  */
+/* ------------------------------------------------------------------ */
+/* From the same samples as rc_records' values (directions, hits, shading,
+ * medium rings, params->seed / rec_base / common_random / ring_step /
+ * max_rings as there; params' other fields are not read): value [P][2]
+ * (SS, MS Monte Carlo values), grad [P][2][3] occlusion-unaware gradients
+ * (single scattering: each direction's hit point held fixed, the sample's
+ * gradient = sample (grad ln T + grad ln G), T = exp(-mu r), G = (yx . n) /
+ * r^3, yx = x - y; multiple scattering: the path x -> ring vertex -> light
+ * moved rigidly, visibility held), moments [P][2] = the means over the
+ * directions of the per-direction sample L_k (channels summed) and of
+ * |grad L_k|, and R [P] = eps * sum L_k / sum |grad L_k| clamped to
+ * [r_min, r_max] (r_max when every gradient is zero).  All device FP64
+ * except R (FP32).  Records with n_theta < 2, n_phi outside [5, RC_MAX_NPHI]
+ * get NaN outputs.  Shadow segments from the scene's light bins of these
+ * lights (built on the first call). */
+int rc_j08_records(const rc_scene* scene, const rc_medium* medium, const rc_point_light* lights, int n_lights,
+                   const float* pos, const int32_t* n_theta, const int32_t* n_phi, int64_t P,
+                   const rc_params* params, float eps, float r_min, float r_max, double* value, double* grad,
+                   double* moments, float* R, void* stream);
+
+/* ------------------------------------------------------------------ */
 /* Diagnostics                                                          */
 /* ------------------------------------------------------------------ */
 const char* rc_last_error(void);

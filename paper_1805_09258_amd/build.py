@@ -11,7 +11,7 @@ from pathlib import Path
 
 PKG = Path(__file__).resolve().parent
 ROOT = PKG.parent
-SRC = ["csrc/api.cpp", "csrc/bvh.cpp", "csrc/lightbins.cpp", "csrc/kernels.hip", "csrc/learned.hip", "csrc/render.hip"]
+SRC = ["csrc/api.cpp", "csrc/bvh.cpp", "csrc/lightbins.cpp", "csrc/kernels.hip", "csrc/learned.hip", "csrc/render.hip", "csrc/j08.hip"]
 OUT = PKG / "librc.so"
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

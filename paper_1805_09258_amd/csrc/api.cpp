@@ -18,6 +18,7 @@
 #include "kernels.hpp"
 #include "learned.hpp"
 #include "render.hpp"
+#include "j08.hpp"
 
 namespace {
 
@@ -1238,6 +1239,65 @@ int rc_composite(const int64_t* offsets, int64_t n_rays, int32_t spp, const doub
   if (n_rays > 0 && (!offsets || !pixel)) return fail(RC_EINVAL, "NULL pointer");
   RC_HIP(rc::launch_composite(reinterpret_cast<const long long*>(offsets), (int)(n_rays / spp), spp, weight, L, pixel,
                               static_cast<hipStream_t>(stream)));
+  return RC_OK;
+}
+
+int rc_j08_records(const rc_scene* s, const rc_medium* m, const rc_point_light* lights, int n_lights,
+                   const float* pos, const int32_t* n_theta, const int32_t* n_phi, int64_t P, const rc_params* params,
+                   float eps, float r_min, float r_max, double* value, double* grad, double* moments, float* R,
+                   void* stream) {
+  if (!s) return fail(RC_EINVAL, "scene is NULL");
+  if (!m || !std::isfinite(m->sigma_s) || !std::isfinite(m->sigma_a) || m->sigma_s < 0 || m->sigma_a < 0)
+    return fail(RC_EINVAL, "medium coefficients must be finite and >= 0");
+  if (n_lights < 0 || n_lights > RC_MAX_LIGHTS || (n_lights > 0 && !lights)) return fail(RC_EINVAL, "bad lights");
+  if (!params || !(params->ring_step > 0.f) || params->max_rings < 0 || params->max_rings > RC_MAX_RINGS ||
+      params->rec_base < 0 || (params->common_random != 0 && params->common_random != 1))
+    return fail(RC_EINVAL, "bad params");
+  if (!(eps > 0.f) || !(r_min > 0.f) || !(r_max >= r_min) || !std::isfinite(r_max))
+    return fail(RC_EINVAL, "need eps > 0 and 0 < r_min <= r_max finite");
+  if (P < 0 || P > 0x7fffffff) return fail(RC_EINVAL, "P out of range");
+  if (P > 0 && (!pos || !n_theta || !n_phi || !value || !grad || !moments || !R)) return fail(RC_EINVAL, "NULL pointer");
+  if (P == 0) return RC_OK;
+  rc::J08Args a;
+  std::memset(&a, 0, sizeof a);
+  a.nodes = s->nodes;
+  a.tris = s->tris;
+  a.tri_stride = s->tri_stride;
+  a.shade = s->shade;
+  a.emission = s->emission;
+  a.box_lo = make_float3(s->box_lo[0], s->box_lo[1], s->box_lo[2]);
+  a.box_hi = make_float3(s->box_hi[0], s->box_hi[1], s->box_hi[2]);
+  a.n_lights = n_lights;
+  for (int l = 0; l < n_lights; l++)
+    a.lights[l] = make_float4(lights[l].pos[0], lights[l].pos[1], lights[l].pos[2], lights[l].intensity);
+  a.sigma_s = m->sigma_s;
+  a.sigma_a = m->sigma_a;
+  a.ring_step = params->ring_step;
+  a.max_rings = params->max_rings;
+  a.seed = params->seed;
+  a.rec_base = params->rec_base;
+  a.common_random = params->common_random;
+  a.pos = pos;
+  a.n_theta = n_theta;
+  a.n_phi = n_phi;
+  a.P = (int)P;
+  a.eps = eps;
+  a.r_min = r_min;
+  a.r_max = r_max;
+  a.value = value;
+  a.grad = grad;
+  a.moments = moments;
+  a.R = R;
+  if (n_lights > 0) {  // shadow segments from the light bins of these lights
+    rc_scene* sm = const_cast<rc_scene*>(s);
+    std::lock_guard<std::mutex> lk(sm->mu);
+    int r = ensure_light_bins(sm, lights, n_lights, 0);
+    if (r) return r;
+    a.lb_desc = sm->lb.desc;
+    a.lb_offs = sm->lb.offs;
+    a.lb_ent = sm->lb.ent;
+  }
+  RC_HIP(rc::launch_j08(a, s->depth, static_cast<hipStream_t>(stream)));
   return RC_OK;
 }
 

@@ -65,6 +65,7 @@ EXPORTS = ["rc_scene_create", "rc_scene_destroy", "rc_scene_info", "rc_bvh_build
            "rc_mlp_load", "rc_mlp_fit_features", "rc_mlp_forward", "rc_mlp_radius", "rc_mlp_train_workspace_bytes",
            "rc_mlp_train_step", "rc_place_gather", "rc_place_accept", "rc_place_cover", "rc_place_cover_grid",
            "rc_ellipsoid_form", "rc_interp", "rc_march_count", "rc_march_emit", "rc_composite",
+           "rc_j08_records",
            "rc_last_error", "rc_version"]
 
 _LIB = None
@@ -156,6 +157,9 @@ def lib():
         L.rc_march_emit.restype = i32
         L.rc_composite.argtypes = [vp, i64, i32, vp, vp, vp, vp]
         L.rc_composite.restype = i32
+        L.rc_j08_records.argtypes = [vp, C.POINTER(rc_medium), C.POINTER(rc_point_light), i32, vp, vp, vp, i64,
+                                     C.POINTER(rc_params), f32, f32, f32, vp, vp, vp, vp, vp]
+        L.rc_j08_records.restype = i32
         L.rc_last_error.restype = C.c_char_p
         L.rc_version.restype = C.c_char_p
         _LIB = L
@@ -454,6 +458,15 @@ def rc_march_emit(orig, dirs, xi, step, sigma_s, sigma_t, offsets, points, weigh
 def rc_composite(offsets, spp, weight, L, pixel, stream=None):
     return _check(lib().rc_composite(_ptr(offsets), int(offsets.shape[0]) - 1, int(spp), _ptr(weight), _ptr(L),
                                      _ptr(pixel), _stream(stream)))
+
+
+def rc_j08_records(scene, sigma_s, sigma_a, lights, pos, n_theta, n_phi, params, eps, r_min, r_max, value, grad,
+                   moments, R, stream=None):
+    li, n = _lights(lights)
+    med = rc_medium(float(sigma_s), float(sigma_a))
+    return _check(lib().rc_j08_records(scene, C.byref(med), li, n, _ptr(pos), _ptr(n_theta), _ptr(n_phi),
+                                       int(pos.shape[0]), C.byref(params), float(eps), float(r_min), float(r_max),
+                                       _ptr(value), _ptr(grad), _ptr(moments), _ptr(R), _stream(stream)))
 
 
 def rc_version():

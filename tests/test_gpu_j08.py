@@ -1,0 +1,112 @@
+"""The comparison method's records (occlusion-unaware gradients, supplement
+Eqs. S.3-S.4; gradient-norm radius, Eq. jaroszRadius) on the GPU against
+the oracle, through the C ABI.
+
+Values to 1e-4 relative (as records); gradients to 2e-3 of the mean
+per-direction gradient norm (the estimator's own scale: a grazing hit's
+1/(yx . n) term amplifies the FP32 normal's rounding in a single sample);
+the moments and the radius to 2e-3 relative.
+"""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from oracle import oracle as O  # noqa: E402
+from paper_1805_09258_amd import rc  # noqa: E402
+from paper_1805_09258_amd import workloads as W  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+EPS, RMIN, RMAX = 0.3, 1e-3, 0.43
+
+
+def _say(*a):
+    print(*a, flush=True)
+
+
+@pytest.fixture(scope="module")
+def dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch.device("cuda:0")
+
+
+def gpu_j08(w, dev, n_theta=None, rec_base=0):
+    sc = rc.Scene.from_workload(w)
+    T = lambda a: torch.as_tensor(a, device=dev)  # noqa: E731
+    P = w.n_rec
+    val = torch.full((P, 2), -1.0, dtype=torch.float64, device=dev)
+    grad = torch.full((P, 2, 3), -1.0, dtype=torch.float64, device=dev)
+    mom = torch.full((P, 2), -1.0, dtype=torch.float64, device=dev)
+    R = torch.full((P,), -1.0, dtype=torch.float32, device=dev)
+    prm = rc.make_params(w.ring_step, w.max_rings, int(w.n_phi.max()), w.seed, rec_base=rec_base)
+    nt = w.n_theta if n_theta is None else n_theta
+    rc.rc_j08_records(sc.handle, w.sigma_s, w.sigma_a, w.lights, T(w.pos), T(nt), T(w.n_phi), prm, EPS, RMIN, RMAX,
+                      val, grad, mom, R)
+    torch.cuda.synchronize()
+    sc.close()
+    return val.cpu().numpy(), grad.cpu().numpy(), mom.cpu().numpy(), R.cpu().numpy()
+
+
+def _compare(got, ref, idx, tag):
+    v, g, m, R = got
+    ov, og, om = ref
+    v, g, m, R = v[idx], g[idx], m[idx], R[idx]
+    scale = np.maximum(np.abs(ov).sum(1, keepdims=True), 1e-300)
+    ev = (np.abs(v - ov) / scale).max()
+    eg = (np.abs(g - og).max(2).max(1) / np.maximum(om[:, 1], 1e-300)).max()
+    em = (np.abs(m - om) / np.maximum(np.abs(om), 1e-300)).max()
+    oR = O.j08_radius(om, EPS, RMIN, RMAX)
+    eR = (np.abs(R - oR) / oR).max()
+    _say(f"{tag}: max rel err value {ev:.2e}, gradient {eg:.2e} (of the mean |grad L_k|), moments {em:.2e}, R {eR:.2e}")
+    assert ev < 1e-4 and eg < 2e-3 and em < 2e-3 and eR < 2e-3
+
+
+def test_c1_all_records_match_oracle(dev):
+    w = W.make_c1()
+    got = gpu_j08(w, dev)
+    ref = O.j08(O.Scene.from_workload(w), w.sigma_s, w.sigma_a, w.lights, w.pos, w.n_theta, w.n_phi,
+                ring_step=w.ring_step, max_rings=w.max_rings, seed=w.seed)
+    _compare(got, ref, np.arange(w.n_rec), "C1 j08")
+
+
+def test_c2_one_percent_of_the_full_launch_matches_oracle(dev):
+    w = W.make_c2()
+    got = gpu_j08(w, dev)
+    idx = np.sort(np.random.default_rng(5).choice(w.n_rec, w.n_rec // 100, replace=False))
+    ref = O.j08(O.Scene.from_workload(w), w.sigma_s, w.sigma_a, w.lights, w.pos[idx], w.n_theta[idx], w.n_phi[idx],
+                rec_id=idx, ring_step=w.ring_step, max_rings=w.max_rings, seed=w.seed)
+    _compare(got, ref, idx, "C2 1% j08")
+    # same value samples as the records: the values equal rc_records' values
+    # to the value tolerance (the record kernel sums in compensated FP32 with
+    # corrected hit distances, this kernel in FP64 from the FP32 distances)
+    sc = rc.Scene.from_workload(w)
+    dw = rc.DeviceWorkload(w, device=dev)
+    v, g, h, ws = rc.compute_records(sc, dw, batched=True)
+    torch.cuda.synchronize()
+    sc.close()
+    np.testing.assert_allclose(got[0], v.cpu().numpy(), rtol=1e-4, atol=1e-12)
+
+
+def test_invalid_sample_counts_give_nan_and_calls_are_deterministic(dev):
+    w = W.make_c1(P=20)
+    nt = w.n_theta.copy()
+    nt[[3, 11]] = 1
+    v, g, m, R = gpu_j08(w, dev, n_theta=nt)
+    bad = np.zeros(20, bool)
+    bad[[3, 11]] = True
+    assert np.isnan(v[bad]).all() and np.isnan(g[bad]).all() and np.isnan(R[bad]).all()
+    assert np.isfinite(v[~bad]).all() and np.isfinite(R[~bad]).all()
+    v2, g2, m2, R2 = gpu_j08(w, dev, n_theta=nt)
+    assert np.array_equal(v[~bad], v2[~bad]) and np.array_equal(g[~bad], g2[~bad]) and np.array_equal(R, R2,
+                                                                                                     equal_nan=True)
+    with pytest.raises(rc.RCError):
+        sc = rc.Scene.from_workload(w)
+        try:
+            prm = rc.make_params(w.ring_step, w.max_rings, 32, w.seed)
+            z = torch.zeros(1, device=dev)
+            rc.rc_j08_records(sc.handle, w.sigma_s, w.sigma_a, w.lights, torch.zeros((1, 3), device=dev),
+                              torch.ones(1, dtype=torch.int32, device=dev), torch.ones(1, dtype=torch.int32, device=dev),
+                              prm, 0.0, RMIN, RMAX, z, z, z, z)  # eps must be > 0
+        finally:
+            sc.close()
