@@ -428,6 +428,35 @@ def interpolate(cache_pos, cache_val, cache_grad, cache_R, query, cache_form=Non
     return out, cov
 
 
+def interpolate_log(cache_pos, cache_val, cache_grad, cache_R, query):
+    """The comparison method's extrapolation (Eq. jaroszExtrapolation):
+    L(x') = exp( sum_k [ln L_k + (grad L_k / L_k) . (x' - x_k)] w_k / sum_k w_k )
+    over the cache points whose radius contains x' (FP32 test as in
+    interpolate) with the same cubic weights; cache points with L_k <= 0 have
+    no logarithm and take no part.  Returns (L [Q], covered [Q])."""
+    cp = np.asarray(cache_pos, np.float64)
+    cv = np.asarray(cache_val, np.float64)
+    cg = np.asarray(cache_grad, np.float64)
+    cR = np.asarray(cache_R, np.float64)
+    q = np.asarray(query, np.float64)
+    q32, cp32, cR32 = (np.asarray(a, np.float32) for a in (query, cache_pos, cache_R))
+    out = np.zeros(len(q))
+    cov = np.zeros(len(q), bool)
+    for i, x in enumerate(q):
+        m = _within32(q32[i][None, :], cp32, cR32) & (cv > 0)
+        if not m.any():
+            continue
+        dx = x[None, :] - cp[m]
+        d = 1.0 - np.sqrt((dx * dx).sum(1)) / cR[m]
+        w = 3 * d * d - 2 * d * d * d
+        lnL = np.log(cv[m]) + ((cg[m] / cv[m][:, None]) * dx).sum(1)
+        den = w.sum()
+        if den > 0:
+            out[i] = np.exp((lnL * w).sum() / den)
+            cov[i] = True
+    return out, cov
+
+
 # --------------------------------------------------------------------------
 # Sec. 6 "Implementation" and Results in 3D: the render pass that consumes the
 # cache (uniform ray marching of camera rays, step 0.1, 16 samples per pixel)

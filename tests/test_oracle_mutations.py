@@ -118,7 +118,15 @@ def _composite_summing_rays(orig):
     return f
 
 
+def _log_interp_in_linear_space(orig):
+    def f(cache_pos, cache_val, cache_grad, cache_R, query):
+        return O.interpolate(cache_pos, cache_val, cache_grad, cache_R, query)
+    return f
+
+
 PY_MUTATIONS = [
+    ("log-space extrapolation done in linear space", "interpolate_log", _log_interp_in_linear_space,
+     ["test_log_space_extrapolation_is_exact_for_exponential_fields"]),
     ("march starts one step late", "march", _march_from_k1,
      ["test_march_points_in_an_empty_room_follow_the_closed_form"]),
     ("march weight without the scattering coefficient", "march", _march_without_sigma_s,

@@ -1065,3 +1065,31 @@ def test_j08_radius_scales_with_eps_and_ignores_the_radiance_scale():
     np.testing.assert_allclose(O.j08_radius(m2, 0.1, 1e-6, 1e6), R1, rtol=1e-6)
     np.testing.assert_allclose(O.j08_radius(m1, 0.2, 1e-6, 1e6), 2 * R1, rtol=1e-6)
     assert (O.j08_radius(m1, 0.1, 0.05, 0.06) >= 0.05).all() and (O.j08_radius(m1, 0.1, 0.05, 0.06) <= 0.06).all()
+
+
+def test_log_space_extrapolation_is_exact_for_exponential_fields():
+    """Eq. jaroszExtrapolation averages first-order expansions of ln L: for
+    L = exp(a + g . x) (so grad L_k / L_k = g) every expansion equals ln L(x')
+    and the result is exp(a + g . x') exactly, whatever the weights; one
+    cache point gives L_k exp(g_k . (x' - x_k)); a point with L_k <= 0 takes
+    no part."""
+    rng = np.random.default_rng(81)
+    K, Q = 40, 300
+    cp = rng.uniform(0.2, 0.8, (K, 3)).astype(np.float32)
+    a, gv = 0.3, np.array([1.5, -2.0, 0.7])
+    cv = np.exp(a + cp.astype(np.float64) @ gv)
+    cg = cv[:, None] * gv[None, :]
+    cR = rng.uniform(0.15, 0.4, K).astype(np.float32)
+    q = rng.uniform(0.2, 0.8, (Q, 3)).astype(np.float32)
+    L, cov = O.interpolate_log(cp, cv, cg, cR, q)
+    assert cov.sum() > Q // 2
+    np.testing.assert_allclose(L[cov], np.exp(a + q[cov].astype(np.float64) @ gv), rtol=1e-12)
+    Lin, _ = O.interpolate(cp, cv, cg, cR, q)  # linear space is not exact here
+    assert np.abs(Lin[cov] / np.exp(a + q[cov].astype(np.float64) @ gv) - 1).max() > 1e-3
+    one, c1 = O.interpolate_log(cp[:1], cv[:1], cg[:1] * 0.5, cR[:1], q)
+    d = q[c1].astype(np.float64) - cp[0].astype(np.float64)
+    np.testing.assert_allclose(one[c1], cv[0] * np.exp(d @ (0.5 * gv)), rtol=1e-12)
+    neg = cv.copy()
+    neg[0] = -1.0
+    _, cn = O.interpolate_log(cp[:1], neg[:1], cg[:1], cR[:1], q)
+    assert not cn.any()
