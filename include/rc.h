@@ -562,6 +562,14 @@ int rc_composite(const int64_t* offsets, int64_t n_rays, int32_t spp, const doub
  * except R (FP32).  Records with n_theta < 2, n_phi outside [5, RC_MAX_NPHI]
  * get NaN outputs.  Shadow segments from the scene's light bins of these
  * lights (built on the first call). */
+/* The comparison method's extrapolation from a cache (Eq. jaroszExtrapolation):
+ * L(x') = exp( sum_k [ln L_k + (grad L_k / L_k) . (x' - x_k)] w_k / sum_k w_k )
+ * over the cache points whose radius contains x' (the FP32 ball test and the
+ * cubic weights of rc_interp), channels summed; points with L_k <= 0 take no
+ * part.  out device double[Q] (0 where uncovered), hits device int32[Q] or
+ * NULL. */
+int rc_interp_log(const float* cache_pos, const double* cache_value, const double* cache_grad, const float* cache_R,
+                  int64_t K, const float* query, int64_t Q, double* out, int32_t* hits, void* stream);
 int rc_j08_records(const rc_scene* scene, const rc_medium* medium, const rc_point_light* lights, int n_lights,
                    const float* pos, const int32_t* n_theta, const int32_t* n_phi, int64_t P,
                    const rc_params* params, float eps, float r_min, float r_max, double* value, double* grad,

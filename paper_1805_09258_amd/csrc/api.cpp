@@ -1196,6 +1196,16 @@ int rc_interp(const float* cache_pos, const double* cache_value, const double* c
   return RC_OK;
 }
 
+int rc_interp_log(const float* cache_pos, const double* cache_value, const double* cache_grad, const float* cache_R,
+                  int64_t K, const float* query, int64_t Q, double* out, int32_t* hits, void* stream) {
+  if (K < 0 || K > 0x7fffffff || Q < 0 || Q > 0x7fffffff) return fail(RC_EINVAL, "K or Q out of range");
+  if ((K > 0 && (!cache_pos || !cache_value || !cache_grad || !cache_R)) || (Q > 0 && (!query || !out)))
+    return fail(RC_EINVAL, "NULL pointer");
+  RC_HIP(rc::launch_interp_log(cache_pos, cache_value, cache_grad, cache_R, (int)K, query, (int)Q, out, hits,
+                               static_cast<hipStream_t>(stream)));
+  return RC_OK;
+}
+
 int rc_ellipsoid_form(const float* axes, int64_t K, float* form, float* r_max, void* stream) {
   if (K < 0 || K > 0x7fffffff) return fail(RC_EINVAL, "K out of range");
   if (K > 0 && (!axes || !form)) return fail(RC_EINVAL, "NULL pointer");

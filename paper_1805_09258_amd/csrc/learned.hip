@@ -1143,6 +1143,10 @@ __global__ __launch_bounds__(256) void place_cover_grid_kernel(const float* __re
 // cval [K][2] and cgrad [K][2][3] are records (the two channels are summed);
 // if ref [Q][2] is given, block b writes (sum (L - L_ref)^2, sum L_ref^2) over
 // its covered queries to err[2b], err[2b+1].
+// LOG: the comparison method's extrapolation (Eq. jaroszExtrapolation): the
+// same weights over first-order expansions of ln L (value ln L_k, gradient
+// grad L_k / L_k; points with L_k <= 0 take no part), exponentiated.
+template <bool LOG>
 __global__ __launch_bounds__(256) void interp_kernel(const float* __restrict__ cpos, const double* __restrict__ cval,
                                                      const double* __restrict__ cgrad, const float* __restrict__ cR,
                                                      const float* __restrict__ cform, int K,
@@ -1182,7 +1186,9 @@ __global__ __launch_bounds__(256) void interp_kernel(const float* __restrict__ c
     float c0 = 0.f, c1 = 0.f, c2 = 0.f, cr = 0.f;
     if (k < K) {
       c0 = cpos[3 * k], c1 = cpos[3 * k + 1], c2 = cpos[3 * k + 2], cr = cform ? 0.f : cR[k];
-      if (cform) {
+      if (LOG && !(cval[2 * k] + cval[2 * k + 1] > 0.0)) {
+        keep = false;
+      } else if (cform) {
         keep = true;
       } else {
         // distance from the ball's centre to the queries' box; a query inside
@@ -1212,10 +1218,13 @@ __global__ __launch_bounds__(256) void interp_kernel(const float* __restrict__ c
       sp[4 * at + 3] = cr;
       if (cform)
         for (int e = 0; e < 6; e++) sf[6 * at + e] = cform[6 * k + e];
-      sv[4 * at] = cval[2 * k] + cval[2 * k + 1];
-      sv[4 * at + 1] = cgrad[6 * k] + cgrad[6 * k + 3];
-      sv[4 * at + 2] = cgrad[6 * k + 1] + cgrad[6 * k + 4];
-      sv[4 * at + 3] = cgrad[6 * k + 2] + cgrad[6 * k + 5];
+      const double lv = cval[2 * k] + cval[2 * k + 1];
+      const double gx = cgrad[6 * k] + cgrad[6 * k + 3], gy = cgrad[6 * k + 1] + cgrad[6 * k + 4],
+                   gz = cgrad[6 * k + 2] + cgrad[6 * k + 5];
+      sv[4 * at] = LOG ? log(lv) : lv;
+      sv[4 * at + 1] = LOG ? gx / lv : gx;
+      sv[4 * at + 2] = LOG ? gy / lv : gy;
+      sv[4 * at + 3] = LOG ? gz / lv : gz;
     }
     __syncthreads();
     for (int j = 0; j < m; j++) {
@@ -1245,7 +1254,7 @@ __global__ __launch_bounds__(256) void interp_kernel(const float* __restrict__ c
       }
     }
   }
-  const double L = den > 0.0 ? num / den : 0.0;
+  const double L = den > 0.0 ? (LOG ? exp(num / den) : num / den) : 0.0;
   if (i < Q) {
     out[i] = L;
     if (hits) hits[i] = den > 0.0 ? nh : 0;
@@ -1396,8 +1405,17 @@ hipError_t launch_interp(const float* cpos, const double* cval, const double* cg
                          double* err, hipStream_t s) {
   const int blocks = (Q + 255) / 256;
   if (blocks > 0)
-    hipLaunchKernelGGL(interp_kernel, dim3(blocks), dim3(256), 0, s, cpos, cval, cgrad, cR, cform, K, q, Q, out, hits,
-                       ref, err);
+    hipLaunchKernelGGL(interp_kernel<false>, dim3(blocks), dim3(256), 0, s, cpos, cval, cgrad, cR, cform, K, q, Q,
+                       out, hits, ref, err);
+  return hipGetLastError();
+}
+
+hipError_t launch_interp_log(const float* cpos, const double* cval, const double* cgrad, const float* cR, int K,
+                             const float* q, int Q, double* out, int* hits, hipStream_t s) {
+  const int blocks = (Q + 255) / 256;
+  if (blocks > 0)
+    hipLaunchKernelGGL(interp_kernel<true>, dim3(blocks), dim3(256), 0, s, cpos, cval, cgrad, cR, nullptr, K, q, Q,
+                       out, hits, nullptr, nullptr);
   return hipGetLastError();
 }
 

@@ -79,6 +79,8 @@ hipError_t launch_place_cover_grid(const float* cand, const PlaceGrid& g, unsign
 hipError_t launch_interp(const float* cpos, const double* cval, const double* cgrad, const float* cR,
                          const float* cform, int K, const float* q, int Q, double* out, int* hits, const double* ref,
                          double* err, hipStream_t s);
+hipError_t launch_interp_log(const float* cpos, const double* cval, const double* cgrad, const float* cR, int K,
+                             const float* q, int Q, double* out, int* hits, hipStream_t s);
 hipError_t launch_ellipsoid_form(const float* axes, int K, float* form, float* Rmax, hipStream_t s);
 hipError_t launch_mlp_init(void* params, float* state, unsigned long long seed, hipStream_t s);
 hipError_t launch_mlp_sync(void* params, const float* master, hipStream_t s);

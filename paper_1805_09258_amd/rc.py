@@ -65,7 +65,7 @@ EXPORTS = ["rc_scene_create", "rc_scene_destroy", "rc_scene_info", "rc_bvh_build
            "rc_mlp_load", "rc_mlp_fit_features", "rc_mlp_forward", "rc_mlp_radius", "rc_mlp_train_workspace_bytes",
            "rc_mlp_train_step", "rc_place_gather", "rc_place_accept", "rc_place_cover", "rc_place_cover_grid",
            "rc_ellipsoid_form", "rc_interp", "rc_march_count", "rc_march_emit", "rc_composite",
-           "rc_j08_records",
+           "rc_j08_records", "rc_interp_log",
            "rc_last_error", "rc_version"]
 
 _LIB = None
@@ -160,6 +160,8 @@ def lib():
         L.rc_j08_records.argtypes = [vp, C.POINTER(rc_medium), C.POINTER(rc_point_light), i32, vp, vp, vp, i64,
                                      C.POINTER(rc_params), f32, f32, f32, vp, vp, vp, vp, vp]
         L.rc_j08_records.restype = i32
+        L.rc_interp_log.argtypes = [vp, vp, vp, vp, i64, vp, i64, vp, vp, vp]
+        L.rc_interp_log.restype = i32
         L.rc_last_error.restype = C.c_char_p
         L.rc_version.restype = C.c_char_p
         _LIB = L
@@ -467,6 +469,12 @@ def rc_j08_records(scene, sigma_s, sigma_a, lights, pos, n_theta, n_phi, params,
     return _check(lib().rc_j08_records(scene, C.byref(med), li, n, _ptr(pos), _ptr(n_theta), _ptr(n_phi),
                                        int(pos.shape[0]), C.byref(params), float(eps), float(r_min), float(r_max),
                                        _ptr(value), _ptr(grad), _ptr(moments), _ptr(R), _stream(stream)))
+
+
+def rc_interp_log(cache_pos, cache_value, cache_grad, cache_R, query, out, hits=None, stream=None):
+    return _check(lib().rc_interp_log(_ptr(cache_pos), _ptr(cache_value), _ptr(cache_grad), _ptr(cache_R),
+                                      int(cache_pos.shape[0]), _ptr(query), int(query.shape[0]), _ptr(out), _ptr(hits),
+                                      _stream(stream)))
 
 
 def rc_version():

@@ -110,3 +110,33 @@ def test_invalid_sample_counts_give_nan_and_calls_are_deterministic(dev):
                               prm, 0.0, RMIN, RMAX, z, z, z, z)  # eps must be > 0
         finally:
             sc.close()
+
+
+@pytest.mark.parametrize("K,Q", [(1, 40), (300, 3000)])
+def test_log_space_extrapolation_matches_oracle(dev, K, Q):
+    """rc_interp_log against the oracle's Eq. jaroszExtrapolation: members
+    and counts exactly, values to 1e-6 like rc_interp (the GPU forms the
+    offset x' - x_k in FP32, relative error 6e-8, and the exponent multiplies
+    it by grad L_k / L_k, up to about 60 here); a point with a non-positive
+    value takes no part."""
+    rng = np.random.default_rng(K + 3)
+    cp = rng.uniform(0.2, 0.8, (K, 3)).astype(np.float32)
+    cv = rng.uniform(0.05, 2.0, (K, 2))
+    cv[0] = [-0.5, 0.2]  # sum <= 0: excluded
+    cg = rng.normal(size=(K, 2, 3))
+    cR = rng.uniform(0.05, 0.3, K).astype(np.float32)
+    q = rng.uniform(0.15, 0.85, (Q, 3)).astype(np.float32)
+    if K == 1:
+        cv[0] = [0.7, 0.4]
+        q = (cp[0] + rng.uniform(-1, 1, (Q, 3)) * cR[0]).astype(np.float32)
+    T = lambda a: torch.as_tensor(a, device=dev)  # noqa: E731
+    out = torch.full((Q,), float("nan"), dtype=torch.float64, device=dev)
+    hits = torch.full((Q,), -1, dtype=torch.int32, device=dev)
+    rc.rc_interp_log(T(cp), T(cv), T(cg), T(cR), T(q), out, hits)
+    torch.cuda.synchronize()
+    L, cov = O.interpolate_log(cp, cv.sum(1), cg.sum(1), cR, q)
+    pos = cv.sum(1) > 0
+    members = np.array([(O._within32(q[i][None], cp, cR) & pos).sum() for i in range(Q)])
+    np.testing.assert_array_equal(hits.cpu().numpy(), np.where(cov, members, 0))
+    assert cov.sum() > Q // 10
+    np.testing.assert_allclose(out.cpu().numpy(), L, rtol=1e-6, atol=0)
