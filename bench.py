@@ -155,6 +155,13 @@ def learned_vs_plain(dev):
         res[k] = r[k]
     an = r["anisotropic_plain"]
     res["anisotropic_plain"] = {k: an[k] for k in keep if k in an}
+    res["j08_by_eps"] = {e: {k: v[k] for k in keep + ("eps_j08",) if k in v} for e, v in r["j08_by_eps"].items()}
+    eq = r["j08_equal_error"]
+    res["j08_equal_error"] = None if eq is None else {k: eq[k] for k in keep + ("eps_j08",) if k in eq}
+    if eq is not None:
+        res["j08_equal_error"]["candidates_per_s"] = r["candidates"] / eq["seconds"]
+        res["j08_equal_error"]["points_over_ours"] = eq["accepted"] / pl["accepted"]
+        res["j08_equal_error"]["seconds_over_ours"] = eq["seconds"] / pl["seconds"]
     res["anisotropic_plain"]["candidates_per_s"] = r["candidates"] / an["seconds"]
     res["plain"]["candidates_per_s"] = r["candidates"] / pl["seconds"]
     res["learned"]["candidates_per_s"] = r["candidates"] / lp["seconds"]

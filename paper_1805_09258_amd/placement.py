@@ -48,6 +48,8 @@ class CacheConfig:
     common_random: bool = True   # every record draws the same random numbers (id record_id)
     record_id: int = 7_000_003   # that id
     anisotropic: bool = False    # plain pipeline: ellipsoidal points (Eq. radiusAniso3D) instead of balls
+    method: str = "ours"         # "j08": the comparison method's radius (Eq. jaroszRadius) and log-space reads
+    j08_eps: float = 0.3         # its tolerance (the paper's Patio comparison)
 
 
 class SceneContext:
@@ -75,6 +77,19 @@ class SceneContext:
                              rec_base=rec_base, common_random=common_random, max_n_theta=max_n_theta)
         rc.rc_records_batched(self.scene.handle, w.sigma_s, w.sigma_a, w.lights, pos, nth[:P], nph[:P], prm, None,
                               False, -1, value[:P], grad[:P], hess[:P], ws)
+        return P
+
+    def j08_records(self, pos, value, grad, moments, R, nth, nph, max_n_phi, rec_base, eps, r_min, r_max,
+                    common_random=False):
+        """The comparison method's records and radii at pos (rc_j08_records)."""
+        w = self.w
+        P = pos.shape[0]
+        if P == 0:
+            return 0
+        prm = rc.make_params(w.ring_step, w.max_rings, max(int(max_n_phi), 5), w.seed, rec_base=rec_base,
+                             common_random=common_random)
+        rc.rc_j08_records(self.scene.handle, w.sigma_s, w.sigma_a, w.lights, pos, nth[:P], nph[:P], prm, eps, r_min,
+                          r_max, value[:P], grad[:P], moments[:P], R[:P])
         return P
 
     def probe(self, pos, feat, cfg: CacheConfig):
@@ -109,6 +124,7 @@ class PlacementResult:
     K: int
     stats: dict = field(default_factory=dict)
     form: object = None          # device float[K][6] (ellipsoids of anisotropic points) or None
+    log_space: bool = False      # read with the comparison method's log-space extrapolation
 
 
 class Placer:
@@ -116,6 +132,8 @@ class Placer:
 
     def __init__(self, ctx: SceneContext, cands: W.GridCandidates, cfg: CacheConfig, device):
         import torch
+        if cfg.method not in ("ours", "j08") or (cfg.method == "j08" and cfg.anisotropic):
+            raise ValueError("method is 'ours' or 'j08' (the comparison method has no anisotropic points)")
         self.ctx, self.cands, self.cfg, self.dev = ctx, cands, cfg, device
         C, B = cands.n, cfg.batch
         t = lambda a: torch.as_tensor(a, device=device)  # noqa: E731
@@ -131,6 +149,7 @@ class Placer:
         self.bgrad = torch.zeros((B, 2, 3), dtype=torch.float64, device=device)
         self.bhess = torch.zeros((B, 2, 6), dtype=torch.float64, device=device)
         self.bws = torch.zeros(rc.rc_workspace_size(B), dtype=torch.uint8, device=device)
+        self.bmom = torch.zeros((B, 2), dtype=torch.float64, device=device) if cfg.method == "j08" else None
         self.acc = torch.zeros(C, dtype=torch.int32, device=device)
         self.accR = torch.zeros(C, dtype=torch.float32, device=device)
         self.accpos = torch.zeros((C, 3), dtype=torch.float32, device=device)
@@ -185,10 +204,17 @@ class Placer:
             m = self._gather(batch)
             if m == 0:
                 break
-            self._records(self.bpos[:m], self.bval, self.bgrad, self.bhess, self.bws, self.nth, self.nph)
             aniso = cfg.anisotropic
-            rc.rc_radius(self.bval[:m], self.bhess[:m], cfg.eps, cfg.r_min, cfg.r_max, self.bR[:m],
-                         self.baxes[:m] if aniso else None)
+            if cfg.method == "j08":  # values, occlusion-unaware gradients and the gradient-norm radius
+                self.ctx.j08_records(self.bpos[:m], self.bval, self.bgrad, self.bmom, self.bR, self.nth, self.nph,
+                                     cfg.n_phi, cfg.record_id if cfg.common_random else self._next_id, cfg.j08_eps,
+                                     cfg.r_min, cfg.r_max, common_random=cfg.common_random)
+                if not cfg.common_random:
+                    self._next_id += m
+            else:
+                self._records(self.bpos[:m], self.bval, self.bgrad, self.bhess, self.bws, self.nth, self.nph)
+                rc.rc_radius(self.bval[:m], self.bhess[:m], cfg.eps, cfg.r_min, cfg.r_max, self.bR[:m],
+                             self.baxes[:m] if aniso else None)
             if aniso:  # ellipsoids; bR becomes the largest radius (the cover's search bound)
                 rc.rc_ellipsoid_form(self.baxes[:m], self.bform[:m], self.bR[:m])
             rc.rc_place_accept(self.cand, self.bidx, self.bR, self.covered, self.state, self.acc, self.accR,
@@ -202,7 +228,7 @@ class Placer:
     def _result(self, stats, form=None):
         K = int(self.state[1].item())
         return PlacementResult(self.accpos[:K], self.cval[:K], self.cgrad[:K], self.accR[:K], K, stats,
-                               None if form is None else form[:K])
+                               None if form is None else form[:K], self.cfg.method == "j08")
 
     # -- pipelines ------------------------------------------------------------
     def plain(self, batch=None):
@@ -264,8 +290,8 @@ class Placer:
         rounds for whatever is left (fewer than plain_below candidates, or
         after the last pass)."""
         import torch
-        if self.cfg.anisotropic:
-            raise ValueError("the learned pipeline places isotropic points (the network predicts one radius)")
+        if self.cfg.anisotropic or self.cfg.method != "ours":
+            raise ValueError("the learned pipeline places isotropic points with this method's radius")
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         self._reset()
@@ -340,10 +366,15 @@ def cache_error(res: PlacementResult, query, ref_value, device, lights=None, lig
     hits = torch.zeros(Q, dtype=torch.int32, device=device)
     nb = (Q + 255) // 256
     err = torch.zeros(2 * max(nb, 1), dtype=torch.float64, device=device)
-    rc.rc_interp(res.pos, res.value, res.grad, res.R, query, out, hits, ref_value, err, cache_form=res.form)
-    e = err.view(-1, 2).sum(0).cpu().numpy()
-    cov = hits > 0
     ref = ref_value.sum(1)
+    if res.log_space:  # the comparison method reads its cache in log space (Eq. jaroszExtrapolation)
+        rc.rc_interp_log(res.pos, res.value, res.grad, res.R, query, out, hits)
+        c = hits > 0
+        e = np.array([float(((out - ref)[c] ** 2).sum().item()), float((ref[c] ** 2).sum().item())])
+    else:
+        rc.rc_interp(res.pos, res.value, res.grad, res.R, query, out, hits, ref_value, err, cache_form=res.form)
+        e = err.view(-1, 2).sum(0).cpu().numpy()
+    cov = hits > 0
     d = {"rel_l2": float(np.sqrt(e[0] / e[1])) if e[1] > 0 else float("nan"),
          "covered": float(cov.double().mean().item()) if Q else 0.0,
          "mean_hits": float(hits.double().mean().item()) if Q else 0.0}
@@ -449,7 +480,7 @@ def training_set(seeds, P, cfg: CacheConfig, device):
 
 def compare(device, train_seeds=range(1000, 1100), P_train=10_000, val_seed=1099, eval_seed=4242, grid_n=128,
             n_test=100_000, safeties=(0.9, 1.0, 1.1, 1.2, 1.35), epochs=20, cfg: CacheConfig | None = None, log=None,
-            plain_batches=(512, 1024, 2048, 4096), error_band=0.05):
+            plain_batches=(512, 1024, 2048, 4096), error_band=0.05, j08_eps=(0.3, 0.5, 0.7, 1.0, 3.0)):
     """Train the radius MLP; pick the learned pipeline's safety factor on a
     validation scene (the fastest whose cache error is within error_band of
     the plain cache's there); then place caches over grid_n^3 candidates of a
@@ -548,6 +579,20 @@ def compare(device, train_seeds=range(1000, 1100), P_train=10_000, val_seed=1099
     if log:
         log("anisotropic plain", out["anisotropic_plain"])
     del placer_a
+    # the comparison method's caches: the same greedy rule with its radius (Eq. jaroszRadius) and
+    # log-space reads, over tolerances from the paper's 0.3 up; the two tolerances mean different
+    # things, so the caches are compared where the comparison method reaches this method's error
+    out["j08_by_eps"] = {}
+    for ej in j08_eps:
+        placer_j = Placer(ctx, cands, replace(cfg, method="j08", j08_eps=ej), device)
+        rj = median_run(lambda: placer_j.plain(best["batch"]))
+        out["j08_by_eps"][str(ej)] = dict(rj.stats, eps_j08=ej, **cache_error(rj, q, ref, device, we.lights))
+        if log:
+            log(f"comparison method eps {ej}", out["j08_by_eps"][str(ej)])
+        del placer_j
+    out["j08_plain"] = out["j08_by_eps"][str(j08_eps[0])]
+    eq = [v for v in out["j08_by_eps"].values() if v["rel_l2"] <= best["rel_l2"] * (1 + error_band)]
+    out["j08_equal_error"] = max(eq, key=lambda v: v["eps_j08"]) if eq else None
     r = median_run(lambda: placer.learned(mlp, safety))
     out["learned"] = dict(r.stats, safety=safety, **cache_error(r, q, ref, device, we.lights))
     if log:

@@ -140,3 +140,37 @@ def test_log_space_extrapolation_matches_oracle(dev, K, Q):
     np.testing.assert_array_equal(hits.cpu().numpy(), np.where(cov, members, 0))
     assert cov.sum() > Q // 10
     np.testing.assert_allclose(out.cpu().numpy(), L, rtol=1e-6, atol=0)
+
+
+def test_comparison_method_cache_obeys_the_insertion_rule(dev):
+    """A cache of the comparison method (its radius, eps 0.3) over a grid of
+    candidates in a seeded visiting order: every candidate ends inside a
+    cached ball, no cached point lies inside the ball of a point cached
+    before it, and the cache is read in log space."""
+    from paper_1805_09258_amd.placement import CacheConfig, Placer, SceneContext, cache_error, direct_records
+    w = W.make_c4_scene(77, P=1)
+    ctx = SceneContext(w)
+    cands = W.GridCandidates(20, w.box_lo, w.box_hi, seed=78)
+    cfg = CacheConfig(n_theta=8, n_phi=32, batch=512, method="j08")
+    res = Placer(ctx, cands, cfg, dev).plain()
+    _say("comparison method cache", res.stats, res.K)
+    assert res.K > 0 and res.log_space
+    pos = cands.pos.astype(np.float32)
+    acc_pos = res.pos.cpu().numpy()
+    R = res.R.cpu().numpy()
+    inside = np.zeros(cands.n, bool)
+    for k in range(res.K):
+        if k:
+            assert not O._within32(acc_pos[k][None], acc_pos[:k], R[:k]).any(), f"cached point {k} was covered"
+        inside |= O._within32(pos, acc_pos[k][None], R[k]) | (np.abs(pos - acc_pos[k]).max(1) == 0)
+    assert inside.all()
+    q = torch.as_tensor(W.uniform_points(2000, w.box_lo, w.box_hi, 79), device=dev)
+    ref, _, _ = direct_records(ctx, q, cfg.n_theta, cfg.n_phi, cfg.record_id, dev, common_random=True)
+    e = cache_error(res, q, ref, dev)
+    _say("comparison method cache error", e)
+    # its radii (median about 0.024 at eps 0.3) are below this grid's spacing
+    # (0.05): the balls cover the candidates, not the whole box
+    assert np.isfinite(e["rel_l2"]) and 0.2 < e["covered"] < 1.0
+    with pytest.raises(ValueError):
+        Placer(ctx, cands, CacheConfig(method="j08", anisotropic=True), dev)
+    ctx.close()
