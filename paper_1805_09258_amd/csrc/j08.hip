@@ -10,8 +10,10 @@
 //     rigidly, so only the light connection I exp(-mu d) / d^2 changes
 //     (visibility held): contribution * (-mu - 2 / d) (m - l) / d;
 //   radius: eps * sum_k L_k / sum_k |grad L_k| over the directions k.
-// One wavefront per record, one direction per lane; per-lane FP64 sums,
-// reduced across the wavefront in a fixed order.
+// One workgroup of kJ08Waves wavefronts per record, one direction per lane
+// (wavefront v takes the 64-direction chunks v, v + kJ08Waves, ...); per-lane
+// FP64 sums, reduced across each wavefront and then over the wavefronts in
+// order through LDS.
 #include <hip/hip_runtime.h>
 
 #include "device.hpp"
@@ -29,24 +31,27 @@ RC_DEV double wave_sum(double v) {
 
 }  // namespace
 
+constexpr int kJ08Waves = 4;  // wavefronts per record
+
 template <int STACK>
-__global__ __launch_bounds__(64) void j08_kernel(J08Args g) {
-  __shared__ int stack[STACK * kWave];
-  const int lane = threadIdx.x;
-  int* stk = stack + lane;
+__global__ __launch_bounds__(kWave * kJ08Waves) void j08_kernel(J08Args g) {
+  __shared__ int stack[kJ08Waves * STACK * kWave];
+  __shared__ double part[kJ08Waves][10];
+  const int lane = threadIdx.x & (kWave - 1), wv = threadIdx.x / kWave;
+  int* stk = stack + wv * STACK * kWave + lane;
   TraceCount tc;
   const double mu = (double)g.sigma_s + (double)g.sigma_a;
   const float muf = g.sigma_s + g.sigma_a;
   const double ms_scale = (double)g.sigma_s / (4.0 * kPi);
   for (int rec = blockIdx.x; rec < g.P; rec += gridDim.x) {
     const int nth = g.n_theta[rec], nph = g.n_phi[rec];
-    if (nth < 2 || nph < 5 || nph > RC_MAX_NPHI) {  // invalid sample counts: NaN outputs
-      if (lane < 2) {
+    if (nth < 2 || nph < 5 || nph > RC_MAX_NPHI) {  // invalid sample counts: NaN outputs (same for the workgroup)
+      if (threadIdx.x < 2) {
         g.value[2 * rec + lane] = __builtin_nan("");
         g.moments[2 * rec + lane] = __builtin_nan("");
         for (int k = 0; k < 3; k++) g.grad[6 * rec + 3 * lane + k] = __builtin_nan("");
       }
-      if (lane == 0) g.R[rec] = __builtin_nanf("");
+      if (threadIdx.x == 0) g.R[rec] = __builtin_nanf("");
       continue;
     }
     const float3 x = make_float3(g.pos[3 * rec], g.pos[3 * rec + 1], g.pos[3 * rec + 2]);
@@ -55,7 +60,7 @@ __global__ __launch_bounds__(64) void j08_kernel(J08Args g) {
     const int N = nth * nph;
     double vs = 0.0, vm = 0.0, lsum = 0.0, nsum = 0.0;
     double gs[3] = {0.0, 0.0, 0.0}, gm[3] = {0.0, 0.0, 0.0};
-    for (int base = 0; base < N; base += kWave) {
+    for (int base = wv * kWave; base < N; base += kWave * kJ08Waves) {
       const int s = base + lane;
       if (s >= N) continue;
       const int a = s / nph, b = s - a * nph;
@@ -138,18 +143,29 @@ __global__ __launch_bounds__(64) void j08_kernel(J08Args g) {
       gm[i] = wave_sum(gm[i]);
     }
     if (lane == 0) {
-      const double inv = 1.0 / N;
-      g.value[2 * rec] = vs * inv;
-      g.value[2 * rec + 1] = vm * inv;
-      for (int i = 0; i < 3; i++) {
-        g.grad[6 * rec + i] = gs[i] * inv;
-        g.grad[6 * rec + 3 + i] = gm[i] * inv;
+      part[wv][0] = vs, part[wv][1] = vm, part[wv][2] = lsum, part[wv][3] = nsum;
+      for (int i = 0; i < 3; i++) part[wv][4 + i] = gs[i], part[wv][7 + i] = gm[i];
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      double t[10];
+      for (int q = 0; q < 10; q++) {
+        t[q] = 0.0;
+        for (int v = 0; v < kJ08Waves; v++) t[q] += part[v][q];
       }
-      g.moments[2 * rec] = lsum * inv;
-      g.moments[2 * rec + 1] = nsum * inv;
-      const double R = nsum > 0.0 ? (double)g.eps * lsum / nsum : (double)g.r_max;
+      const double inv = 1.0 / N;
+      g.value[2 * rec] = t[0] * inv;
+      g.value[2 * rec + 1] = t[1] * inv;
+      for (int i = 0; i < 3; i++) {
+        g.grad[6 * rec + i] = t[4 + i] * inv;
+        g.grad[6 * rec + 3 + i] = t[7 + i] * inv;
+      }
+      g.moments[2 * rec] = t[2] * inv;
+      g.moments[2 * rec + 1] = t[3] * inv;
+      const double R = t[3] > 0.0 ? (double)g.eps * t[2] / t[3] : (double)g.r_max;
       g.R[rec] = (float)fmin(fmax(R, (double)g.r_min), (double)g.r_max);
     }
+    __syncthreads();  // part is rewritten by the next record
   }
 }
 
@@ -157,10 +173,11 @@ hipError_t launch_j08(const J08Args& a, int depth, hipStream_t s) {
   if (a.P <= 0) return hipSuccess;
   const int grid = a.P < 65536 ? a.P : 65536;
   const int st = stack_variant(depth);
-  if (st <= 16) hipLaunchKernelGGL(j08_kernel<16>, dim3(grid), dim3(kWave), 0, s, a);
-  else if (st <= 32) hipLaunchKernelGGL(j08_kernel<32>, dim3(grid), dim3(kWave), 0, s, a);
-  else if (st <= 48) hipLaunchKernelGGL(j08_kernel<48>, dim3(grid), dim3(kWave), 0, s, a);
-  else hipLaunchKernelGGL(j08_kernel<64>, dim3(grid), dim3(kWave), 0, s, a);
+  const dim3 block(kWave * kJ08Waves);
+  if (st <= 16) hipLaunchKernelGGL(j08_kernel<16>, dim3(grid), block, 0, s, a);
+  else if (st <= 32) hipLaunchKernelGGL(j08_kernel<32>, dim3(grid), block, 0, s, a);
+  else if (st <= 48) hipLaunchKernelGGL(j08_kernel<48>, dim3(grid), block, 0, s, a);
+  else hipLaunchKernelGGL(j08_kernel<64>, dim3(grid), block, 0, s, a);
   return hipGetLastError();
 }
 
