@@ -364,3 +364,16 @@ def test_render_pass_entries_reject_bad_arguments_without_a_device():
     assert L.rc_composite(vp(8), 10, 0, vp(8), vp(8), vp(8), None) == rc.RC_EINVAL
     assert L.rc_composite(None, 8, 2, vp(8), vp(8), vp(8), None) == rc.RC_EINVAL
     assert rc.RC_MARCH_MAX_POINTS_PER_RAY == 1 << 20
+
+
+def test_comparison_method_entries_reject_bad_arguments_without_a_device():
+    L = rc.lib()
+    vp = rc.C.c_void_p
+    med = rc.rc_medium(1.0, 0.2)
+    prm = rc.make_params(0.1, 20, 64, 1)
+    args = (rc.C.byref(med), None, 0, vp(8), vp(8), vp(8), 4, rc.C.byref(prm))
+    outs = (vp(8), vp(8), vp(8), vp(8), None)
+    assert L.rc_j08_records(None, *args, 0.3, 1e-3, 0.4, *outs) == rc.RC_EINVAL  # no scene
+    assert L.rc_interp_log(vp(8), vp(8), vp(8), vp(8), -1, vp(8), 4, vp(8), None, None) == rc.RC_EINVAL
+    assert L.rc_interp_log(None, None, None, None, 3, vp(8), 4, vp(8), None, None) == rc.RC_EINVAL
+    assert L.rc_interp_log(vp(8), vp(8), vp(8), vp(8), 3, None, 4, vp(8), None, None) == rc.RC_EINVAL
