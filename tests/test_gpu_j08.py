@@ -174,3 +174,14 @@ def test_comparison_method_cache_obeys_the_insertion_rule(dev):
     with pytest.raises(ValueError):
         Placer(ctx, cands, CacheConfig(method="j08", anisotropic=True), dev)
     ctx.close()
+
+
+def test_c3_mixed_sample_counts_match_oracle(dev):
+    """128 points of the 100k-triangle slab scene with 256 to 4096 directions
+    each (several strata shapes in one launch, a deeper BVH)."""
+    w = W.make_c3().subset(np.arange(128))
+    got = gpu_j08(w, dev)
+    ref = O.j08(O.Scene.from_workload(w), w.sigma_s, w.sigma_a, w.lights, w.pos, w.n_theta, w.n_phi,
+                ring_step=w.ring_step, max_rings=w.max_rings, seed=w.seed)
+    _say(f"C3 sample counts {int((w.n_theta * w.n_phi).min())}..{int((w.n_theta * w.n_phi).max())}")
+    _compare(got, ref, np.arange(w.n_rec), "C3[128] j08")
