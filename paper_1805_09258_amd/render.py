@@ -13,6 +13,10 @@ Results in 3D: 16 samples per pixel, uniform ray marching with step 0.1).
 3. The in-scattered radiance at every march point is interpolated from the
    final cache (Eq. radianceTaylor) and the pixels are composited.
 
+With CacheConfig(method="j08") the same pass runs the paper's comparison
+method: its records and gradient-norm radii place the cache, and the march
+points read it in log space.
+
 Every step runs in the library's kernels (rc.*); this module sequences the
 calls and holds device buffers.
 """
@@ -145,7 +149,10 @@ def render(ctx: SceneContext, cam: W.CameraRays, prepop: W.CameraRays, cfg: Cach
     M = m1.n_points
     L = torch.zeros(M, dtype=torch.float64, device=device)
     hits = torch.zeros(M, dtype=torch.int32, device=device)
-    rc.rc_interp(res.pos, res.value, res.grad, res.R, m1.points, L, hits)
+    if cfg.method == "j08":  # the comparison method reads its cache in log space (Eq. jaroszExtrapolation)
+        rc.rc_interp_log(res.pos, res.value, res.grad, res.R, m1.points, L, hits)
+    else:
+        rc.rc_interp(res.pos, res.value, res.grad, res.R, m1.points, L, hits)
     mark("interpolate")
     pix = torch.empty(cam.n_pixels, dtype=torch.float64, device=device)
     rc.rc_composite(m1.offsets, cam.spp, m1.weight, L, pix)

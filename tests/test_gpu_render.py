@@ -249,3 +249,23 @@ def test_render_pass_without_prepopulation_and_without_rays(dev):
     pix0, st0, _ = RD.render(ctx, none, none, cfg, dev)
     assert pix0.shape[0] == 0 and st0["cache_points"] == 0 and st0["march_points"] == 0
     ctx.close()
+
+
+def test_render_pass_of_the_comparison_method(dev):
+    """The same pass with the comparison method's records, radii and
+    log-space reads: the insertion rule holds, every march point is read
+    from a valid cache point, and the pixels are finite and positive on
+    average."""
+    w = W.make_c2(seed=33, P=1, n_soup=2000)
+    ctx = SceneContext(w)
+    cfg = CacheConfig(n_theta=8, n_phi=32, batch=256, method="j08", j08_eps=0.7)
+    cam = W.CameraRays(16, 12, 2, eye=(0.5, 0.5, 0.04), look_at=(0.5, 0.5, 1.0), fov_deg=60.0, seed=12)
+    pre = W.CameraRays(16, 12, 1, eye=(0.5, 0.5, 0.04), look_at=(0.5, 0.5, 1.0), fov_deg=60.0, seed=13, shuffle=True)
+    pix, st, (m1, res, L, hits, cand, pl) = RD.render(ctx, cam, pre, cfg, dev)
+    _say("comparison-method render", st)
+    assert res.log_space and st["uncovered_after"] == 0 and (hits > 0).all()
+    _check_insertion_rule(cand.cpu().numpy(), pl.acc[:res.K].cpu().numpy().astype(np.int64), res.R.cpu().numpy(),
+                          st["prepop_cache"])
+    p = pix.cpu().numpy()
+    assert np.isfinite(p).all() and p.mean() > 0
+    ctx.close()
